@@ -1,0 +1,174 @@
+"""Benchmark: LML + adjoint gradient of the sparsity-discovering exact GP at
+N = 1,000,000 points on one MI355X (FP64).
+
+One step = one full evaluation through the C ABI (sdgp_lml_grad): point
+ordering, bump precompute, tile pruning, count + fill assembly of the sparse
+covariance, block CG on [y, z_1..z_32], SLQ log-det from the CG
+coefficients, and the adjoint gradient over all 387 hyperparameters.  Inputs
+(x, y) are resident in HBM before the timed region.
+
+Prints one JSON line: the headline value (evaluations per second), plus the
+assembly rate, the SpMV bandwidth, the roofline of the dominant kernel (the
+CG SpMM) measured with HIP events on the library's stream, and the oracle's
+rate on a bounded sample of the same workload (CPU).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "LML+grad evals/s at N=1M (FP64); assembly nnz/s; SpMV GB/s vs HBM peak"
+HBM_PEAK_GBPS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=3)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--probes", type=int, default=32)
+    p.add_argument("--rtol", type=float, default=1e-10)
+    p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    p.add_argument("--spmv-reps", type=int, default=50)
+    return p.parse_args()
+
+
+def cpu_baseline(w):
+    """Dense FP64 oracle (Cholesky LML + analytic gradient) on a spatial
+    window of the same point set (same density, kernel and hyperparameters),
+    scaled to N by the oracle's O(N^3) cost."""
+    from oracle import gp
+    side = 0.12
+    m = np.all(w.x < side, axis=1)
+    xs, ys = w.x[m], w.y[m]
+    ns = xs.shape[0]
+    t0 = time.perf_counter()
+    gp.lml_grad(w.desc, w.h, xs, ys)
+    dt = time.perf_counter() - t0
+    n = w.x.shape[0]
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": (1.0 / dt) * (ns / n) ** 3, "unit": "evals/s", "cores": threads, "kind": "oracle",
+            "sample": "dense FP64 oracle LML+gradient on the %d points of the [0,%.2f)^3 window of the "
+                      "same 1M-point set (%.2f s); value scaled to N=%d by (n/N)^3" % (ns, side, dt, n),
+            "sample_evals_per_s": 1.0 / dt, "sample_points": ns}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
+              "(see the sharding paragraph of the design notes)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2205_09070_amd as sd
+    from paper_2205_09070_amd import workloads as wl
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda", 0)
+    w = wl.uniform3d_1m()
+    n = w.x.shape[0]
+    x = torch.from_numpy(w.x).to(dev)
+    y = torch.from_numpy(w.y).to(dev)
+    est = sd.estimator(probes=args.probes, seed=1, cg_rtol=args.rtol, cg_max_iter=20000)
+    ctx = sd.Context(0, timing=True)
+    print("bench: N=%d dim=%d n1=%d n2=%d probes=%d" % (n, w.desc.dim, w.desc.n1, w.desc.n2, args.probes),
+          file=sys.stderr, flush=True)
+    for i in range(args.warmup):
+        val, g, info = ctx.lml_grad(w.desc, x, y, w.h, est)
+        print("warmup %d: lml %.10g cg iters %d (%.1f ms)" % (i, val, info.cg_iters, sum(info.ms)),
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    infos = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        val, g, info = ctx.lml_grad(w.desc, x, y, w.h, est)
+        infos.append(info.to_dict())
+        print("step %d: lml %.10g cg iters %d" % (i, val, info.cg_iters), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    K = args.steps
+    value = K / dt
+    ms_step = 1000.0 * dt / K
+    # phases (mean over timed steps)
+    ms = np.mean(np.array([d["ms"] for d in infos]), axis=0)
+    nnz = infos[-1]["nnz"]
+    cand = infos[-1]["candidates"]
+    asm_ms = float(ms[0] + ms[1] + ms[2] + ms[3] + ms[4])
+    R = 1 + args.probes
+    spmm_launches = sum(d["spmm_launches"] for d in infos)
+    spmm_ms = sum(d["spmm_ms"] for d in infos)
+    spmm_avg_ms = spmm_ms / max(1, spmm_launches)
+    # algorithmic bytes of one CG SpMM launch: CSR (8 B value + 4 B column per
+    # entry, 8 B row pointer per row), P read once, Q written once
+    spmm_bytes = 12.0 * nnz + 8.0 * (n + 1) + 2.0 * 8.0 * n * R
+    spmm_gbps = spmm_bytes / (spmm_avg_ms * 1e-3) / 1e9
+    # plain SpMV (R = 1) on the assembled matrix in the solver's order
+    rp, col, vv, perm = ctx.kernel_assemble(w.desc, x, w.h, add_noise=True, sorted_order=True)
+    xv = torch.randn(n, dtype=torch.float64, device=dev)
+    yv = torch.empty_like(xv)
+    for _ in range(3):
+        ctx.csr_spmm(rp, col, vv, xv, out=yv)
+    s = ctx.stream
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(args.spmv_reps):
+        ctx.csr_spmm(rp, col, vv, xv, out=yv)
+    e1.record(s)
+    e1.synchronize()
+    spmv_ms = e0.elapsed_time(e1) / args.spmv_reps
+    spmv_bytes = 12.0 * nnz + 8.0 * (n + 1) + 8.0 * n + 8.0 * n
+    spmv_gbps = spmv_bytes / (spmv_ms * 1e-3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "uniform3d_n1000000: 1,000,000 points uniform in [0,1)^3, Wendland C2 core "
+                               "(~60 core neighbours/row) + 16x4 bump functions, SUM combine, "
+                               "32 Rademacher probes, CG rtol %g" % args.rtol,
+                   "points": n, "dim": 3, "n1": w.desc.n1, "n2": w.desc.n2, "n_hyper": int(len(w.h)),
+                   "probes": args.probes, "cg_rtol": args.rtol},
+        "nnz": int(nnz),
+        "nnz_per_row": nnz / n,
+        "candidates": int(cand),
+        "cg_iters": infos[-1]["cg_iters"],
+        "phase_ms": {"order": ms[0], "bump": ms[1], "prune": ms[2], "count": ms[3], "fill": ms[4],
+                     "cg": ms[5], "slq": ms[6], "adjoint": ms[7]},
+        "assembly_nnz_per_s": nnz / (asm_ms * 1e-3),
+        "spmv": {"ms": spmv_ms, "GBps": spmv_gbps, "frac_hbm": spmv_gbps / HBM_PEAK_GBPS, "bytes": spmv_bytes},
+        "roofline": {"kernel": "k_cg_spmm (CG SpMM, %d right-hand sides)" % R, "bound": "hbm",
+                     "achieved": spmm_gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": spmm_gbps / HBM_PEAK_GBPS, "traffic": None,
+                     "avg_launch_ms": spmm_avg_ms, "launches": spmm_launches,
+                     "algorithmic_bytes_per_launch": spmm_bytes},
+        "lml": val,
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,204 @@
+/*
+ * sdgp.h -- sparsity-discovering exact Gaussian processes on AMD Instinct
+ * MI355X (gfx950): C ABI of libsdgp.so.
+ *
+ * Method: Noack, Krishnan, Risser, Reyes, "Exact Gaussian Processes for
+ * Massive Datasets via Non-Stationary Sparsity-Discovering Kernels"
+ * (arXiv:2205.09070).  The library assembles the sparse covariance of the
+ * compactly supported, non-stationary kernel of Section 2.2 and evaluates the
+ * log marginal likelihood of Section 2.1 (eqn:log_likelihood), its gradient
+ * and the posterior of eq:pred_distr, entirely on one GPU in FP64.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Points: x is a DEVICE array of n*dim doubles, row-major (point a's
+ *   coordinates at x[a*dim .. a*dim+dim-1]), 1 <= dim <= 4, in the caller's
+ *   order.  Observations y: DEVICE array of n doubles (prior mean 0: centre y
+ *   first).  All device arrays belong to the caller unless stated.
+ * - Hyperparameters h: HOST array of sdgp_num_hyper(desc) doubles laid out
+ *     [sigma2, r_core, {a_ij, beta_ij, r_ij, c_ij[0..dim-1]} for i<n1, j<n2
+ *      (j fastest), noise_var]
+ *   sigma2 > 0 scales the core, r_core > 0 is its support radius, (a, beta,
+ *   r, c) are the peak height, shape, radius and centre of bump function i's
+ *   j-th bump (eq:bump, with the indicator taken as "inside the ball"), and
+ *   noise_var >= 0 is the diagonal noise V = noise_var * I.  n1 <= 64.
+ * - Kernel (Section 2.2, eq:bump_kernel): with psi the core profile of
+ *   u = |x_a - x_b| / r_core and F_i(x) = sum_j f_ij(x),
+ *     PRODUCT: k(x_a, x_b) = sigma2 psi(u) * sum_i F_i(x_a) F_i(x_b)
+ *     SUM:     k(x_a, x_b) = sigma2 psi(u) + sum_i F_i(x_a) F_i(x_b)
+ *   Core KSTAT is eq:kstat; core WENDLAND_C2 is (1-u)^(l+1)((l+1)u+1) with
+ *   l = floor(dim/2)+2.
+ * - Stored pattern: (a, b) is stored iff a == b, or the core support
+ *   (|x_a-x_b|^2 < r_core^2) and/or (PRODUCT: and, SUM: or) a shared bump
+ *   support (both points strictly inside some ball of one bump function i).
+ *   Stored values may be exactly 0.0 (exp underflow inside a support).
+ * - Streams: every call enqueues its work on the stream given to
+ *   sdgp_create and returns after that work is complete when it writes host
+ *   outputs.  A context is not thread-safe; use one per stream.
+ * - Errors: a non-zero sdgp_status means the outputs are unspecified;
+ *   sdgp_last_error returns a message.  No C++ exception crosses the ABI.
+ *   INVALID_ARG: bad sizes, NULL pointers, non-finite or non-positive radii,
+ *   dim outside 1..4, n1 > 64.  OOM: device allocation failed.  NOT_SPD: CG
+ *   met p^T A p <= 0.  NOT_CONVERGED: some CG column missed cg_rtol within
+ *   cg_max_iter (outputs are then best effort).  HIP: a HIP runtime error.
+ *   CAPACITY: a caller buffer is too small (required size is returned).
+ */
+#ifndef SDGP_H
+#define SDGP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sdgp_ctx sdgp_ctx;
+
+typedef enum {
+  SDGP_OK = 0,
+  SDGP_ERR_INVALID_ARG = 1,
+  SDGP_ERR_OOM = 2,
+  SDGP_ERR_NOT_SPD = 3,
+  SDGP_ERR_NOT_CONVERGED = 4,
+  SDGP_ERR_HIP = 5,
+  SDGP_ERR_CAPACITY = 6
+} sdgp_status;
+
+enum { SDGP_CORE_WENDLAND_C2 = 0, SDGP_CORE_KSTAT = 1 };
+enum { SDGP_COMBINE_PRODUCT = 0, SDGP_COMBINE_SUM = 1 };
+enum { SDGP_PROBE_RADEMACHER = 0, SDGP_PROBE_IDENTITY = 2 };
+
+typedef struct {
+  int32_t dim;      /* 1..4 */
+  int32_t n1;       /* number of bump functions f_i, 0..64 */
+  int32_t n2;       /* bumps per function, >= 1 when n1 > 0 */
+  int32_t core;     /* SDGP_CORE_* */
+  int32_t combine;  /* SDGP_COMBINE_* */
+} sdgp_kernel_desc;
+
+/* Estimator options for the log-det (stochastic Lanczos quadrature on the
+ * coefficients of the CG solves) and the gradient's trace term (Hutchinson
+ * through the same solves).  SDGP_PROBE_RADEMACHER uses `probes` sign
+ * vectors from the counter-based SplitMix64 generator keyed by `seed`
+ * (probe p, row a of the caller's order: output number p*2^32 + a + 1,
+ * sign of bit 63); SDGP_PROBE_IDENTITY uses the n unit vectors, which makes
+ * both terms exact up to the CG tolerance (n <= 16384).  lanczos_steps caps
+ * the quadrature's tridiagonal size per probe (0: all CG steps). */
+typedef struct {
+  int32_t probes;          /* P, 1..64 for Rademacher */
+  int32_t lanczos_steps;   /* 0 = use every CG step */
+  int32_t kind;            /* SDGP_PROBE_* */
+  int32_t cg_max_iter;     /* > 0 */
+  uint64_t seed;
+  double cg_rtol;          /* per column: |r| <= cg_rtol |b| */
+} sdgp_estimator;
+
+/* Per-call diagnostics (all optional). ms[] phase times when timing is on:
+ * [0] ordering, [1] bump precompute, [2] pruning, [3] count+scan, [4] fill,
+ * [5] CG, [6] SLQ, [7] adjoint. */
+typedef struct {
+  int64_t nnz;             /* stored entries of K */
+  int64_t candidates;      /* candidate pairs examined by the fill pass */
+  int32_t cg_iters;        /* block-CG iterations run */
+  int32_t cg_iters_y;      /* iterations of the y column */
+  double cg_relres_max;    /* max final relative residual over columns */
+  double yKy;              /* y^T A^{-1} y */
+  double logdet;           /* estimate of ln det A */
+  double logdet_stderr;    /* standard error over probes (0 for identity) */
+  double ritz_min;         /* extreme Ritz values over probes */
+  double ritz_max;
+  double ms[8];
+  int64_t spmm_launches;   /* SpMM launches inside CG */
+  double spmm_ms;          /* summed SpMM launch time (timing on) */
+} sdgp_info;
+
+/* Create a context on HIP device `device` that enqueues on `hip_stream`
+ * (a hipStream_t, may be NULL for the null stream).  The context owns its
+ * device workspace, freed by sdgp_destroy. */
+sdgp_status sdgp_create(sdgp_ctx** out, int device, void* hip_stream);
+void sdgp_destroy(sdgp_ctx* ctx);
+/* Last error message of ctx (or of the last failed sdgp_create if NULL). */
+const char* sdgp_last_error(const sdgp_ctx* ctx);
+/* Enable (1) or disable (0) per-phase and per-SpMM-launch HIP-event timing. */
+sdgp_status sdgp_set_timing(sdgp_ctx* ctx, int enable);
+/* 2 + n1*n2*(3+dim) + 1, or -1 for an invalid descriptor. */
+int64_t sdgp_num_hyper(const sdgp_kernel_desc* desc);
+
+/* Number of stored entries of K for (x, h) (Section 2.3: the sparse
+ * covariance, assembled tile by tile); nnz_out is a host pointer. */
+sdgp_status sdgp_kernel_nnz(sdgp_ctx* ctx, const sdgp_kernel_desc* desc,
+                            const double* x, int64_t n, const double* h,
+                            int64_t* nnz_out);
+
+/* Assemble K (+ noise_var on the diagonal when add_noise) as CSR in the
+ * caller's point order with ascending columns (Section 2.2 kernel, Section
+ * 2.3 sparse assembly).  row_ptr: device int64[n+1]; col: device
+ * int32[capacity]; val: device double[capacity].  *nnz_out (host) receives
+ * the entry count; if it exceeds capacity the call returns SDGP_ERR_CAPACITY
+ * without writing col/val.  Requires nnz < 2^31. */
+sdgp_status sdgp_kernel_assemble(sdgp_ctx* ctx, const sdgp_kernel_desc* desc,
+                                 const double* x, int64_t n, const double* h,
+                                 int add_noise, int64_t* row_ptr, int32_t* col,
+                                 double* val, int64_t capacity, int64_t* nnz_out);
+
+/* Same matrix in the library's locality order (points sorted by grid cell):
+ * row/column s of the output is caller point perm[s]; perm: device
+ * int32[n].  This is the order the solver runs in. */
+sdgp_status sdgp_kernel_assemble_sorted(sdgp_ctx* ctx, const sdgp_kernel_desc* desc,
+                                        const double* x, int64_t n, const double* h,
+                                        int add_noise, int64_t* row_ptr, int32_t* col,
+                                        double* val, int32_t* perm, int64_t capacity,
+                                        int64_t* nnz_out);
+
+/* Y = A X for a caller CSR A (device int64 row_ptr[n+1], int32 col, double
+ * val) and row-major X, Y: device double[n*R], 1 <= R.  The SpMM of the CG
+ * solver (Section 2.5: iterative solves on the sparse covariance). */
+sdgp_status sdgp_csr_spmm(sdgp_ctx* ctx, int64_t n, const int64_t* row_ptr,
+                          const int32_t* col, const double* val,
+                          const double* X, int32_t R, double* Y);
+
+/* Log marginal likelihood (eqn:log_likelihood with V = noise_var I, prior
+ * mean 0, additive constant dropped):
+ *   ln L = -1/2 y^T A^{-1} y - 1/2 ln det A,  A = K + noise_var I,
+ * with A^{-1} y by CG (Section 2.5) and ln det A by stochastic Lanczos
+ * quadrature over the probe columns' CG coefficients.  lml_out: host. */
+sdgp_status sdgp_lml(sdgp_ctx* ctx, const sdgp_kernel_desc* desc, const double* x,
+                     const double* y, int64_t n, const double* h,
+                     const sdgp_estimator* est, double* lml_out, sdgp_info* info);
+
+/* ln L and its gradient with respect to every entry of h (grad_out: host
+ * double[sdgp_num_hyper]):
+ *   d lnL/d theta = 1/2 alpha^T (dA/dtheta) alpha - 1/2 tr(A^{-1} dA/dtheta),
+ * alpha = A^{-1} y, the trace by Hutchinson through the probe solves, and
+ * dA/dtheta recomputed per stored entry (never stored). */
+sdgp_status sdgp_lml_grad(sdgp_ctx* ctx, const sdgp_kernel_desc* desc, const double* x,
+                          const double* y, int64_t n, const double* h,
+                          const sdgp_estimator* est, double* lml_out, double* grad_out,
+                          sdgp_info* info);
+
+/* A population of B hyperparameter vectors on one shared point set: H is a
+ * host array B*n_h (member m at H[m*n_h]); lml_out: host double[B];
+ * grad_out: host double[B*n_h]; member_status: host int32[B] (per-member
+ * sdgp_status; one failing member does not affect the others); info: host
+ * array of B sdgp_info or NULL.  Returns SDGP_OK when the batch ran, even if
+ * some members failed. */
+sdgp_status sdgp_lml_grad_batched(sdgp_ctx* ctx, const sdgp_kernel_desc* desc,
+                                  const double* x, const double* y, int64_t n,
+                                  const double* H, int32_t B, const sdgp_estimator* est,
+                                  double* lml_out, double* grad_out,
+                                  int32_t* member_status, sdgp_info* info);
+
+/* Posterior at n0 test points x0 (device n0*dim) per eq:pred_distr with
+ * m0 = 0: mean = kappa^T A^{-1} y, var = k(x0,x0) - kappa^T A^{-1} kappa,
+ * kappa = k(x, x0).  mean_out, var_out: device double[n0]. */
+sdgp_status sdgp_posterior_mean_var(sdgp_ctx* ctx, const sdgp_kernel_desc* desc,
+                                    const double* x, const double* y, int64_t n,
+                                    const double* h, const double* x0, int64_t n0,
+                                    const sdgp_estimator* est, double* mean_out,
+                                    double* var_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SDGP_H */

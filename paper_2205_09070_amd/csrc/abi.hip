@@ -1,0 +1,335 @@
+// extern "C" entry points of libsdgp.so (declared in include/sdgp.h).
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "sdgp_internal.hpp"
+
+struct sdgp_ctx : sdgp::Ctx {};
+
+namespace sdgp {
+
+void Ctx::release_all() {
+  for (auto& b : buf)
+    if (b.p) { (void)hipFree(b.p); b.p = nullptr; b.bytes = 0; }
+  for (auto e : ev_pool) (void)hipEventDestroy(e);
+  ev_pool.clear();
+  ev_used = 0;
+}
+
+namespace {
+
+thread_local std::string g_create_error;
+
+template <class F>
+sdgp_status guarded(sdgp_ctx* ctx, F&& f) {
+  if (!ctx) return SDGP_ERR_INVALID_ARG;
+  try {
+    SDGP_HIP(hipSetDevice(ctx->device));
+    ctx->ev_used = 0;
+    f();
+    ctx->err.clear();
+    return SDGP_OK;
+  } catch (const Error& e) {
+    ctx->err = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    ctx->err = "host allocation failed";
+    return SDGP_ERR_OOM;
+  } catch (const std::exception& e) {
+    ctx->err = e.what();
+    return SDGP_ERR_HIP;
+  } catch (...) {
+    ctx->err = "unknown failure";
+    return SDGP_ERR_HIP;
+  }
+}
+
+// Phases shared by every evaluation on one hyperparameter vector.
+struct Assembled {
+  KParams kp;
+  Bumps b;
+  Csr A;
+  int64_t candidates = 0;
+};
+
+Assembled assemble_all(Ctx* c, const Sorted& s, const sdgp_kernel_desc& d, const double* h, bool add_noise,
+                       PhaseTimer* t) {
+  Assembled r;
+  r.kp = make_params(d, h);
+  r.b = bump_precompute(c, s, r.kp, h);
+  if (t) t->mark(2);
+  int32_t* iv_ptr;
+  int2* iv;
+  prune(c, s, r.kp, r.b, &iv_ptr, &iv);
+  if (t) t->mark(3);
+  r.A = assemble_sorted(c, s, r.kp, r.b, iv_ptr, iv, add_noise, &r.candidates, t);
+  if (t) t->mark(5);
+  return r;
+}
+
+void check_estimator(const sdgp_estimator* e, int64_t n) {
+  require(e != nullptr, "estimator is NULL");
+  require(e->kind == SDGP_PROBE_RADEMACHER || e->kind == SDGP_PROBE_IDENTITY, "unknown probe kind");
+  if (e->kind == SDGP_PROBE_RADEMACHER) require(e->probes >= 1 && e->probes <= 64, "probes must be 1..64");
+  if (e->kind == SDGP_PROBE_IDENTITY) require(n <= 16384, "identity probes need n <= 16384");
+  require(e->cg_max_iter >= 1, "cg_max_iter must be >= 1");
+  require(e->cg_rtol > 0.0 && std::isfinite(e->cg_rtol), "cg_rtol must be > 0");
+  require(e->lanczos_steps >= 0, "lanczos_steps must be >= 0");
+}
+
+void finish_timing(Ctx* c, PhaseTimer& t, sdgp_info* info) {
+  if (!c->timing || !info) return;
+  SDGP_HIP(hipStreamSynchronize(c->stream));
+  for (int k = 0; k < 8; ++k) {
+    info->ms[k] = 0.0;
+    if (t.set[k] && t.set[k + 1]) {
+      float ms = 0.0f;
+      SDGP_HIP(hipEventElapsedTime(&ms, t.marks[k], t.marks[k + 1]));
+      info->ms[k] = ms;
+    }
+  }
+  double tot = 0.0;
+  for (auto& pr : c->spmm_events) {
+    float ms = 0.0f;
+    SDGP_HIP(hipEventElapsedTime(&ms, pr.first, pr.second));
+    tot += ms;
+  }
+  info->spmm_ms = tot;
+  info->spmm_launches = (int64_t)c->spmm_events.size();
+}
+
+// One LML (+ gradient) evaluation on points already ordered.
+sdgp_status evaluate(Ctx* c, const Sorted& s, const double* ys, const sdgp_kernel_desc& d, const double* h,
+                     const sdgp_estimator& e, double* lml_out, double* grad_out, sdgp_info* info,
+                     PhaseTimer& t) {
+  Assembled as = assemble_all(c, s, d, h, true, &t);
+  const int kind = e.kind == SDGP_PROBE_IDENTITY ? PK_IDENTITY : PK_RADEMACHER;
+  const int P = kind == PK_IDENTITY ? (int)s.n : e.probes;
+  CgResult cg = block_cg(c, as.A, s, ys, kind, P, e.seed, e.cg_rtol, e.cg_max_iter, nullptr, 0, &t);
+  if (cg.not_spd) throw Error(SDGP_ERR_NOT_SPD, "CG met p^T A p <= 0: the covariance is not positive definite");
+  t.mark(6);
+  const double yKy = dot_device(c, ys, 1, cg.X, cg.R, s.n);
+  double logdet = 0.0, se = 0.0, rmin = 0.0, rmax = 0.0;
+  slq_from_cg(c, cg, kind, P, s.n, e.lanczos_steps, &logdet, &se, &rmin, &rmax);
+  t.mark(7);
+  if (lml_out) *lml_out = -0.5 * yKy - 0.5 * logdet;
+  if (grad_out) adjoint_gradient(c, s, as.kp, as.b, as.A, cg, kind, P, e.seed, h, grad_out);
+  t.mark(8);
+  if (info) {
+    info->nnz = as.A.nnz;
+    info->candidates = as.candidates;
+    info->cg_iters = cg.iters;
+    info->cg_iters_y = cg.iters_y;
+    info->cg_relres_max = cg.relres_max;
+    info->yKy = yKy;
+    info->logdet = logdet;
+    info->logdet_stderr = se;
+    info->ritz_min = rmin;
+    info->ritz_max = rmax;
+  }
+  finish_timing(c, t, info);
+  return cg.converged ? SDGP_OK : SDGP_ERR_NOT_CONVERGED;
+}
+
+}  // namespace
+}  // namespace sdgp
+
+using namespace sdgp;
+
+extern "C" {
+
+sdgp_status sdgp_create(sdgp_ctx** out, int device, void* hip_stream) {
+  if (!out) return SDGP_ERR_INVALID_ARG;
+  *out = nullptr;
+  try {
+    int count = 0;
+    SDGP_HIP(hipGetDeviceCount(&count));
+    require(device >= 0 && device < count, "no such HIP device");
+    SDGP_HIP(hipSetDevice(device));
+    sdgp_ctx* c = new sdgp_ctx();
+    c->device = device;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->cu_count = prop.multiProcessorCount;
+    *out = c;
+    return SDGP_OK;
+  } catch (const Error& e) {
+    g_create_error = e.what();
+    return e.code;
+  } catch (const std::exception& e) {
+    g_create_error = e.what();
+    return SDGP_ERR_HIP;
+  }
+}
+
+void sdgp_destroy(sdgp_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  ctx->release_all();
+  delete ctx;
+}
+
+const char* sdgp_last_error(const sdgp_ctx* ctx) {
+  return ctx ? ctx->err.c_str() : g_create_error.c_str();
+}
+
+sdgp_status sdgp_set_timing(sdgp_ctx* ctx, int enable) {
+  if (!ctx) return SDGP_ERR_INVALID_ARG;
+  ctx->timing = enable != 0;
+  return SDGP_OK;
+}
+
+int64_t sdgp_num_hyper(const sdgp_kernel_desc* d) {
+  if (!d || d->dim < 1 || d->dim > kMaxDim || d->n1 < 0 || d->n1 > kMaxN1 || (d->n1 > 0 && d->n2 < 1))
+    return -1;
+  return 2 + (int64_t)d->n1 * d->n2 * (3 + d->dim) + 1;
+}
+
+sdgp_status sdgp_kernel_nnz(sdgp_ctx* ctx, const sdgp_kernel_desc* desc, const double* x, int64_t n,
+                            const double* h, int64_t* nnz_out) {
+  return guarded(ctx, [&] {
+    require(desc && x && nnz_out, "NULL argument");
+    validate(*desc, h, n);
+    Sorted s = order_points(ctx, x, n, desc->dim, h[1]);
+    Assembled as = assemble_all(ctx, s, *desc, h, true, nullptr);
+    *nnz_out = as.A.nnz;
+  });
+}
+
+sdgp_status sdgp_kernel_assemble(sdgp_ctx* ctx, const sdgp_kernel_desc* desc, const double* x, int64_t n,
+                                 const double* h, int add_noise, int64_t* row_ptr, int32_t* col, double* val,
+                                 int64_t capacity, int64_t* nnz_out) {
+  sdgp_status st = guarded(ctx, [&] {
+    require(desc && x && nnz_out && row_ptr, "NULL argument");
+    validate(*desc, h, n);
+    Sorted s = order_points(ctx, x, n, desc->dim, h[1]);
+    Assembled as = assemble_all(ctx, s, *desc, h, add_noise != 0, nullptr);
+    *nnz_out = as.A.nnz;
+    if (as.A.nnz > capacity) throw Error(SDGP_ERR_CAPACITY, "capacity smaller than nnz");
+    require(col && val, "NULL col/val");
+    canonicalize(ctx, s, as.A, row_ptr, col, val);
+    SDGP_HIP(hipStreamSynchronize(ctx->stream));
+  });
+  return st;
+}
+
+sdgp_status sdgp_kernel_assemble_sorted(sdgp_ctx* ctx, const sdgp_kernel_desc* desc, const double* x, int64_t n,
+                                        const double* h, int add_noise, int64_t* row_ptr, int32_t* col,
+                                        double* val, int32_t* perm, int64_t capacity, int64_t* nnz_out) {
+  return guarded(ctx, [&] {
+    require(desc && x && nnz_out && row_ptr && perm, "NULL argument");
+    validate(*desc, h, n);
+    Sorted s = order_points(ctx, x, n, desc->dim, h[1]);
+    Assembled as = assemble_all(ctx, s, *desc, h, add_noise != 0, nullptr);
+    *nnz_out = as.A.nnz;
+    if (as.A.nnz > capacity) throw Error(SDGP_ERR_CAPACITY, "capacity smaller than nnz");
+    require(col && val, "NULL col/val");
+    SDGP_HIP(hipMemcpyAsync(row_ptr, as.A.row_ptr, (n + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice, ctx->stream));
+    SDGP_HIP(hipMemcpyAsync(col, as.A.col, as.A.nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, ctx->stream));
+    SDGP_HIP(hipMemcpyAsync(val, as.A.val, as.A.nnz * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    SDGP_HIP(hipMemcpyAsync(perm, s.perm, n * sizeof(int32_t), hipMemcpyDeviceToDevice, ctx->stream));
+    SDGP_HIP(hipStreamSynchronize(ctx->stream));
+  });
+}
+
+sdgp_status sdgp_csr_spmm(sdgp_ctx* ctx, int64_t n, const int64_t* row_ptr, const int32_t* col,
+                          const double* val, const double* X, int32_t R, double* Y) {
+  return guarded(ctx, [&] {
+    require(row_ptr && col && val && X && Y, "NULL argument");
+    require(n >= 1, "n must be >= 1");
+    Csr A;
+    A.n = n; A.nnz = -1;
+    A.row_ptr = const_cast<int64_t*>(row_ptr);
+    A.col = const_cast<int32_t*>(col);
+    A.val = const_cast<double*>(val);
+    spmm(ctx, A, X, R, Y);
+  });
+}
+
+static sdgp_status lml_common(sdgp_ctx* ctx, const sdgp_kernel_desc* desc, const double* x, const double* y,
+                              int64_t n, const double* h, const sdgp_estimator* est, double* lml_out,
+                              double* grad_out, sdgp_info* info) {
+  sdgp_status inner = SDGP_OK;
+  sdgp_status st = guarded(ctx, [&] {
+    require(desc && x && y && lml_out, "NULL argument");
+    validate(*desc, h, n);
+    check_estimator(est, n);
+    if (info) std::memset(info, 0, sizeof(*info));
+    PhaseTimer t(ctx);
+    t.mark(0);
+    Sorted s = order_points(ctx, x, n, desc->dim, h[1]);
+    double* ys = ctx->get<double>(S_YS, n);
+    gather_vector(ctx, s, y, ys);
+    t.mark(1);
+    inner = evaluate(ctx, s, ys, *desc, h, *est, lml_out, grad_out, info, t);
+  });
+  if (st != SDGP_OK) return st;
+  if (inner == SDGP_ERR_NOT_CONVERGED) ctx->err = "CG did not reach cg_rtol within cg_max_iter";
+  return inner;
+}
+
+sdgp_status sdgp_lml(sdgp_ctx* ctx, const sdgp_kernel_desc* desc, const double* x, const double* y, int64_t n,
+                     const double* h, const sdgp_estimator* est, double* lml_out, sdgp_info* info) {
+  return lml_common(ctx, desc, x, y, n, h, est, lml_out, nullptr, info);
+}
+
+sdgp_status sdgp_lml_grad(sdgp_ctx* ctx, const sdgp_kernel_desc* desc, const double* x, const double* y,
+                          int64_t n, const double* h, const sdgp_estimator* est, double* lml_out,
+                          double* grad_out, sdgp_info* info) {
+  if (!grad_out) return SDGP_ERR_INVALID_ARG;
+  return lml_common(ctx, desc, x, y, n, h, est, lml_out, grad_out, info);
+}
+
+sdgp_status sdgp_lml_grad_batched(sdgp_ctx* ctx, const sdgp_kernel_desc* desc, const double* x, const double* y,
+                                  int64_t n, const double* H, int32_t B, const sdgp_estimator* est,
+                                  double* lml_out, double* grad_out, int32_t* member_status, sdgp_info* info) {
+  return guarded(ctx, [&] {
+    require(desc && x && y && H && lml_out && grad_out && member_status, "NULL argument");
+    require(B >= 1, "B must be >= 1");
+    const int64_t nh = sdgp_num_hyper(desc);
+    require(nh > 0, "invalid kernel descriptor");
+    check_estimator(est, n);
+    // shared ordering: the cell side must cover every member's core radius
+    double rmax = 0.0;
+    for (int m = 0; m < B; ++m) {
+      const double r = H[(int64_t)m * nh + 1];
+      if (std::isfinite(r) && r > rmax) rmax = r;
+    }
+    require(rmax > 0.0, "no member has a valid core radius");
+    validate_shape(*desc, n);
+    Sorted s = order_points(ctx, x, n, desc->dim, rmax);
+    double* ys = ctx->get<double>(S_YS, n);
+    gather_vector(ctx, s, y, ys);
+    for (int m = 0; m < B; ++m) {
+      const double* hm = H + (int64_t)m * nh;
+      sdgp_info* im = info ? info + m : nullptr;
+      if (im) std::memset(im, 0, sizeof(*im));
+      try {
+        validate(*desc, hm, n);
+        PhaseTimer t(ctx);
+        member_status[m] = evaluate(ctx, s, ys, *desc, hm, *est, lml_out + m, grad_out + (int64_t)m * nh, im, t);
+      } catch (const Error& e) {
+        member_status[m] = e.code;
+        lml_out[m] = NAN;
+        for (int64_t k = 0; k < nh; ++k) grad_out[(int64_t)m * nh + k] = NAN;
+        if (e.code == SDGP_ERR_HIP) throw;
+      }
+    }
+  });
+}
+
+sdgp_status sdgp_posterior_mean_var(sdgp_ctx* ctx, const sdgp_kernel_desc* desc, const double* x,
+                                    const double* y, int64_t n, const double* h, const double* x0, int64_t n0,
+                                    const sdgp_estimator* est, double* mean_out, double* var_out) {
+  return guarded(ctx, [&] {
+    require(false, "posterior_mean_var is not available in this build");
+    (void)desc; (void)x; (void)y; (void)n; (void)h; (void)x0; (void)n0; (void)est; (void)mean_out;
+    (void)var_out;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,664 @@
+// Sparse covariance assembly of the sparsity-discovering kernel
+// (Section 2.2 kernel, Section 2.3 sparse assembly) for gfx950.
+//
+// Points are sorted into a grid of cells whose side is at least the core
+// radius, so every core neighbour of a point lies in the 3^dim block of
+// cells around it.  For each cell the candidate columns are a sorted list of
+// disjoint point intervals: the x-runs of the neighbouring cells, merged
+// (SUM combine) with the cell runs of every bump function whose support
+// touches the cell.  One wavefront per row sweeps its cell's intervals 64
+// columns at a time, tests the support predicate, and compacts the kept
+// columns with a ballot + lane prefix count, so rows come out with ascending
+// columns and coalesced stores, and no dense block is ever formed.
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "kernel_math.hpp"
+#include "sdgp_internal.hpp"
+
+namespace sdgp {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+inline int grid_for(int64_t work, int per_block) {
+  int64_t g = (work + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > 0x7fffffff) throw Error(SDGP_ERR_INVALID_ARG, "problem too large for one launch");
+  return (int)g;
+}
+
+// ---------------------------------------------------------------- ordering
+__global__ void k_bbox(const double* __restrict__ x, int64_t n, int dim, double* __restrict__ part) {
+  __shared__ double smin[kBlock][kMaxDim];
+  __shared__ double smax[kBlock][kMaxDim];
+  double lo[kMaxDim], hi[kMaxDim];
+  for (int k = 0; k < kMaxDim; ++k) { lo[k] = INFINITY; hi[k] = -INFINITY; }
+  for (int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; a < n;
+       a += (int64_t)gridDim.x * blockDim.x) {
+    for (int k = 0; k < dim; ++k) {
+      double v = x[a * dim + k];
+      lo[k] = fmin(lo[k], v);
+      hi[k] = fmax(hi[k], v);
+    }
+  }
+  for (int k = 0; k < kMaxDim; ++k) { smin[threadIdx.x][k] = lo[k]; smax[threadIdx.x][k] = hi[k]; }
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s)
+      for (int k = 0; k < kMaxDim; ++k) {
+        smin[threadIdx.x][k] = fmin(smin[threadIdx.x][k], smin[threadIdx.x + s][k]);
+        smax[threadIdx.x][k] = fmax(smax[threadIdx.x][k], smax[threadIdx.x + s][k]);
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int k = 0; k < kMaxDim; ++k) {
+      part[blockIdx.x * 2 * kMaxDim + k] = smin[0][k];
+      part[blockIdx.x * 2 * kMaxDim + kMaxDim + k] = smax[0][k];
+    }
+}
+
+__device__ __forceinline__ int cell_coord(double v, double lo, double inv, int G) {
+  double t = (v - lo) * inv;
+  int c = (int)t;
+  if (t < 0.0) c = 0;
+  return c >= G ? G - 1 : c;
+}
+
+__global__ void k_cell_keys(const double* __restrict__ x, int64_t n, Grid g,
+                            uint32_t* __restrict__ keys, int32_t* __restrict__ idx) {
+  int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (a >= n) return;
+  int64_t key = 0;
+  for (int k = g.dim - 1; k >= 0; --k)
+    key = key * g.G[k] + cell_coord(x[a * g.dim + k], g.lo[k], g.inv_side[k], g.G[k]);
+  keys[a] = (uint32_t)key;
+  idx[a] = (int32_t)a;
+}
+
+__global__ void k_cell_start(const uint32_t* __restrict__ keys, int64_t n, int64_t n_cells,
+                             int32_t* __restrict__ cell_start) {
+  int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  int64_t key = keys[s];
+  int64_t prev = s > 0 ? (int64_t)keys[s - 1] : -1;
+  for (int64_t c = prev + 1; c <= key; ++c) cell_start[c] = (int32_t)s;
+  if (s == n - 1)
+    for (int64_t c = key + 1; c <= n_cells; ++c) cell_start[c] = (int32_t)n;
+}
+
+__global__ void k_gather_points(const double* __restrict__ x, const int32_t* __restrict__ perm,
+                                int64_t n, int dim, double4* __restrict__ xs) {
+  int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  int64_t a = perm[s];
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int k = 0; k < dim; ++k) v[k] = x[a * dim + k];
+  xs[s] = make_double4(v[0], v[1], v[2], v[3]);
+}
+
+__global__ void k_gather_vec(const double* __restrict__ src, const int32_t* __restrict__ perm,
+                             int64_t n, double* __restrict__ dst) {
+  int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (s < n) dst[s] = src[perm[s]];
+}
+
+// ------------------------------------------------------------ bump values
+// F[s, i] = sum_j a_ij exp(beta_ij - beta_ij / (1 - q_ij(x_s))) over the
+// balls that strictly contain x_s (q < 1, decided as |x-c|^2 < r^2), and the
+// membership mask M[s] (bit i: x_s inside some ball of bump function i).
+__global__ void k_bumps(const double4* __restrict__ xs, int64_t n, int dim, int n1, int n2,
+                        const double* __restrict__ bp, double* __restrict__ F,
+                        uint64_t* __restrict__ M) {
+  int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const double4 p = xs[s];
+  const int stride = 3 + dim;
+  uint64_t m = 0;
+  for (int i = 0; i < n1; ++i) {
+    double f = 0.0;
+    for (int j = 0; j < n2; ++j) {
+      const double* q = bp + (i * n2 + j) * stride;
+      double d2 = 0.0;
+      for (int k = 0; k < dim; ++k) {
+        double d = comp(p, k) - q[3 + k];
+        d2 += d * d;
+      }
+      const double r2 = q[2] * q[2];
+      if (d2 < r2) {
+        const double qq = d2 / r2;
+        f += q[0] * exp(q[1] - q[1] / (1.0 - qq));
+        m |= (1ull << i);
+      }
+    }
+    F[s * n1 + i] = f;
+  }
+  M[s] = m;
+}
+
+// ---------------------------------------------------------------- pruning
+__global__ void k_cellmask(const int32_t* __restrict__ cell_start, int64_t n_cells,
+                           const uint64_t* __restrict__ M, uint64_t* __restrict__ cm) {
+  int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= n_cells) return;
+  uint64_t m = 0;
+  for (int32_t s = cell_start[c]; s < cell_start[c + 1]; ++s) m |= M[s];
+  cm[c] = m;
+}
+
+// Runs of consecutive cells whose mask has bit i: one block per bump
+// function scans all cells in order (count pass, then fill pass).
+template <bool kFill>
+__global__ void k_bump_runs(const uint64_t* __restrict__ cm, int64_t n_cells,
+                            int32_t* __restrict__ run_cnt, const int32_t* __restrict__ run_ptr,
+                            int2* __restrict__ runs) {
+  const int i = blockIdx.x;
+  typedef hipcub::BlockScan<int, kBlock> Scan;
+  __shared__ typename Scan::TempStorage tmp;
+  __shared__ int base_s, base_e;
+  if (threadIdx.x == 0) { base_s = 0; base_e = 0; }
+  __syncthreads();
+  for (int64_t c0 = 0; c0 < n_cells; c0 += kBlock) {
+    const int64_t c = c0 + threadIdx.x;
+    const bool in = c < n_cells;
+    const bool f = in && ((cm[c] >> i) & 1ull);
+    const bool fp = in && c > 0 && ((cm[c - 1] >> i) & 1ull);
+    const bool fn = in && c + 1 < n_cells && ((cm[c + 1] >> i) & 1ull);
+    const int st = (f && !fp) ? 1 : 0;
+    const int en = (f && !fn) ? 1 : 0;
+    int ps, pe, ts, te;
+    Scan(tmp).ExclusiveSum(st, ps, ts);
+    __syncthreads();
+    Scan(tmp).ExclusiveSum(en, pe, te);
+    if (kFill) {
+      const int64_t o = run_ptr[i];
+      if (st) runs[o + base_s + ps].x = (int)c;
+      if (en) runs[o + base_e + pe].y = (int)c;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) { base_s += ts; base_e += te; }
+    __syncthreads();
+  }
+  if (!kFill && threadIdx.x == 0) run_cnt[i] = base_s;
+}
+
+struct IvArgs {
+  Grid g;
+  const int32_t* cell_start;
+  const uint64_t* cm;
+  const int32_t* run_ptr;   // [n1 + 1], null for PRODUCT
+  const int2* runs;
+  int use_bumps;
+};
+
+// Merged candidate intervals of one cell.  Lists: the x-runs of the
+// neighbouring cells (ascending by construction) and, when bumps are used,
+// the runs of every bump function present in the cell.  A k-way merge emits
+// maximal disjoint point intervals in ascending order.
+template <bool kFill>
+__global__ void k_cell_intervals(IvArgs A, int32_t* __restrict__ iv_cnt,
+                                 const int32_t* __restrict__ iv_ptr, int2* __restrict__ iv) {
+  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= A.g.n_cells) return;
+  const int dim = A.g.dim;
+  int cc[kMaxDim];
+  {
+    int64_t r = c;
+    for (int k = 0; k < dim; ++k) { cc[k] = (int)(r % A.g.G[k]); r /= A.g.G[k]; }
+  }
+  // core x-runs enumerated with the highest axis outermost -> ascending
+  int n_off = 1;
+  for (int k = 1; k < dim; ++k) n_off *= 3;
+  const int xlo = cc[0] > 0 ? cc[0] - 1 : 0;
+  const int xhi = cc[0] + 1 < A.g.G[0] ? cc[0] + 1 : A.g.G[0] - 1;
+
+  // bump lists present in this cell
+  int lst_pos[kMaxN1], lst_end[kMaxN1];
+  int nl = 0;
+  if (A.use_bumps) {
+    uint64_t m = A.cm[c];
+    while (m) {
+      const int i = __builtin_ctzll(m);
+      m &= m - 1;
+      lst_pos[nl] = A.run_ptr[i];
+      lst_end[nl] = A.run_ptr[i + 1];
+      ++nl;
+    }
+  }
+  int core_k = 0;  // next core offset index
+  auto core_run = [&](int k, int64_t& lo, int64_t& hi) -> bool {
+    // offset digits (base 3) for axes 1..dim-1, lowest axis fastest
+    int64_t base = 0;
+    int64_t mul = A.g.G[0];
+    int t = k;
+    for (int ax = 1; ax < dim; ++ax) {
+      const int o = t % 3 - 1;
+      t /= 3;
+      const int v = cc[ax] + o;
+      if (v < 0 || v >= A.g.G[ax]) return false;
+      base += (int64_t)v * mul;
+      mul *= A.g.G[ax];
+    }
+    lo = base + xlo;
+    hi = base + xhi;
+    return true;
+  };
+  int64_t next_core_lo = -1, next_core_hi = -1;
+  auto advance_core = [&]() {
+    next_core_lo = -1;
+    while (core_k < n_off) {
+      int64_t lo, hi;
+      const bool ok = core_run(core_k, lo, hi);
+      ++core_k;
+      if (ok) { next_core_lo = lo; next_core_hi = hi; return; }
+    }
+  };
+  advance_core();
+
+  int count = 0;
+  const int64_t out0 = kFill ? iv_ptr[c] : 0;
+  int64_t cur_lo = -1, cur_hi = -1;        // current merged cell run
+  int32_t last_s = -1, last_e = -1;        // last point interval (pending)
+  auto flush_point = [&](int32_t s, int32_t e) {
+    if (e <= s) return;
+    if (last_e == s) { last_e = e; return; }
+    if (last_s >= 0) {
+      if (kFill) iv[out0 + count] = make_int2(last_s, last_e);
+      ++count;
+    }
+    last_s = s;
+    last_e = e;
+  };
+  auto emit_cells = [&](int64_t lo, int64_t hi) {
+    flush_point(A.cell_start[lo], A.cell_start[hi + 1]);
+  };
+  for (;;) {
+    // pick the list whose next run starts lowest
+    int64_t best_lo = -1, best_hi = -1;
+    int best = -2;
+    if (next_core_lo >= 0) { best_lo = next_core_lo; best_hi = next_core_hi; best = -1; }
+    for (int l = 0; l < nl; ++l) {
+      if (lst_pos[l] < lst_end[l]) {
+        const int2 r = A.runs[lst_pos[l]];
+        if (best == -2 || r.x < best_lo) { best_lo = r.x; best_hi = r.y; best = l; }
+      }
+    }
+    if (best == -2) break;
+    if (best == -1) advance_core(); else ++lst_pos[best];
+    if (cur_lo < 0) { cur_lo = best_lo; cur_hi = best_hi; }
+    else if (best_lo <= cur_hi + 1) { if (best_hi > cur_hi) cur_hi = best_hi; }
+    else { emit_cells(cur_lo, cur_hi); cur_lo = best_lo; cur_hi = best_hi; }
+  }
+  if (cur_lo >= 0) emit_cells(cur_lo, cur_hi);
+  if (last_s >= 0) {
+    if (kFill) iv[out0 + count] = make_int2(last_s, last_e);
+    ++count;
+  }
+  if (!kFill) iv_cnt[c] = count;
+}
+
+// ------------------------------------------------------------ count / fill
+struct RowArgs {
+  const double4* xs;
+  const uint64_t* M;
+  const double* F;
+  const int32_t* cell_of;
+  const int32_t* iv_ptr;
+  const int2* iv;
+  int64_t n;
+  int dim, n1, core, ell, combine, add_noise;
+  double sigma2, r_core, rc2, noise;
+};
+
+// One wavefront per row.  kFill == false: count kept columns (and the
+// candidates examined); kFill == true: write them at row_ptr[a].
+template <bool kFill>
+__global__ __launch_bounds__(kBlock) void k_rows(RowArgs A, int64_t* __restrict__ row_nnz,
+                                                 unsigned long long* __restrict__ cand_total,
+                                                 const int64_t* __restrict__ row_ptr,
+                                                 int32_t* __restrict__ col, double* __restrict__ val) {
+  const int64_t a = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+  if (a >= A.n) return;
+  const int lane = lane_id();
+  const double4 xa = A.xs[a];
+  const uint64_t Ma = A.M[a];
+  const int32_t cell = A.cell_of[a];
+  const int32_t i0 = A.iv_ptr[cell], i1 = A.iv_ptr[cell + 1];
+  const double* Fa = A.F + a * (int64_t)A.n1;
+  int64_t pos = kFill ? row_ptr[a] : 0;
+  int64_t cnt = 0, cand = 0;
+  for (int32_t q = i0; q < i1; ++q) {
+    const int2 r = A.iv[q];
+    cand += r.y - r.x;
+    for (int32_t b0 = r.x; b0 < r.y; b0 += kWave) {
+      const int32_t b = b0 + lane;
+      bool keep = false;
+      double d2 = 0.0;
+      uint64_t mm = 0;
+      bool core = false;
+      if (b < r.y) {
+        const double4 xb = A.xs[b];
+        d2 = dist2(xa, xb, A.dim);
+        core = d2 < A.rc2;
+        mm = Ma & A.M[b];
+        const bool bump = mm != 0;
+        keep = (b == a) || (A.combine == 0 ? (core && bump) : (core || bump));
+      }
+      const uint64_t bal = ballot64(keep);
+      if (kFill) {
+        if (keep) {
+          double psi = 0.0;
+          if (core) psi = core_psi(sqrt(d2) / A.r_core, A.core, A.ell);
+          double B = 0.0;
+          const double* Fb = A.F + (int64_t)b * A.n1;
+          uint64_t t = mm;
+          while (t) {
+            const int i = __builtin_ctzll(t);
+            t &= t - 1;
+            B += Fa[i] * Fb[i];
+          }
+          double kv = A.combine == 0 ? A.sigma2 * psi * B : A.sigma2 * psi + B;
+          if (b == a && A.add_noise) kv += A.noise;
+          const int64_t o = pos + lanes_below(bal);
+          col[o] = b;
+          val[o] = kv;
+        }
+        pos += __popcll(bal);
+      } else {
+        cnt += __popcll(bal);
+      }
+    }
+  }
+  if (!kFill && lane == 0) {
+    row_nnz[a] = cnt;
+    atomicAdd(cand_total, (unsigned long long)cand);
+  }
+}
+
+// ---------------------------------------------------------- canonical CSR
+__global__ void k_canon_len(const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ perm,
+                            int64_t n, int64_t* __restrict__ len) {
+  int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (s < n) len[perm[s]] = row_ptr[s + 1] - row_ptr[s];
+  if (s == 0) len[n] = 0;
+}
+
+__global__ void k_canon_copy(const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                             const double* __restrict__ val, const int32_t* __restrict__ perm,
+                             int64_t n, const int64_t* __restrict__ out_ptr,
+                             int32_t* __restrict__ col2, double* __restrict__ val2) {
+  const int64_t s = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+  if (s >= n) return;
+  const int lane = lane_id();
+  const int64_t src = row_ptr[s], len = row_ptr[s + 1] - src;
+  const int64_t dst = out_ptr[perm[s]];
+  for (int64_t k = lane; k < len; k += kWave) {
+    col2[dst + k] = perm[col[src + k]];
+    val2[dst + k] = val[src + k];
+  }
+}
+
+__global__ void k_iota_i64(int64_t* p, int64_t n) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+}  // namespace
+
+// =========================================================== host side
+KParams make_params(const sdgp_kernel_desc& d, const double* h) {
+  KParams k;
+  k.dim = d.dim; k.n1 = d.n1; k.n2 = d.n2; k.core = d.core; k.combine = d.combine;
+  k.sigma2 = h[0];
+  k.r_core = h[1];
+  k.rc2 = h[1] * h[1];
+  k.inv_rc = 1.0 / h[1];
+  k.noise = h[2 + (int64_t)d.n1 * d.n2 * (3 + d.dim)];
+  return k;
+}
+
+void validate_shape(const sdgp_kernel_desc& d, int64_t n) {
+  require(d.dim >= 1 && d.dim <= kMaxDim, "dim must be in 1..4");
+  require(d.n1 >= 0 && d.n1 <= kMaxN1, "n1 must be in 0..64");
+  require(d.n1 == 0 || d.n2 >= 1, "n2 must be >= 1");
+  require(d.core == SDGP_CORE_WENDLAND_C2 || d.core == SDGP_CORE_KSTAT, "unknown core");
+  require(d.combine == SDGP_COMBINE_PRODUCT || d.combine == SDGP_COMBINE_SUM, "unknown combine");
+  require(n >= 1 && n < (int64_t)0x7fffffff, "n must be in 1..2^31-2");
+}
+
+void validate(const sdgp_kernel_desc& d, const double* h, int64_t n) {
+  validate_shape(d, n);
+  require(h != nullptr, "h is NULL");
+  const int64_t nh = 2 + (int64_t)d.n1 * d.n2 * (3 + d.dim) + 1;
+  for (int64_t i = 0; i < nh; ++i) require(std::isfinite(h[i]), "hyperparameters must be finite");
+  require(h[0] >= 0.0, "sigma2 must be >= 0");
+  require(h[1] > 0.0, "core radius must be > 0");
+  require(h[nh - 1] >= 0.0, "noise variance must be >= 0");
+  for (int i = 0; i < d.n1; ++i)
+    for (int j = 0; j < d.n2; ++j) {
+      const double* q = h + 2 + (int64_t)(i * d.n2 + j) * (3 + d.dim);
+      require(q[2] > 0.0, "bump radius must be > 0");
+      require(q[1] >= 0.0, "bump shape beta must be >= 0");
+    }
+}
+
+Sorted order_points(Ctx* c, const double* x, int64_t n, int dim, double r_cell) {
+  Sorted s;
+  s.n = n;
+  // bounding box
+  const int nb = std::min<int64_t>(1024, (n + kBlock - 1) / kBlock);
+  double* part = c->get<double>(S_BBOX, (size_t)nb * 2 * kMaxDim);
+  k_bbox<<<nb, kBlock, 0, c->stream>>>(x, n, dim, part);
+  SDGP_CHECK_LAUNCH();
+  std::vector<double> hp((size_t)nb * 2 * kMaxDim);
+  SDGP_HIP(hipMemcpyAsync(hp.data(), part, hp.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  SDGP_HIP(hipStreamSynchronize(c->stream));
+  double lo[kMaxDim], hi[kMaxDim];
+  for (int k = 0; k < kMaxDim; ++k) { lo[k] = INFINITY; hi[k] = -INFINITY; }
+  for (int b = 0; b < nb; ++b)
+    for (int k = 0; k < dim; ++k) {
+      lo[k] = std::min(lo[k], hp[b * 2 * kMaxDim + k]);
+      hi[k] = std::max(hi[k], hp[b * 2 * kMaxDim + kMaxDim + k]);
+    }
+  for (int k = 0; k < dim; ++k) require(std::isfinite(lo[k]) && std::isfinite(hi[k]), "x must be finite");
+  // grid: side >= r_cell (1 + 1e-9) so any pair closer than r_cell is at most
+  // one cell apart per axis; capped at ~2 cells per point
+  Grid g;
+  g.dim = dim;
+  const double side = r_cell * (1.0 + 1e-9);
+  double G[kMaxDim];
+  for (int k = 0; k < dim; ++k) {
+    const double ext = hi[k] - lo[k];
+    G[k] = std::max(1.0, std::floor(ext / side));
+    G[k] = std::min(G[k], 1e6);
+  }
+  const double cap = std::max<double>(1024.0, 2.0 * (double)n);
+  for (;;) {
+    double tot = 1.0;
+    for (int k = 0; k < dim; ++k) tot *= G[k];
+    if (tot <= cap) break;
+    int kmax = 0;
+    for (int k = 1; k < dim; ++k) if (G[k] > G[kmax]) kmax = k;
+    G[kmax] = std::max(1.0, std::floor(G[kmax] / 2.0));
+  }
+  g.n_cells = 1;
+  for (int k = 0; k < kMaxDim; ++k) {
+    if (k < dim) {
+      g.G[k] = (int)G[k];
+      g.lo[k] = lo[k];
+      const double ext = hi[k] - lo[k];
+      g.inv_side[k] = ext > 0.0 ? G[k] / ext : 0.0;
+      g.n_cells *= g.G[k];
+    } else {
+      g.G[k] = 1; g.lo[k] = 0.0; g.inv_side[k] = 0.0;
+    }
+  }
+  s.grid = g;
+  // keys + radix sort (stable: equal cells keep caller order)
+  uint32_t* keys = c->get<uint32_t>(S_KEYS, n);
+  uint32_t* keys_out = c->get<uint32_t>(S_KEYS_ALT, n);
+  int32_t* idx = c->get<int32_t>(S_IDX, n);
+  int32_t* perm = c->get<int32_t>(S_PERM, n);
+  k_cell_keys<<<grid_for(n, kBlock), kBlock, 0, c->stream>>>(x, n, g, keys, idx);
+  SDGP_CHECK_LAUNCH();
+  int bits = 1;
+  while (((int64_t)1 << bits) < g.n_cells) ++bits;
+  size_t tb = 0;
+  SDGP_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, keys, keys_out, idx, perm, (int)n, 0, bits, c->stream));
+  void* tmp = c->get<char>(S_SORT_TMP, tb);
+  SDGP_HIP(hipcub::DeviceRadixSort::SortPairs(tmp, tb, keys, keys_out, idx, perm, (int)n, 0, bits, c->stream));
+  int32_t* cell_start = c->get<int32_t>(S_CELL_START, g.n_cells + 1);
+  k_cell_start<<<grid_for(n, kBlock), kBlock, 0, c->stream>>>(keys_out, n, g.n_cells, cell_start);
+  SDGP_CHECK_LAUNCH();
+  double4* xs = c->get<double4>(S_XS, n);
+  k_gather_points<<<grid_for(n, kBlock), kBlock, 0, c->stream>>>(x, perm, n, dim, xs);
+  SDGP_CHECK_LAUNCH();
+  s.perm = perm;
+  s.xs = xs;
+  s.cell_start = cell_start;
+  s.cell_of = reinterpret_cast<int32_t*>(keys_out);
+  return s;
+}
+
+void gather_vector(Ctx* c, const Sorted& s, const double* src, double* dst) {
+  k_gather_vec<<<grid_for(s.n, kBlock), kBlock, 0, c->stream>>>(src, s.perm, s.n, dst);
+  SDGP_CHECK_LAUNCH();
+}
+
+Bumps bump_precompute(Ctx* c, const Sorted& s, const KParams& kp, const double* h) {
+  Bumps b;
+  const int n1 = kp.n1;
+  const int64_t np = (int64_t)kp.n1 * kp.n2 * (3 + kp.dim);
+  b.bp = c->get<double>(S_BP, np > 0 ? np : 1);
+  if (np > 0)
+    SDGP_HIP(hipMemcpyAsync(b.bp, h + 2, np * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  b.F = c->get<double>(S_F, (size_t)s.n * (n1 > 0 ? n1 : 1));
+  b.M = c->get<uint64_t>(S_M, s.n);
+  k_bumps<<<grid_for(s.n, kBlock), kBlock, 0, c->stream>>>(s.xs, s.n, kp.dim, n1, kp.n2, b.bp, b.F, b.M);
+  SDGP_CHECK_LAUNCH();
+  return b;
+}
+
+void prune(Ctx* c, const Sorted& s, const KParams& kp, const Bumps& b, int32_t** iv_ptr_out,
+           int2** iv_out) {
+  const int64_t nc = s.grid.n_cells;
+  uint64_t* cm = c->get<uint64_t>(S_CELLMASK, nc);
+  k_cellmask<<<grid_for(nc, kBlock), kBlock, 0, c->stream>>>(s.cell_start, nc, b.M, cm);
+  SDGP_CHECK_LAUNCH();
+  IvArgs A;
+  A.g = s.grid;
+  A.cell_start = s.cell_start;
+  A.cm = cm;
+  A.run_ptr = nullptr;
+  A.runs = nullptr;
+  A.use_bumps = (kp.combine == SDGP_COMBINE_SUM && kp.n1 > 0) ? 1 : 0;
+  if (A.use_bumps) {
+    int32_t* run_cnt = c->get<int32_t>(S_RUN_CNT, kp.n1);
+    k_bump_runs<false><<<kp.n1, kBlock, 0, c->stream>>>(cm, nc, run_cnt, nullptr, nullptr);
+    SDGP_CHECK_LAUNCH();
+    std::vector<int32_t> cnt(kp.n1);
+    SDGP_HIP(hipMemcpyAsync(cnt.data(), run_cnt, kp.n1 * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    SDGP_HIP(hipStreamSynchronize(c->stream));
+    std::vector<int32_t> ptr(kp.n1 + 1, 0);
+    for (int i = 0; i < kp.n1; ++i) ptr[i + 1] = ptr[i] + cnt[i];
+    int32_t* run_ptr = c->get<int32_t>(S_RUN_PTR, kp.n1 + 1);
+    SDGP_HIP(hipMemcpyAsync(run_ptr, ptr.data(), ptr.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
+    int2* runs = c->get<int2>(S_RUNS, ptr[kp.n1] > 0 ? ptr[kp.n1] : 1);
+    k_bump_runs<true><<<kp.n1, kBlock, 0, c->stream>>>(cm, nc, nullptr, run_ptr, runs);
+    SDGP_CHECK_LAUNCH();
+    A.run_ptr = run_ptr;
+    A.runs = runs;
+  }
+  int32_t* iv_cnt = c->get<int32_t>(S_IV_CNT, nc + 1);
+  k_cell_intervals<false><<<grid_for(nc, kBlock), kBlock, 0, c->stream>>>(A, iv_cnt, nullptr, nullptr);
+  SDGP_CHECK_LAUNCH();
+  int32_t* iv_ptr = c->get<int32_t>(S_IV_PTR, nc + 1);
+  size_t tb = 0;
+  SDGP_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, iv_cnt, iv_ptr, (int)(nc + 1), c->stream));
+  void* tmp = c->get<char>(S_SORT_TMP, tb);
+  // iv_cnt[nc] is scratch: zero it so the scan's last entry is the total
+  SDGP_HIP(hipMemsetAsync(iv_cnt + nc, 0, sizeof(int32_t), c->stream));
+  SDGP_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, tb, iv_cnt, iv_ptr, (int)(nc + 1), c->stream));
+  int32_t total = 0;
+  SDGP_HIP(hipMemcpyAsync(&total, iv_ptr + nc, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+  SDGP_HIP(hipStreamSynchronize(c->stream));
+  int2* iv = c->get<int2>(S_IV, total > 0 ? total : 1);
+  k_cell_intervals<true><<<grid_for(nc, kBlock), kBlock, 0, c->stream>>>(A, nullptr, iv_ptr, iv);
+  SDGP_CHECK_LAUNCH();
+  *iv_ptr_out = iv_ptr;
+  *iv_out = iv;
+}
+
+static RowArgs row_args(const Sorted& s, const KParams& kp, const Bumps& b, const int32_t* iv_ptr,
+                        const int2* iv, bool add_noise) {
+  RowArgs A;
+  A.xs = s.xs; A.M = b.M; A.F = b.F; A.cell_of = s.cell_of; A.iv_ptr = iv_ptr; A.iv = iv;
+  A.n = s.n; A.dim = kp.dim; A.n1 = kp.n1; A.core = kp.core; A.ell = kp.dim / 2 + 2;
+  A.combine = kp.combine; A.add_noise = add_noise ? 1 : 0;
+  A.sigma2 = kp.sigma2; A.r_core = kp.r_core; A.rc2 = kp.rc2; A.noise = kp.noise;
+  return A;
+}
+
+Csr assemble_sorted(Ctx* c, const Sorted& s, const KParams& kp, const Bumps& b, const int32_t* iv_ptr,
+                    const int2* iv, bool add_noise, int64_t* candidates, PhaseTimer* t) {
+  const int64_t n = s.n;
+  RowArgs A = row_args(s, kp, b, iv_ptr, iv, add_noise);
+  int64_t* row_nnz = c->get<int64_t>(S_ROW_NNZ, n + 1);
+  unsigned long long* cand = c->get<unsigned long long>(S_COUNTER, 4);
+  SDGP_HIP(hipMemsetAsync(cand, 0, sizeof(unsigned long long), c->stream));
+  SDGP_HIP(hipMemsetAsync(row_nnz + n, 0, sizeof(int64_t), c->stream));
+  const int rows_per_block = kBlock / kWave;
+  k_rows<false><<<grid_for(n, rows_per_block), kBlock, 0, c->stream>>>(A, row_nnz, cand, nullptr, nullptr, nullptr);
+  SDGP_CHECK_LAUNCH();
+  int64_t* row_ptr = c->get<int64_t>(S_ROW_PTR, n + 1);
+  size_t tb = 0;
+  SDGP_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, row_nnz, row_ptr, (int)(n + 1), c->stream));
+  void* tmp = c->get<char>(S_SORT_TMP, tb);
+  SDGP_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, tb, row_nnz, row_ptr, (int)(n + 1), c->stream));
+  int64_t nnz = 0;
+  unsigned long long ncand = 0;
+  SDGP_HIP(hipMemcpyAsync(&nnz, row_ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+  SDGP_HIP(hipMemcpyAsync(&ncand, cand, sizeof(unsigned long long), hipMemcpyDeviceToHost, c->stream));
+  SDGP_HIP(hipStreamSynchronize(c->stream));
+  if (candidates) *candidates = (int64_t)ncand;
+  if (t) t->mark(4);
+  int32_t* col = c->get<int32_t>(S_COL, nnz);
+  double* val = c->get<double>(S_VAL, nnz);
+  k_rows<true><<<grid_for(n, rows_per_block), kBlock, 0, c->stream>>>(A, nullptr, nullptr, row_ptr, col, val);
+  SDGP_CHECK_LAUNCH();
+  Csr k;
+  k.n = n; k.nnz = nnz; k.row_ptr = row_ptr; k.col = col; k.val = val;
+  return k;
+}
+
+void canonicalize(Ctx* c, const Sorted& s, const Csr& k, int64_t* row_ptr, int32_t* col, double* val) {
+  const int64_t n = s.n;
+  require(k.nnz < (int64_t)0x7fffffff, "canonical CSR output needs nnz < 2^31");
+  int64_t* len = c->get<int64_t>(S_ROWLEN2, n + 1);
+  k_canon_len<<<grid_for(n, kBlock), kBlock, 0, c->stream>>>(k.row_ptr, s.perm, n, len);
+  SDGP_CHECK_LAUNCH();
+  size_t tb = 0;
+  SDGP_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, len, row_ptr, (int)(n + 1), c->stream));
+  void* tmp = c->get<char>(S_SORT_TMP, tb);
+  SDGP_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, tb, len, row_ptr, (int)(n + 1), c->stream));
+  int32_t* col2 = c->get<int32_t>(S_COL2, k.nnz);
+  double* val2 = c->get<double>(S_VAL2, k.nnz);
+  k_canon_copy<<<grid_for(n, kBlock / kWave), kBlock, 0, c->stream>>>(k.row_ptr, k.col, k.val, s.perm, n,
+                                                                       row_ptr, col2, val2);
+  SDGP_CHECK_LAUNCH();
+  int bits = 1;
+  while (((int64_t)1 << bits) < n) ++bits;
+  tb = 0;
+  SDGP_HIP(hipcub::DeviceSegmentedRadixSort::SortPairs(nullptr, tb, col2, col, val2, val, (int)k.nnz, (int)n,
+                                                       row_ptr, row_ptr + 1, 0, bits, c->stream));
+  tmp = c->get<char>(S_SORT_TMP, tb);
+  SDGP_HIP(hipcub::DeviceSegmentedRadixSort::SortPairs(tmp, tb, col2, col, val2, val, (int)k.nnz, (int)n,
+                                                       row_ptr, row_ptr + 1, 0, bits, c->stream));
+}
+
+}  // namespace sdgp

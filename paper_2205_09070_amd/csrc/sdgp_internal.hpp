@@ -1,0 +1,216 @@
+// Internal declarations shared by the libsdgp translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/sdgp.h"
+
+namespace sdgp {
+
+constexpr int kWave = 64;
+constexpr int kMaxDim = 4;
+constexpr int kMaxN1 = 64;
+
+// Exception type used inside the library; converted to sdgp_status at the
+// ABI boundary.
+struct Error : std::runtime_error {
+  sdgp_status code;
+  Error(sdgp_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define SDGP_HIP(expr)                                                        \
+  do {                                                                        \
+    hipError_t e_ = (expr);                                                   \
+    if (e_ != hipSuccess)                                                     \
+      throw ::sdgp::Error(e_ == hipErrorOutOfMemory ? SDGP_ERR_OOM            \
+                                                    : SDGP_ERR_HIP,           \
+                          std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define SDGP_CHECK_LAUNCH() SDGP_HIP(hipGetLastError())
+
+inline void require(bool ok, const std::string& msg) {
+  if (!ok) throw Error(SDGP_ERR_INVALID_ARG, msg);
+}
+
+// Growable device buffer owned by a context.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  template <class T>
+  T* as() const { return static_cast<T*>(p); }
+};
+
+// Kernel parameters of one hyperparameter vector, in device-friendly form.
+struct KParams {
+  int dim, n1, n2, core, combine;
+  double sigma2, r_core, rc2, inv_rc, noise;
+};
+
+// Cell grid of the locality ordering.
+struct Grid {
+  int dim;
+  int G[kMaxDim];          // cells per axis
+  double lo[kMaxDim];      // lower corner
+  double inv_side[kMaxDim];
+  int64_t n_cells;
+};
+
+struct Ctx;
+
+// Workspace slots.
+enum Slot {
+  S_KEYS, S_KEYS_ALT, S_IDX, S_PERM, S_XS, S_YS, S_CELL_START, S_BBOX,
+  S_F, S_M, S_BP, S_CELLMASK, S_RUN_CNT, S_RUN_PTR, S_RUNS, S_IV_CNT, S_IV_PTR, S_IV,
+  S_ROW_NNZ, S_ROW_PTR, S_COL, S_VAL, S_SORT_TMP, S_COL2, S_VAL2, S_ROWLEN2,
+  S_CG_X, S_CG_R, S_CG_P, S_CG_Q, S_CG_SCAL, S_CG_PART, S_CG_HIST_A, S_CG_HIST_B,
+  S_CG_STATE, S_ZBITS, S_SLQ_WORK, S_SLQ_OUT, S_ADJ_ROW, S_ADJ_G, S_ADJ_PART,
+  S_RED_PART, S_RED_OUT, S_X0S, S_MISC, S_POST, S_COUNTER,
+  S_NUM
+};
+
+struct Ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  bool timing = false;
+  DevBuf buf[S_NUM];
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> spmm_events;
+  int cu_count = 256;
+
+  template <class T>
+  T* get(Slot s, size_t count) {
+    size_t need = count * sizeof(T);
+    if (need == 0) need = sizeof(T);
+    DevBuf& b = buf[s];
+    if (b.bytes < need) {
+      if (b.p) SDGP_HIP(hipFree(b.p));
+      b.p = nullptr;
+      b.bytes = 0;
+      size_t cap = need + need / 8 + 256;
+      SDGP_HIP(hipMalloc(&b.p, cap));
+      b.bytes = cap;
+    }
+    return static_cast<T*>(b.p);
+  }
+  hipEvent_t event() {
+    if (ev_used == ev_pool.size()) {
+      hipEvent_t e;
+      SDGP_HIP(hipEventCreate(&e));
+      ev_pool.push_back(e);
+    }
+    return ev_pool[ev_used++];
+  }
+  void release_all();
+};
+
+// Phase timer (HIP events on the context stream) used when timing is on.
+struct PhaseTimer {
+  Ctx* ctx;
+  hipEvent_t marks[9];
+  bool set[9] = {false};
+  explicit PhaseTimer(Ctx* c) : ctx(c) {}
+  void mark(int i) {
+    if (!ctx->timing) return;
+    marks[i] = ctx->event();
+    SDGP_HIP(hipEventRecord(marks[i], ctx->stream));
+    set[i] = true;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Assembly (assemble.hip)
+// ---------------------------------------------------------------------------
+struct Sorted {
+  int64_t n;
+  Grid grid;
+  int32_t* perm;        // sorted position -> caller index
+  double4* xs;          // sorted coordinates (padded to 4)
+  int32_t* cell_start;  // [n_cells + 1]
+  int32_t* cell_of;     // sorted position -> cell (the sorted keys)
+};
+
+struct Bumps {
+  double* F;       // [n, n1] sorted order
+  uint64_t* M;     // [n]
+  double* bp;      // device copy of bump parameters [n1*n2*(3+dim)]
+};
+
+struct Csr {
+  int64_t n, nnz;
+  int64_t* row_ptr;
+  int32_t* col;
+  double* val;
+};
+
+KParams make_params(const sdgp_kernel_desc& d, const double* h);
+void validate_shape(const sdgp_kernel_desc& d, int64_t n);
+void validate(const sdgp_kernel_desc& d, const double* h, int64_t n);
+
+// Sort points into grid cells whose side is at least r_cell.
+Sorted order_points(Ctx* c, const double* x, int64_t n, int dim, double r_cell);
+void gather_vector(Ctx* c, const Sorted& s, const double* src, double* dst);
+Bumps bump_precompute(Ctx* c, const Sorted& s, const KParams& kp, const double* h);
+// Candidate column intervals per cell (pruning); returns interval count.
+void prune(Ctx* c, const Sorted& s, const KParams& kp, const Bumps& b,
+           int32_t** iv_ptr, int2** iv);
+// Count + fill; the CSR lives in context buffers (S_ROW_PTR, S_COL, S_VAL).
+Csr assemble_sorted(Ctx* c, const Sorted& s, const KParams& kp, const Bumps& b,
+                    const int32_t* iv_ptr, const int2* iv, bool add_noise,
+                    int64_t* candidates, PhaseTimer* t);
+// Canonical (caller order, ascending columns) copy of a sorted-order CSR.
+void canonicalize(Ctx* c, const Sorted& s, const Csr& k, int64_t* row_ptr,
+                  int32_t* col, double* val);
+// Rectangular cross-kernel kappa between sorted training points and test
+// points, as dense-free CSR over test rows (used by the posterior).
+Csr assemble_cross(Ctx* c, const Sorted& s, const KParams& kp, const Bumps& b,
+                   const double* x0, int64_t n0, const double* h,
+                   double** kxx_out);
+
+// ---------------------------------------------------------------------------
+// Solver (solve.hip)
+// ---------------------------------------------------------------------------
+struct CgResult {
+  int iters;
+  int iters_y;
+  double relres_max;
+  bool not_spd;
+  bool converged;
+  double* X;        // [n, R] solution block (device, context-owned)
+  double* hist_a;   // [max_iter, R] CG alphas
+  double* hist_b;   // [max_iter, R] CG betas
+  int32_t* col_iters;  // [R] device iterations per column
+  int R;
+};
+
+enum ProbeKind { PK_RADEMACHER = 0, PK_IDENTITY = 2, PK_NONE = 3, PK_DENSE = 4 };
+
+// Block CG on A X = [y, z_1..z_P] (or caller dense RHS when kind==PK_DENSE).
+CgResult block_cg(Ctx* c, const Csr& A, const Sorted& s, const double* ys,
+                  int kind, int P, uint64_t seed, double rtol, int max_iter,
+                  const double* dense_rhs, int dense_R, PhaseTimer* t);
+void spmm(Ctx* c, const Csr& A, const double* X, int R, double* Y);
+// Stochastic Lanczos quadrature from CG coefficients of columns 1..R-1.
+void slq_from_cg(Ctx* c, const CgResult& cg, int kind, int P, int64_t n,
+                 int lanczos_steps, double* logdet, double* stderr_out,
+                 double* ritz_min, double* ritz_max);
+double dot_device(Ctx* c, const double* a, int64_t stride_a, const double* b,
+                  int64_t stride_b, int64_t n);
+void probe_bits(Ctx* c, const Sorted& s, int P, uint64_t seed, uint64_t* zbits);
+
+// ---------------------------------------------------------------------------
+// Adjoint (adjoint.hip)
+// ---------------------------------------------------------------------------
+void adjoint_gradient(Ctx* c, const Sorted& s, const KParams& kp, const Bumps& b,
+                      const Csr& A, const CgResult& cg, int kind, int P,
+                      uint64_t seed, const double* h, double* grad_host);
+
+}  // namespace sdgp
