@@ -67,6 +67,7 @@ typedef enum {
 enum { SDGP_CORE_WENDLAND_C2 = 0, SDGP_CORE_KSTAT = 1 };
 enum { SDGP_COMBINE_PRODUCT = 0, SDGP_COMBINE_SUM = 1 };
 enum { SDGP_PROBE_RADEMACHER = 0, SDGP_PROBE_IDENTITY = 2 };
+enum { SDGP_PRECOND_NONE = 0, SDGP_PRECOND_LOWRANK = 1 };
 
 typedef struct {
   int32_t dim;      /* 1..4 */
@@ -83,7 +84,20 @@ typedef struct {
  * (probe p, row a of the caller's order: output number p*2^32 + a + 1,
  * sign of bit 63); SDGP_PROBE_IDENTITY uses the n unit vectors, which makes
  * both terms exact up to the CG tolerance (n <= 16384).  lanczos_steps caps
- * the quadrature's tridiagonal size per probe (0: all CG steps). */
+ * the quadrature's tridiagonal size per probe (0: all CG steps).
+ *
+ * precond = SDGP_PRECOND_LOWRANK (SUM combine, Rademacher probes only):
+ * under SUM, A = K_core + F F^T + noise_var I with F[a,i] = F_i(x_a), and
+ * the core part plus noise has the constant diagonal c = sigma2 psi(0) +
+ * noise_var, so M = c I + F F^T holds the whole (rank <= n1) bump part.  The
+ * CG becomes preconditioned CG with M (applied through the n1 x n1 matrix
+ * c I + F^T F), probes become b_p = sqrt(c) w_p + F v_p (w_p as above, v_p
+ * n1 signs from outputs p*2^32 + 2^32 - 1 - i) with covariance M, and
+ *   ln det A = ln det M + tr ln(M^{-1/2} A M^{-1/2}),
+ * the second term by Lanczos quadrature from the preconditioned CG
+ * coefficients weighted by b_p^T M^{-1} b_p, and the gradient's trace by
+ * (A^{-1} b_p)^T dA (M^{-1} b_p).  Estimates stay unbiased; the CG needs far
+ * fewer iterations when the bump functions hold many points. */
 typedef struct {
   int32_t probes;          /* P, 1..64 for Rademacher */
   int32_t lanczos_steps;   /* 0 = use every CG step */
@@ -91,6 +105,8 @@ typedef struct {
   int32_t cg_max_iter;     /* > 0 */
   uint64_t seed;
   double cg_rtol;          /* per column: |r| <= cg_rtol |b| */
+  int32_t precond;         /* SDGP_PRECOND_* */
+  int32_t reserved;        /* must be 0 */
 } sdgp_estimator;
 
 /* Per-call diagnostics (all optional). ms[] phase times when timing is on:

@@ -141,3 +141,84 @@ def boutsidis_logdet(A, Z, m, identity: bool = False):
         V = V - (A @ V) / alpha          # V = C^k Z
         acc += s * float(np.sum(Z * V)) / k
     return n * np.log(alpha) - acc, alpha
+
+
+# ---------------------------------------------------------------------------
+# Low-rank preconditioned estimators (SUM combine).
+#
+# Under the SUM combine A = K_core + F F^T + noise_var I with F[a, i] =
+# F_i(x_a) of rank <= n1, and the core part plus noise has the constant
+# diagonal c = sigma2 psi(0) + noise_var.  M = c I + F F^T is therefore an
+# SPD preconditioner that holds the whole bump part of A, and
+#     ln det A = ln det M + tr ln(M^{-1/2} A M^{-1/2}),
+#     ln det M = (N - n1) ln c + ln det(c I_{n1} + F^T F).
+# Probes b_p = sqrt(c) w_p + F v_p with Rademacher w_p (N entries, counters
+# p*2^32 + row + 1) and v_p (n1 entries, counters p*2^32 + 2^32 - 1 - i) have
+# covariance M, so u_p = M^{-1/2} b_p has identity covariance:
+#     tr ln(M^{-1/2} A M^{-1/2}) ~= (1/P) sum_p |u_p|^2 e_1^T ln(T_p) e_1
+# with T_p the Lanczos tridiagonal of M^{-1/2} A M^{-1/2} from u_p / |u_p|,
+# and E[M^{-1} b b^T] = I gives the trace term of the gradient
+#     tr(A^{-1} dA) ~= (1/P) sum_p (A^{-1} b_p)^T dA (M^{-1} b_p).
+# (The preconditioned-Lanczos estimator of Gardner et al., NeurIPS 2018.)
+# ---------------------------------------------------------------------------
+
+def lowrank_terms(desc, h, x):
+    """(c, F) of the SUM-combine preconditioner M = c I + F F^T."""
+    if desc.combine != kn.COMBINE_SUM:
+        raise ValueError("the low-rank preconditioner needs the SUM combine")
+    p = kn.unpack(desc, h)
+    F, _ = kn.bump_F(desc, h, x)
+    psi0 = float(kn.core_psi(np.array([0.0]), desc.core, desc.dim)[0])
+    return p["sigma2"] * psi0 + p["noise_var"], F
+
+
+def lowrank_probe_signs(seed: int, n1: int, probes: int):
+    """V[n1, probes] Rademacher signs from counters p*2^32 + 2^32 - 1 - i."""
+    V = np.empty((n1, probes))
+    idx = np.arange(n1, dtype=np.uint64)
+    for p in range(probes):
+        k = (np.uint64(p) << np.uint64(32)) + (np.uint64(0xFFFFFFFF) - idx)
+        bits = splitmix64_output(seed, k) >> np.uint64(63)
+        V[:, p] = np.where(bits == 0, 1.0, -1.0)
+    return V
+
+
+def lowrank_probes(seed: int, c: float, F, probes: int):
+    n, n1 = F.shape
+    W = rademacher(seed, n, probes)
+    V = lowrank_probe_signs(seed, n1, probes)
+    return np.sqrt(c) * W + F @ V
+
+
+def preconditioned_lml_grad(desc, h, x, y, seed: int, probes: int, m: int):
+    """LML and gradient with the preconditioned SLQ / Hutchinson estimators
+    (exact solves).  Returns (lml, grad, logdet, logdet_se)."""
+    A = kn.kernel_matrix(desc, h, x, add_noise=True)
+    c, F = lowrank_terms(desc, h, x)
+    n, n1 = F.shape
+    M = c * np.eye(n) + F @ F.T
+    S = c * np.eye(n1) + F.T @ F
+    logdetM = (n - n1) * np.log(c) + np.linalg.slogdet(S)[1]
+    lam, U = np.linalg.eigh(M)
+    Mmh = (U / np.sqrt(lam)) @ U.T
+    Ah = Mmh @ A @ Mmh
+    B = lowrank_probes(seed, c, F, probes)
+    vals = np.empty(probes)
+    for p in range(probes):
+        u = Mmh @ B[:, p]
+        al, be = lanczos(Ah, u, m)
+        vals[p] = float(u @ u) * quad_log(al, be)
+    est = float(vals.mean())
+    se = float(vals.std(ddof=1) / np.sqrt(probes)) if probes > 1 else float("nan")
+    logdet = logdetM + est
+    cf = sla.cho_factor(A, lower=True)
+    y = np.asarray(y, dtype=np.float64)
+    alpha = sla.cho_solve(cf, y)
+    val = -0.5 * float(y @ alpha) - 0.5 * logdet
+    W = sla.cho_solve(cf, B)
+    V = np.linalg.solve(M, B)
+    grad = np.zeros(len(h))
+    for idx, dA in gp.dA_dtheta(desc, h, x):
+        tr = float(np.sum(W * (dA @ V))) / probes
+        grad[idx] = 0.5 * float(alpha @ dA @ alpha) - 0.5 * tr
+    return val, grad, logdet, se

@@ -24,6 +24,7 @@ STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "OOM", 3: "NOT_SPD", 4: "NOT_CONVE
 CORE_WENDLAND_C2, CORE_KSTAT = 0, 1
 COMBINE_PRODUCT, COMBINE_SUM = 0, 1
 PROBE_RADEMACHER, PROBE_IDENTITY = 0, 2
+PRECOND_NONE, PRECOND_LOWRANK = 0, 1
 
 
 class KernelDesc(C.Structure):
@@ -33,7 +34,8 @@ class KernelDesc(C.Structure):
 
 class Estimator(C.Structure):
     _fields_ = [("probes", C.c_int32), ("lanczos_steps", C.c_int32), ("kind", C.c_int32),
-                ("cg_max_iter", C.c_int32), ("seed", C.c_uint64), ("cg_rtol", C.c_double)]
+                ("cg_max_iter", C.c_int32), ("seed", C.c_uint64), ("cg_rtol", C.c_double),
+                ("precond", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -110,9 +112,9 @@ def desc_of(d) -> KernelDesc:
 
 
 def estimator(probes=32, lanczos_steps=0, kind=PROBE_RADEMACHER, cg_max_iter=5000, seed=0,
-              cg_rtol=1e-10) -> Estimator:
+              cg_rtol=1e-10, precond=PRECOND_NONE) -> Estimator:
     return Estimator(int(probes), int(lanczos_steps), int(kind), int(cg_max_iter), int(seed),
-                     float(cg_rtol))
+                     float(cg_rtol), int(precond), 0)
 
 
 def exact_estimator(cg_max_iter=20000, cg_rtol=1e-13) -> Estimator:

@@ -78,6 +78,10 @@ void check_estimator(const sdgp_estimator* e, int64_t n) {
   require(e->cg_max_iter >= 1, "cg_max_iter must be >= 1");
   require(e->cg_rtol > 0.0 && std::isfinite(e->cg_rtol), "cg_rtol must be > 0");
   require(e->lanczos_steps >= 0, "lanczos_steps must be >= 0");
+  require(e->precond == SDGP_PRECOND_NONE || e->precond == SDGP_PRECOND_LOWRANK, "unknown preconditioner");
+  require(e->reserved == 0, "reserved estimator field must be 0");
+  if (e->precond == SDGP_PRECOND_LOWRANK)
+    require(e->kind == SDGP_PROBE_RADEMACHER, "the low-rank preconditioner needs Rademacher probes");
 }
 
 void finish_timing(Ctx* c, PhaseTimer& t, sdgp_info* info) {
@@ -108,7 +112,14 @@ sdgp_status evaluate(Ctx* c, const Sorted& s, const double* ys, const sdgp_kerne
   Assembled as = assemble_all(c, s, d, h, true, &t);
   const int kind = e.kind == SDGP_PROBE_IDENTITY ? PK_IDENTITY : PK_RADEMACHER;
   const int P = kind == PK_IDENTITY ? (int)s.n : e.probes;
-  CgResult cg = block_cg(c, as.A, s, ys, kind, P, e.seed, e.cg_rtol, e.cg_max_iter, nullptr, 0, &t);
+  Precond pc;
+  const bool use_pc = e.precond == SDGP_PRECOND_LOWRANK;
+  if (use_pc) {
+    require(d.combine == SDGP_COMBINE_SUM, "the low-rank preconditioner needs the SUM combine");
+    pc = lowrank_precond(c, s, as.kp, as.b);
+  }
+  CgResult cg = block_cg(c, as.A, s, ys, kind, P, e.seed, e.cg_rtol, e.cg_max_iter, nullptr, 0,
+                         use_pc ? &pc : nullptr, grad_out != nullptr, &t);
   if (cg.not_spd) throw Error(SDGP_ERR_NOT_SPD, "CG met p^T A p <= 0: the covariance is not positive definite");
   t.mark(6);
   const double yKy = dot_device(c, ys, 1, cg.X, cg.R, s.n);
@@ -325,11 +336,37 @@ sdgp_status sdgp_lml_grad_batched(sdgp_ctx* ctx, const sdgp_kernel_desc* desc, c
 sdgp_status sdgp_posterior_mean_var(sdgp_ctx* ctx, const sdgp_kernel_desc* desc, const double* x,
                                     const double* y, int64_t n, const double* h, const double* x0, int64_t n0,
                                     const sdgp_estimator* est, double* mean_out, double* var_out) {
-  return guarded(ctx, [&] {
-    require(false, "posterior_mean_var is not available in this build");
-    (void)desc; (void)x; (void)y; (void)n; (void)h; (void)x0; (void)n0; (void)est; (void)mean_out;
-    (void)var_out;
+  bool conv = true;
+  sdgp_status st = guarded(ctx, [&] {
+    require(desc && x && y && x0 && mean_out && var_out && est, "NULL argument");
+    validate(*desc, h, n);
+    require(est->cg_max_iter >= 1 && est->cg_rtol > 0.0 && std::isfinite(est->cg_rtol), "bad CG options");
+    Sorted s = order_points(ctx, x, n, desc->dim, h[1]);
+    double* ys = ctx->get<double>(S_YS, n);
+    gather_vector(ctx, s, y, ys);
+    Assembled as = assemble_all(ctx, s, *desc, h, true, nullptr);
+    double* kxx = nullptr;
+    Csr K0 = assemble_cross(ctx, s, as.kp, as.b, x0, n0, h, &kxx);
+    Precond pc;
+    const bool use_pc = est->precond == SDGP_PRECOND_LOWRANK && desc->combine == SDGP_COMBINE_SUM;
+    if (use_pc) pc = lowrank_precond(ctx, s, as.kp, as.b);
+    CgResult cg = block_cg(ctx, as.A, s, ys, PK_NONE, 0, 0, est->cg_rtol, est->cg_max_iter, nullptr, 0,
+                           use_pc ? &pc : nullptr, false, nullptr);
+    if (cg.not_spd) throw Error(SDGP_ERR_NOT_SPD, "CG met p^T A p <= 0: the covariance is not positive definite");
+    conv = cg.converged;
+    spmm(ctx, K0, cg.X, 1, mean_out);
+    bool c2 = true;
+    posterior_variance(ctx, as.A, s, K0, kxx, est->cg_rtol, est->cg_max_iter, use_pc ? &pc : nullptr, var_out,
+                       &c2);
+    conv = conv && c2;
+    SDGP_HIP(hipStreamSynchronize(ctx->stream));
   });
+  if (st != SDGP_OK) return st;
+  if (!conv) {
+    ctx->err = "CG did not reach cg_rtol within cg_max_iter";
+    return SDGP_ERR_NOT_CONVERGED;
+  }
+  return SDGP_OK;
 }
 
 }  // extern "C"

@@ -31,9 +31,11 @@ struct AdjArgs {
   const uint64_t* M;
   const double* F;
   const int32_t* perm;
+  const int32_t* sched;
   const int64_t* row_ptr;
   const int32_t* col;
   const double* X;      // [n][R]
+  const double* V;      // [n][R] M^{-1} b (preconditioned probes) or null
   const uint64_t* zbits;
   int64_t n;
   int R, P, kind;
@@ -44,8 +46,9 @@ struct AdjArgs {
 };
 
 __global__ __launch_bounds__(kAdjBlock) void k_adjoint_rows(AdjArgs A) {
-  const int64_t a = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
-  if (a >= A.n) return;
+  const int64_t pos = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+  if (pos >= A.n) return;
+  const int64_t a = A.sched ? (int64_t)A.sched[pos] : pos;
   const int lane = lane_id();
   const int64_t R = A.R;
   const double4 xa = A.xs[a];
@@ -53,11 +56,16 @@ __global__ __launch_bounds__(kAdjBlock) void k_adjoint_rows(AdjArgs A) {
   const double alpha_a = A.X[a * R];
   const double* Fa = A.F + a * (int64_t)A.n1;
   const bool rad = A.kind == PK_RADEMACHER;
+  const bool pre = A.V != nullptr;
   uint64_t za = 0;
-  double wa = 0.0;  // lane p holds w_p(a); broadcast by readlane
+  double wa = 0.0, va = 0.0;  // lane p holds w_p(a), v_p(a); broadcast by readlane
   if (rad) {
-    za = A.zbits[a];
     if (lane < A.P) wa = A.X[a * R + 1 + lane];
+    if (pre) {
+      if (lane < A.P) va = A.V[a * R + 1 + lane];
+    } else {
+      za = A.zbits[a];
+    }
   }
   const int64_t k0 = A.row_ptr[a], k1 = A.row_ptr[a + 1];
   const int pa = A.perm[a];
@@ -107,7 +115,17 @@ __global__ __launch_bounds__(kAdjBlock) void k_adjoint_rows(AdjArgs A) {
       }
       // trace part of Omega
       double tr;
-      if (rad) {
+      if (rad && pre) {
+        // pairs (w_p, v_p) = (A^{-1} b_p, M^{-1} b_p)
+        const double* Wb = A.X + (int64_t)b * R + 1;
+        const double* Vb = A.V + (int64_t)b * R + 1;
+        double t1 = 0.0, t2 = 0.0;
+        for (int p = 0; p < A.P; ++p) {
+          t1 += readlane_f64(wa, p) * Vb[p];
+          t2 += Wb[p] * readlane_f64(va, p);
+        }
+        tr = 0.5 * (t1 + t2);
+      } else if (rad) {
         const uint64_t zb = A.zbits[b];
         const double* Wb = A.X + (int64_t)b * R + 1;
         double t1 = 0.0, t2 = 0.0;
@@ -234,14 +252,14 @@ void adjoint_gradient(Ctx* c, const Sorted& s, const KParams& kp, const Bumps& b
                       const CgResult& cg, int kind, int P, uint64_t seed, const double* h, double* grad) {
   const int64_t n = s.n;
   AdjArgs A;
-  A.xs = s.xs; A.M = b.M; A.F = b.F; A.perm = s.perm;
-  A.row_ptr = Am.row_ptr; A.col = Am.col; A.X = cg.X;
+  A.xs = s.xs; A.M = b.M; A.F = b.F; A.perm = s.perm; A.sched = s.sched;
+  A.row_ptr = Am.row_ptr; A.col = Am.col; A.X = cg.X; A.V = cg.V;
   A.n = n; A.R = cg.R; A.P = P; A.kind = kind;
   A.dim = kp.dim; A.n1 = kp.n1; A.core = kp.core; A.ell = kp.dim / 2 + 2; A.combine = kp.combine;
   A.sigma2 = kp.sigma2; A.r_core = kp.r_core; A.rc2 = kp.rc2;
   A.s_scale = kind == PK_IDENTITY ? 1.0 : 1.0 / P;
   A.zbits = nullptr;
-  if (kind == PK_RADEMACHER) {
+  if (kind == PK_RADEMACHER && A.V == nullptr) {
     require(P >= 1 && P <= 64, "Rademacher probes must be 1..64");
     uint64_t* zb = c->get<uint64_t>(S_ZBITS, n);
     probe_bits(c, s, P, seed, zb);

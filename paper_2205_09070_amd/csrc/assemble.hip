@@ -108,6 +108,47 @@ __global__ void k_gather_vec(const double* __restrict__ src, const int32_t* __re
   if (s < n) dst[s] = src[perm[s]];
 }
 
+// Processing schedule: cells in Morton (bit-interleaved) order of their grid
+// coordinates, rows of each cell in storage order.  Kernels that gather
+// neighbour rows walk this schedule so that consecutive work stays inside a
+// compact 3-D block (the storage order itself is untouched).
+__device__ __forceinline__ uint64_t spread_bits(uint64_t v, int dim, int nb) {
+  uint64_t out = 0;
+  for (int b = 0; b < nb; ++b) out |= ((v >> b) & 1ull) << (b * dim);
+  return out;
+}
+
+__global__ void k_cell_morton(Grid g, uint64_t* __restrict__ keys, int32_t* __restrict__ ids) {
+  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= g.n_cells) return;
+  int64_t r = c;
+  uint64_t key = 0;
+  const int nb = 64 / g.dim;
+  for (int k = 0; k < g.dim; ++k) {
+    const uint64_t ck = (uint64_t)(r % g.G[k]);
+    r /= g.G[k];
+    key |= spread_bits(ck, g.dim, nb) << k;
+  }
+  keys[c] = key;
+  ids[c] = (int32_t)c;
+}
+
+__global__ void k_cell_sizes(const int32_t* __restrict__ order, const int32_t* __restrict__ cell_start,
+                             int64_t n_cells, int32_t* __restrict__ sz) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k < n_cells) sz[k] = cell_start[order[k] + 1] - cell_start[order[k]];
+  if (k == 0) sz[n_cells] = 0;
+}
+
+__global__ void k_fill_sched(const int32_t* __restrict__ order, const int32_t* __restrict__ off,
+                             const int32_t* __restrict__ cell_start, int64_t n_cells, int32_t* __restrict__ sched) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= n_cells) return;
+  const int32_t c = order[k];
+  const int32_t s0 = cell_start[c], s1 = cell_start[c + 1];
+  for (int32_t j = s0; j < s1; ++j) sched[off[k] + (j - s0)] = j;
+}
+
 // ------------------------------------------------------------ bump values
 // F[s, i] = sum_j a_ij exp(beta_ij - beta_ij / (1 - q_ij(x_s))) over the
 // balls that strictly contain x_s (q < 1, decided as |x-c|^2 < r^2), and the
@@ -196,32 +237,26 @@ struct IvArgs {
   int use_bumps;
 };
 
-// Merged candidate intervals of one cell.  Lists: the x-runs of the
-// neighbouring cells (ascending by construction) and, when bumps are used,
-// the runs of every bump function present in the cell.  A k-way merge emits
-// maximal disjoint point intervals in ascending order.
+// Merged candidate intervals of one query (a training cell, or a test point
+// placed in its clamped cell).  Lists: the x-runs of the neighbouring cells
+// (ascending by construction) and, when bumps are used, the runs of every
+// bump function in `mask`.  A k-way merge emits maximal disjoint point
+// intervals in ascending order; returns their number and, when kFill, writes
+// them to out.
 template <bool kFill>
-__global__ void k_cell_intervals(IvArgs A, int32_t* __restrict__ iv_cnt,
-                                 const int32_t* __restrict__ iv_ptr, int2* __restrict__ iv) {
-  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (c >= A.g.n_cells) return;
+__device__ int merge_intervals(const IvArgs& A, const int* cc, uint64_t mask, int2* __restrict__ out) {
   const int dim = A.g.dim;
-  int cc[kMaxDim];
-  {
-    int64_t r = c;
-    for (int k = 0; k < dim; ++k) { cc[k] = (int)(r % A.g.G[k]); r /= A.g.G[k]; }
-  }
   // core x-runs enumerated with the highest axis outermost -> ascending
   int n_off = 1;
   for (int k = 1; k < dim; ++k) n_off *= 3;
   const int xlo = cc[0] > 0 ? cc[0] - 1 : 0;
   const int xhi = cc[0] + 1 < A.g.G[0] ? cc[0] + 1 : A.g.G[0] - 1;
 
-  // bump lists present in this cell
+  // bump lists of the query
   int lst_pos[kMaxN1], lst_end[kMaxN1];
   int nl = 0;
   if (A.use_bumps) {
-    uint64_t m = A.cm[c];
+    uint64_t m = mask;
     while (m) {
       const int i = __builtin_ctzll(m);
       m &= m - 1;
@@ -261,14 +296,13 @@ __global__ void k_cell_intervals(IvArgs A, int32_t* __restrict__ iv_cnt,
   advance_core();
 
   int count = 0;
-  const int64_t out0 = kFill ? iv_ptr[c] : 0;
   int64_t cur_lo = -1, cur_hi = -1;        // current merged cell run
   int32_t last_s = -1, last_e = -1;        // last point interval (pending)
   auto flush_point = [&](int32_t s, int32_t e) {
     if (e <= s) return;
     if (last_e == s) { last_e = e; return; }
     if (last_s >= 0) {
-      if (kFill) iv[out0 + count] = make_int2(last_s, last_e);
+      if (kFill) out[count] = make_int2(last_s, last_e);
       ++count;
     }
     last_s = s;
@@ -296,10 +330,42 @@ __global__ void k_cell_intervals(IvArgs A, int32_t* __restrict__ iv_cnt,
   }
   if (cur_lo >= 0) emit_cells(cur_lo, cur_hi);
   if (last_s >= 0) {
-    if (kFill) iv[out0 + count] = make_int2(last_s, last_e);
+    if (kFill) out[count] = make_int2(last_s, last_e);
     ++count;
   }
-  if (!kFill) iv_cnt[c] = count;
+  return count;
+}
+
+template <bool kFill>
+__global__ void k_cell_intervals(IvArgs A, int32_t* __restrict__ iv_cnt,
+                                 const int32_t* __restrict__ iv_ptr, int2* __restrict__ iv) {
+  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= A.g.n_cells) return;
+  int cc[kMaxDim];
+  {
+    int64_t r = c;
+    for (int k = 0; k < A.g.dim; ++k) { cc[k] = (int)(r % A.g.G[k]); r /= A.g.G[k]; }
+  }
+  const uint64_t mask = A.use_bumps ? A.cm[c] : 0ull;
+  const int cnt = merge_intervals<kFill>(A, cc, mask, kFill ? iv + iv_ptr[c] : nullptr);
+  if (!kFill) iv_cnt[c] = cnt;
+}
+
+// Candidate intervals of test points: the clamped cell of each point (a
+// training point within the core radius lies at most one cell away per axis
+// also after clamping) and the bump functions whose support holds the point.
+template <bool kFill>
+__global__ void k_query_intervals(IvArgs A, const double4* __restrict__ q, const uint64_t* __restrict__ qm,
+                                  int64_t nq, int32_t* __restrict__ iv_cnt, const int32_t* __restrict__ iv_ptr,
+                                  int2* __restrict__ iv) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= nq) return;
+  const double4 p = q[t];
+  int cc[kMaxDim];
+  for (int k = 0; k < A.g.dim; ++k) cc[k] = cell_coord(comp(p, k), A.g.lo[k], A.g.inv_side[k], A.g.G[k]);
+  const uint64_t mask = A.use_bumps ? qm[t] : 0ull;
+  const int cnt = merge_intervals<kFill>(A, cc, mask, kFill ? iv + iv_ptr[t] : nullptr);
+  if (!kFill) iv_cnt[t] = cnt;
 }
 
 // ------------------------------------------------------------ count / fill
@@ -378,6 +444,98 @@ __global__ __launch_bounds__(kBlock) void k_rows(RowArgs A, int64_t* __restrict_
     row_nnz[a] = cnt;
     atomicAdd(cand_total, (unsigned long long)cand);
   }
+}
+
+// ------------------------------------------------------- cross covariance
+// Rows are test points (caller order), columns sorted training points; the
+// stored predicate has no diagonal rule (the sets are distinct).
+struct CrossArgs {
+  const double4* xs;
+  const uint64_t* M;
+  const double* F;
+  const double4* q;
+  const uint64_t* qm;
+  const double* qF;
+  const int32_t* iv_ptr;
+  const int2* iv;
+  int64_t nq;
+  int dim, n1, core, ell, combine;
+  double sigma2, r_core, rc2;
+};
+
+template <bool kFill>
+__global__ __launch_bounds__(kBlock) void k_cross_rows(CrossArgs A, int64_t* __restrict__ row_nnz,
+                                                       const int64_t* __restrict__ row_ptr,
+                                                       int32_t* __restrict__ col, double* __restrict__ val) {
+  const int64_t t = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+  if (t >= A.nq) return;
+  const int lane = lane_id();
+  const double4 xt = A.q[t];
+  const uint64_t Mt = A.qm[t];
+  const double* Ft = A.qF + t * (int64_t)A.n1;
+  int64_t pos = kFill ? row_ptr[t] : 0;
+  int64_t cnt = 0;
+  for (int32_t k = A.iv_ptr[t]; k < A.iv_ptr[t + 1]; ++k) {
+    const int2 r = A.iv[k];
+    for (int32_t b0 = r.x; b0 < r.y; b0 += kWave) {
+      const int32_t b = b0 + lane;
+      bool keep = false, core = false;
+      double d2 = 0.0;
+      uint64_t mm = 0;
+      if (b < r.y) {
+        d2 = dist2(xt, A.xs[b], A.dim);
+        core = d2 < A.rc2;
+        mm = Mt & A.M[b];
+        keep = A.combine == 0 ? (core && mm != 0) : (core || mm != 0);
+      }
+      const uint64_t bal = ballot64(keep);
+      if (kFill) {
+        if (keep) {
+          const double psi = core ? core_psi(sqrt(d2) / A.r_core, A.core, A.ell) : 0.0;
+          double B = 0.0;
+          const double* Fb = A.F + (int64_t)b * A.n1;
+          uint64_t m = mm;
+          while (m) {
+            const int i = __builtin_ctzll(m);
+            m &= m - 1;
+            B += Ft[i] * Fb[i];
+          }
+          const int64_t o = pos + lanes_below(bal);
+          col[o] = b;
+          val[o] = A.combine == 0 ? A.sigma2 * psi * B : A.sigma2 * psi + B;
+        }
+        pos += __popcll(bal);
+      } else {
+        cnt += __popcll(bal);
+      }
+    }
+  }
+  if (!kFill && lane == 0) row_nnz[t] = cnt;
+}
+
+// Prior variance k(x0, x0) of each test point.
+__global__ void k_prior_diag(const uint64_t* __restrict__ qm, const double* __restrict__ qF, int64_t nq, int n1,
+                             int core, int ell, int combine, double sigma2, double* __restrict__ kxx) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= nq) return;
+  double B = 0.0;
+  uint64_t m = qm[t];
+  while (m) {
+    const int i = __builtin_ctzll(m);
+    m &= m - 1;
+    const double f = qF[t * (int64_t)n1 + i];
+    B += f * f;
+  }
+  const double psi0 = core_psi(0.0, core, ell);
+  kxx[t] = combine == 0 ? sigma2 * psi0 * B : sigma2 * psi0 + B;
+}
+
+__global__ void k_pack_points(const double* __restrict__ x, int64_t n, int dim, double4* __restrict__ out) {
+  const int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (a >= n) return;
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int k = 0; k < dim; ++k) v[k] = x[a * dim + k];
+  out[a] = make_double4(v[0], v[1], v[2], v[3]);
 }
 
 // ---------------------------------------------------------- canonical CSR
@@ -518,6 +676,32 @@ Sorted order_points(Ctx* c, const double* x, int64_t n, int dim, double r_cell) 
   double4* xs = c->get<double4>(S_XS, n);
   k_gather_points<<<grid_for(n, kBlock), kBlock, 0, c->stream>>>(x, perm, n, dim, xs);
   SDGP_CHECK_LAUNCH();
+  // Morton schedule of the cells
+  {
+    const int64_t nc = g.n_cells;
+    uint64_t* mk = c->get<uint64_t>(S_MORTON_KEYS, nc);
+    uint64_t* mk2 = c->get<uint64_t>(S_MORTON_KEYS2, nc);
+    int32_t* ids = c->get<int32_t>(S_MORTON_IDS, nc);
+    int32_t* order = c->get<int32_t>(S_MORTON_ORDER, nc);
+    k_cell_morton<<<grid_for(nc, kBlock), kBlock, 0, c->stream>>>(g, mk, ids);
+    SDGP_CHECK_LAUNCH();
+    size_t tb2 = 0;
+    SDGP_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tb2, mk, mk2, ids, order, (int)nc, 0, 64, c->stream));
+    void* tmp2 = c->get<char>(S_SORT_TMP, tb2);
+    SDGP_HIP(hipcub::DeviceRadixSort::SortPairs(tmp2, tb2, mk, mk2, ids, order, (int)nc, 0, 64, c->stream));
+    int32_t* sz = c->get<int32_t>(S_MORTON_SZ, nc + 1);
+    int32_t* off = c->get<int32_t>(S_MORTON_OFF, nc + 1);
+    k_cell_sizes<<<grid_for(nc, kBlock), kBlock, 0, c->stream>>>(order, cell_start, nc, sz);
+    SDGP_CHECK_LAUNCH();
+    tb2 = 0;
+    SDGP_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tb2, sz, off, (int)(nc + 1), c->stream));
+    tmp2 = c->get<char>(S_SORT_TMP, tb2);
+    SDGP_HIP(hipcub::DeviceScan::ExclusiveSum(tmp2, tb2, sz, off, (int)(nc + 1), c->stream));
+    int32_t* sched = c->get<int32_t>(S_SCHED, n);
+    k_fill_sched<<<grid_for(nc, kBlock), kBlock, 0, c->stream>>>(order, off, cell_start, nc, sched);
+    SDGP_CHECK_LAUNCH();
+    s.sched = sched;
+  }
   s.perm = perm;
   s.xs = xs;
   s.cell_start = cell_start;
@@ -633,6 +817,89 @@ Csr assemble_sorted(Ctx* c, const Sorted& s, const KParams& kp, const Bumps& b, 
   SDGP_CHECK_LAUNCH();
   Csr k;
   k.n = n; k.nnz = nnz; k.row_ptr = row_ptr; k.col = col; k.val = val;
+  return k;
+}
+
+Csr assemble_cross(Ctx* c, const Sorted& s, const KParams& kp, const Bumps& b, const double* x0, int64_t n0,
+                   const double* h, double** kxx_out) {
+  require(x0 != nullptr, "x0 is NULL");
+  require(n0 >= 1 && n0 < (int64_t)0x7fffffff, "n0 must be in 1..2^31-2");
+  const int dim = kp.dim;
+  // finiteness of the test points
+  {
+    const int nb = std::min<int64_t>(1024, (n0 + kBlock - 1) / kBlock);
+    double* part = c->get<double>(S_BBOX, (size_t)nb * 2 * kMaxDim);
+    k_bbox<<<nb, kBlock, 0, c->stream>>>(x0, n0, dim, part);
+    SDGP_CHECK_LAUNCH();
+    std::vector<double> hp((size_t)nb * 2 * kMaxDim);
+    SDGP_HIP(hipMemcpyAsync(hp.data(), part, hp.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    SDGP_HIP(hipStreamSynchronize(c->stream));
+    for (int bb = 0; bb < nb; ++bb)
+      for (int k = 0; k < dim; ++k)
+        require(std::isfinite(hp[bb * 2 * kMaxDim + k]) && std::isfinite(hp[bb * 2 * kMaxDim + kMaxDim + k]),
+                "x0 must be finite");
+  }
+  double4* q = c->get<double4>(S_X0S, n0);
+  k_pack_points<<<grid_for(n0, kBlock), kBlock, 0, c->stream>>>(x0, n0, dim, q);
+  SDGP_CHECK_LAUNCH();
+  const int n1 = kp.n1;
+  double* qF = c->get<double>(S_QF, (size_t)n0 * (n1 > 0 ? n1 : 1));
+  uint64_t* qm = c->get<uint64_t>(S_QM, n0);
+  k_bumps<<<grid_for(n0, kBlock), kBlock, 0, c->stream>>>(q, n0, dim, n1, kp.n2, b.bp, qF, qm);
+  SDGP_CHECK_LAUNCH();
+  double* kxx = c->get<double>(S_KXX, n0);
+  k_prior_diag<<<grid_for(n0, kBlock), kBlock, 0, c->stream>>>(qm, qF, n0, n1, kp.core, dim / 2 + 2, kp.combine,
+                                                               kp.sigma2, kxx);
+  SDGP_CHECK_LAUNCH();
+  // candidate intervals per test point (runs of the last prune())
+  IvArgs A;
+  A.g = s.grid;
+  A.cell_start = s.cell_start;
+  A.cm = c->buf[S_CELLMASK].as<uint64_t>();
+  A.use_bumps = (kp.combine == SDGP_COMBINE_SUM && kp.n1 > 0) ? 1 : 0;
+  A.run_ptr = A.use_bumps ? c->buf[S_RUN_PTR].as<int32_t>() : nullptr;
+  A.runs = A.use_bumps ? c->buf[S_RUNS].as<int2>() : nullptr;
+  int32_t* iv_cnt = c->get<int32_t>(S_QIV_CNT, n0 + 1);
+  SDGP_HIP(hipMemsetAsync(iv_cnt + n0, 0, sizeof(int32_t), c->stream));
+  k_query_intervals<false><<<grid_for(n0, kBlock), kBlock, 0, c->stream>>>(A, q, qm, n0, iv_cnt, nullptr, nullptr);
+  SDGP_CHECK_LAUNCH();
+  int32_t* iv_ptr = c->get<int32_t>(S_QIV_PTR, n0 + 1);
+  size_t tb = 0;
+  SDGP_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, iv_cnt, iv_ptr, (int)(n0 + 1), c->stream));
+  void* tmp = c->get<char>(S_SORT_TMP, tb);
+  SDGP_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, tb, iv_cnt, iv_ptr, (int)(n0 + 1), c->stream));
+  int32_t total = 0;
+  SDGP_HIP(hipMemcpyAsync(&total, iv_ptr + n0, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+  SDGP_HIP(hipStreamSynchronize(c->stream));
+  int2* iv = c->get<int2>(S_QIV, total > 0 ? total : 1);
+  k_query_intervals<true><<<grid_for(n0, kBlock), kBlock, 0, c->stream>>>(A, q, qm, n0, nullptr, iv_ptr, iv);
+  SDGP_CHECK_LAUNCH();
+  // count, scan, fill
+  CrossArgs X;
+  X.xs = s.xs; X.M = b.M; X.F = b.F; X.q = q; X.qm = qm; X.qF = qF; X.iv_ptr = iv_ptr; X.iv = iv;
+  X.nq = n0; X.dim = dim; X.n1 = n1; X.core = kp.core; X.ell = dim / 2 + 2; X.combine = kp.combine;
+  X.sigma2 = kp.sigma2; X.r_core = kp.r_core; X.rc2 = kp.rc2;
+  int64_t* rn = c->get<int64_t>(S_QROW_NNZ, n0 + 1);
+  SDGP_HIP(hipMemsetAsync(rn + n0, 0, sizeof(int64_t), c->stream));
+  const int rpb = kBlock / kWave;
+  k_cross_rows<false><<<grid_for(n0, rpb), kBlock, 0, c->stream>>>(X, rn, nullptr, nullptr, nullptr);
+  SDGP_CHECK_LAUNCH();
+  int64_t* rp = c->get<int64_t>(S_QROW_PTR, n0 + 1);
+  tb = 0;
+  SDGP_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, rn, rp, (int)(n0 + 1), c->stream));
+  tmp = c->get<char>(S_SORT_TMP, tb);
+  SDGP_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, tb, rn, rp, (int)(n0 + 1), c->stream));
+  int64_t nnz = 0;
+  SDGP_HIP(hipMemcpyAsync(&nnz, rp + n0, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+  SDGP_HIP(hipStreamSynchronize(c->stream));
+  int32_t* col = c->get<int32_t>(S_QCOL, nnz);
+  double* val = c->get<double>(S_QVAL, nnz);
+  k_cross_rows<true><<<grid_for(n0, rpb), kBlock, 0, c->stream>>>(X, nullptr, rp, col, val);
+  SDGP_CHECK_LAUNCH();
+  Csr k;
+  k.n = n0; k.nnz = nnz; k.row_ptr = rp; k.col = col; k.val = val;
+  *kxx_out = kxx;
+  (void)h;
   return k;
 }
 

@@ -72,6 +72,9 @@ enum Slot {
   S_CG_X, S_CG_R, S_CG_P, S_CG_Q, S_CG_SCAL, S_CG_PART, S_CG_HIST_A, S_CG_HIST_B,
   S_CG_STATE, S_ZBITS, S_SLQ_WORK, S_SLQ_OUT, S_ADJ_ROW, S_ADJ_G, S_ADJ_PART,
   S_RED_PART, S_RED_OUT, S_X0S, S_MISC, S_POST, S_COUNTER,
+  S_CG_V, S_CG_PARTG, S_CG_G, S_PC_PART, S_PC_SINV,
+  S_MORTON_KEYS, S_MORTON_KEYS2, S_MORTON_IDS, S_MORTON_ORDER, S_MORTON_SZ, S_MORTON_OFF, S_SCHED,
+  S_QF, S_QM, S_KXX, S_QIV_CNT, S_QIV_PTR, S_QIV, S_QROW_NNZ, S_QROW_PTR, S_QCOL, S_QVAL,
   S_NUM
 };
 
@@ -136,6 +139,7 @@ struct Sorted {
   double4* xs;          // sorted coordinates (padded to 4)
   int32_t* cell_start;  // [n_cells + 1]
   int32_t* cell_of;     // sorted position -> cell (the sorted keys)
+  int32_t* sched;       // processing order of rows (cells in Morton order)
 };
 
 struct Bumps {
@@ -169,8 +173,9 @@ Csr assemble_sorted(Ctx* c, const Sorted& s, const KParams& kp, const Bumps& b,
 // Canonical (caller order, ascending columns) copy of a sorted-order CSR.
 void canonicalize(Ctx* c, const Sorted& s, const Csr& k, int64_t* row_ptr,
                   int32_t* col, double* val);
-// Rectangular cross-kernel kappa between sorted training points and test
-// points, as dense-free CSR over test rows (used by the posterior).
+// Cross-covariance kappa between test points (rows, caller order) and the
+// sorted training points (columns) as CSR, and the prior variances
+// k(x0, x0); requires prune() to have run for the same hyperparameters.
 Csr assemble_cross(Ctx* c, const Sorted& s, const KParams& kp, const Bumps& b,
                    const double* x0, int64_t n0, const double* h,
                    double** kxx_out);
@@ -178,7 +183,20 @@ Csr assemble_cross(Ctx* c, const Sorted& s, const KParams& kp, const Bumps& b,
 // ---------------------------------------------------------------------------
 // Solver (solve.hip)
 // ---------------------------------------------------------------------------
+// Low-rank preconditioner M = c I + F F^T of the SUM combine (F: the sorted
+// bump values); Sinv = (c I + F^T F)^{-1} on the device.
+struct Precond {
+  int n1 = 0;
+  const double* F = nullptr;
+  const double* Sinv = nullptr;
+  double c = 1.0;
+  double logdetM = 0.0;
+};
+
 struct CgResult {
+  double* V = nullptr;      // [n, R] M^{-1} b when preconditioned and kept
+  double* rz0 = nullptr;    // [R] b^T M^{-1} b
+  double logdetM = 0.0;
   int iters;
   int iters_y;
   double relres_max;
@@ -194,9 +212,12 @@ struct CgResult {
 enum ProbeKind { PK_RADEMACHER = 0, PK_IDENTITY = 2, PK_NONE = 3, PK_DENSE = 4 };
 
 // Block CG on A X = [y, z_1..z_P] (or caller dense RHS when kind==PK_DENSE).
+// pc (optional) preconditions every column; keep_v stores M^{-1} b.
 CgResult block_cg(Ctx* c, const Csr& A, const Sorted& s, const double* ys,
                   int kind, int P, uint64_t seed, double rtol, int max_iter,
-                  const double* dense_rhs, int dense_R, PhaseTimer* t);
+                  const double* dense_rhs, int dense_R, const Precond* pc,
+                  bool keep_v, PhaseTimer* t);
+Precond lowrank_precond(Ctx* c, const Sorted& s, const KParams& kp, const Bumps& b);
 void spmm(Ctx* c, const Csr& A, const double* X, int R, double* Y);
 // Stochastic Lanczos quadrature from CG coefficients of columns 1..R-1.
 void slq_from_cg(Ctx* c, const CgResult& cg, int kind, int P, int64_t n,
@@ -205,6 +226,10 @@ void slq_from_cg(Ctx* c, const CgResult& cg, int kind, int P, int64_t n,
 double dot_device(Ctx* c, const double* a, int64_t stride_a, const double* b,
                   int64_t stride_b, int64_t n);
 void probe_bits(Ctx* c, const Sorted& s, int P, uint64_t seed, uint64_t* zbits);
+// var[t] = kxx[t] - kappa_t^T A^{-1} kappa_t, by block CG over chunks of 64
+// test columns.
+void posterior_variance(Ctx* c, const Csr& A, const Sorted& s, const Csr& K0, const double* kxx, double rtol,
+                        int max_iter, const Precond* pc, double* var, bool* converged);
 
 // ---------------------------------------------------------------------------
 // Adjoint (adjoint.hip)

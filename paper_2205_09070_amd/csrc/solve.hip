@@ -12,7 +12,9 @@
 // column chunk in a fixed order inside every block (so every block obtains
 // bit-identical scalars without atomics or grid-wide barriers).
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <thread>
 #include <vector>
 
 #include "kernel_math.hpp"
@@ -26,6 +28,9 @@ constexpr int kCgBlock = 1024;             // 16 wavefronts
 constexpr int kCgWaves = kCgBlock / kWave;
 
 // y = sum_k val[k] X[col[k], rc] over one CSR row (the calling wave's row).
+// The row's entries are loaded 64 at a time by the lanes and broadcast with
+// readlane; 16 gathers are issued before their products are summed so that
+// enough loads are in flight to cover the cache latency.
 __device__ __forceinline__ double row_dot(const int64_t k0, const int64_t k1, const int32_t* __restrict__ col,
                                           const double* __restrict__ val, const double* __restrict__ Xc,
                                           const int64_t R) {
@@ -38,55 +43,119 @@ __device__ __forceinline__ double row_dot(const int64_t k0, const int64_t k1, co
     if (k < k1) { cj = col[k]; vj = val[k]; }
     const int cnt = (int)min((int64_t)kWave, k1 - kb);
     int j = 0;
+    for (; j + 16 <= cnt; j += 16) {
+      double xv[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) xv[u] = Xc[(int64_t)readlane_i32(cj, j + u) * R];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) acc += readlane_f64(vj, j + u) * xv[u];
+    }
     for (; j + 4 <= cnt; j += 4) {
-      const int c0 = readlane_i32(cj, j), c1 = readlane_i32(cj, j + 1);
-      const int c2 = readlane_i32(cj, j + 2), c3 = readlane_i32(cj, j + 3);
-      const double x0 = Xc[(int64_t)c0 * R], x1 = Xc[(int64_t)c1 * R];
-      const double x2 = Xc[(int64_t)c2 * R], x3 = Xc[(int64_t)c3 * R];
-      acc += readlane_f64(vj, j) * x0;
-      acc += readlane_f64(vj, j + 1) * x1;
-      acc += readlane_f64(vj, j + 2) * x2;
-      acc += readlane_f64(vj, j + 3) * x3;
+      double xv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) xv[u] = Xc[(int64_t)readlane_i32(cj, j + u) * R];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc += readlane_f64(vj, j + u) * xv[u];
     }
     for (; j < cnt; ++j) acc += readlane_f64(vj, j) * Xc[(int64_t)readlane_i32(cj, j) * R];
   }
   return acc;
 }
 
+// Rows handled by the calling wave under an XCD-aware mapping: the grid's
+// blocks are dealt round-robin to the 8 XCDs, so XCD x (blocks with
+// blockIdx.x % 8 == x) takes the x-th eighth of the rows and all its waves
+// sweep that range together, keeping the gathered neighbour rows in the
+// XCD's own L2.  gridDim.x must be a multiple of 8.
+struct RowSweep {
+  int64_t a, hi, step;
+  __device__ RowSweep(int64_t n, int waves_per_block) {
+    const int xcd = blockIdx.x & 7;
+    const int64_t bi = blockIdx.x >> 3;
+    const int64_t nbx = gridDim.x >> 3;
+    const int64_t nx = (n + 7) >> 3;
+    const int64_t lo = xcd * nx;
+    hi = min(n, lo + nx);
+    step = nbx * waves_per_block;
+    a = lo + bi * waves_per_block + (threadIdx.x >> 6);
+  }
+};
+
 // Plain SpMM: Y = A X (one wave per row, lanes over a 64-column chunk).
 __global__ __launch_bounds__(256) void k_spmm(int64_t n, const int64_t* __restrict__ row_ptr,
                                               const int32_t* __restrict__ col, const double* __restrict__ val,
                                               const double* __restrict__ X, int R, double* __restrict__ Y) {
-  const int64_t a = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
-  if (a >= n) return;
   const int rc = blockIdx.y * kWave + lane_id();
   const int rcc = rc < R ? rc : R - 1;
-  const double v = row_dot(row_ptr[a], row_ptr[a + 1], col, val, X + rcc, R);
-  if (rc < R) Y[a * (int64_t)R + rc] = v;
+  for (RowSweep w(n, 4); w.a < w.hi; w.a += w.step) {
+    const int64_t a = w.a;
+    const double v = row_dot(row_ptr[a], row_ptr[a + 1], col, val, X + rcc, R);
+    if (rc < R) Y[a * (int64_t)R + rc] = v;
+  }
+}
+
+// SpMV (one right-hand side): 16 lanes per row, 4 rows per wave; each lane
+// first loads up to 8 of its row's (column, value) pairs, then issues the 8
+// gathers together (two round trips per 128 entries instead of sixteen).
+__global__ __launch_bounds__(256) void k_spmv(int64_t n, const int64_t* __restrict__ row_ptr,
+                                              const int32_t* __restrict__ col, const double* __restrict__ val,
+                                              const double* __restrict__ x, double* __restrict__ y) {
+  const int sub = threadIdx.x & 15;
+  const int xcd = blockIdx.x & 7;
+  const int64_t bi = blockIdx.x >> 3, nbx = gridDim.x >> 3;
+  const int64_t nx = (n + 7) >> 3, lo = xcd * nx, hi = min(n, lo + nx);
+  const int64_t groups = blockDim.x >> 4;
+  for (int64_t a = lo + bi * groups + (threadIdx.x >> 4); a - (threadIdx.x >> 4) < hi; a += nbx * groups) {
+    double acc = 0.0;
+    if (a < hi) {
+      const int64_t k1 = row_ptr[a + 1];
+      for (int64_t k0 = row_ptr[a] + sub; k0 < k1; k0 += 16 * 8) {
+        int cj[8];
+        double vj[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int64_t k = k0 + 16 * u;
+          cj[u] = k < k1 ? col[k] : 0;
+          vj[u] = k < k1 ? val[k] : 0.0;
+        }
+        double xv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) xv[u] = x[cj[u]];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += vj[u] * xv[u];
+      }
+    }
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 16);
+    if (a < hi && sub == 0) y[a] = acc;
+  }
 }
 
 struct CgState {
-  double* rr;       // [2][R] parity buffers of r.r
+  double* rz;       // [2][R] parity buffers of the CG scalar r.z (r.r unpreconditioned)
+  double* rz0;      // [R] b^T M^{-1} b (b^T b unpreconditioned): SLQ weight
   int32_t* act;     // [2][R] active flags
   int32_t* failed;  // [R] p^T A p <= 0 met
   double* bnorm2;   // [R]
+  double* rr_last;  // [R] |r|^2 at each column's last iteration
   int32_t* iters;   // [R]
-  int32_t* done;    // [1]
+  int32_t* done;    // [1] executed iterations once every column stopped
   int32_t* not_spd; // [1]
   double* hist_a;   // [max_iter][R]
   double* hist_b;   // [max_iter][R]
 };
 
-// Fixed-order reduction of per-block partials part[b][r] (b < nb) for the
-// 64-column chunk of this block into sh[0..63].  All blocks get identical
-// values.
-__device__ void chunk_reduce(const double* __restrict__ part, int nb, int R, double* sh, double* scratch) {
+// Fixed-order reduction of per-block partials part[b*stride + rc] (b < nb)
+// for the 64-column chunk of this block into sh[0..63].  All blocks obtain
+// bit-identical values.
+__device__ void chunk_reduce(const double* __restrict__ part, int nb, int64_t stride, int R, double* sh,
+                             double* scratch) {
   const int t = threadIdx.x;
   const int l = t & 63, w = t >> 6;
   const int rc = blockIdx.y * kWave + l;
   double s = 0.0;
   if (rc < R)
-    for (int b = w; b < nb; b += kCgWaves) s += part[(int64_t)b * R + rc];
+    for (int b = w; b < nb; b += kCgWaves) s += part[(int64_t)b * stride + rc];
   scratch[w * kWave + l] = s;
   __syncthreads();
   if (t < kWave) {
@@ -97,17 +166,19 @@ __device__ void chunk_reduce(const double* __restrict__ part, int nb, int R, dou
   __syncthreads();
 }
 
-// Block partial of per-lane values over the block's waves.
-__device__ void block_partial(double v, double* scratch, double* part, int R) {
+// Block partial of per-lane values over the block's waves into
+// part[blockIdx.x*stride + rc].
+__device__ void block_partial(double v, double* scratch, double* part, int64_t stride, int R) {
   const int t = threadIdx.x;
   const int l = t & 63, w = t >> 6;
+  __syncthreads();
   scratch[w * kWave + l] = v;
   __syncthreads();
   if (t < kWave) {
     double tot = 0.0;
     for (int q = 0; q < kCgWaves; ++q) tot += scratch[q * kWave + t];
     const int rc = blockIdx.y * kWave + t;
-    if (rc < R) part[(int64_t)blockIdx.x * R + rc] = tot;
+    if (rc < R) part[(int64_t)blockIdx.x * stride + rc] = tot;
   }
 }
 
@@ -118,11 +189,85 @@ struct CgArgs {
   const int32_t* col;
   const double* val;
   double *X, *Rr, *P, *Q;
-  double* part;     // [nb][R]
+  double* part;        // [nb][R]
+  double* partg;       // [nb][n1][R]  F^T r partials (preconditioned)
+  double* g;           // [n1][R]
+  double* V;           // [n][R] M^{-1} b (preconditioned, may be null)
+  const int32_t* sched;  // row processing order for the SpMM (may be null)
+  const double* F;     // [n][n1] sorted bump values
+  const double* Sinv;  // [n1][n1] (c I + F^T F)^{-1}
+  int n1;
+  double inv_c, sqrt_c;
   int nb;
   CgState st;
   double rtol2;
 };
+
+// Per-block partials of F^T v (v: this lane's column of the block's rows)
+// given per-lane accumulators acc[NI]: reduced 4 at a time through LDS.
+template <int NI>
+__device__ void block_partial_g(const double* acc, double* gs, const CgArgs& A) {
+  const int t = threadIdx.x;
+  const int l = t & 63, w = t >> 6;
+  const int rc = blockIdx.y * kWave + l;
+#pragma unroll
+  for (int i0 = 0; i0 < NI; i0 += 4) {
+    if (i0 >= A.n1) break;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) gs[(q * kCgWaves + w) * kWave + l] = acc[i0 + q];
+    __syncthreads();
+    if (t < 4 * kWave) {
+      const int q = t >> 6;
+      const int i = i0 + q;
+      double tot = 0.0;
+      for (int ww = 0; ww < kCgWaves; ++ww) tot += gs[(q * kCgWaves + ww) * kWave + l];
+      if (i < A.n1 && rc < A.R) A.partg[((int64_t)blockIdx.x * A.n1 + i) * A.R + rc] = tot;
+    }
+  }
+}
+
+// u = Sinv g for the block's 64 columns into us[i][l] (gs, us in LDS), then
+// gu[l] = g.u per column.  g is read from A.g.
+template <int NI>
+__device__ void solve_small(const CgArgs& A, double* gs, double* us, double* gu) {
+  const int t = threadIdx.x;
+  const int l = t & 63;
+  const int rc = blockIdx.y * kWave + l;
+  for (int idx = t; idx < A.n1 * kWave; idx += blockDim.x) {
+    const int i = idx >> 6, ll = idx & 63;
+    const int r = blockIdx.y * kWave + ll;
+    gs[i * kWave + ll] = r < A.R ? A.g[(int64_t)i * A.R + r] : 0.0;
+  }
+  __syncthreads();
+  for (int idx = t; idx < A.n1 * kWave; idx += blockDim.x) {
+    const int i = idx >> 6, ll = idx & 63;
+    double u = 0.0;
+    for (int j = 0; j < A.n1; ++j) u += A.Sinv[i * A.n1 + j] * gs[j * kWave + ll];
+    us[i * kWave + ll] = u;
+  }
+  __syncthreads();
+  if (t < kWave) {
+    double d = 0.0;
+    for (int i = 0; i < A.n1; ++i) d += gs[i * kWave + t] * us[i * kWave + t];
+    gu[t] = d;
+  }
+  __syncthreads();
+  (void)rc;
+}
+
+// z_a = M^{-1} r at row a, column lane: (r - F_a . u) / c.
+template <int NI>
+__device__ __forceinline__ double apply_prec(const CgArgs& A, int64_t a, double r, const double* us) {
+  if (NI == 0) return r;
+  const int lane = lane_id();
+  const double* Fa = A.F + a * (int64_t)A.n1;
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < NI; ++i)
+    if (i < A.n1) s += Fa[i] * us[i * kWave + lane];
+  return (r - s) * A.inv_c;
+}
 
 // Q = A P, partial p.q per column.
 __global__ __launch_bounds__(kCgBlock) void k_cg_spmm(CgArgs A) {
@@ -132,24 +277,26 @@ __global__ __launch_bounds__(kCgBlock) void k_cg_spmm(CgArgs A) {
   const int rc = blockIdx.y * kWave + lane;
   const int rcc = rc < A.R ? rc : A.R - 1;
   const int64_t R = A.R;
-  const int64_t W = (int64_t)gridDim.x * kCgWaves;
   double pq = 0.0;
-  for (int64_t a = blockIdx.x * (int64_t)kCgWaves + (threadIdx.x >> 6); a < A.n; a += W) {
+  for (RowSweep w(A.n, kCgWaves); w.a < w.hi; w.a += w.step) {
+    const int64_t a = A.sched ? (int64_t)A.sched[w.a] : w.a;
     const double q = row_dot(A.row_ptr[a], A.row_ptr[a + 1], A.col, A.val, A.P + rcc, R);
     if (rc < A.R) {
       A.Q[a * R + rc] = q;
       pq += A.P[a * R + rc] * q;
     }
   }
-  block_partial(pq, scratch, A.part, A.R);
+  block_partial(pq, scratch, A.part, A.R, A.R);
 }
 
-// alpha = r.r / p.q; x += alpha p; r -= alpha q; partial r.r.
+// alpha = r.z / p.q; x += alpha p; r -= alpha q; partials r.r and F^T r.
+template <int NI>
 __global__ __launch_bounds__(kCgBlock) void k_cg_update_xr(CgArgs A, int it) {
   if (*A.st.done) return;
   __shared__ double scratch[kCgBlock];
   __shared__ double pAp[kWave];
-  chunk_reduce(A.part, A.nb, A.R, pAp, scratch);
+  __shared__ double gsh[NI > 0 ? 4 * kCgBlock : 1];
+  chunk_reduce(A.part, A.nb, A.R, A.R, pAp, scratch);
   const int lane = lane_id();
   const int rc = blockIdx.y * kWave + lane;
   const int par = it & 1;
@@ -159,7 +306,7 @@ __global__ __launch_bounds__(kCgBlock) void k_cg_update_xr(CgArgs A, int it) {
     act = A.st.act[par * A.R + rc] != 0;
     if (act) {
       const double d = pAp[lane];
-      if (d > 0.0 && isfinite(d)) alpha = A.st.rr[par * A.R + rc] / d;
+      if (d > 0.0 && isfinite(d)) alpha = A.st.rz[par * A.R + rc] / d;
       else act = false;
     }
   }
@@ -168,10 +315,12 @@ __global__ __launch_bounds__(kCgBlock) void k_cg_update_xr(CgArgs A, int it) {
     if (was) A.st.hist_a[(int64_t)it * A.R + rc] = alpha;
     if (was && !act) { A.st.failed[rc] = 1; *A.st.not_spd = 1; }
   }
-  __syncthreads();
   const int64_t R = A.R;
   const int64_t W = (int64_t)gridDim.x * kCgWaves;
   double rr = 0.0;
+  double gacc[NI > 0 ? NI : 1];
+#pragma unroll
+  for (int i = 0; i < (NI > 0 ? NI : 1); ++i) gacc[i] = 0.0;
   for (int64_t a = blockIdx.x * (int64_t)kCgWaves + (threadIdx.x >> 6); a < A.n; a += W) {
     if (act) {
       const int64_t o = a * R + rc;
@@ -179,40 +328,75 @@ __global__ __launch_bounds__(kCgBlock) void k_cg_update_xr(CgArgs A, int it) {
       const double r = A.Rr[o] - alpha * A.Q[o];
       A.Rr[o] = r;
       rr += r * r;
+      if (NI > 0) {
+        const double* Fa = A.F + a * (int64_t)A.n1;
+#pragma unroll
+        for (int i = 0; i < NI; ++i)
+          if (i < A.n1) gacc[i] += Fa[i] * r;
+      }
     }
   }
-  __syncthreads();
-  block_partial(rr, scratch, A.part, A.R);
+  block_partial(rr, scratch, A.part, A.R, A.R);
+  if (NI > 0) block_partial_g<NI>(gacc, gsh, A);
 }
 
-// beta = r.r_new / r.r; convergence test; p = r + beta p.
+// g[i][r] = sum_b partg[b][i][r] (fixed order); grid (n1, chunks).
+__global__ __launch_bounds__(kCgBlock) void k_cg_reduce_g(CgArgs A) {
+  if (*A.st.done) return;
+  __shared__ double scratch[kCgBlock];
+  const int i = blockIdx.x;
+  const int t = threadIdx.x;
+  const int l = t & 63, w = t >> 6;
+  const int rc = blockIdx.y * kWave + l;
+  double s = 0.0;
+  if (rc < A.R)
+    for (int b = w; b < A.nb; b += kCgWaves) s += A.partg[((int64_t)b * A.n1 + i) * A.R + rc];
+  scratch[w * kWave + l] = s;
+  __syncthreads();
+  if (t < kWave && rc < A.R) {
+    double tot = 0.0;
+    for (int q = 0; q < kCgWaves; ++q) tot += scratch[q * kWave + t];
+    A.g[(int64_t)i * A.R + rc] = tot;
+  }
+}
+
+// beta = r.z_new / r.z; convergence on |r|; p = z + beta p with
+// z = M^{-1} r formed on the fly (r.z_new = (r.r - g.u)/c, g = F^T r,
+// u = (cI + F^T F)^{-1} g, so no extra pass is needed).
+template <int NI>
 __global__ __launch_bounds__(kCgBlock) void k_cg_update_p(CgArgs A, int it) {
   if (*A.st.done) return;
   __shared__ double scratch[kCgBlock];
   __shared__ double rrn[kWave];
-  chunk_reduce(A.part, A.nb, A.R, rrn, scratch);
+  __shared__ double gu[kWave];
+  __shared__ double gs[NI > 0 ? NI * kWave : 1];
+  __shared__ double us[NI > 0 ? NI * kWave : 1];
+  chunk_reduce(A.part, A.nb, A.R, A.R, rrn, scratch);
+  if (NI > 0) solve_small<NI>(A, gs, us, gu);
   const int lane = lane_id();
   const int rc = blockIdx.y * kWave + lane;
   const int par = it & 1, nxt = par ^ 1;
   double beta = 0.0;
   bool cont = false;
   bool act = false;
-  double rr_new = 0.0, rr_old = 0.0;
+  double rz_new = 0.0, rz_old = 0.0;
   if (rc < A.R) {
     act = A.st.act[par * A.R + rc] != 0 && A.st.failed[rc] == 0;
-    rr_old = A.st.rr[par * A.R + rc];
-    rr_new = rrn[lane];
+    rz_old = A.st.rz[par * A.R + rc];
+    const double rr_new = rrn[lane];
+    rz_new = NI > 0 ? (rr_new - gu[lane]) * A.inv_c : rr_new;
     if (act) {
-      beta = rr_new / rr_old;
+      beta = rz_new / rz_old;
       cont = !(rr_new <= A.rtol2 * A.st.bnorm2[rc]);
     }
   }
   if (blockIdx.x == 0 && threadIdx.x < kWave && rc < A.R) {
-    A.st.rr[nxt * A.R + rc] = act ? rr_new : rr_old;
+    A.st.rz[nxt * A.R + rc] = act ? rz_new : rz_old;
     A.st.act[nxt * A.R + rc] = cont ? 1 : 0;
     if (act) {
       A.st.hist_b[(int64_t)it * A.R + rc] = beta;
       A.st.iters[rc] += 1;
+      A.st.rr_last[rc] = rrn[lane];
     }
   }
   const int64_t R = A.R;
@@ -220,7 +404,7 @@ __global__ __launch_bounds__(kCgBlock) void k_cg_update_p(CgArgs A, int it) {
   for (int64_t a = blockIdx.x * (int64_t)kCgWaves + (threadIdx.x >> 6); a < A.n; a += W) {
     if (cont) {
       const int64_t o = a * R + rc;
-      A.P[o] = A.Rr[o] + beta * A.P[o];
+      A.P[o] = apply_prec<NI>(A, a, A.Rr[o], us) + beta * A.P[o];
     }
   }
 }
@@ -228,6 +412,7 @@ __global__ __launch_bounds__(kCgBlock) void k_cg_update_p(CgArgs A, int it) {
 // Records the executed iteration count in done when no column is active
 // (one block, after update_p).
 __global__ void k_cg_check(CgArgs A, int it) {
+  if (*A.st.done) return;
   const int nxt = (it & 1) ^ 1;
   __shared__ int left;
   if (threadIdx.x == 0) left = 0;
@@ -239,7 +424,9 @@ __global__ void k_cg_check(CgArgs A, int it) {
   if (threadIdx.x == 0 && !left) *A.st.done = it + 1;
 }
 
-// Right-hand sides and CG initial state (x = 0, r = p = b).
+// Right-hand sides and x = 0, r = b.  Probe p (column 1+p) is the Rademacher
+// vector w_p of caller row perm[a], or with the preconditioner
+// sqrt(c) w_p + F v_p (v_p: n1 Rademacher signs), whose covariance is M.
 __global__ void k_cg_init(CgArgs A, const double* __restrict__ ys, const int32_t* __restrict__ perm,
                           int kind, uint64_t seed, const double* __restrict__ dense) {
   const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -255,137 +442,84 @@ __global__ void k_cg_init(CgArgs A, const double* __restrict__ ys, const int32_t
   } else if (kind == PK_IDENTITY) {
     b = (perm[a] == r - 1) ? 1.0 : 0.0;
   } else {
-    const uint64_t k = ((uint64_t)(r - 1) << 32) + (uint64_t)perm[a] + 1ull;
-    b = (splitmix64_at(seed, k) >> 63) ? -1.0 : 1.0;
+    const uint64_t pbase = (uint64_t)(r - 1) << 32;
+    b = (splitmix64_at(seed, pbase + (uint64_t)perm[a] + 1ull) >> 63) ? -1.0 : 1.0;
+    if (A.n1 > 0 && A.F != nullptr) {
+      double fv = 0.0;
+      const double* Fa = A.F + a * (int64_t)A.n1;
+      for (int i = 0; i < A.n1; ++i) {
+        const double v = (splitmix64_at(seed, pbase + 0xFFFFFFFFull - (uint64_t)i) >> 63) ? -1.0 : 1.0;
+        fv += Fa[i] * v;
+      }
+      b = A.sqrt_c * b + fv;
+    }
   }
   A.X[idx] = 0.0;
   A.Rr[idx] = b;
-  A.P[idx] = b;
 }
 
-// Column norms of b (fixed-order partials then one block).
+// Partials of b.b and F^T b.
+template <int NI>
 __global__ __launch_bounds__(kCgBlock) void k_cg_norm_part(CgArgs A) {
   __shared__ double scratch[kCgBlock];
+  __shared__ double gsh[NI > 0 ? 4 * kCgBlock : 1];
   const int rc = blockIdx.y * kWave + lane_id();
   const int64_t R = A.R;
   const int64_t W = (int64_t)gridDim.x * kCgWaves;
   double s = 0.0;
+  double gacc[NI > 0 ? NI : 1];
+#pragma unroll
+  for (int i = 0; i < (NI > 0 ? NI : 1); ++i) gacc[i] = 0.0;
   if (rc < A.R)
     for (int64_t a = blockIdx.x * (int64_t)kCgWaves + (threadIdx.x >> 6); a < A.n; a += W) {
       const double v = A.Rr[a * R + rc];
       s += v * v;
+      if (NI > 0) {
+        const double* Fa = A.F + a * (int64_t)A.n1;
+#pragma unroll
+        for (int i = 0; i < NI; ++i)
+          if (i < A.n1) gacc[i] += Fa[i] * v;
+      }
     }
-  block_partial(s, scratch, A.part, A.R);
+  block_partial(s, scratch, A.part, A.R, A.R);
+  if (NI > 0) block_partial_g<NI>(gacc, gsh, A);
 }
 
-__global__ __launch_bounds__(kCgBlock) void k_cg_norm_fin(CgArgs A) {
+// Initial state: p = z0 = M^{-1} b (b when unpreconditioned), V = z0,
+// rz0 = b.z0, bnorm2 = b.b.
+template <int NI>
+__global__ __launch_bounds__(kCgBlock) void k_cg_init_fin(CgArgs A) {
   __shared__ double scratch[kCgBlock];
   __shared__ double nrm[kWave];
-  chunk_reduce(A.part, A.nb, A.R, nrm, scratch);
-  if (blockIdx.x != 0) return;
-  const int t = threadIdx.x;
-  const int rc = blockIdx.y * kWave + t;
-  if (t < kWave && rc < A.R) {
-    A.st.bnorm2[rc] = nrm[t];
-    A.st.rr[rc] = nrm[t];
-    A.st.rr[A.R + rc] = nrm[t];
-    A.st.act[rc] = nrm[t] > 0.0 ? 1 : 0;
+  __shared__ double gu[kWave];
+  __shared__ double gs[NI > 0 ? NI * kWave : 1];
+  __shared__ double us[NI > 0 ? NI * kWave : 1];
+  chunk_reduce(A.part, A.nb, A.R, A.R, nrm, scratch);
+  if (NI > 0) solve_small<NI>(A, gs, us, gu);
+  const int lane = lane_id();
+  const int rc = blockIdx.y * kWave + lane;
+  if (blockIdx.x == 0 && threadIdx.x < kWave && rc < A.R) {
+    const double bb = nrm[lane];
+    const double rz0 = NI > 0 ? (bb - gu[lane]) * A.inv_c : bb;
+    A.st.bnorm2[rc] = bb;
+    A.st.rr_last[rc] = bb;
+    A.st.rz[rc] = rz0;
+    A.st.rz[A.R + rc] = rz0;
+    A.st.rz0[rc] = rz0;
+    A.st.act[rc] = bb > 0.0 ? 1 : 0;
     A.st.act[A.R + rc] = 0;
     A.st.failed[rc] = 0;
     A.st.iters[rc] = 0;
   }
-}
-
-// ------------------------------------------------------------------- SLQ
-// One thread per probe column: build the Lanczos tridiagonal from the CG
-// coefficients (T_00 = 1/a_0, T_kk = 1/a_k + b_{k-1}/a_{k-1},
-// T_k,k+1 = sqrt(b_k)/a_k), diagonalise it by the implicit QL method with
-// Wilkinson shifts (Bowdler, Martin, Reinsch, Wilkinson 1968), carrying only
-// the first row of the eigenvector matrix, and return
-// e_1^T ln(T) e_1 = sum_j tau_j^2 ln theta_j and the extreme Ritz values.
-__global__ void k_slq(const double* __restrict__ ha, const double* __restrict__ hb,
-                      const int32_t* __restrict__ iters, int R, int col0, int ncols, int mcap,
-                      int64_t stride, double* __restrict__ d, double* __restrict__ e,
-                      double* __restrict__ z, double* __restrict__ out) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= ncols) return;
-  const int r = col0 + p;
-  int m = iters[r];
-  if (mcap > 0 && m > mcap) m = mcap;
-  double* D = d + p;
-  double* E = e + p;
-  double* Z = z + p;
-#define AT(arr, k) arr[(int64_t)(k) * stride]
-  if (m <= 0) {
-    out[p * 4 + 0] = 0.0; out[p * 4 + 1] = 0.0; out[p * 4 + 2] = INFINITY; out[p * 4 + 3] = -INFINITY;
-    return;
-  }
-  for (int k = 0; k < m; ++k) {
-    const double ak = ha[(int64_t)k * R + r];
-    double dk = 1.0 / ak;
-    if (k > 0) dk += hb[(int64_t)(k - 1) * R + r] / ha[(int64_t)(k - 1) * R + r];
-    AT(D, k) = dk;
-    AT(E, k) = (k + 1 < m) ? sqrt(hb[(int64_t)k * R + r]) / ak : 0.0;
-    AT(Z, k) = (k == 0) ? 1.0 : 0.0;
-  }
-  bool ok = true;
-  for (int l = 0; l < m && ok; ++l) {
-    for (int iter = 0;; ++iter) {
-      int mm = l;
-      for (; mm < m - 1; ++mm) {
-        const double dd = fabs(AT(D, mm)) + fabs(AT(D, mm + 1));
-        if (fabs(AT(E, mm)) <= 1e-16 * dd) break;
-      }
-      if (mm == l) break;
-      if (iter >= 60) { ok = false; break; }
-      double g = (AT(D, l + 1) - AT(D, l)) / (2.0 * AT(E, l));
-      double rr = hypot(g, 1.0);
-      g = AT(D, mm) - AT(D, l) + AT(E, l) / (g + copysign(rr, g));
-      double s = 1.0, c = 1.0, pp = 0.0;
-      bool deflated = false;
-      for (int i = mm - 1; i >= l; --i) {
-        double f = s * AT(E, i);
-        const double b = c * AT(E, i);
-        rr = hypot(f, g);
-        AT(E, i + 1) = rr;
-        if (rr == 0.0) {
-          AT(D, i + 1) -= pp;
-          AT(E, mm) = 0.0;
-          deflated = true;
-          break;
-        }
-        s = f / rr;
-        c = g / rr;
-        g = AT(D, i + 1) - pp;
-        rr = (AT(D, i) - g) * s + 2.0 * c * b;
-        pp = s * rr;
-        AT(D, i + 1) = g + pp;
-        g = c * rr - b;
-        f = AT(Z, i + 1);
-        AT(Z, i + 1) = s * AT(Z, i) + c * f;
-        AT(Z, i) = c * AT(Z, i) - s * f;
-      }
-      if (deflated) continue;
-      AT(D, l) -= pp;
-      AT(E, l) = g;
-      AT(E, mm) = 0.0;
+  const int64_t R = A.R;
+  const int64_t W = (int64_t)gridDim.x * kCgWaves;
+  if (rc < A.R)
+    for (int64_t a = blockIdx.x * (int64_t)kCgWaves + (threadIdx.x >> 6); a < A.n; a += W) {
+      const int64_t o = a * R + rc;
+      const double z = apply_prec<NI>(A, a, A.Rr[o], us);
+      A.P[o] = z;
+      if (A.V) A.V[o] = z;
     }
-  }
-  double q = 0.0, lo = INFINITY, hi = -INFINITY;
-  bool pos = ok;
-  for (int k = 0; k < m; ++k) {
-    const double th = AT(D, k);
-    const double tau = AT(Z, k);
-    if (!(th > 0.0)) pos = false;
-    lo = fmin(lo, th);
-    hi = fmax(hi, th);
-    q += tau * tau * log(th);
-  }
-#undef AT
-  out[p * 4 + 0] = pos ? q : NAN;
-  out[p * 4 + 1] = (double)m;
-  out[p * 4 + 2] = lo;
-  out[p * 4 + 3] = hi;
 }
 
 // ------------------------------------------------------------ utilities
@@ -416,20 +550,77 @@ __global__ void k_probe_bits(const int32_t* __restrict__ perm, int64_t n, int P,
   bits[s] = m;
 }
 
+// Dense right-hand sides B[b][j] = kappa[t0 + j, b] for a chunk of test rows
+// (B zeroed beforehand; every (b, j) is written at most once).
+__global__ void k_scatter_chunk(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                const double* __restrict__ val, int64_t t0, int Rc, int64_t nq,
+                                double* __restrict__ B) {
+  const int64_t j = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+  if (j >= Rc || t0 + j >= nq) return;
+  const int64_t t = t0 + j;
+  for (int64_t k = rp[t] + lane_id(); k < rp[t + 1]; k += kWave) B[(int64_t)col[k] * Rc + j] = val[k];
+}
+
+// var[t] = kxx[t] - sum_b kappa[t, b] V[b][j] for the chunk's test rows.
+__global__ void k_rowdot_chunk(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                               const double* __restrict__ val, int64_t t0, int Rc, int64_t nq,
+                               const double* __restrict__ V, const double* __restrict__ kxx,
+                               double* __restrict__ var) {
+  const int64_t j = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+  if (j >= Rc || t0 + j >= nq) return;
+  const int64_t t = t0 + j;
+  double s = 0.0;
+  for (int64_t k = rp[t] + lane_id(); k < rp[t + 1]; k += kWave) s += val[k] * V[(int64_t)col[k] * Rc + j];
+  s = wave_sum(s);
+  if (lane_id() == 0) var[t] = kxx[t] - s;
+}
+
+// Blocks per column chunk for the CG kernels: about two 1024-thread blocks
+// per CU, a multiple of 8 (the XCD-aware row sweep needs it).
 inline int cg_nb(int64_t n, int R) {
   const int chunks = (R + kWave - 1) / kWave;
   int64_t nb = std::max<int64_t>(1, 512 / chunks);
   nb = std::min<int64_t>(nb, (n + kCgWaves - 1) / kCgWaves);
-  return (int)std::max<int64_t>(nb, 1);
+  nb = (nb + 7) / 8 * 8;
+  return (int)nb;
 }
 
 }  // namespace
 
+void posterior_variance(Ctx* c, const Csr& A, const Sorted& s, const Csr& K0, const double* kxx, double rtol,
+                        int max_iter, const Precond* pc, double* var, bool* converged) {
+  const int64_t n = A.n, n0 = K0.n;
+  *converged = true;
+  for (int64_t t0 = 0; t0 < n0; t0 += kWave) {
+    const int Rc = (int)std::min<int64_t>(kWave, n0 - t0);
+    double* B = c->get<double>(S_POST, (size_t)n * Rc);
+    SDGP_HIP(hipMemsetAsync(B, 0, (size_t)n * Rc * sizeof(double), c->stream));
+    const unsigned g = (unsigned)((Rc + 3) / 4);
+    k_scatter_chunk<<<g, 256, 0, c->stream>>>(K0.row_ptr, K0.col, K0.val, t0, Rc, n0, B);
+    SDGP_CHECK_LAUNCH();
+    CgResult cg = block_cg(c, A, s, nullptr, PK_DENSE, 0, 0, rtol, max_iter, B, Rc, pc, false, nullptr);
+    if (cg.not_spd) throw Error(SDGP_ERR_NOT_SPD, "CG met p^T A p <= 0: the covariance is not positive definite");
+    if (!cg.converged) *converged = false;
+    k_rowdot_chunk<<<g, 256, 0, c->stream>>>(K0.row_ptr, K0.col, K0.val, t0, Rc, n0, cg.X, kxx, var);
+    SDGP_CHECK_LAUNCH();
+  }
+}
+
 void spmm(Ctx* c, const Csr& A, const double* X, int R, double* Y) {
   require(R >= 1 && R <= (1 << 20), "R must be in 1..2^20");
-  const int64_t blocks = (A.n + 3) / 4;
-  require(blocks < 0x7fffffff, "n too large");
-  dim3 grid((unsigned)blocks, (unsigned)((R + kWave - 1) / kWave));
+  const int64_t cu = std::max(8, c->cu_count);
+  if (R == 1) {
+    // 16 rows per 256-thread block; about 8 blocks per CU in flight
+    int64_t blocks = std::min<int64_t>((A.n + 15) / 16, cu * 8);
+    blocks = std::max<int64_t>(8, (blocks + 7) / 8 * 8);
+    k_spmv<<<(unsigned)blocks, 256, 0, c->stream>>>(A.n, A.row_ptr, A.col, A.val, X, Y);
+    SDGP_CHECK_LAUNCH();
+    return;
+  }
+  const int chunks = (R + kWave - 1) / kWave;
+  int64_t blocks = std::min<int64_t>((A.n + 3) / 4, std::max<int64_t>(8, cu * 8 / chunks));
+  blocks = std::max<int64_t>(8, (blocks + 7) / 8 * 8);
+  dim3 grid((unsigned)blocks, (unsigned)chunks);
   k_spmm<<<grid, 256, 0, c->stream>>>(A.n, A.row_ptr, A.col, A.val, X, R, Y);
   SDGP_CHECK_LAUNCH();
 }
@@ -452,8 +643,143 @@ void probe_bits(Ctx* c, const Sorted& s, int P, uint64_t seed, uint64_t* zbits) 
   SDGP_CHECK_LAUNCH();
 }
 
+namespace {
+
+// Gram matrix F^T F: block b accumulates rows [b*slab, (b+1)*slab) staged
+// 64 at a time in LDS; thread t owns the pairs idx = t, t+256, ...
+__global__ __launch_bounds__(256) void k_gram(const double* __restrict__ F, int64_t n, int n1, int64_t slab,
+                                              double* __restrict__ part) {
+  __shared__ double rows[64 * kMaxN1];
+  const int np = n1 * n1;
+  double acc[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+  const int64_t lo = blockIdx.x * slab, hi = min(n, lo + slab);
+  for (int64_t a0 = lo; a0 < hi; a0 += 64) {
+    const int cnt = (int)min((int64_t)64, hi - a0);
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < cnt * n1; idx += blockDim.x) rows[idx] = F[a0 * n1 + idx];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int idx = threadIdx.x + q * 256;
+      if (idx < np) {
+        const int i = idx / n1, j = idx % n1;
+        double s = 0.0;
+        for (int k = 0; k < cnt; ++k) s += rows[k * n1 + i] * rows[k * n1 + j];
+        acc[q] += s;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int idx = threadIdx.x + q * 256;
+    if (idx < np) part[(int64_t)blockIdx.x * np + idx] = acc[q];
+  }
+}
+
+template <int NI>
+void launch_cg_iteration(Ctx* c, const CgArgs& A, dim3 grid, int chunks, int it) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (c->timing) { e0 = c->event(); SDGP_HIP(hipEventRecord(e0, c->stream)); }
+  k_cg_spmm<<<grid, kCgBlock, 0, c->stream>>>(A);
+  SDGP_CHECK_LAUNCH();
+  if (c->timing) {
+    e1 = c->event();
+    SDGP_HIP(hipEventRecord(e1, c->stream));
+    c->spmm_events.push_back({e0, e1});
+  }
+  k_cg_update_xr<NI><<<grid, kCgBlock, 0, c->stream>>>(A, it);
+  SDGP_CHECK_LAUNCH();
+  if (NI > 0) {
+    k_cg_reduce_g<<<dim3(A.n1, chunks), kCgBlock, 0, c->stream>>>(A);
+    SDGP_CHECK_LAUNCH();
+  }
+  k_cg_update_p<NI><<<grid, kCgBlock, 0, c->stream>>>(A, it);
+  SDGP_CHECK_LAUNCH();
+  k_cg_check<<<1, 256, 0, c->stream>>>(A, it);
+  SDGP_CHECK_LAUNCH();
+}
+
+template <int NI>
+void launch_cg_init(Ctx* c, const CgArgs& A, dim3 grid, int chunks) {
+  k_cg_norm_part<NI><<<grid, kCgBlock, 0, c->stream>>>(A);
+  SDGP_CHECK_LAUNCH();
+  if (NI > 0) {
+    k_cg_reduce_g<<<dim3(A.n1, chunks), kCgBlock, 0, c->stream>>>(A);
+    SDGP_CHECK_LAUNCH();
+  }
+  k_cg_init_fin<NI><<<grid, kCgBlock, 0, c->stream>>>(A);
+  SDGP_CHECK_LAUNCH();
+}
+
+}  // namespace
+
+Precond lowrank_precond(Ctx* c, const Sorted& s, const KParams& kp, const Bumps& b) {
+  Precond pc;
+  const int n1 = kp.n1;
+  const int64_t n = s.n;
+  const double psi0 = kp.core == SDGP_CORE_KSTAT ? 0.26596152026762178529 : 1.0;
+  pc.c = kp.sigma2 * psi0 + kp.noise;
+  require(pc.c > 0.0, "the low-rank preconditioner needs sigma2 psi(0) + noise_var > 0");
+  pc.n1 = n1;
+  pc.F = b.F;
+  if (n1 == 0) {
+    pc.logdetM = (double)n * std::log(pc.c);
+    return pc;
+  }
+  const int64_t nbk = std::min<int64_t>(256, (n + 4095) / 4096);
+  const int64_t slab = (n + nbk - 1) / nbk;
+  const int np = n1 * n1;
+  double* part = c->get<double>(S_PC_PART, (size_t)nbk * np);
+  k_gram<<<(unsigned)nbk, 256, 0, c->stream>>>(b.F, n, n1, slab, part);
+  SDGP_CHECK_LAUNCH();
+  std::vector<double> hp((size_t)nbk * np);
+  SDGP_HIP(hipMemcpyAsync(hp.data(), part, hp.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  SDGP_HIP(hipStreamSynchronize(c->stream));
+  // S = c I + F^T F; Cholesky S = L L^T; ln det S; S^{-1}
+  std::vector<double> S((size_t)np, 0.0), L((size_t)np, 0.0), Si((size_t)np, 0.0);
+  for (int64_t bb = 0; bb < nbk; ++bb)
+    for (int q = 0; q < np; ++q) S[q] += hp[bb * np + q];
+  for (int i = 0; i < n1; ++i) S[i * n1 + i] += pc.c;
+  double logdetS = 0.0;
+  for (int j = 0; j < n1; ++j) {
+    double d = S[j * n1 + j];
+    for (int k = 0; k < j; ++k) d -= L[j * n1 + k] * L[j * n1 + k];
+    require(d > 0.0, "preconditioner factor is not positive definite");
+    const double ljj = std::sqrt(d);
+    L[j * n1 + j] = ljj;
+    logdetS += 2.0 * std::log(ljj);
+    for (int i = j + 1; i < n1; ++i) {
+      double v = S[i * n1 + j];
+      for (int k = 0; k < j; ++k) v -= L[i * n1 + k] * L[j * n1 + k];
+      L[i * n1 + j] = v / ljj;
+    }
+  }
+  for (int col = 0; col < n1; ++col) {  // solve L L^T x = e_col
+    std::vector<double> y(n1, 0.0);
+    for (int i = 0; i < n1; ++i) {
+      double v = (i == col) ? 1.0 : 0.0;
+      for (int k = 0; k < i; ++k) v -= L[i * n1 + k] * y[k];
+      y[i] = v / L[i * n1 + i];
+    }
+    for (int i = n1 - 1; i >= 0; --i) {
+      double v = y[i];
+      for (int k = i + 1; k < n1; ++k) v -= L[k * n1 + i] * Si[k * n1 + col];
+      Si[i * n1 + col] = v / L[i * n1 + i];
+    }
+  }
+  double* dSi = c->get<double>(S_PC_SINV, np);
+  SDGP_HIP(hipMemcpyAsync(dSi, Si.data(), np * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  SDGP_HIP(hipStreamSynchronize(c->stream));
+  pc.Sinv = dSi;
+  pc.logdetM = (double)(n - n1) * std::log(pc.c) + logdetS;
+  return pc;
+}
+
 CgResult block_cg(Ctx* c, const Csr& Am, const Sorted& s, const double* ys, int kind, int P, uint64_t seed,
-                  double rtol, int max_iter, const double* dense_rhs, int dense_R, PhaseTimer* t) {
+                  double rtol, int max_iter, const double* dense_rhs, int dense_R, const Precond* pc,
+                  bool keep_v, PhaseTimer* t) {
   const int64_t n = Am.n;
   int R;
   if (kind == PK_DENSE) R = dense_R;
@@ -463,6 +789,9 @@ CgResult block_cg(Ctx* c, const Csr& Am, const Sorted& s, const double* ys, int 
   require(R >= 1, "no right-hand sides");
   require(max_iter >= 1, "cg_max_iter must be >= 1");
   require(rtol > 0.0 && std::isfinite(rtol), "cg_rtol must be > 0");
+  const bool use_pc = pc != nullptr && pc->n1 > 0;
+  const int n1 = use_pc ? pc->n1 : 0;
+  const int NI = n1 == 0 ? 0 : (n1 <= 8 ? 8 : (n1 <= 16 ? 16 : (n1 <= 32 ? 32 : 64)));
   const size_t NR = (size_t)n * R;
   CgArgs A;
   A.n = n;
@@ -474,16 +803,28 @@ CgResult block_cg(Ctx* c, const Csr& Am, const Sorted& s, const double* ys, int 
   A.Rr = c->get<double>(S_CG_R, NR);
   A.P = c->get<double>(S_CG_P, NR);
   A.Q = c->get<double>(S_CG_Q, NR);
+  A.V = (use_pc && keep_v) ? c->get<double>(S_CG_V, NR) : nullptr;
+  A.sched = s.sched;
   const int nb = cg_nb(n, R);
   const int chunks = (R + kWave - 1) / kWave;
   A.nb = nb;
   A.part = c->get<double>(S_CG_PART, (size_t)nb * R);
-  // state block
-  size_t words = 2 * (size_t)R + R + 2 + 2 * (size_t)R + R + 8;
-  char* sb = c->get<char>(S_CG_STATE, words * 8 + 64);
-  A.st.rr = reinterpret_cast<double*>(sb);
-  A.st.bnorm2 = A.st.rr + 2 * (size_t)R;
-  int32_t* ib = reinterpret_cast<int32_t*>(A.st.bnorm2 + R);
+  A.n1 = n1;
+  A.F = use_pc ? pc->F : nullptr;
+  A.Sinv = use_pc ? pc->Sinv : nullptr;
+  A.inv_c = use_pc ? 1.0 / pc->c : 1.0;
+  A.sqrt_c = use_pc ? std::sqrt(pc->c) : 1.0;
+  A.partg = use_pc ? c->get<double>(S_CG_PARTG, (size_t)nb * n1 * R) : nullptr;
+  A.g = use_pc ? c->get<double>(S_CG_G, (size_t)n1 * R) : nullptr;
+  // state block: doubles rz[2R], rz0[R], bnorm2[R], rr_last[R];
+  // ints act[2R], failed[R], iters[R], done, not_spd
+  const size_t bytes = (5 * (size_t)R) * 8 + (4 * (size_t)R + 2) * 4 + 64;
+  char* sb = c->get<char>(S_CG_STATE, bytes);
+  A.st.rz = reinterpret_cast<double*>(sb);
+  A.st.rz0 = A.st.rz + 2 * (size_t)R;
+  A.st.bnorm2 = A.st.rz0 + R;
+  A.st.rr_last = A.st.bnorm2 + R;
+  int32_t* ib = reinterpret_cast<int32_t*>(A.st.rr_last + R);
   A.st.act = ib;
   A.st.failed = ib + 2 * (size_t)R;
   A.st.iters = A.st.failed + R;
@@ -501,10 +842,13 @@ CgResult block_cg(Ctx* c, const Csr& Am, const Sorted& s, const double* ys, int 
     SDGP_CHECK_LAUNCH();
   }
   dim3 grid(nb, chunks);
-  k_cg_norm_part<<<grid, kCgBlock, 0, c->stream>>>(A);
-  SDGP_CHECK_LAUNCH();
-  k_cg_norm_fin<<<dim3(1, chunks), kCgBlock, 0, c->stream>>>(A);
-  SDGP_CHECK_LAUNCH();
+  switch (NI) {
+    case 0: launch_cg_init<0>(c, A, grid, chunks); break;
+    case 8: launch_cg_init<8>(c, A, grid, chunks); break;
+    case 16: launch_cg_init<16>(c, A, grid, chunks); break;
+    case 32: launch_cg_init<32>(c, A, grid, chunks); break;
+    default: launch_cg_init<64>(c, A, grid, chunks); break;
+  }
   // iterate; poll the done flag now and then
   int it = 0;
   int check = 8;
@@ -513,21 +857,13 @@ CgResult block_cg(Ctx* c, const Csr& Am, const Sorted& s, const double* ys, int 
   while (it < max_iter) {
     const int upto = std::min(max_iter, it + check);
     for (; it < upto; ++it) {
-      hipEvent_t e0 = nullptr, e1 = nullptr;
-      if (c->timing) { e0 = c->event(); SDGP_HIP(hipEventRecord(e0, c->stream)); }
-      k_cg_spmm<<<grid, kCgBlock, 0, c->stream>>>(A);
-      SDGP_CHECK_LAUNCH();
-      if (c->timing) {
-        e1 = c->event();
-        SDGP_HIP(hipEventRecord(e1, c->stream));
-        c->spmm_events.push_back({e0, e1});
+      switch (NI) {
+        case 0: launch_cg_iteration<0>(c, A, grid, chunks, it); break;
+        case 8: launch_cg_iteration<8>(c, A, grid, chunks, it); break;
+        case 16: launch_cg_iteration<16>(c, A, grid, chunks, it); break;
+        case 32: launch_cg_iteration<32>(c, A, grid, chunks, it); break;
+        default: launch_cg_iteration<64>(c, A, grid, chunks, it); break;
       }
-      k_cg_update_xr<<<grid, kCgBlock, 0, c->stream>>>(A, it);
-      SDGP_CHECK_LAUNCH();
-      k_cg_update_p<<<grid, kCgBlock, 0, c->stream>>>(A, it);
-      SDGP_CHECK_LAUNCH();
-      k_cg_check<<<1, 256, 0, c->stream>>>(A, it);
-      SDGP_CHECK_LAUNCH();
     }
     SDGP_HIP(hipMemcpyAsync(flags, A.st.done, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
     SDGP_HIP(hipStreamSynchronize(c->stream));
@@ -537,83 +873,189 @@ CgResult block_cg(Ctx* c, const Csr& Am, const Sorted& s, const double* ys, int 
   CgResult res;
   res.R = R;
   res.X = A.X;
+  res.V = A.V;
+  res.rz0 = A.st.rz0;
   res.hist_a = A.st.hist_a;
   res.hist_b = A.st.hist_b;
   res.col_iters = A.st.iters;
   res.not_spd = flags[1] != 0;
+  res.logdetM = use_pc ? pc->logdetM : 0.0;
   std::vector<int32_t> its(R);
-  std::vector<double> rr(2 * (size_t)R), bn(R);
-  SDGP_HIP(hipMemcpyAsync(its.data(), A.st.iters, R * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
-  SDGP_HIP(hipMemcpyAsync(rr.data(), A.st.rr, 2 * R * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-  SDGP_HIP(hipMemcpyAsync(bn.data(), A.st.bnorm2, R * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  std::vector<double> bn(R);
   std::vector<int32_t> actv(2 * (size_t)R);
+  SDGP_HIP(hipMemcpyAsync(its.data(), A.st.iters, R * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+  SDGP_HIP(hipMemcpyAsync(bn.data(), A.st.bnorm2, R * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   SDGP_HIP(hipMemcpyAsync(actv.data(), A.st.act, 2 * R * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
   SDGP_HIP(hipStreamSynchronize(c->stream));
-  int mx = 0;
-  double relmax = 0.0;
-  bool conv = true;
   const int executed = flags[0] > 0 ? flags[0] : it;
-  const int lastpar = executed & 1;  // parity holding the latest rr / act
-  for (int r = 0; r < R; ++r) {
-    mx = std::max(mx, its[r]);
-    const double rel = bn[r] > 0.0 ? std::sqrt(rr[lastpar * R + r] / bn[r]) : 0.0;
-    relmax = std::max(relmax, rel);
+  const int lastpar = executed & 1;  // parity holding the latest state
+  bool conv = true;
+  for (int r = 0; r < R; ++r)
     if (actv[lastpar * R + r]) conv = false;
-  }
+  // recursively updated residuals at each column's last iteration
+  std::vector<double> rl(R);
+  SDGP_HIP(hipMemcpyAsync(rl.data(), A.st.rr_last, R * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  SDGP_HIP(hipStreamSynchronize(c->stream));
   res.iters = executed;
   res.iters_y = its[0];
-  res.relres_max = relmax;
+  res.relres_max = 0.0;
+  for (int r = 0; r < R; ++r)
+    if (bn[r] > 0.0) res.relres_max = std::max(res.relres_max, std::sqrt(rl[r] / bn[r]));
   res.converged = conv && !res.not_spd;
-  (void)mx;
   (void)t;
   return res;
 }
 
+namespace {
+
+// Number of eigenvalues of the symmetric tridiagonal T (d, e) below x
+// (Sturm sequence of the LDL^T pivots of T - xI).
+int sturm_count(const std::vector<double>& d, const std::vector<double>& e, double x) {
+  const int m = (int)d.size();
+  int cnt = 0;
+  double q = d[0] - x;
+  if (q < 0.0) ++cnt;
+  for (int k = 1; k < m; ++k) {
+    if (q == 0.0) q = 1e-300;
+    q = d[k] - x - e[k - 1] * e[k - 1] / q;
+    if (q < 0.0) ++cnt;
+  }
+  return cnt;
+}
+
+// e_1^T ln(T) e_1 for the symmetric positive definite tridiagonal T by the
+// integral ln(theta) = int_0^inf [1/(1+t) - 1/(theta+t)] dt applied to the
+// spectral measure of e_1: with t = exp(s),
+//   e_1^T ln(T) e_1 = int_R t [1/(1+t) - e_1^T (T + tI)^{-1} e_1] ds.
+// The integrand is analytic in the strip |Im s| < pi (poles at
+// s = ln(theta_j) + i pi), so the trapezoidal rule with step h converges like
+// exp(-2 pi^2 / h); the tails decay like exp(-|s|) beyond the spectrum.
+// e_1^T (T + tI)^{-1} e_1 is the continued fraction of the bottom-up
+// pivots of T + tI (O(m) per node).  Returns NaN if T is not positive
+// definite; lo/hi receive the extreme Ritz values (bisection).
+double quad_log_tridiag(const std::vector<double>& d, const std::vector<double>& e, double* lo, double* hi) {
+  const int m = (int)d.size();
+  // Gershgorin interval
+  double glo = INFINITY, ghi = -INFINITY;
+  for (int k = 0; k < m; ++k) {
+    const double r = (k > 0 ? std::fabs(e[k - 1]) : 0.0) + (k + 1 < m ? std::fabs(e[k]) : 0.0);
+    glo = std::min(glo, d[k] - r);
+    ghi = std::max(ghi, d[k] + r);
+  }
+  if (!(ghi > 0.0) || !std::isfinite(glo) || !std::isfinite(ghi)) return NAN;
+  if (sturm_count(d, e, 0.0) != 0) return NAN;          // some theta <= 0
+  // extreme eigenvalues by bisection (relative accuracy 1e-10)
+  double a = std::max(glo, 0.0), b = ghi;
+  for (int it = 0; it < 200 && b - a > 1e-10 * b; ++it) {
+    const double mid = 0.5 * (a + b);
+    if (sturm_count(d, e, mid) >= 1) b = mid; else a = mid;
+  }
+  const double tmin = b;
+  a = std::max(glo, 0.0);
+  b = ghi;
+  for (int it = 0; it < 200 && b - a > 1e-10 * b; ++it) {
+    const double mid = 0.5 * (a + b);
+    if (sturm_count(d, e, mid) >= m) b = mid; else a = mid;
+  }
+  const double tmax = b;
+  *lo = tmin;
+  *hi = tmax;
+  if (!(tmin > 0.0)) return NAN;
+  const double h = 0.4;
+  const double s0 = std::log(tmin) - 42.0, s1 = std::log(tmax) + 42.0;
+  const int nodes = (int)std::ceil((s1 - s0) / h);
+  double acc = 0.0;
+  for (int j = 0; j <= nodes; ++j) {
+    const double t = std::exp(s0 + j * h);
+    double f = d[m - 1] + t;
+    for (int k = m - 2; k >= 0; --k) f = d[k] + t - e[k] * e[k] / f;
+    acc += t * (1.0 / (1.0 + t) - 1.0 / f);
+  }
+  return h * acc;
+}
+
+}  // namespace
+
 void slq_from_cg(Ctx* c, const CgResult& cg, int kind, int P, int64_t n, int lanczos_steps, double* logdet,
                  double* stderr_out, double* ritz_min, double* ritz_max) {
+  (void)P;
+  (void)n;
   const int ncols = cg.R - 1;
   if (ncols <= 0) {
     *logdet = 0.0; *stderr_out = 0.0; *ritz_min = 0.0; *ritz_max = 0.0;
     return;
   }
   std::vector<int32_t> its(cg.R);
+  std::vector<double> w0(cg.R);
   SDGP_HIP(hipMemcpyAsync(its.data(), cg.col_iters, cg.R * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+  SDGP_HIP(hipMemcpyAsync(w0.data(), cg.rz0, cg.R * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   SDGP_HIP(hipStreamSynchronize(c->stream));
-  int mmax = 1;
+  int mmax = 0;
   for (int r = 1; r < cg.R; ++r) mmax = std::max(mmax, its[r]);
   if (lanczos_steps > 0) mmax = std::min(mmax, lanczos_steps);
-  const size_t W = (size_t)ncols * mmax;
-  double* work = c->get<double>(S_SLQ_WORK, 3 * W);
-  double* out = c->get<double>(S_SLQ_OUT, (size_t)ncols * 4);
-  k_slq<<<(ncols + 63) / 64, 64, 0, c->stream>>>(cg.hist_a, cg.hist_b, cg.col_iters, cg.R, 1, ncols,
-                                                 lanczos_steps, ncols, work, work + W, work + 2 * W, out);
-  SDGP_CHECK_LAUNCH();
-  std::vector<double> ho((size_t)ncols * 4);
-  SDGP_HIP(hipMemcpyAsync(ho.data(), out, ho.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-  SDGP_HIP(hipStreamSynchronize(c->stream));
-  const double zz = (kind == PK_IDENTITY) ? 1.0 : (double)n;
-  double sum = 0.0, sum2 = 0.0, lo = INFINITY, hi = -INFINITY;
+  // coefficient history rows 0..mmax-1 (all columns) to the host
+  std::vector<double> ha((size_t)std::max(mmax, 1) * cg.R), hb((size_t)std::max(mmax, 1) * cg.R);
+  if (mmax > 0) {
+    SDGP_HIP(hipMemcpyAsync(ha.data(), cg.hist_a, (size_t)mmax * cg.R * sizeof(double), hipMemcpyDeviceToHost,
+                            c->stream));
+    SDGP_HIP(hipMemcpyAsync(hb.data(), cg.hist_b, (size_t)mmax * cg.R * sizeof(double), hipMemcpyDeviceToHost,
+                            c->stream));
+    SDGP_HIP(hipStreamSynchronize(c->stream));
+  }
+  std::vector<double> q(ncols), lo(ncols), hi(ncols);
+  auto work = [&](int p) {
+    const int r = 1 + p;
+    int m = its[r];
+    if (lanczos_steps > 0) m = std::min(m, lanczos_steps);
+    if (m <= 0) { q[p] = 0.0; lo[p] = INFINITY; hi[p] = -INFINITY; return; }
+    std::vector<double> d(m), e(std::max(m - 1, 1), 0.0);
+    for (int k = 0; k < m; ++k) {
+      const double ak = ha[(size_t)k * cg.R + r];
+      double dk = 1.0 / ak;
+      if (k > 0) dk += hb[(size_t)(k - 1) * cg.R + r] / ha[(size_t)(k - 1) * cg.R + r];
+      d[k] = dk;
+      if (k + 1 < m) e[k] = std::sqrt(hb[(size_t)k * cg.R + r]) / ak;
+    }
+    q[p] = quad_log_tridiag(d, e, &lo[p], &hi[p]);
+  };
+  unsigned hw = std::thread::hardware_concurrency();
+  int nt = (int)std::max(1u, std::min(hw == 0 ? 1u : hw, 16u));
+  nt = std::min(nt, ncols);
+  if (nt <= 1) {
+    for (int p = 0; p < ncols; ++p) work(p);
+  } else {
+    std::vector<std::thread> th;
+    std::atomic<int> next(0);
+    for (int t = 0; t < nt; ++t)
+      th.emplace_back([&] {
+        for (int p = next.fetch_add(1); p < ncols; p = next.fetch_add(1)) work(p);
+      });
+    for (auto& t : th) t.join();
+  }
+  // weight of probe p: |M^{-1/2} b_p|^2 = b_p^T M^{-1} b_p (|z|^2 without a
+  // preconditioner: n for Rademacher, 1 for unit vectors)
+  double sum = 0.0, sum2 = 0.0, mn = INFINITY, mx = -INFINITY;
   bool bad = false;
   for (int p = 0; p < ncols; ++p) {
-    const double v = zz * ho[p * 4 + 0];
+    const double v = w0[1 + p] * q[p];
     if (!std::isfinite(v)) bad = true;
     sum += v;
     sum2 += v * v;
-    lo = std::min(lo, ho[p * 4 + 2]);
-    hi = std::max(hi, ho[p * 4 + 3]);
+    mn = std::min(mn, lo[p]);
+    mx = std::max(mx, hi[p]);
   }
   if (bad) throw Error(SDGP_ERR_NOT_SPD, "Lanczos quadrature met a non-positive Ritz value");
   if (kind == PK_IDENTITY) {
-    *logdet = sum;
+    *logdet = cg.logdetM + sum;
     *stderr_out = 0.0;
   } else {
     const double mean = sum / ncols;
-    *logdet = mean;
+    *logdet = cg.logdetM + mean;
     const double var = ncols > 1 ? std::max(0.0, (sum2 - ncols * mean * mean) / (ncols - 1)) : 0.0;
     *stderr_out = ncols > 1 ? std::sqrt(var / ncols) : NAN;
   }
-  *ritz_min = lo;
-  *ritz_max = hi;
+  *ritz_min = mn;
+  *ritz_max = mx;
 }
 
 }  // namespace sdgp

@@ -112,3 +112,57 @@ def test_boutsidis_converges_on_well_conditioned_matrix():
     Z = es.rademacher(3, 80, 400)
     est, _ = es.boutsidis_logdet(A, Z, 80)
     assert est == pytest.approx(np.linalg.slogdet(A)[1], rel=2e-2)
+
+
+def _sum_case(n=200, seed=5, noise=1e-2):
+    return wl.random_small(n, 2, 3, 2, seed, combine=kn.COMBINE_SUM, per_row=10.0, noise_var=noise)
+
+
+def test_lowrank_preconditioner_holds_the_bump_part():
+    w = _sum_case()
+    A = kn.kernel_matrix(w.desc, w.h, w.x)
+    c, F = es.lowrank_terms(w.desc, w.h, w.x)
+    R = A - F @ F.T                       # core part + noise
+    assert np.allclose(np.diag(R), c, rtol=1e-14, atol=0)
+    w.h[0] = 0.0                          # no core: A = noise I + F F^T = M exactly
+    A0 = kn.kernel_matrix(w.desc, w.h, w.x)
+    c0, F0 = es.lowrank_terms(w.desc, w.h, w.x)
+    assert np.allclose(A0, c0 * np.eye(len(A0)) + F0 @ F0.T, rtol=0, atol=1e-15)
+
+
+def test_lowrank_probe_covariance_is_M():
+    w = _sum_case(n=60)
+    c, F = es.lowrank_terms(w.desc, w.h, w.x)
+    B = es.lowrank_probes(3, c, F, 40000)
+    C = B @ B.T / B.shape[1]
+    M = c * np.eye(60) + F @ F.T
+    assert np.abs(C - M).max() < 5 * np.sqrt(np.diag(M).max() ** 2 / 40000) * 3
+
+
+def test_preconditioned_estimator_exact_when_A_equals_M():
+    # sigma2 = 0: A = M, so ln det A = ln det M and the SLQ part vanishes
+    w = _sum_case()
+    w.h[0] = 0.0
+    val, g, logdet, _ = es.preconditioned_lml_grad(w.desc, w.h, w.x, w.y, 7, 4, 30)
+    v0, g0 = gp.lml_grad(w.desc, w.h, w.x, w.y)
+    exact = np.linalg.slogdet(kn.kernel_matrix(w.desc, w.h, w.x))[1]
+    assert logdet == pytest.approx(exact, rel=1e-11)
+    assert val == pytest.approx(v0, rel=1e-11)
+
+
+def test_preconditioned_estimator_unbiased():
+    w = _sum_case(n=150)
+    A = kn.kernel_matrix(w.desc, w.h, w.x)
+    exact = np.linalg.slogdet(A)[1]
+    _, g0 = gp.lml_grad(w.desc, w.h, w.x, w.y)
+    lds, ses, gs = [], [], []
+    for s in range(8):
+        _, g, ld, se = es.preconditioned_lml_grad(w.desc, w.h, w.x, w.y, 50 + s, 30, 60)
+        lds.append(ld); ses.append(se); gs.append(g)
+    se_mean = np.sqrt(np.sum(np.square(ses))) / len(ses)
+    assert abs(np.mean(lds) - exact) < 4.5 * se_mean + 1e-9
+    gs = np.array(gs)
+    m = gs.mean(axis=0)
+    sd = gs.std(axis=0, ddof=1) / np.sqrt(len(gs))
+    ok = np.abs(m - g0) <= 4.5 * sd + 1e-9 * np.abs(g0).max()
+    assert ok.mean() >= 0.9
