@@ -40,6 +40,8 @@ def parse():
     p.add_argument("--rtol", type=float, default=1e-10)
     p.add_argument("--precond", choices=["lowrank", "none"], default="lowrank",
                    help="CG preconditioner (low-rank bump part of the SUM kernel, or none)")
+    p.add_argument("--operator", choices=["assembled", "factored"], default="assembled",
+                   help="CG operator: the fully assembled sparse K, or K_core (sparse) + F F^T")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--spmv-reps", type=int, default=50)
     return p.parse_args()
@@ -85,7 +87,9 @@ def main():
     x = torch.from_numpy(w.x).to(dev)
     y = torch.from_numpy(w.y).to(dev)
     pc = sd.PRECOND_LOWRANK if args.precond == "lowrank" else sd.PRECOND_NONE
-    est = sd.estimator(probes=args.probes, seed=1, cg_rtol=args.rtol, cg_max_iter=20000, precond=pc)
+    op = sd.OPERATOR_FACTORED if args.operator == "factored" else sd.OPERATOR_ASSEMBLED
+    est = sd.estimator(probes=args.probes, seed=1, cg_rtol=args.rtol, cg_max_iter=20000, precond=pc,
+                       operator_form=op)
     ctx = sd.Context(0, timing=True)
     print("bench: N=%d dim=%d n1=%d n2=%d probes=%d" % (n, w.desc.dim, w.desc.n1, w.desc.n2, args.probes),
           file=sys.stderr, flush=True)
@@ -150,10 +154,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": "uniform3d_n1000000: 1,000,000 points uniform in [0,1)^3, Wendland C2 core "
                                "(~60 core neighbours/row) + 16x4 bump functions, SUM combine, "
-                               "%d Rademacher probes, CG rtol %g, preconditioner %s"
-                               % (args.probes, args.rtol, args.precond),
+                               "%d Rademacher probes, CG rtol %g, preconditioner %s, operator %s"
+                               % (args.probes, args.rtol, args.precond, args.operator),
                    "points": n, "dim": 3, "n1": w.desc.n1, "n2": w.desc.n2, "n_hyper": int(len(w.h)),
-                   "probes": args.probes, "cg_rtol": args.rtol, "precond": args.precond},
+                   "probes": args.probes, "cg_rtol": args.rtol, "precond": args.precond,
+                   "operator": args.operator},
         "nnz": int(nnz),
         "nnz_per_row": nnz / n,
         "candidates": int(cand),

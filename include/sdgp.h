@@ -68,6 +68,7 @@ enum { SDGP_CORE_WENDLAND_C2 = 0, SDGP_CORE_KSTAT = 1 };
 enum { SDGP_COMBINE_PRODUCT = 0, SDGP_COMBINE_SUM = 1 };
 enum { SDGP_PROBE_RADEMACHER = 0, SDGP_PROBE_IDENTITY = 2 };
 enum { SDGP_PRECOND_NONE = 0, SDGP_PRECOND_LOWRANK = 1 };
+enum { SDGP_OPERATOR_ASSEMBLED = 0, SDGP_OPERATOR_FACTORED = 1 };
 
 typedef struct {
   int32_t dim;      /* 1..4 */
@@ -97,7 +98,16 @@ typedef struct {
  * the second term by Lanczos quadrature from the preconditioned CG
  * coefficients weighted by b_p^T M^{-1} b_p, and the gradient's trace by
  * (A^{-1} b_p)^T dA (M^{-1} b_p).  Estimates stay unbiased; the CG needs far
- * fewer iterations when the bump functions hold many points. */
+ * fewer iterations when the bump functions hold many points.
+ *
+ * operator_form = SDGP_OPERATOR_FACTORED (needs SUM, Rademacher probes and
+ * the low-rank preconditioner): the CG and the adjoint use the exact
+ * identity K = K_core + F F^T of the SUM combine -- the sparse matrix holds
+ * only the core supports (and the diagonal), F (F^T P) is applied in the
+ * solver's update pass, and the bump-parameter adjoint is formed from F^T X
+ * and F^T V instead of a loop over the bump cliques.  Same results as the
+ * assembled operator up to rounding; sdgp_info.nnz then counts the core
+ * pattern.  SDGP_OPERATOR_ASSEMBLED (default) stores every entry of K. */
 typedef struct {
   int32_t probes;          /* P, 1..64 for Rademacher */
   int32_t lanczos_steps;   /* 0 = use every CG step */
@@ -106,7 +116,7 @@ typedef struct {
   uint64_t seed;
   double cg_rtol;          /* per column: |r| <= cg_rtol |b| */
   int32_t precond;         /* SDGP_PRECOND_* */
-  int32_t reserved;        /* must be 0 */
+  int32_t operator_form;   /* SDGP_OPERATOR_* */
 } sdgp_estimator;
 
 /* Per-call diagnostics (all optional). ms[] phase times when timing is on:
@@ -212,6 +222,34 @@ sdgp_status sdgp_posterior_mean_var(sdgp_ctx* ctx, const sdgp_kernel_desc* desc,
                                     const double* h, const double* x0, int64_t n0,
                                     const sdgp_estimator* est, double* mean_out,
                                     double* var_out);
+
+/* Randomised Taylor-series log-det of Boutsidis et al. (2017), the estimator
+ * Section 2.5 names: with alpha = max_a sum_b |A_ab| (>= lambda_max) and
+ * C = I - A/alpha,
+ *   ln det A ~= N ln alpha - sum_{k=1}^{terms} (1/k) (1/P) sum_p z_p^T C^k z_p
+ * for A = K + noise_var I and P Rademacher probes z_p (the generator of
+ * sdgp_estimator, keyed by seed).  The truncation error is at most
+ * N rho^(terms+1) / ((terms+1)(1-rho)), rho = 1 - lambda_min/alpha, so it
+ * needs many terms for ill-conditioned A (Stochastic Lanczos quadrature in
+ * sdgp_lml is the default).  logdet_out, alpha_out: host. */
+sdgp_status sdgp_logdet_taylor(sdgp_ctx* ctx, const sdgp_kernel_desc* desc, const double* x,
+                               int64_t n, const double* h, int32_t probes, int32_t terms,
+                               uint64_t seed, double* logdet_out, double* alpha_out);
+
+/* Upper bound of the fraction s of stored covariances contributed by the bump
+ * part of the kernel (Section 2.2, eq:sparsity_estimate, disjoint-support
+ * bound):  s <= sum_i sum_j sum_k Vol(dim, r_ij) Vol(dim, r_ik) / V_X^2 with
+ * Vol(dim, r) = pi^(dim/2) / Gamma(dim/2 + 1) r^dim and V_X the volume of the
+ * input domain (1 for the unit cube).  h: host array as above.  Host-only
+ * (no device work); s_out: host. */
+sdgp_status sdgp_sparsity_bound(const sdgp_kernel_desc* desc, const double* h,
+                                double domain_volume, double* s_out);
+
+/* Section 2.4 objectives for a likelihood value lml and sparsity s:
+ * augmented (eq:augmented) lml + (1 - s) lml; feasible (eq:constrained) is 1
+ * when s < requirement.  Host-only; outputs are host pointers. */
+sdgp_status sdgp_sparsity_objective(double lml, double s, double requirement,
+                                    double* augmented_out, int32_t* feasible_out);
 
 #ifdef __cplusplus
 }

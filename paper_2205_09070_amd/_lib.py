@@ -25,6 +25,7 @@ CORE_WENDLAND_C2, CORE_KSTAT = 0, 1
 COMBINE_PRODUCT, COMBINE_SUM = 0, 1
 PROBE_RADEMACHER, PROBE_IDENTITY = 0, 2
 PRECOND_NONE, PRECOND_LOWRANK = 0, 1
+OPERATOR_ASSEMBLED, OPERATOR_FACTORED = 0, 1
 
 
 class KernelDesc(C.Structure):
@@ -35,7 +36,7 @@ class KernelDesc(C.Structure):
 class Estimator(C.Structure):
     _fields_ = [("probes", C.c_int32), ("lanczos_steps", C.c_int32), ("kind", C.c_int32),
                 ("cg_max_iter", C.c_int32), ("seed", C.c_uint64), ("cg_rtol", C.c_double),
-                ("precond", C.c_int32), ("reserved", C.c_int32)]
+                ("precond", C.c_int32), ("operator_form", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -80,7 +81,34 @@ _SIGS = {
                                     C.POINTER(Estimator), VP, VP, VP, VP]),
     "sdgp_posterior_mean_var": (I32, [VP, C.POINTER(KernelDesc), VP, VP, I64, VP, VP, I64,
                                       C.POINTER(Estimator), VP, VP]),
+    "sdgp_logdet_taylor": (I32, [VP, C.POINTER(KernelDesc), VP, I64, VP, I32, I32, C.c_uint64,
+                                 C.POINTER(D), C.POINTER(D)]),
+    "sdgp_sparsity_bound": (I32, [C.POINTER(KernelDesc), VP, D, C.POINTER(D)]),
+    "sdgp_sparsity_objective": (I32, [D, D, D, C.POINTER(D), C.POINTER(I32)]),
 }
+
+
+def sparsity_bound(desc, h, domain_volume=1.0) -> float:
+    """Sparsity upper bound of eq:sparsity_estimate (host-only library call)."""
+    lib = load()
+    d = desc_of(desc)
+    hh = np.ascontiguousarray(np.asarray(h, dtype=np.float64))
+    out = D(0.0)
+    st = lib.sdgp_sparsity_bound(C.byref(d), hh.ctypes.data, float(domain_volume), C.byref(out))
+    if st != OK:
+        raise SdgpError(st, "sdgp_sparsity_bound failed")
+    return float(out.value)
+
+
+def sparsity_objective(lml, s, requirement):
+    """(augmented objective, feasible) of Section 2.4 (host-only)."""
+    lib = load()
+    a = D(0.0)
+    f = I32(0)
+    st = lib.sdgp_sparsity_objective(float(lml), float(s), float(requirement), C.byref(a), C.byref(f))
+    if st != OK:
+        raise SdgpError(st, "sdgp_sparsity_objective failed")
+    return float(a.value), bool(f.value)
 
 
 def header_functions() -> list:
@@ -112,9 +140,9 @@ def desc_of(d) -> KernelDesc:
 
 
 def estimator(probes=32, lanczos_steps=0, kind=PROBE_RADEMACHER, cg_max_iter=5000, seed=0,
-              cg_rtol=1e-10, precond=PRECOND_NONE) -> Estimator:
+              cg_rtol=1e-10, precond=PRECOND_NONE, operator_form=OPERATOR_ASSEMBLED) -> Estimator:
     return Estimator(int(probes), int(lanczos_steps), int(kind), int(cg_max_iter), int(seed),
-                     float(cg_rtol), int(precond), 0)
+                     float(cg_rtol), int(precond), int(operator_form))
 
 
 def exact_estimator(cg_max_iter=20000, cg_rtol=1e-13) -> Estimator:
@@ -262,6 +290,16 @@ class Context:
                                                    _hptr(H), B, C.byref(e), _hptr(v), _hptr(g), _hptr(ms),
                                                    C.cast(infos, VP)))
         return v, g, ms, list(infos)
+
+    def logdet_taylor(self, desc, x, h, probes=32, terms=50, seed=0):
+        """Randomised Taylor-series log-det; returns (logdet, alpha)."""
+        x = _dev_f64(x)
+        hh = self._h(h)
+        d = desc_of(desc)
+        ld, al = D(0.0), D(0.0)
+        self._check(self.lib.sdgp_logdet_taylor(self.h, C.byref(d), _ptr(x), x.shape[0], _hptr(hh), int(probes),
+                                                int(terms), int(seed), C.byref(ld), C.byref(al)))
+        return float(ld.value), float(al.value)
 
     def posterior_mean_var(self, desc, x, y, h, x0, est=None):
         import torch

@@ -56,16 +56,16 @@ struct Assembled {
 };
 
 Assembled assemble_all(Ctx* c, const Sorted& s, const sdgp_kernel_desc& d, const double* h, bool add_noise,
-                       PhaseTimer* t) {
+                       PhaseTimer* t, bool core_only = false) {
   Assembled r;
   r.kp = make_params(d, h);
   r.b = bump_precompute(c, s, r.kp, h);
   if (t) t->mark(2);
   int32_t* iv_ptr;
   int2* iv;
-  prune(c, s, r.kp, r.b, &iv_ptr, &iv);
+  prune(c, s, r.kp, r.b, &iv_ptr, &iv, core_only);
   if (t) t->mark(3);
-  r.A = assemble_sorted(c, s, r.kp, r.b, iv_ptr, iv, add_noise, &r.candidates, t);
+  r.A = assemble_sorted(c, s, r.kp, r.b, iv_ptr, iv, add_noise, &r.candidates, t, core_only);
   if (t) t->mark(5);
   return r;
 }
@@ -79,9 +79,12 @@ void check_estimator(const sdgp_estimator* e, int64_t n) {
   require(e->cg_rtol > 0.0 && std::isfinite(e->cg_rtol), "cg_rtol must be > 0");
   require(e->lanczos_steps >= 0, "lanczos_steps must be >= 0");
   require(e->precond == SDGP_PRECOND_NONE || e->precond == SDGP_PRECOND_LOWRANK, "unknown preconditioner");
-  require(e->reserved == 0, "reserved estimator field must be 0");
+  require(e->operator_form == SDGP_OPERATOR_ASSEMBLED || e->operator_form == SDGP_OPERATOR_FACTORED,
+          "unknown operator form");
   if (e->precond == SDGP_PRECOND_LOWRANK)
     require(e->kind == SDGP_PROBE_RADEMACHER, "the low-rank preconditioner needs Rademacher probes");
+  if (e->operator_form == SDGP_OPERATOR_FACTORED)
+    require(e->precond == SDGP_PRECOND_LOWRANK, "the factored operator needs the low-rank preconditioner");
 }
 
 void finish_timing(Ctx* c, PhaseTimer& t, sdgp_info* info) {
@@ -109,7 +112,9 @@ void finish_timing(Ctx* c, PhaseTimer& t, sdgp_info* info) {
 sdgp_status evaluate(Ctx* c, const Sorted& s, const double* ys, const sdgp_kernel_desc& d, const double* h,
                      const sdgp_estimator& e, double* lml_out, double* grad_out, sdgp_info* info,
                      PhaseTimer& t) {
-  Assembled as = assemble_all(c, s, d, h, true, &t);
+  const bool factored = e.operator_form == SDGP_OPERATOR_FACTORED;
+  if (factored) require(d.combine == SDGP_COMBINE_SUM, "the factored operator needs the SUM combine");
+  Assembled as = assemble_all(c, s, d, h, true, &t, factored);
   const int kind = e.kind == SDGP_PROBE_IDENTITY ? PK_IDENTITY : PK_RADEMACHER;
   const int P = kind == PK_IDENTITY ? (int)s.n : e.probes;
   Precond pc;
@@ -117,6 +122,7 @@ sdgp_status evaluate(Ctx* c, const Sorted& s, const double* ys, const sdgp_kerne
   if (use_pc) {
     require(d.combine == SDGP_COMBINE_SUM, "the low-rank preconditioner needs the SUM combine");
     pc = lowrank_precond(c, s, as.kp, as.b);
+    pc.lowrank_op = factored ? 1 : 0;
   }
   CgResult cg = block_cg(c, as.A, s, ys, kind, P, e.seed, e.cg_rtol, e.cg_max_iter, nullptr, 0,
                          use_pc ? &pc : nullptr, grad_out != nullptr, &t);
@@ -127,7 +133,7 @@ sdgp_status evaluate(Ctx* c, const Sorted& s, const double* ys, const sdgp_kerne
   slq_from_cg(c, cg, kind, P, s.n, e.lanczos_steps, &logdet, &se, &rmin, &rmax);
   t.mark(7);
   if (lml_out) *lml_out = -0.5 * yKy - 0.5 * logdet;
-  if (grad_out) adjoint_gradient(c, s, as.kp, as.b, as.A, cg, kind, P, e.seed, h, grad_out);
+  if (grad_out) adjoint_gradient(c, s, as.kp, as.b, as.A, cg, kind, P, e.seed, h, grad_out, factored);
   t.mark(8);
   if (info) {
     info->nnz = as.A.nnz;
@@ -366,6 +372,49 @@ sdgp_status sdgp_posterior_mean_var(sdgp_ctx* ctx, const sdgp_kernel_desc* desc,
     ctx->err = "CG did not reach cg_rtol within cg_max_iter";
     return SDGP_ERR_NOT_CONVERGED;
   }
+  return SDGP_OK;
+}
+
+sdgp_status sdgp_logdet_taylor(sdgp_ctx* ctx, const sdgp_kernel_desc* desc, const double* x, int64_t n,
+                               const double* h, int32_t probes, int32_t terms, uint64_t seed, double* logdet_out,
+                               double* alpha_out) {
+  return guarded(ctx, [&] {
+    require(desc && x && logdet_out && alpha_out, "NULL argument");
+    validate(*desc, h, n);
+    Sorted s = order_points(ctx, x, n, desc->dim, h[1]);
+    Assembled as = assemble_all(ctx, s, *desc, h, true, nullptr);
+    *logdet_out = logdet_taylor(ctx, as.A, s, probes, terms, seed, alpha_out);
+  });
+}
+
+sdgp_status sdgp_sparsity_bound(const sdgp_kernel_desc* desc, const double* h, double domain_volume,
+                                double* s_out) {
+  if (!desc || !h || !s_out) return SDGP_ERR_INVALID_ARG;
+  if (sdgp_num_hyper(desc) < 0 || !(domain_volume > 0.0) || !std::isfinite(domain_volume))
+    return SDGP_ERR_INVALID_ARG;
+  const int d = desc->dim;
+  const double unit = std::pow(M_PI, d / 2.0) / std::tgamma(d / 2.0 + 1.0);
+  double tot = 0.0;
+  for (int i = 0; i < desc->n1; ++i)
+    for (int j = 0; j < desc->n2; ++j) {
+      const double rj = h[2 + (int64_t)(i * desc->n2 + j) * (3 + d) + 2];
+      if (!(rj > 0.0) || !std::isfinite(rj)) return SDGP_ERR_INVALID_ARG;
+      for (int k = 0; k < desc->n2; ++k) {
+        const double rk = h[2 + (int64_t)(i * desc->n2 + k) * (3 + d) + 2];
+        if (!(rk > 0.0) || !std::isfinite(rk)) return SDGP_ERR_INVALID_ARG;
+        tot += unit * std::pow(rj, d) * unit * std::pow(rk, d);
+      }
+    }
+  *s_out = tot / (domain_volume * domain_volume);
+  return SDGP_OK;
+}
+
+sdgp_status sdgp_sparsity_objective(double lml, double s, double requirement, double* augmented_out,
+                                    int32_t* feasible_out) {
+  if (!augmented_out || !feasible_out) return SDGP_ERR_INVALID_ARG;
+  if (!std::isfinite(lml) || !std::isfinite(s)) return SDGP_ERR_INVALID_ARG;
+  *augmented_out = lml + (1.0 - s) * lml;
+  *feasible_out = s < requirement ? 1 : 0;
   return SDGP_OK;
 }
 

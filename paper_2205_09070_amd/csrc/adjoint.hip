@@ -43,6 +43,7 @@ struct AdjArgs {
   double sigma2, r_core, rc2, s_scale;
   double* rowacc;       // [n][3]: sigma2, r_core, noise terms
   double* G;            // [n][n1]
+  int lowrank;          // core-only pattern; bump adjoint computed separately
 };
 
 __global__ __launch_bounds__(kAdjBlock) void k_adjoint_rows(AdjArgs A) {
@@ -69,7 +70,7 @@ __global__ __launch_bounds__(kAdjBlock) void k_adjoint_rows(AdjArgs A) {
   }
   const int64_t k0 = A.row_ptr[a], k1 = A.row_ptr[a + 1];
   const int pa = A.perm[a];
-  const int nbits = __popcll(Ma);
+  const int nbits = A.lowrank ? 0 : __popcll(Ma);
   double g_s2 = 0.0, g_rc = 0.0, g_nz = 0.0;
   for (int g0 = 0; g0 < (nbits > 0 ? nbits : 1); g0 += kGroup) {
     // bump functions of this pass: the (g0..g0+7)-th set bits of Ma
@@ -150,7 +151,7 @@ __global__ __launch_bounds__(kAdjBlock) void k_adjoint_rows(AdjArgs A) {
         }
         if (valid && b == a) g_nz += om;
       }
-      if (mm) {
+      if (mm && !A.lowrank) {
         const double cab = A.combine == 0 ? A.sigma2 * psi : 1.0;
         const double oc = om * cab;
 #pragma unroll
@@ -246,10 +247,107 @@ __global__ __launch_bounds__(256) void k_bump_grad(const double4* __restrict__ x
   }
 }
 
+// Per-block partials of F^T Y (Y: [n][R] row-major), lane = column:
+// part[b][i][r]; grid (nb, chunks), 256 threads.
+template <int NI>
+__global__ __launch_bounds__(256) void k_ft_part(const double* __restrict__ F, const double* __restrict__ Y,
+                                                 int64_t n, int n1, int R, double* __restrict__ part) {
+  __shared__ double sh[4][kWave];
+  const int lane = lane_id(), w = threadIdx.x >> 6;
+  const int rc = blockIdx.y * kWave + lane;
+  double acc[NI];
+#pragma unroll
+  for (int i = 0; i < NI; ++i) acc[i] = 0.0;
+  if (rc < R)
+    for (int64_t a = blockIdx.x * 4 + w; a < n; a += (int64_t)gridDim.x * 4) {
+      const double y = Y[a * R + rc];
+      const double* Fa = F + a * n1;
+#pragma unroll
+      for (int i = 0; i < NI; ++i)
+        if (i < n1) acc[i] += Fa[i] * y;
+    }
+#pragma unroll
+  for (int i = 0; i < NI; ++i) {
+    if (i >= n1) break;
+    __syncthreads();
+    sh[w][lane] = acc[i];
+    __syncthreads();
+    if (threadIdx.x < kWave && rc < R)
+      part[((int64_t)blockIdx.x * n1 + i) * R + rc] = sh[0][lane] + sh[1][lane] + sh[2][lane] + sh[3][lane];
+  }
+}
+
+// out[i][r] = sum_b part[b][i][r] in fixed order; grid (n1, chunks).
+__global__ void k_ft_reduce(const double* __restrict__ part, int nb, int n1, int R, double* __restrict__ out) {
+  const int i = blockIdx.x;
+  const int rc = blockIdx.y * kWave + lane_id();
+  if (threadIdx.x >= kWave || rc >= R) return;
+  double s = 0.0;
+  for (int b = 0; b < nb; ++b) s += part[((int64_t)b * n1 + i) * R + rc];
+  out[(int64_t)i * R + rc] = s;
+}
+
+// Bump part of the per-point adjoint for K = K_core + F F^T:
+//   G[a,i] = sum_b Omega_ab F_bi
+//          = 1/2 alpha_a (F^T X)[i][0]
+//            - 1/4 s sum_p (w_pa (F^T V)[i][1+p] + v_pa (F^T X)[i][1+p]),
+// with X = [alpha, w_1..w_P] and V = [., v_1..v_P]; only where x_a lies in
+// a support of bump function i (elsewhere dF_ai/dtheta = 0).
+__global__ void k_lowrank_G(const double* __restrict__ X, const double* __restrict__ V,
+                            const uint64_t* __restrict__ M, const double* __restrict__ FX,
+                            const double* __restrict__ FV, int64_t n, int n1, int R, int P, double s_scale,
+                            double* __restrict__ G) {
+  const int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (a >= n) return;
+  uint64_t m = M[a];
+  const double* Xa = X + a * R;
+  const double* Va = V + a * R;
+  while (m) {
+    const int i = __builtin_ctzll(m);
+    m &= m - 1;
+    double t = 0.0;
+    for (int p = 0; p < P; ++p) t += Xa[1 + p] * FV[(int64_t)i * R + 1 + p] + Va[1 + p] * FX[(int64_t)i * R + 1 + p];
+    G[a * n1 + i] = 0.5 * Xa[0] * FX[(int64_t)i * R] - 0.25 * s_scale * t;
+  }
+}
+
+template <int NI>
+void launch_ft(Ctx* c, const double* F, const double* Y, int64_t n, int n1, int R, double* part, int nb,
+               double* out) {
+  const int chunks = (R + kWave - 1) / kWave;
+  k_ft_part<NI><<<dim3(nb, chunks), 256, 0, c->stream>>>(F, Y, n, n1, R, part);
+  SDGP_CHECK_LAUNCH();
+  k_ft_reduce<<<dim3(n1, chunks), kWave, 0, c->stream>>>(part, nb, n1, R, out);
+  SDGP_CHECK_LAUNCH();
+}
+
+void lowrank_bump_adjoint(Ctx* c, const Sorted& s, const KParams& kp, const Bumps& b, const CgResult& cg, int P,
+                          double s_scale, double* G) {
+  const int n1 = kp.n1;
+  const int64_t n = s.n;
+  const int R = cg.R;
+  require(cg.V != nullptr, "the factored operator needs the preconditioned probe solves");
+  const int nb = (int)std::min<int64_t>(256, (n + 1023) / 1024);
+  double* part = c->get<double>(S_LR_PART, (size_t)nb * n1 * R);
+  double* FX = c->get<double>(S_LR_FX, (size_t)n1 * R);
+  double* FV = c->get<double>(S_LR_FV, (size_t)n1 * R);
+  auto ft = [&](const double* Y, double* out) {
+    if (n1 <= 8) launch_ft<8>(c, b.F, Y, n, n1, R, part, nb, out);
+    else if (n1 <= 16) launch_ft<16>(c, b.F, Y, n, n1, R, part, nb, out);
+    else if (n1 <= 32) launch_ft<32>(c, b.F, Y, n, n1, R, part, nb, out);
+    else launch_ft<64>(c, b.F, Y, n, n1, R, part, nb, out);
+  };
+  ft(cg.X, FX);
+  ft(cg.V, FV);
+  k_lowrank_G<<<(unsigned)((n + 255) / 256), 256, 0, c->stream>>>(cg.X, cg.V, b.M, FX, FV, n, n1, R, P, s_scale, G);
+  SDGP_CHECK_LAUNCH();
+}
+
 }  // namespace
 
 void adjoint_gradient(Ctx* c, const Sorted& s, const KParams& kp, const Bumps& b, const Csr& Am,
-                      const CgResult& cg, int kind, int P, uint64_t seed, const double* h, double* grad) {
+                      const CgResult& cg, int kind, int P, uint64_t seed, const double* h, double* grad,
+                      bool lowrank) {
   const int64_t n = s.n;
   AdjArgs A;
   A.xs = s.xs; A.M = b.M; A.F = b.F; A.perm = s.perm; A.sched = s.sched;
@@ -269,9 +367,11 @@ void adjoint_gradient(Ctx* c, const Sorted& s, const KParams& kp, const Bumps& b
   const int n1 = kp.n1;
   A.G = c->get<double>(S_ADJ_G, (size_t)n * (n1 > 0 ? n1 : 1));
   if (n1 > 0) SDGP_HIP(hipMemsetAsync(A.G, 0, (size_t)n * n1 * sizeof(double), c->stream));
+  A.lowrank = lowrank ? 1 : 0;
   const int64_t blocks = (n + 3) / 4;
   k_adjoint_rows<<<(unsigned)blocks, kAdjBlock, 0, c->stream>>>(A);
   SDGP_CHECK_LAUNCH();
+  if (lowrank && n1 > 0) lowrank_bump_adjoint(c, s, kp, b, cg, P, A.s_scale, A.G);
   // core / noise terms
   const int nbp = (int)std::min<int64_t>(256, (n + 255) / 256);
   double* part = c->get<double>(S_ADJ_PART, (size_t)nbp * 3);

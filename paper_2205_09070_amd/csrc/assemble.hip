@@ -378,6 +378,7 @@ struct RowArgs {
   const int2* iv;
   int64_t n;
   int dim, n1, core, ell, combine, add_noise;
+  int core_only;   // keep only the core part (+ diagonal), values without B
   double sigma2, r_core, rc2, noise;
 };
 
@@ -413,7 +414,8 @@ __global__ __launch_bounds__(kBlock) void k_rows(RowArgs A, int64_t* __restrict_
         core = d2 < A.rc2;
         mm = Ma & A.M[b];
         const bool bump = mm != 0;
-        keep = (b == a) || (A.combine == 0 ? (core && bump) : (core || bump));
+        keep = (b == a) || (A.core_only ? core : (A.combine == 0 ? (core && bump) : (core || bump)));
+        if (A.core_only) mm = 0;
       }
       const uint64_t bal = ballot64(keep);
       if (kFill) {
@@ -729,7 +731,7 @@ Bumps bump_precompute(Ctx* c, const Sorted& s, const KParams& kp, const double* 
 }
 
 void prune(Ctx* c, const Sorted& s, const KParams& kp, const Bumps& b, int32_t** iv_ptr_out,
-           int2** iv_out) {
+           int2** iv_out, bool core_only) {
   const int64_t nc = s.grid.n_cells;
   uint64_t* cm = c->get<uint64_t>(S_CELLMASK, nc);
   k_cellmask<<<grid_for(nc, kBlock), kBlock, 0, c->stream>>>(s.cell_start, nc, b.M, cm);
@@ -740,7 +742,7 @@ void prune(Ctx* c, const Sorted& s, const KParams& kp, const Bumps& b, int32_t**
   A.cm = cm;
   A.run_ptr = nullptr;
   A.runs = nullptr;
-  A.use_bumps = (kp.combine == SDGP_COMBINE_SUM && kp.n1 > 0) ? 1 : 0;
+  A.use_bumps = (kp.combine == SDGP_COMBINE_SUM && kp.n1 > 0 && !core_only) ? 1 : 0;
   if (A.use_bumps) {
     int32_t* run_cnt = c->get<int32_t>(S_RUN_CNT, kp.n1);
     k_bump_runs<false><<<kp.n1, kBlock, 0, c->stream>>>(cm, nc, run_cnt, nullptr, nullptr);
@@ -779,19 +781,19 @@ void prune(Ctx* c, const Sorted& s, const KParams& kp, const Bumps& b, int32_t**
 }
 
 static RowArgs row_args(const Sorted& s, const KParams& kp, const Bumps& b, const int32_t* iv_ptr,
-                        const int2* iv, bool add_noise) {
+                        const int2* iv, bool add_noise, bool core_only) {
   RowArgs A;
   A.xs = s.xs; A.M = b.M; A.F = b.F; A.cell_of = s.cell_of; A.iv_ptr = iv_ptr; A.iv = iv;
   A.n = s.n; A.dim = kp.dim; A.n1 = kp.n1; A.core = kp.core; A.ell = kp.dim / 2 + 2;
-  A.combine = kp.combine; A.add_noise = add_noise ? 1 : 0;
+  A.combine = kp.combine; A.add_noise = add_noise ? 1 : 0; A.core_only = core_only ? 1 : 0;
   A.sigma2 = kp.sigma2; A.r_core = kp.r_core; A.rc2 = kp.rc2; A.noise = kp.noise;
   return A;
 }
 
 Csr assemble_sorted(Ctx* c, const Sorted& s, const KParams& kp, const Bumps& b, const int32_t* iv_ptr,
-                    const int2* iv, bool add_noise, int64_t* candidates, PhaseTimer* t) {
+                    const int2* iv, bool add_noise, int64_t* candidates, PhaseTimer* t, bool core_only) {
   const int64_t n = s.n;
-  RowArgs A = row_args(s, kp, b, iv_ptr, iv, add_noise);
+  RowArgs A = row_args(s, kp, b, iv_ptr, iv, add_noise, core_only);
   int64_t* row_nnz = c->get<int64_t>(S_ROW_NNZ, n + 1);
   unsigned long long* cand = c->get<unsigned long long>(S_COUNTER, 4);
   SDGP_HIP(hipMemsetAsync(cand, 0, sizeof(unsigned long long), c->stream));

@@ -72,7 +72,7 @@ enum Slot {
   S_CG_X, S_CG_R, S_CG_P, S_CG_Q, S_CG_SCAL, S_CG_PART, S_CG_HIST_A, S_CG_HIST_B,
   S_CG_STATE, S_ZBITS, S_SLQ_WORK, S_SLQ_OUT, S_ADJ_ROW, S_ADJ_G, S_ADJ_PART,
   S_RED_PART, S_RED_OUT, S_X0S, S_MISC, S_POST, S_COUNTER,
-  S_CG_V, S_CG_PARTG, S_CG_G, S_PC_PART, S_PC_SINV,
+  S_CG_V, S_CG_PART2, S_CG_PARTG, S_CG_G, S_CG_GP, S_PC_PART, S_PC_SINV, S_LR_PART, S_LR_FX, S_LR_FV,
   S_MORTON_KEYS, S_MORTON_KEYS2, S_MORTON_IDS, S_MORTON_ORDER, S_MORTON_SZ, S_MORTON_OFF, S_SCHED,
   S_QF, S_QM, S_KXX, S_QIV_CNT, S_QIV_PTR, S_QIV, S_QROW_NNZ, S_QROW_PTR, S_QCOL, S_QVAL,
   S_NUM
@@ -164,12 +164,14 @@ Sorted order_points(Ctx* c, const double* x, int64_t n, int dim, double r_cell);
 void gather_vector(Ctx* c, const Sorted& s, const double* src, double* dst);
 Bumps bump_precompute(Ctx* c, const Sorted& s, const KParams& kp, const double* h);
 // Candidate column intervals per cell (pruning); returns interval count.
+// core_only: only the core supports (the factored SUM operator).
 void prune(Ctx* c, const Sorted& s, const KParams& kp, const Bumps& b,
-           int32_t** iv_ptr, int2** iv);
+           int32_t** iv_ptr, int2** iv, bool core_only = false);
 // Count + fill; the CSR lives in context buffers (S_ROW_PTR, S_COL, S_VAL).
+// core_only: store the core part only (K_core + noise on the diagonal).
 Csr assemble_sorted(Ctx* c, const Sorted& s, const KParams& kp, const Bumps& b,
                     const int32_t* iv_ptr, const int2* iv, bool add_noise,
-                    int64_t* candidates, PhaseTimer* t);
+                    int64_t* candidates, PhaseTimer* t, bool core_only = false);
 // Canonical (caller order, ascending columns) copy of a sorted-order CSR.
 void canonicalize(Ctx* c, const Sorted& s, const Csr& k, int64_t* row_ptr,
                   int32_t* col, double* val);
@@ -186,6 +188,8 @@ Csr assemble_cross(Ctx* c, const Sorted& s, const KParams& kp, const Bumps& b,
 // Low-rank preconditioner M = c I + F F^T of the SUM combine (F: the sorted
 // bump values); Sinv = (c I + F^T F)^{-1} on the device.
 struct Precond {
+  int apply = 1;        // precondition the CG with M
+  int lowrank_op = 0;   // the CSR holds only the core part; A = K_core + F F^T
   int n1 = 0;
   const double* F = nullptr;
   const double* Sinv = nullptr;
@@ -219,6 +223,8 @@ CgResult block_cg(Ctx* c, const Csr& A, const Sorted& s, const double* ys,
                   bool keep_v, PhaseTimer* t);
 Precond lowrank_precond(Ctx* c, const Sorted& s, const KParams& kp, const Bumps& b);
 void spmm(Ctx* c, const Csr& A, const double* X, int R, double* Y);
+// Randomised Taylor-series log-det (Boutsidis et al. 2017) on A.
+double logdet_taylor(Ctx* c, const Csr& A, const Sorted& s, int P, int terms, uint64_t seed, double* alpha_out);
 // Stochastic Lanczos quadrature from CG coefficients of columns 1..R-1.
 void slq_from_cg(Ctx* c, const CgResult& cg, int kind, int P, int64_t n,
                  int lanczos_steps, double* logdet, double* stderr_out,
@@ -234,8 +240,9 @@ void posterior_variance(Ctx* c, const Csr& A, const Sorted& s, const Csr& K0, co
 // ---------------------------------------------------------------------------
 // Adjoint (adjoint.hip)
 // ---------------------------------------------------------------------------
+// lowrank: A holds only the core part and the bump part is F F^T (SUM).
 void adjoint_gradient(Ctx* c, const Sorted& s, const KParams& kp, const Bumps& b,
                       const Csr& A, const CgResult& cg, int kind, int P,
-                      uint64_t seed, const double* h, double* grad_host);
+                      uint64_t seed, const double* h, double* grad_host, bool lowrank = false);
 
 }  // namespace sdgp

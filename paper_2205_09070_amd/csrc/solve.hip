@@ -189,14 +189,18 @@ struct CgArgs {
   const int32_t* col;
   const double* val;
   double *X, *Rr, *P, *Q;
-  double* part;        // [nb][R]
-  double* partg;       // [nb][n1][R]  F^T r partials (preconditioned)
+  double* part;        // [nb][R] p.Ap partials (written by the SpMM, read by update_xr)
+  double* part2;       // [nb][R] r.r partials (written by update_xr / norm_part, read after)
+  double* partg;       // [nb][n1][R]  F^T p / F^T r partials (each reduced by its own launch)
   double* g;           // [n1][R]
   double* V;           // [n][R] M^{-1} b (preconditioned, may be null)
   const int32_t* sched;  // row processing order for the SpMM (may be null)
   const double* F;     // [n][n1] sorted bump values
   const double* Sinv;  // [n1][n1] (c I + F^T F)^{-1}
   int n1;
+  int use_pc;          // preconditioned: g = F^T r, z = M^{-1} r on the fly
+  int lowrank_op;      // operator K_core P + F (F^T P) (SUM combine)
+  double* gp;          // [n1][R] F^T p (lowrank_op)
   double inv_c, sqrt_c;
   int nb;
   CgState st;
@@ -206,7 +210,7 @@ struct CgArgs {
 // Per-block partials of F^T v (v: this lane's column of the block's rows)
 // given per-lane accumulators acc[NI]: reduced 4 at a time through LDS.
 template <int NI>
-__device__ void block_partial_g(const double* acc, double* gs, const CgArgs& A) {
+__device__ void block_partial_g(const double* acc, double* gs, const CgArgs& A, double* out) {
   const int t = threadIdx.x;
   const int l = t & 63, w = t >> 6;
   const int rc = blockIdx.y * kWave + l;
@@ -222,7 +226,7 @@ __device__ void block_partial_g(const double* acc, double* gs, const CgArgs& A) 
       const int i = i0 + q;
       double tot = 0.0;
       for (int ww = 0; ww < kCgWaves; ++ww) tot += gs[(q * kCgWaves + ww) * kWave + l];
-      if (i < A.n1 && rc < A.R) A.partg[((int64_t)blockIdx.x * A.n1 + i) * A.R + rc] = tot;
+      if (i < A.n1 && rc < A.R) out[((int64_t)blockIdx.x * A.n1 + i) * A.R + rc] = tot;
     }
   }
 }
@@ -269,36 +273,113 @@ __device__ __forceinline__ double apply_prec(const CgArgs& A, int64_t a, double 
   return (r - s) * A.inv_c;
 }
 
-// Q = A P, partial p.q per column.
+// Q = A P (with the factored operator: Q = K_core P, and F^T P partials),
+// partial p.q per column.
+template <int NI>
 __global__ __launch_bounds__(kCgBlock) void k_cg_spmm(CgArgs A) {
   if (*A.st.done) return;
   __shared__ double scratch[kCgBlock];
+  __shared__ double gsh[NI > 0 ? 4 * kCgBlock : 1];
   const int lane = lane_id();
   const int rc = blockIdx.y * kWave + lane;
   const int rcc = rc < A.R ? rc : A.R - 1;
   const int64_t R = A.R;
   double pq = 0.0;
+  double gacc[NI > 0 ? NI : 1];
+#pragma unroll
+  for (int i = 0; i < (NI > 0 ? NI : 1); ++i) gacc[i] = 0.0;
+  const bool lr = NI > 0 && A.lowrank_op;
   for (RowSweep w(A.n, kCgWaves); w.a < w.hi; w.a += w.step) {
     const int64_t a = A.sched ? (int64_t)A.sched[w.a] : w.a;
     const double q = row_dot(A.row_ptr[a], A.row_ptr[a + 1], A.col, A.val, A.P + rcc, R);
     if (rc < A.R) {
       A.Q[a * R + rc] = q;
-      pq += A.P[a * R + rc] * q;
+      const double pa = A.P[a * R + rc];
+      pq += pa * q;
+      if (lr) {
+        const double* Fa = A.F + a * (int64_t)A.n1;
+#pragma unroll
+        for (int i = 0; i < (NI > 0 ? NI : 1); ++i)
+          if (i < A.n1) gacc[i] += Fa[i] * pa;
+      }
     }
   }
   block_partial(pq, scratch, A.part, A.R, A.R);
+  if (lr) block_partial_g<NI>(gacc, gsh, A, A.partg);
 }
 
-// alpha = r.z / p.q; x += alpha p; r -= alpha q; partials r.r and F^T r.
+// out[i][r] = sum_b partg[b][i][r] (fixed order); grid (n1, chunks).
+__global__ __launch_bounds__(kCgBlock) void k_cg_reduce_g(CgArgs A, double* __restrict__ out) {
+  if (*A.st.done) return;
+  __shared__ double scratch[kCgBlock];
+  const int i = blockIdx.x;
+  const int t = threadIdx.x;
+  const int l = t & 63, w = t >> 6;
+  const int rc = blockIdx.y * kWave + l;
+  double s = 0.0;
+  if (rc < A.R)
+    for (int b = w; b < A.nb; b += kCgWaves) s += A.partg[((int64_t)b * A.n1 + i) * A.R + rc];
+  scratch[w * kWave + l] = s;
+  __syncthreads();
+  if (t < kWave && rc < A.R) {
+    double tot = 0.0;
+    for (int q = 0; q < kCgWaves; ++q) tot += scratch[q * kWave + t];
+    out[(int64_t)i * A.R + rc] = tot;
+  }
+}
+
+// One row of the x/r update (lane = column): returns the new residual.
+template <int NI>
+__device__ __forceinline__ void xr_row(const CgArgs& A, int64_t a, int rc, double alpha, const double* gpl,
+                                       double& rr, double* gacc) {
+  const int64_t o = a * (int64_t)A.R + rc;
+  double q = A.Q[o];
+  const double* Fa = A.F + a * (int64_t)A.n1;
+  if (NI > 0 && A.lowrank_op) {
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < (NI > 0 ? NI : 1); ++i)
+      if (i < A.n1) s += Fa[i] * gpl[i * kWave + (rc & 63)];
+    q += s;
+  }
+  A.X[o] += alpha * A.P[o];
+  const double r = A.Rr[o] - alpha * q;
+  A.Rr[o] = r;
+  rr += r * r;
+  if (NI > 0 && A.use_pc) {
+#pragma unroll
+    for (int i = 0; i < (NI > 0 ? NI : 1); ++i)
+      if (i < A.n1) gacc[i] += Fa[i] * r;
+  }
+}
+
+// alpha = r.z / p.A p; x += alpha p; r -= alpha A p; partials r.r and F^T r.
+// With the factored operator p.A p = p.(K_core p) + |F^T p|^2 and
+// A p = K_core p + F (F^T p) is completed here on the fly.
 template <int NI>
 __global__ __launch_bounds__(kCgBlock) void k_cg_update_xr(CgArgs A, int it) {
   if (*A.st.done) return;
   __shared__ double scratch[kCgBlock];
   __shared__ double pAp[kWave];
   __shared__ double gsh[NI > 0 ? 4 * kCgBlock : 1];
+  __shared__ double gpl[NI > 0 ? NI * kWave : 1];
   chunk_reduce(A.part, A.nb, A.R, A.R, pAp, scratch);
   const int lane = lane_id();
   const int rc = blockIdx.y * kWave + lane;
+  if (NI > 0 && A.lowrank_op) {
+    for (int idx = threadIdx.x; idx < A.n1 * kWave; idx += blockDim.x) {
+      const int i = idx >> 6, ll = idx & 63;
+      const int r = blockIdx.y * kWave + ll;
+      gpl[i * kWave + ll] = r < A.R ? A.gp[(int64_t)i * A.R + r] : 0.0;
+    }
+    __syncthreads();
+    if (threadIdx.x < kWave) {
+      double gg = 0.0;
+      for (int i = 0; i < A.n1; ++i) gg += gpl[i * kWave + threadIdx.x] * gpl[i * kWave + threadIdx.x];
+      pAp[threadIdx.x] += gg;
+    }
+    __syncthreads();
+  }
   const int par = it & 1;
   double alpha = 0.0;
   bool act = false;
@@ -315,49 +396,22 @@ __global__ __launch_bounds__(kCgBlock) void k_cg_update_xr(CgArgs A, int it) {
     if (was) A.st.hist_a[(int64_t)it * A.R + rc] = alpha;
     if (was && !act) { A.st.failed[rc] = 1; *A.st.not_spd = 1; }
   }
-  const int64_t R = A.R;
   const int64_t W = (int64_t)gridDim.x * kCgWaves;
   double rr = 0.0;
   double gacc[NI > 0 ? NI : 1];
 #pragma unroll
   for (int i = 0; i < (NI > 0 ? NI : 1); ++i) gacc[i] = 0.0;
-  for (int64_t a = blockIdx.x * (int64_t)kCgWaves + (threadIdx.x >> 6); a < A.n; a += W) {
-    if (act) {
-      const int64_t o = a * R + rc;
-      A.X[o] += alpha * A.P[o];
-      const double r = A.Rr[o] - alpha * A.Q[o];
-      A.Rr[o] = r;
-      rr += r * r;
-      if (NI > 0) {
-        const double* Fa = A.F + a * (int64_t)A.n1;
-#pragma unroll
-        for (int i = 0; i < NI; ++i)
-          if (i < A.n1) gacc[i] += Fa[i] * r;
-      }
+  if (act) {
+    // two rows in flight per wave
+    int64_t a = blockIdx.x * (int64_t)kCgWaves + (threadIdx.x >> 6);
+    for (; a + W < A.n; a += 2 * W) {
+      xr_row<NI>(A, a, rc, alpha, gpl, rr, gacc);
+      xr_row<NI>(A, a + W, rc, alpha, gpl, rr, gacc);
     }
+    if (a < A.n) xr_row<NI>(A, a, rc, alpha, gpl, rr, gacc);
   }
-  block_partial(rr, scratch, A.part, A.R, A.R);
-  if (NI > 0) block_partial_g<NI>(gacc, gsh, A);
-}
-
-// g[i][r] = sum_b partg[b][i][r] (fixed order); grid (n1, chunks).
-__global__ __launch_bounds__(kCgBlock) void k_cg_reduce_g(CgArgs A) {
-  if (*A.st.done) return;
-  __shared__ double scratch[kCgBlock];
-  const int i = blockIdx.x;
-  const int t = threadIdx.x;
-  const int l = t & 63, w = t >> 6;
-  const int rc = blockIdx.y * kWave + l;
-  double s = 0.0;
-  if (rc < A.R)
-    for (int b = w; b < A.nb; b += kCgWaves) s += A.partg[((int64_t)b * A.n1 + i) * A.R + rc];
-  scratch[w * kWave + l] = s;
-  __syncthreads();
-  if (t < kWave && rc < A.R) {
-    double tot = 0.0;
-    for (int q = 0; q < kCgWaves; ++q) tot += scratch[q * kWave + t];
-    A.g[(int64_t)i * A.R + rc] = tot;
-  }
+  block_partial(rr, scratch, A.part2, A.R, A.R);
+  if (NI > 0 && A.use_pc) block_partial_g<NI>(gacc, gsh, A, A.partg);
 }
 
 // beta = r.z_new / r.z; convergence on |r|; p = z + beta p with
@@ -371,8 +425,9 @@ __global__ __launch_bounds__(kCgBlock) void k_cg_update_p(CgArgs A, int it) {
   __shared__ double gu[kWave];
   __shared__ double gs[NI > 0 ? NI * kWave : 1];
   __shared__ double us[NI > 0 ? NI * kWave : 1];
-  chunk_reduce(A.part, A.nb, A.R, A.R, rrn, scratch);
-  if (NI > 0) solve_small<NI>(A, gs, us, gu);
+  chunk_reduce(A.part2, A.nb, A.R, A.R, rrn, scratch);
+  const bool pc = NI > 0 && A.use_pc;
+  if (pc) solve_small<NI>(A, gs, us, gu);
   const int lane = lane_id();
   const int rc = blockIdx.y * kWave + lane;
   const int par = it & 1, nxt = par ^ 1;
@@ -384,7 +439,7 @@ __global__ __launch_bounds__(kCgBlock) void k_cg_update_p(CgArgs A, int it) {
     act = A.st.act[par * A.R + rc] != 0 && A.st.failed[rc] == 0;
     rz_old = A.st.rz[par * A.R + rc];
     const double rr_new = rrn[lane];
-    rz_new = NI > 0 ? (rr_new - gu[lane]) * A.inv_c : rr_new;
+    rz_new = pc ? (rr_new - gu[lane]) * A.inv_c : rr_new;
     if (act) {
       beta = rz_new / rz_old;
       cont = !(rr_new <= A.rtol2 * A.st.bnorm2[rc]);
@@ -401,10 +456,20 @@ __global__ __launch_bounds__(kCgBlock) void k_cg_update_p(CgArgs A, int it) {
   }
   const int64_t R = A.R;
   const int64_t W = (int64_t)gridDim.x * kCgWaves;
-  for (int64_t a = blockIdx.x * (int64_t)kCgWaves + (threadIdx.x >> 6); a < A.n; a += W) {
-    if (cont) {
+  if (cont) {
+    int64_t a = blockIdx.x * (int64_t)kCgWaves + (threadIdx.x >> 6);
+    for (; a + W < A.n; a += 2 * W) {
+      const int64_t o0 = a * R + rc, o1 = (a + W) * R + rc;
+      const double r0 = A.Rr[o0], r1 = A.Rr[o1];
+      const double p0 = A.P[o0], p1 = A.P[o1];
+      const double z0 = pc ? apply_prec<NI>(A, a, r0, us) : r0;
+      const double z1 = pc ? apply_prec<NI>(A, a + W, r1, us) : r1;
+      A.P[o0] = z0 + beta * p0;
+      A.P[o1] = z1 + beta * p1;
+    }
+    if (a < A.n) {
       const int64_t o = a * R + rc;
-      A.P[o] = apply_prec<NI>(A, a, A.Rr[o], us) + beta * A.P[o];
+      A.P[o] = (pc ? apply_prec<NI>(A, a, A.Rr[o], us) : A.Rr[o]) + beta * A.P[o];
     }
   }
 }
@@ -444,7 +509,7 @@ __global__ void k_cg_init(CgArgs A, const double* __restrict__ ys, const int32_t
   } else {
     const uint64_t pbase = (uint64_t)(r - 1) << 32;
     b = (splitmix64_at(seed, pbase + (uint64_t)perm[a] + 1ull) >> 63) ? -1.0 : 1.0;
-    if (A.n1 > 0 && A.F != nullptr) {
+    if (A.use_pc) {
       double fv = 0.0;
       const double* Fa = A.F + a * (int64_t)A.n1;
       for (int i = 0; i < A.n1; ++i) {
@@ -474,15 +539,15 @@ __global__ __launch_bounds__(kCgBlock) void k_cg_norm_part(CgArgs A) {
     for (int64_t a = blockIdx.x * (int64_t)kCgWaves + (threadIdx.x >> 6); a < A.n; a += W) {
       const double v = A.Rr[a * R + rc];
       s += v * v;
-      if (NI > 0) {
+      if (NI > 0 && A.use_pc) {
         const double* Fa = A.F + a * (int64_t)A.n1;
 #pragma unroll
         for (int i = 0; i < NI; ++i)
           if (i < A.n1) gacc[i] += Fa[i] * v;
       }
     }
-  block_partial(s, scratch, A.part, A.R, A.R);
-  if (NI > 0) block_partial_g<NI>(gacc, gsh, A);
+  block_partial(s, scratch, A.part2, A.R, A.R);
+  if (NI > 0 && A.use_pc) block_partial_g<NI>(gacc, gsh, A, A.partg);
 }
 
 // Initial state: p = z0 = M^{-1} b (b when unpreconditioned), V = z0,
@@ -494,13 +559,14 @@ __global__ __launch_bounds__(kCgBlock) void k_cg_init_fin(CgArgs A) {
   __shared__ double gu[kWave];
   __shared__ double gs[NI > 0 ? NI * kWave : 1];
   __shared__ double us[NI > 0 ? NI * kWave : 1];
-  chunk_reduce(A.part, A.nb, A.R, A.R, nrm, scratch);
-  if (NI > 0) solve_small<NI>(A, gs, us, gu);
+  chunk_reduce(A.part2, A.nb, A.R, A.R, nrm, scratch);
+  const bool pc = NI > 0 && A.use_pc;
+  if (pc) solve_small<NI>(A, gs, us, gu);
   const int lane = lane_id();
   const int rc = blockIdx.y * kWave + lane;
   if (blockIdx.x == 0 && threadIdx.x < kWave && rc < A.R) {
     const double bb = nrm[lane];
-    const double rz0 = NI > 0 ? (bb - gu[lane]) * A.inv_c : bb;
+    const double rz0 = pc ? (bb - gu[lane]) * A.inv_c : bb;
     A.st.bnorm2[rc] = bb;
     A.st.rr_last[rc] = bb;
     A.st.rz[rc] = rz0;
@@ -516,7 +582,7 @@ __global__ __launch_bounds__(kCgBlock) void k_cg_init_fin(CgArgs A) {
   if (rc < A.R)
     for (int64_t a = blockIdx.x * (int64_t)kCgWaves + (threadIdx.x >> 6); a < A.n; a += W) {
       const int64_t o = a * R + rc;
-      const double z = apply_prec<NI>(A, a, A.Rr[o], us);
+      const double z = pc ? apply_prec<NI>(A, a, A.Rr[o], us) : A.Rr[o];
       A.P[o] = z;
       if (A.V) A.V[o] = z;
     }
@@ -577,6 +643,57 @@ __global__ void k_rowdot_chunk(const int64_t* __restrict__ rp, const int32_t* __
 
 // Blocks per column chunk for the CG kernels: about two 1024-thread blocks
 // per CU, a multiple of 8 (the XCD-aware row sweep needs it).
+// Gershgorin bound: per-block partial maxima of sum_b |A_ab| over rows.
+__global__ void k_rowabs_max(const int64_t* __restrict__ rp, const double* __restrict__ val, int64_t n,
+                             double* __restrict__ part) {
+  __shared__ double sh[256];
+  double m = 0.0;
+  for (int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; a < n; a += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int64_t k = rp[a]; k < rp[a + 1]; ++k) s += fabs(val[k]);
+    m = fmax(m, s);
+  }
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+// Rademacher probe block Z[n][P] (caller row perm[a]) and V = Z.
+__global__ void k_taylor_init(const int32_t* __restrict__ perm, int64_t n, int P, uint64_t seed,
+                              double* __restrict__ Z, double* __restrict__ V) {
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= n * P) return;
+  const int64_t a = idx / P;
+  const int p = (int)(idx % P);
+  const uint64_t k = ((uint64_t)p << 32) + (uint64_t)perm[a] + 1ull;
+  const double z = (splitmix64_at(seed, k) >> 63) ? -1.0 : 1.0;
+  Z[idx] = z;
+  V[idx] = z;
+}
+
+// V <- V - W / alpha (= C V) and partial sums of Z . V.
+__global__ void k_taylor_step(int64_t len, const double* __restrict__ Z, const double* __restrict__ W,
+                              double* __restrict__ V, double inv_alpha, double* __restrict__ part) {
+  __shared__ double sh[256];
+  double s = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < len; i += (int64_t)gridDim.x * blockDim.x) {
+    const double v = V[i] - W[i] * inv_alpha;
+    V[i] = v;
+    s += Z[i] * v;
+  }
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
 inline int cg_nb(int64_t n, int R) {
   const int chunks = (R + kWave - 1) / kWave;
   int64_t nb = std::max<int64_t>(1, 512 / chunks);
@@ -604,6 +721,46 @@ void posterior_variance(Ctx* c, const Csr& A, const Sorted& s, const Csr& K0, co
     k_rowdot_chunk<<<g, 256, 0, c->stream>>>(K0.row_ptr, K0.col, K0.val, t0, Rc, n0, cg.X, kxx, var);
     SDGP_CHECK_LAUNCH();
   }
+}
+
+double logdet_taylor(Ctx* c, const Csr& A, const Sorted& s, int P, int terms, uint64_t seed, double* alpha_out) {
+  require(P >= 1 && P <= 4096, "probes must be 1..4096");
+  require(terms >= 1, "terms must be >= 1");
+  const int64_t n = A.n;
+  const int nbm = (int)std::min<int64_t>(1024, (n + 255) / 256);
+  double* pm = c->get<double>(S_RED_PART, std::max(nbm, 1024));
+  k_rowabs_max<<<nbm, 256, 0, c->stream>>>(A.row_ptr, A.val, n, pm);
+  SDGP_CHECK_LAUNCH();
+  std::vector<double> hm(nbm);
+  SDGP_HIP(hipMemcpyAsync(hm.data(), pm, nbm * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  SDGP_HIP(hipStreamSynchronize(c->stream));
+  double alpha = 0.0;
+  for (double v : hm) alpha = std::max(alpha, v);
+  require(alpha > 0.0 && std::isfinite(alpha), "matrix has no positive row sums");
+  const size_t len = (size_t)n * P;
+  double* Z = c->get<double>(S_CG_X, len);
+  double* V = c->get<double>(S_CG_R, len);
+  double* W = c->get<double>(S_CG_Q, len);
+  k_taylor_init<<<(unsigned)((len + 255) / 256), 256, 0, c->stream>>>(s.perm, n, P, seed, Z, V);
+  SDGP_CHECK_LAUNCH();
+  const int nb = (int)std::min<int64_t>(1024, ((int64_t)len + 255) / 256);
+  std::vector<double> hp((size_t)nb * terms);
+  double* part = c->get<double>(S_RED_OUT, (size_t)nb * terms);
+  for (int k = 1; k <= terms; ++k) {
+    spmm(c, A, V, P, W);
+    k_taylor_step<<<nb, 256, 0, c->stream>>>((int64_t)len, Z, W, V, 1.0 / alpha, part + (size_t)(k - 1) * nb);
+    SDGP_CHECK_LAUNCH();
+  }
+  SDGP_HIP(hipMemcpyAsync(hp.data(), part, hp.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  SDGP_HIP(hipStreamSynchronize(c->stream));
+  double acc = 0.0;
+  for (int k = 1; k <= terms; ++k) {
+    double t = 0.0;
+    for (int b = 0; b < nb; ++b) t += hp[(size_t)(k - 1) * nb + b];
+    acc += t / P / k;
+  }
+  *alpha_out = alpha;
+  return (double)n * std::log(alpha) - acc;
 }
 
 void spmm(Ctx* c, const Csr& A, const double* X, int R, double* Y) {
@@ -682,17 +839,21 @@ template <int NI>
 void launch_cg_iteration(Ctx* c, const CgArgs& A, dim3 grid, int chunks, int it) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (c->timing) { e0 = c->event(); SDGP_HIP(hipEventRecord(e0, c->stream)); }
-  k_cg_spmm<<<grid, kCgBlock, 0, c->stream>>>(A);
+  k_cg_spmm<NI><<<grid, kCgBlock, 0, c->stream>>>(A);
   SDGP_CHECK_LAUNCH();
   if (c->timing) {
     e1 = c->event();
     SDGP_HIP(hipEventRecord(e1, c->stream));
     c->spmm_events.push_back({e0, e1});
   }
+  if (NI > 0 && A.lowrank_op) {
+    k_cg_reduce_g<<<dim3(A.n1, chunks), kCgBlock, 0, c->stream>>>(A, A.gp);
+    SDGP_CHECK_LAUNCH();
+  }
   k_cg_update_xr<NI><<<grid, kCgBlock, 0, c->stream>>>(A, it);
   SDGP_CHECK_LAUNCH();
-  if (NI > 0) {
-    k_cg_reduce_g<<<dim3(A.n1, chunks), kCgBlock, 0, c->stream>>>(A);
+  if (NI > 0 && A.use_pc) {
+    k_cg_reduce_g<<<dim3(A.n1, chunks), kCgBlock, 0, c->stream>>>(A, A.g);
     SDGP_CHECK_LAUNCH();
   }
   k_cg_update_p<NI><<<grid, kCgBlock, 0, c->stream>>>(A, it);
@@ -705,8 +866,8 @@ template <int NI>
 void launch_cg_init(Ctx* c, const CgArgs& A, dim3 grid, int chunks) {
   k_cg_norm_part<NI><<<grid, kCgBlock, 0, c->stream>>>(A);
   SDGP_CHECK_LAUNCH();
-  if (NI > 0) {
-    k_cg_reduce_g<<<dim3(A.n1, chunks), kCgBlock, 0, c->stream>>>(A);
+  if (NI > 0 && A.use_pc) {
+    k_cg_reduce_g<<<dim3(A.n1, chunks), kCgBlock, 0, c->stream>>>(A, A.g);
     SDGP_CHECK_LAUNCH();
   }
   k_cg_init_fin<NI><<<grid, kCgBlock, 0, c->stream>>>(A);
@@ -789,8 +950,9 @@ CgResult block_cg(Ctx* c, const Csr& Am, const Sorted& s, const double* ys, int 
   require(R >= 1, "no right-hand sides");
   require(max_iter >= 1, "cg_max_iter must be >= 1");
   require(rtol > 0.0 && std::isfinite(rtol), "cg_rtol must be > 0");
-  const bool use_pc = pc != nullptr && pc->n1 > 0;
-  const int n1 = use_pc ? pc->n1 : 0;
+  const bool use_pc = pc != nullptr && pc->n1 > 0 && pc->apply;
+  const bool use_lr = pc != nullptr && pc->n1 > 0 && pc->lowrank_op;
+  const int n1 = (use_pc || use_lr) ? pc->n1 : 0;
   const int NI = n1 == 0 ? 0 : (n1 <= 8 ? 8 : (n1 <= 16 ? 16 : (n1 <= 32 ? 32 : 64)));
   const size_t NR = (size_t)n * R;
   CgArgs A;
@@ -809,13 +971,17 @@ CgResult block_cg(Ctx* c, const Csr& Am, const Sorted& s, const double* ys, int 
   const int chunks = (R + kWave - 1) / kWave;
   A.nb = nb;
   A.part = c->get<double>(S_CG_PART, (size_t)nb * R);
+  A.part2 = c->get<double>(S_CG_PART2, (size_t)nb * R);
   A.n1 = n1;
-  A.F = use_pc ? pc->F : nullptr;
+  A.use_pc = use_pc ? 1 : 0;
+  A.lowrank_op = use_lr ? 1 : 0;
+  A.F = n1 > 0 ? pc->F : nullptr;
   A.Sinv = use_pc ? pc->Sinv : nullptr;
   A.inv_c = use_pc ? 1.0 / pc->c : 1.0;
   A.sqrt_c = use_pc ? std::sqrt(pc->c) : 1.0;
-  A.partg = use_pc ? c->get<double>(S_CG_PARTG, (size_t)nb * n1 * R) : nullptr;
+  A.partg = n1 > 0 ? c->get<double>(S_CG_PARTG, (size_t)nb * n1 * R) : nullptr;
   A.g = use_pc ? c->get<double>(S_CG_G, (size_t)n1 * R) : nullptr;
+  A.gp = use_lr ? c->get<double>(S_CG_GP, (size_t)n1 * R) : nullptr;
   // state block: doubles rz[2R], rz0[R], bnorm2[R], rr_last[R];
   // ints act[2R], failed[R], iters[R], done, not_spd
   const size_t bytes = (5 * (size_t)R) * 8 + (4 * (size_t)R + 2) * 4 + 64;

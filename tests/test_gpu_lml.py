@@ -209,3 +209,51 @@ def test_preconditioned_posterior_matches():
     m0, v0 = gp.posterior_mean_var(w.desc, w.h, w.x, w.y, x0)
     assert np.allclose(m.cpu().numpy(), m0, rtol=1e-8, atol=1e-10)
     assert np.allclose(v.cpu().numpy(), v0, rtol=1e-7, atol=1e-10)
+
+
+@pytest.mark.parametrize("dim,n1", [(2, 3), (3, 12)])
+def test_factored_operator_matches_oracle_and_assembled(dim, n1):
+    gu.need_gpu()
+    import paper_2205_09070_amd as sd
+    w = wl.random_small(1200, dim, n1, 2, 31, combine=1, per_row=14.0, noise_var=1e-3)
+    gu.log("factored operator dim=%d n1=%d" % (dim, n1))
+    P, seed = 12, 4242
+    c = gu.ctx()
+    base = dict(probes=P, seed=seed, cg_rtol=1e-12, cg_max_iter=5000, precond=sd.PRECOND_LOWRANK)
+    vf, gf, inf_f = c.lml_grad(w.desc, gu.dev(w.x), gu.dev(w.y), w.h,
+                               sd.estimator(operator_form=sd.OPERATOR_FACTORED, **base))
+    va, ga, inf_a = c.lml_grad(w.desc, gu.dev(w.x), gu.dev(w.y), w.h, sd.estimator(**base))
+    v0, g0, ld0, _ = es.preconditioned_lml_grad(w.desc, w.h, w.x, w.y, seed, P, 400)
+    gu.log("  factored %.12g assembled %.12g oracle %.12g; nnz %d vs %d" % (vf, va, v0, inf_f.nnz, inf_a.nnz))
+    assert inf_f.nnz <= inf_a.nnz
+    assert abs(vf - v0) <= 1e-7 * abs(v0)
+    assert abs(vf - va) <= 1e-9 * abs(va)
+    assert gu.grad_close(gf, g0, rel=1e-6).all()
+    assert gu.grad_close(gf, ga, rel=1e-8).all()
+
+
+def test_factored_operator_requires_preconditioner():
+    gu.need_gpu()
+    import paper_2205_09070_amd as sd
+    w = wl.random_small(300, 2, 2, 2, 1, combine=1, per_row=10.0)
+    c = gu.ctx()
+    with pytest.raises(sd.SdgpError) as e:
+        c.lml(w.desc, gu.dev(w.x), gu.dev(w.y), w.h,
+              sd.estimator(probes=4, operator_form=sd.OPERATOR_FACTORED))
+    assert e.value.status == 1
+
+
+@pytest.mark.parametrize("terms", [1, 7, 60])
+def test_taylor_logdet_matches_oracle_estimator(terms):
+    gu.need_gpu()
+    from oracle import kernel as kn
+    w = wl.random_small(900, 2, 2, 2, 5, per_row=12.0, noise_var=0.3)
+    gu.log("taylor logdet terms=%d" % terms)
+    P, seed = 16, 99
+    c = gu.ctx()
+    ld, alpha = c.logdet_taylor(w.desc, gu.dev(w.x), w.h, probes=P, terms=terms, seed=seed)
+    A = kn.kernel_matrix(w.desc, w.h, w.x)
+    Z = es.rademacher(seed, w.x.shape[0], P)
+    ld0, alpha0 = es.boutsidis_logdet(A, Z, terms)
+    assert alpha == pytest.approx(alpha0, rel=1e-13)
+    assert ld == pytest.approx(ld0, rel=1e-11, abs=1e-9)
