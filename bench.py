@@ -42,6 +42,8 @@ def parse():
                    help="CG preconditioner (low-rank bump part of the SUM kernel, or none)")
     p.add_argument("--operator", choices=["assembled", "factored"], default="assembled",
                    help="CG operator: the fully assembled sparse K, or K_core (sparse) + F F^T")
+    p.add_argument("--graph", type=int, default=0,
+                   help="replay the CG iterations from a HIP graph (1; the SpMM is then not timed per launch)")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--spmv-reps", type=int, default=50)
     return p.parse_args()
@@ -91,6 +93,7 @@ def main():
     est = sd.estimator(probes=args.probes, seed=1, cg_rtol=args.rtol, cg_max_iter=20000, precond=pc,
                        operator_form=op)
     ctx = sd.Context(0, timing=True)
+    ctx.set_option("graph", args.graph)
     print("bench: N=%d dim=%d n1=%d n2=%d probes=%d" % (n, w.desc.dim, w.desc.n1, w.desc.n2, args.probes),
           file=sys.stderr, flush=True)
     for i in range(args.warmup):
@@ -117,7 +120,7 @@ def main():
     R = 1 + args.probes
     spmm_launches = sum(d["spmm_launches"] for d in infos)
     spmm_ms = sum(d["spmm_ms"] for d in infos)
-    spmm_avg_ms = spmm_ms / max(1, spmm_launches)
+    spmm_avg_ms = spmm_ms / spmm_launches if spmm_launches else float("nan")
     # algorithmic bytes of one CG SpMM launch: CSR (8 B value + 4 B column per
     # entry, 8 B row pointer per row), P read once, Q written once
     spmm_bytes = 12.0 * nnz + 8.0 * (n + 1) + 2.0 * 8.0 * n * R
@@ -137,7 +140,8 @@ def main():
     e1.record(s)
     e1.synchronize()
     spmv_ms = e0.elapsed_time(e1) / args.spmv_reps
-    spmv_bytes = 12.0 * nnz + 8.0 * (n + 1) + 8.0 * n + 8.0 * n
+    spmv_nnz = col.numel()
+    spmv_bytes = 12.0 * spmv_nnz + 8.0 * (n + 1) + 8.0 * n + 8.0 * n
     spmv_gbps = spmv_bytes / (spmv_ms * 1e-3) / 1e9
     out = {
         "metric": METRIC,
@@ -158,7 +162,7 @@ def main():
                                % (args.probes, args.rtol, args.precond, args.operator),
                    "points": n, "dim": 3, "n1": w.desc.n1, "n2": w.desc.n2, "n_hyper": int(len(w.h)),
                    "probes": args.probes, "cg_rtol": args.rtol, "precond": args.precond,
-                   "operator": args.operator},
+                   "operator": args.operator, "graph": bool(args.graph)},
         "nnz": int(nnz),
         "nnz_per_row": nnz / n,
         "candidates": int(cand),
@@ -166,7 +170,8 @@ def main():
         "phase_ms": {"order": ms[0], "bump": ms[1], "prune": ms[2], "count": ms[3], "fill": ms[4],
                      "cg": ms[5], "slq": ms[6], "adjoint": ms[7]},
         "assembly_nnz_per_s": nnz / (asm_ms * 1e-3),
-        "spmv": {"ms": spmv_ms, "GBps": spmv_gbps, "frac_hbm": spmv_gbps / HBM_PEAK_GBPS, "bytes": spmv_bytes},
+        "spmv": {"ms": spmv_ms, "GBps": spmv_gbps, "frac_hbm": spmv_gbps / HBM_PEAK_GBPS, "bytes": spmv_bytes,
+                 "matrix": "full assembled K + noise (%d nnz)" % spmv_nnz},
         "roofline": {"kernel": "k_cg_spmm (CG SpMM, %d right-hand sides)" % R, "bound": "hbm",
                      "achieved": spmm_gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": spmm_gbps / HBM_PEAK_GBPS, "traffic": None,

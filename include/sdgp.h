@@ -147,6 +147,13 @@ void sdgp_destroy(sdgp_ctx* ctx);
 const char* sdgp_last_error(const sdgp_ctx* ctx);
 /* Enable (1) or disable (0) per-phase and per-SpMM-launch HIP-event timing. */
 sdgp_status sdgp_set_timing(sdgp_ctx* ctx, int enable);
+/* Context options: "timing" (0/1, as sdgp_set_timing) and "graph" (0/1):
+ * run the CG iterations as a captured hipGraph of 8 iterations replayed
+ * until every column (and every population member) has converged; the
+ * iteration counters live on the device, so replays past convergence or
+ * past cg_max_iter do nothing.  Results are bitwise identical either way. */
+sdgp_status sdgp_set_option(sdgp_ctx* ctx, const char* name, int64_t value);
+
 /* 2 + n1*n2*(3+dim) + 1, or -1 for an invalid descriptor. */
 int64_t sdgp_num_hyper(const sdgp_kernel_desc* desc);
 
@@ -202,8 +209,14 @@ sdgp_status sdgp_lml_grad(sdgp_ctx* ctx, const sdgp_kernel_desc* desc, const dou
                           const sdgp_estimator* est, double* lml_out, double* grad_out,
                           sdgp_info* info);
 
-/* A population of B hyperparameter vectors on one shared point set: H is a
- * host array B*n_h (member m at H[m*n_h]); lml_out: host double[B];
+/* A population of B hyperparameter vectors on one shared point set
+ * (Section 2.4 training repeats eqn:log_likelihood for many h): the points
+ * are ordered once (cell side = the largest core radius), every member is
+ * assembled into storage of its own, and all members' block CGs advance
+ * together -- every solver kernel is one launch with the member as grid
+ * z, so members with uneven entry counts share the GPU -- followed by each
+ * member's quadrature and adjoint.  Probes are common to all members.
+ * H is a host array B*n_h (member m at H[m*n_h]); lml_out: host double[B];
  * grad_out: host double[B*n_h]; member_status: host int32[B] (per-member
  * sdgp_status; one failing member does not affect the others); info: host
  * array of B sdgp_info or NULL.  Returns SDGP_OK when the batch ran, even if

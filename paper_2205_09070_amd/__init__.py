@@ -12,7 +12,8 @@ from . import workloads  # noqa: F401
 from ._lib import (Context, SdgpError, estimator, exact_estimator, load,  # noqa: F401
                    CORE_KSTAT, CORE_WENDLAND_C2, COMBINE_PRODUCT, COMBINE_SUM,
                    PROBE_IDENTITY, PROBE_RADEMACHER, PRECOND_LOWRANK, PRECOND_NONE,
-                   OPERATOR_ASSEMBLED, OPERATOR_FACTORED)
+                   OPERATOR_ASSEMBLED, OPERATOR_FACTORED, OK, INVALID_ARG, OOM, NOT_SPD,
+                   NOT_CONVERGED, HIP, CAPACITY)
 
 
 def __getattr__(name):

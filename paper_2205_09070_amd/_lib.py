@@ -66,6 +66,7 @@ _SIGS = {
     "sdgp_destroy": (None, [VP]),
     "sdgp_last_error": (C.c_char_p, [VP]),
     "sdgp_set_timing": (I32, [VP, C.c_int]),
+    "sdgp_set_option": (I32, [VP, C.c_char_p, I64]),
     "sdgp_num_hyper": (I64, [C.POINTER(KernelDesc)]),
     "sdgp_kernel_nnz": (I32, [VP, C.POINTER(KernelDesc), VP, I64, VP, C.POINTER(I64)]),
     "sdgp_kernel_assemble": (I32, [VP, C.POINTER(KernelDesc), VP, I64, VP, C.c_int, VP, VP, VP, I64,
@@ -197,6 +198,9 @@ class Context:
 
     def set_timing(self, on: bool):
         self._check(self.lib.sdgp_set_timing(self.h, 1 if on else 0))
+
+    def set_option(self, name: str, value: int):
+        self._check(self.lib.sdgp_set_option(self.h, name.encode(), int(value)))
 
     def num_hyper(self, desc) -> int:
         d = desc_of(desc)

@@ -16,6 +16,10 @@ void Ctx::release_all() {
     if (b.p) { (void)hipFree(b.p); b.p = nullptr; b.bytes = 0; }
   for (auto e : ev_pool) (void)hipEventDestroy(e);
   ev_pool.clear();
+  if (gstream) { (void)hipStreamDestroy(gstream); gstream = nullptr; }
+  for (auto& b : member_bufs)
+    if (b.p) { (void)hipFree(b.p); b.p = nullptr; b.bytes = 0; }
+  member_bufs.clear();
   ev_used = 0;
 }
 
@@ -306,10 +310,16 @@ sdgp_status sdgp_lml_grad_batched(sdgp_ctx* ctx, const sdgp_kernel_desc* desc, c
                                   double* lml_out, double* grad_out, int32_t* member_status, sdgp_info* info) {
   return guarded(ctx, [&] {
     require(desc && x && y && H && lml_out && grad_out && member_status, "NULL argument");
-    require(B >= 1, "B must be >= 1");
+    require(B >= 1 && B <= 65535, "B must be in 1..65535");
     const int64_t nh = sdgp_num_hyper(desc);
     require(nh > 0, "invalid kernel descriptor");
     check_estimator(est, n);
+    validate_shape(*desc, n);
+    const bool factored = est->operator_form == SDGP_OPERATOR_FACTORED;
+    const bool use_pc = est->precond == SDGP_PRECOND_LOWRANK;
+    if (factored || use_pc) require(desc->combine == SDGP_COMBINE_SUM, "preconditioner/factored form need SUM");
+    const int kind = est->kind == SDGP_PROBE_IDENTITY ? PK_IDENTITY : PK_RADEMACHER;
+    const int P = kind == PK_IDENTITY ? (int)n : est->probes;
     // shared ordering: the cell side must cover every member's core radius
     double rmax = 0.0;
     for (int m = 0; m < B; ++m) {
@@ -317,26 +327,131 @@ sdgp_status sdgp_lml_grad_batched(sdgp_ctx* ctx, const sdgp_kernel_desc* desc, c
       if (std::isfinite(r) && r > rmax) rmax = r;
     }
     require(rmax > 0.0, "no member has a valid core radius");
-    validate_shape(*desc, n);
+    PhaseTimer t0(ctx);
     Sorted s = order_points(ctx, x, n, desc->dim, rmax);
     double* ys = ctx->get<double>(S_YS, n);
     gather_vector(ctx, s, y, ys);
+    // assemble every valid member into storage of its own
+    struct Member {
+      int idx;
+      KParams kp;
+      Bumps b;
+      Csr A;
+      Precond pc;
+      int64_t candidates;
+    };
+    std::vector<Member> mem;
+    ctx->member_bufs.resize(B);
+    const int n1 = desc->n1;
+    const int64_t np = (int64_t)n1 * desc->n2 * (3 + desc->dim);
     for (int m = 0; m < B; ++m) {
       const double* hm = H + (int64_t)m * nh;
-      sdgp_info* im = info ? info + m : nullptr;
-      if (im) std::memset(im, 0, sizeof(*im));
+      if (info) std::memset(info + m, 0, sizeof(sdgp_info));
+      lml_out[m] = NAN;
+      for (int64_t k = 0; k < nh; ++k) grad_out[(int64_t)m * nh + k] = NAN;
       try {
         validate(*desc, hm, n);
-        PhaseTimer t(ctx);
-        member_status[m] = evaluate(ctx, s, ys, *desc, hm, *est, lml_out + m, grad_out + (int64_t)m * nh, im, t);
+        Assembled as = assemble_all(ctx, s, *desc, hm, true, nullptr, factored);
+        Precond pc;
+        if (use_pc) {
+          pc = lowrank_precond(ctx, s, as.kp, as.b);
+          pc.lowrank_op = factored ? 1 : 0;
+        }
+        // member-owned copies (the context slots are reused by the next member)
+        const size_t szs[7] = {(size_t)(n + 1) * 8, (size_t)as.A.nnz * 4, (size_t)as.A.nnz * 8,
+                               (size_t)n * (n1 > 0 ? n1 : 1) * 8, (size_t)n * 8, (size_t)(np > 0 ? np : 1) * 8,
+                               (size_t)(n1 > 0 ? n1 * n1 : 1) * 8};
+        size_t off[8] = {0};
+        for (int q = 0; q < 7; ++q) off[q + 1] = off[q] + (szs[q] + 255) / 256 * 256;
+        DevBuf& db = ctx->member_bufs[m];
+        if (db.bytes < off[7]) {
+          if (db.p) SDGP_HIP(hipFree(db.p));
+          db.p = nullptr;
+          db.bytes = 0;
+          SDGP_HIP(hipMalloc(&db.p, off[7]));
+          db.bytes = off[7];
+        }
+        char* base = static_cast<char*>(db.p);
+        const void* src[7] = {as.A.row_ptr, as.A.col, as.A.val, as.b.F, as.b.M, as.b.bp,
+                              pc.Sinv ? (const void*)pc.Sinv : nullptr};
+        for (int q = 0; q < 7; ++q)
+          if (src[q] && szs[q] > 0)
+            SDGP_HIP(hipMemcpyAsync(base + off[q], src[q], szs[q], hipMemcpyDeviceToDevice, ctx->stream));
+        Member mb;
+        mb.idx = m;
+        mb.kp = as.kp;
+        mb.A = as.A;
+        mb.A.row_ptr = reinterpret_cast<int64_t*>(base + off[0]);
+        mb.A.col = reinterpret_cast<int32_t*>(base + off[1]);
+        mb.A.val = reinterpret_cast<double*>(base + off[2]);
+        mb.b.F = reinterpret_cast<double*>(base + off[3]);
+        mb.b.M = reinterpret_cast<uint64_t*>(base + off[4]);
+        mb.b.bp = reinterpret_cast<double*>(base + off[5]);
+        mb.pc = pc;
+        mb.pc.F = mb.b.F;
+        if (pc.Sinv) mb.pc.Sinv = reinterpret_cast<double*>(base + off[6]);
+        mb.candidates = as.candidates;
+        mem.push_back(mb);
+        member_status[m] = SDGP_OK;
+      } catch (const Error& e) {
+        member_status[m] = e.code;
+        if (e.code == SDGP_ERR_HIP || e.code == SDGP_ERR_OOM) throw;
+      }
+    }
+    if (mem.empty()) return;
+    // one batched (preconditioned) CG for every valid member
+    std::vector<CgMember> cm(mem.size());
+    for (size_t q = 0; q < mem.size(); ++q) {
+      cm[q].A = mem[q].A;
+      cm[q].pc = use_pc ? &mem[q].pc : nullptr;
+    }
+    std::vector<CgResult> res = block_cg_multi(ctx, cm, s, ys, kind, P, est->seed, est->cg_rtol, est->cg_max_iter,
+                                               nullptr, 0, true, ctx->use_graph);
+    for (size_t q = 0; q < mem.size(); ++q) {
+      const Member& mb = mem[q];
+      const int m = mb.idx;
+      const double* hm = H + (int64_t)m * nh;
+      try {
+        const CgResult& cg = res[q];
+        if (cg.not_spd) throw Error(SDGP_ERR_NOT_SPD, "CG met p^T A p <= 0");
+        const double yKy = dot_device(ctx, ys, 1, cg.X, cg.R, s.n);
+        double logdet = 0.0, se = 0.0, rmin = 0.0, rmax2 = 0.0;
+        slq_from_cg(ctx, cg, kind, P, s.n, est->lanczos_steps, &logdet, &se, &rmin, &rmax2);
+        lml_out[m] = -0.5 * yKy - 0.5 * logdet;
+        adjoint_gradient(ctx, s, mb.kp, mb.b, mb.A, cg, kind, P, est->seed, hm, grad_out + (int64_t)m * nh,
+                         factored);
+        if (info) {
+          sdgp_info& I = info[m];
+          I.nnz = mb.A.nnz;
+          I.candidates = mb.candidates;
+          I.cg_iters = cg.iters;
+          I.cg_iters_y = cg.iters_y;
+          I.cg_relres_max = cg.relres_max;
+          I.yKy = yKy;
+          I.logdet = logdet;
+          I.logdet_stderr = se;
+          I.ritz_min = rmin;
+          I.ritz_max = rmax2;
+        }
+        member_status[m] = cg.converged ? SDGP_OK : SDGP_ERR_NOT_CONVERGED;
       } catch (const Error& e) {
         member_status[m] = e.code;
         lml_out[m] = NAN;
         for (int64_t k = 0; k < nh; ++k) grad_out[(int64_t)m * nh + k] = NAN;
-        if (e.code == SDGP_ERR_HIP) throw;
+        if (e.code == SDGP_ERR_HIP || e.code == SDGP_ERR_OOM) throw;
       }
     }
+    (void)t0;
   });
+}
+
+sdgp_status sdgp_set_option(sdgp_ctx* ctx, const char* name, int64_t value) {
+  if (!ctx || !name) return SDGP_ERR_INVALID_ARG;
+  const std::string k(name);
+  if (k == "timing") { ctx->timing = value != 0; return SDGP_OK; }
+  if (k == "graph") { ctx->use_graph = value != 0; return SDGP_OK; }
+  ctx->err = "unknown option '" + k + "'";
+  return SDGP_ERR_INVALID_ARG;
 }
 
 sdgp_status sdgp_posterior_mean_var(sdgp_ctx* ctx, const sdgp_kernel_desc* desc, const double* x,

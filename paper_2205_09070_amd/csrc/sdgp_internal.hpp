@@ -72,7 +72,7 @@ enum Slot {
   S_CG_X, S_CG_R, S_CG_P, S_CG_Q, S_CG_SCAL, S_CG_PART, S_CG_HIST_A, S_CG_HIST_B,
   S_CG_STATE, S_ZBITS, S_SLQ_WORK, S_SLQ_OUT, S_ADJ_ROW, S_ADJ_G, S_ADJ_PART,
   S_RED_PART, S_RED_OUT, S_X0S, S_MISC, S_POST, S_COUNTER,
-  S_CG_V, S_CG_PART2, S_CG_PARTG, S_CG_G, S_CG_GP, S_PC_PART, S_PC_SINV, S_LR_PART, S_LR_FX, S_LR_FV,
+  S_CG_V, S_CG_PART2, S_CG_ARGS, S_CG_PARTG, S_CG_G, S_CG_GP, S_PC_PART, S_PC_SINV, S_LR_PART, S_LR_FX, S_LR_FV,
   S_MORTON_KEYS, S_MORTON_KEYS2, S_MORTON_IDS, S_MORTON_ORDER, S_MORTON_SZ, S_MORTON_OFF, S_SCHED,
   S_QF, S_QM, S_KXX, S_QIV_CNT, S_QIV_PTR, S_QIV, S_QROW_NNZ, S_QROW_PTR, S_QCOL, S_QVAL,
   S_NUM
@@ -88,6 +88,13 @@ struct Ctx {
   size_t ev_used = 0;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> spmm_events;
   int cu_count = 256;
+  bool use_graph = false;        // replay captured CG iterations (hipGraph)
+  std::vector<DevBuf> member_bufs;  // per-member storage of the population path
+  hipStream_t gstream = nullptr; // private default-priority stream for graph capture
+  hipStream_t graph_stream() {
+    if (!gstream) SDGP_HIP(hipStreamCreateWithFlags(&gstream, hipStreamNonBlocking));
+    return gstream;
+  }
 
   template <class T>
   T* get(Slot s, size_t count) {
@@ -221,6 +228,16 @@ CgResult block_cg(Ctx* c, const Csr& A, const Sorted& s, const double* ys,
                   int kind, int P, uint64_t seed, double rtol, int max_iter,
                   const double* dense_rhs, int dense_R, const Precond* pc,
                   bool keep_v, PhaseTimer* t);
+// All members (own matrix and preconditioner, shared points, probes and
+// options) advance together: one launch per kernel with grid z = member.
+struct CgMember {
+  Csr A;
+  const Precond* pc = nullptr;
+};
+std::vector<CgResult> block_cg_multi(Ctx* c, const std::vector<CgMember>& mem, const Sorted& s,
+                                     const double* ys, int kind, int P, uint64_t seed, double rtol,
+                                     int max_iter, const double* dense_rhs, int dense_R, bool keep_v,
+                                     bool use_graph);
 Precond lowrank_precond(Ctx* c, const Sorted& s, const KParams& kp, const Bumps& b);
 void spmm(Ctx* c, const Csr& A, const double* X, int R, double* Y);
 // Randomised Taylor-series log-det (Boutsidis et al. 2017) on A.

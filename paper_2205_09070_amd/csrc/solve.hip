@@ -141,6 +141,7 @@ struct CgState {
   int32_t* iters;   // [R]
   int32_t* done;    // [1] executed iterations once every column stopped
   int32_t* not_spd; // [1]
+  int32_t* it;      // [1] iteration counter (advanced by k_cg_check)
   double* hist_a;   // [max_iter][R]
   double* hist_b;   // [max_iter][R]
 };
@@ -203,6 +204,7 @@ struct CgArgs {
   double* gp;          // [n1][R] F^T p (lowrank_op)
   double inv_c, sqrt_c;
   int nb;
+  int max_iter;
   CgState st;
   double rtol2;
 };
@@ -276,8 +278,9 @@ __device__ __forceinline__ double apply_prec(const CgArgs& A, int64_t a, double 
 // Q = A P (with the factored operator: Q = K_core P, and F^T P partials),
 // partial p.q per column.
 template <int NI>
-__global__ __launch_bounds__(kCgBlock) void k_cg_spmm(CgArgs A) {
-  if (*A.st.done) return;
+__global__ __launch_bounds__(kCgBlock) void k_cg_spmm(const CgArgs* __restrict__ AA) {
+  const CgArgs& A = AA[blockIdx.z];
+  if (*A.st.done || *A.st.it >= A.max_iter) return;
   __shared__ double scratch[kCgBlock];
   __shared__ double gsh[NI > 0 ? 4 * kCgBlock : 1];
   const int lane = lane_id();
@@ -309,8 +312,10 @@ __global__ __launch_bounds__(kCgBlock) void k_cg_spmm(CgArgs A) {
 }
 
 // out[i][r] = sum_b partg[b][i][r] (fixed order); grid (n1, chunks).
-__global__ __launch_bounds__(kCgBlock) void k_cg_reduce_g(CgArgs A, double* __restrict__ out) {
-  if (*A.st.done) return;
+__global__ __launch_bounds__(kCgBlock) void k_cg_reduce_g(const CgArgs* __restrict__ AA, int which) {
+  const CgArgs& A = AA[blockIdx.z];
+  if (*A.st.done || *A.st.it >= A.max_iter) return;
+  double* __restrict__ out = which == 0 ? A.gp : A.g;
   __shared__ double scratch[kCgBlock];
   const int i = blockIdx.x;
   const int t = threadIdx.x;
@@ -357,8 +362,11 @@ __device__ __forceinline__ void xr_row(const CgArgs& A, int64_t a, int rc, doubl
 // With the factored operator p.A p = p.(K_core p) + |F^T p|^2 and
 // A p = K_core p + F (F^T p) is completed here on the fly.
 template <int NI>
-__global__ __launch_bounds__(kCgBlock) void k_cg_update_xr(CgArgs A, int it) {
+__global__ __launch_bounds__(kCgBlock) void k_cg_update_xr(const CgArgs* __restrict__ AA) {
+  const CgArgs& A = AA[blockIdx.z];
   if (*A.st.done) return;
+  const int it = *A.st.it;
+  if (it >= A.max_iter) return;
   __shared__ double scratch[kCgBlock];
   __shared__ double pAp[kWave];
   __shared__ double gsh[NI > 0 ? 4 * kCgBlock : 1];
@@ -418,8 +426,11 @@ __global__ __launch_bounds__(kCgBlock) void k_cg_update_xr(CgArgs A, int it) {
 // z = M^{-1} r formed on the fly (r.z_new = (r.r - g.u)/c, g = F^T r,
 // u = (cI + F^T F)^{-1} g, so no extra pass is needed).
 template <int NI>
-__global__ __launch_bounds__(kCgBlock) void k_cg_update_p(CgArgs A, int it) {
+__global__ __launch_bounds__(kCgBlock) void k_cg_update_p(const CgArgs* __restrict__ AA) {
+  const CgArgs& A = AA[blockIdx.z];
   if (*A.st.done) return;
+  const int it = *A.st.it;
+  if (it >= A.max_iter) return;
   __shared__ double scratch[kCgBlock];
   __shared__ double rrn[kWave];
   __shared__ double gu[kWave];
@@ -476,8 +487,11 @@ __global__ __launch_bounds__(kCgBlock) void k_cg_update_p(CgArgs A, int it) {
 
 // Records the executed iteration count in done when no column is active
 // (one block, after update_p).
-__global__ void k_cg_check(CgArgs A, int it) {
+__global__ void k_cg_check(const CgArgs* __restrict__ AA) {
+  const CgArgs& A = AA[blockIdx.z];
   if (*A.st.done) return;
+  const int it = *A.st.it;
+  if (it >= A.max_iter) return;
   const int nxt = (it & 1) ^ 1;
   __shared__ int left;
   if (threadIdx.x == 0) left = 0;
@@ -486,14 +500,19 @@ __global__ void k_cg_check(CgArgs A, int it) {
   for (int r = threadIdx.x; r < A.R; r += blockDim.x) mine |= A.st.act[nxt * A.R + r];
   if (mine) atomicOr(&left, 1);
   __syncthreads();
-  if (threadIdx.x == 0 && !left) *A.st.done = it + 1;
+  if (threadIdx.x == 0) {
+    if (!left) *A.st.done = it + 1;
+    *A.st.it = it + 1;
+  }
 }
 
 // Right-hand sides and x = 0, r = b.  Probe p (column 1+p) is the Rademacher
 // vector w_p of caller row perm[a], or with the preconditioner
 // sqrt(c) w_p + F v_p (v_p: n1 Rademacher signs), whose covariance is M.
-__global__ void k_cg_init(CgArgs A, const double* __restrict__ ys, const int32_t* __restrict__ perm,
-                          int kind, uint64_t seed, const double* __restrict__ dense) {
+__global__ void k_cg_init(const CgArgs* __restrict__ AA, const double* __restrict__ ys,
+                          const int32_t* __restrict__ perm, int kind, uint64_t seed,
+                          const double* __restrict__ dense) {
+  const CgArgs& A = AA[blockIdx.z];
   const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int64_t tot = A.n * (int64_t)A.R;
   if (idx >= tot) return;
@@ -525,7 +544,8 @@ __global__ void k_cg_init(CgArgs A, const double* __restrict__ ys, const int32_t
 
 // Partials of b.b and F^T b.
 template <int NI>
-__global__ __launch_bounds__(kCgBlock) void k_cg_norm_part(CgArgs A) {
+__global__ __launch_bounds__(kCgBlock) void k_cg_norm_part(const CgArgs* __restrict__ AA) {
+  const CgArgs& A = AA[blockIdx.z];
   __shared__ double scratch[kCgBlock];
   __shared__ double gsh[NI > 0 ? 4 * kCgBlock : 1];
   const int rc = blockIdx.y * kWave + lane_id();
@@ -553,7 +573,8 @@ __global__ __launch_bounds__(kCgBlock) void k_cg_norm_part(CgArgs A) {
 // Initial state: p = z0 = M^{-1} b (b when unpreconditioned), V = z0,
 // rz0 = b.z0, bnorm2 = b.b.
 template <int NI>
-__global__ __launch_bounds__(kCgBlock) void k_cg_init_fin(CgArgs A) {
+__global__ __launch_bounds__(kCgBlock) void k_cg_init_fin(const CgArgs* __restrict__ AA) {
+  const CgArgs& A = AA[blockIdx.z];
   __shared__ double scratch[kCgBlock];
   __shared__ double nrm[kWave];
   __shared__ double gu[kWave];
@@ -835,43 +856,56 @@ __global__ __launch_bounds__(256) void k_gram(const double* __restrict__ F, int6
   }
 }
 
+// One CG iteration for every member (grid z = member).
 template <int NI>
-void launch_cg_iteration(Ctx* c, const CgArgs& A, dim3 grid, int chunks, int it) {
+void launch_cg_iteration(hipStream_t st, const CgArgs* dA, const CgArgs& h0, dim3 grid, int chunks, int B,
+                         Ctx* c) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (c->timing) { e0 = c->event(); SDGP_HIP(hipEventRecord(e0, c->stream)); }
-  k_cg_spmm<NI><<<grid, kCgBlock, 0, c->stream>>>(A);
+  if (c != nullptr && c->timing) { e0 = c->event(); SDGP_HIP(hipEventRecord(e0, st)); }
+  k_cg_spmm<NI><<<grid, kCgBlock, 0, st>>>(dA);
   SDGP_CHECK_LAUNCH();
-  if (c->timing) {
+  if (c != nullptr && c->timing) {
     e1 = c->event();
-    SDGP_HIP(hipEventRecord(e1, c->stream));
+    SDGP_HIP(hipEventRecord(e1, st));
     c->spmm_events.push_back({e0, e1});
   }
-  if (NI > 0 && A.lowrank_op) {
-    k_cg_reduce_g<<<dim3(A.n1, chunks), kCgBlock, 0, c->stream>>>(A, A.gp);
+  if (NI > 0 && h0.lowrank_op) {
+    k_cg_reduce_g<<<dim3(h0.n1, chunks, B), kCgBlock, 0, st>>>(dA, 0);
     SDGP_CHECK_LAUNCH();
   }
-  k_cg_update_xr<NI><<<grid, kCgBlock, 0, c->stream>>>(A, it);
+  k_cg_update_xr<NI><<<grid, kCgBlock, 0, st>>>(dA);
   SDGP_CHECK_LAUNCH();
-  if (NI > 0 && A.use_pc) {
-    k_cg_reduce_g<<<dim3(A.n1, chunks), kCgBlock, 0, c->stream>>>(A, A.g);
+  if (NI > 0 && h0.use_pc) {
+    k_cg_reduce_g<<<dim3(h0.n1, chunks, B), kCgBlock, 0, st>>>(dA, 1);
     SDGP_CHECK_LAUNCH();
   }
-  k_cg_update_p<NI><<<grid, kCgBlock, 0, c->stream>>>(A, it);
+  k_cg_update_p<NI><<<grid, kCgBlock, 0, st>>>(dA);
   SDGP_CHECK_LAUNCH();
-  k_cg_check<<<1, 256, 0, c->stream>>>(A, it);
+  k_cg_check<<<dim3(1, 1, B), 256, 0, st>>>(dA);
   SDGP_CHECK_LAUNCH();
 }
 
 template <int NI>
-void launch_cg_init(Ctx* c, const CgArgs& A, dim3 grid, int chunks) {
-  k_cg_norm_part<NI><<<grid, kCgBlock, 0, c->stream>>>(A);
+void launch_cg_init(hipStream_t st, const CgArgs* dA, const CgArgs& h0, dim3 grid, int chunks, int B) {
+  k_cg_norm_part<NI><<<grid, kCgBlock, 0, st>>>(dA);
   SDGP_CHECK_LAUNCH();
-  if (NI > 0 && A.use_pc) {
-    k_cg_reduce_g<<<dim3(A.n1, chunks), kCgBlock, 0, c->stream>>>(A, A.g);
+  if (NI > 0 && h0.use_pc) {
+    k_cg_reduce_g<<<dim3(h0.n1, chunks, B), kCgBlock, 0, st>>>(dA, 1);
     SDGP_CHECK_LAUNCH();
   }
-  k_cg_init_fin<NI><<<grid, kCgBlock, 0, c->stream>>>(A);
+  k_cg_init_fin<NI><<<grid, kCgBlock, 0, st>>>(dA);
   SDGP_CHECK_LAUNCH();
+}
+
+void cg_iteration(int NI, hipStream_t st, const CgArgs* dA, const CgArgs& h0, dim3 grid, int chunks, int B,
+                  Ctx* c) {
+  switch (NI) {
+    case 0: launch_cg_iteration<0>(st, dA, h0, grid, chunks, B, c); break;
+    case 8: launch_cg_iteration<8>(st, dA, h0, grid, chunks, B, c); break;
+    case 16: launch_cg_iteration<16>(st, dA, h0, grid, chunks, B, c); break;
+    case 32: launch_cg_iteration<32>(st, dA, h0, grid, chunks, B, c); break;
+    default: launch_cg_iteration<64>(st, dA, h0, grid, chunks, B, c); break;
+  }
 }
 
 }  // namespace
@@ -938,10 +972,12 @@ Precond lowrank_precond(Ctx* c, const Sorted& s, const KParams& kp, const Bumps&
   return pc;
 }
 
-CgResult block_cg(Ctx* c, const Csr& Am, const Sorted& s, const double* ys, int kind, int P, uint64_t seed,
-                  double rtol, int max_iter, const double* dense_rhs, int dense_R, const Precond* pc,
-                  bool keep_v, PhaseTimer* t) {
-  const int64_t n = Am.n;
+std::vector<CgResult> block_cg_multi(Ctx* c, const std::vector<CgMember>& mem, const Sorted& s, const double* ys,
+                                     int kind, int P, uint64_t seed, double rtol, int max_iter,
+                                     const double* dense_rhs, int dense_R, bool keep_v, bool use_graph) {
+  const int B = (int)mem.size();
+  require(B >= 1 && B <= 65535, "1..65535 members");
+  const int64_t n = s.n;
   int R;
   if (kind == PK_DENSE) R = dense_R;
   else if (kind == PK_IDENTITY) R = (int)(1 + n);
@@ -950,126 +986,213 @@ CgResult block_cg(Ctx* c, const Csr& Am, const Sorted& s, const double* ys, int 
   require(R >= 1, "no right-hand sides");
   require(max_iter >= 1, "cg_max_iter must be >= 1");
   require(rtol > 0.0 && std::isfinite(rtol), "cg_rtol must be > 0");
-  const bool use_pc = pc != nullptr && pc->n1 > 0 && pc->apply;
-  const bool use_lr = pc != nullptr && pc->n1 > 0 && pc->lowrank_op;
-  const int n1 = (use_pc || use_lr) ? pc->n1 : 0;
+  require(kind != PK_DENSE || B == 1, "dense right-hand sides take one member");
+  const Precond* pc0 = mem[0].pc;
+  const bool use_pc = pc0 != nullptr && pc0->n1 > 0 && pc0->apply;
+  const bool use_lr = pc0 != nullptr && pc0->n1 > 0 && pc0->lowrank_op;
+  const int n1 = (use_pc || use_lr) ? pc0->n1 : 0;
+  for (int m = 0; m < B; ++m) {
+    const Precond* p = mem[m].pc;
+    const bool up = p != nullptr && p->n1 > 0 && p->apply;
+    const bool ul = p != nullptr && p->n1 > 0 && p->lowrank_op;
+    require(up == use_pc && ul == use_lr && (!(up || ul) || p->n1 == n1), "members must share the solver form");
+    require(mem[m].A.n == n, "members must share the point set");
+  }
   const int NI = n1 == 0 ? 0 : (n1 <= 8 ? 8 : (n1 <= 16 ? 16 : (n1 <= 32 ? 32 : 64)));
   const size_t NR = (size_t)n * R;
-  CgArgs A;
-  A.n = n;
-  A.R = R;
-  A.row_ptr = Am.row_ptr;
-  A.col = Am.col;
-  A.val = Am.val;
-  A.X = c->get<double>(S_CG_X, NR);
-  A.Rr = c->get<double>(S_CG_R, NR);
-  A.P = c->get<double>(S_CG_P, NR);
-  A.Q = c->get<double>(S_CG_Q, NR);
-  A.V = (use_pc && keep_v) ? c->get<double>(S_CG_V, NR) : nullptr;
-  A.sched = s.sched;
   const int nb = cg_nb(n, R);
   const int chunks = (R + kWave - 1) / kWave;
-  A.nb = nb;
-  A.part = c->get<double>(S_CG_PART, (size_t)nb * R);
-  A.part2 = c->get<double>(S_CG_PART2, (size_t)nb * R);
-  A.n1 = n1;
-  A.use_pc = use_pc ? 1 : 0;
-  A.lowrank_op = use_lr ? 1 : 0;
-  A.F = n1 > 0 ? pc->F : nullptr;
-  A.Sinv = use_pc ? pc->Sinv : nullptr;
-  A.inv_c = use_pc ? 1.0 / pc->c : 1.0;
-  A.sqrt_c = use_pc ? std::sqrt(pc->c) : 1.0;
-  A.partg = n1 > 0 ? c->get<double>(S_CG_PARTG, (size_t)nb * n1 * R) : nullptr;
-  A.g = use_pc ? c->get<double>(S_CG_G, (size_t)n1 * R) : nullptr;
-  A.gp = use_lr ? c->get<double>(S_CG_GP, (size_t)n1 * R) : nullptr;
-  // state block: doubles rz[2R], rz0[R], bnorm2[R], rr_last[R];
-  // ints act[2R], failed[R], iters[R], done, not_spd
-  const size_t bytes = (5 * (size_t)R) * 8 + (4 * (size_t)R + 2) * 4 + 64;
-  char* sb = c->get<char>(S_CG_STATE, bytes);
-  A.st.rz = reinterpret_cast<double*>(sb);
-  A.st.rz0 = A.st.rz + 2 * (size_t)R;
-  A.st.bnorm2 = A.st.rz0 + R;
-  A.st.rr_last = A.st.bnorm2 + R;
-  int32_t* ib = reinterpret_cast<int32_t*>(A.st.rr_last + R);
-  A.st.act = ib;
-  A.st.failed = ib + 2 * (size_t)R;
-  A.st.iters = A.st.failed + R;
-  A.st.done = A.st.iters + R;
-  A.st.not_spd = A.st.done + 1;
-  A.st.hist_a = c->get<double>(S_CG_HIST_A, (size_t)max_iter * R);
-  A.st.hist_b = c->get<double>(S_CG_HIST_B, (size_t)max_iter * R);
-  A.rtol2 = rtol * rtol;
-  SDGP_HIP(hipMemsetAsync(A.st.done, 0, 2 * sizeof(int32_t), c->stream));
+  double* X = c->get<double>(S_CG_X, NR * B);
+  double* Rr = c->get<double>(S_CG_R, NR * B);
+  double* Pp = c->get<double>(S_CG_P, NR * B);
+  double* Q = c->get<double>(S_CG_Q, NR * B);
+  double* V = (use_pc && keep_v) ? c->get<double>(S_CG_V, NR * B) : nullptr;
+  double* part = c->get<double>(S_CG_PART, (size_t)nb * R * B);
+  double* part2 = c->get<double>(S_CG_PART2, (size_t)nb * R * B);
+  double* partg = n1 > 0 ? c->get<double>(S_CG_PARTG, (size_t)nb * n1 * R * B) : nullptr;
+  double* g = use_pc ? c->get<double>(S_CG_G, (size_t)n1 * R * B) : nullptr;
+  double* gp = use_lr ? c->get<double>(S_CG_GP, (size_t)n1 * R * B) : nullptr;
+  double* ha = c->get<double>(S_CG_HIST_A, (size_t)max_iter * R * B);
+  double* hb = c->get<double>(S_CG_HIST_B, (size_t)max_iter * R * B);
+  // per-member state block: doubles rz[2R], rz0[R], bnorm2[R], rr_last[R];
+  // ints act[2R], failed[R], iters[R], done, not_spd, it
+  const size_t sbytes = ((5 * (size_t)R) * 8 + (4 * (size_t)R + 3) * 4 + 255) / 256 * 256;
+  char* sb = c->get<char>(S_CG_STATE, sbytes * B);
+  SDGP_HIP(hipMemsetAsync(sb, 0, sbytes * B, c->stream));
+  std::vector<CgArgs> hA(B);
+  for (int m = 0; m < B; ++m) {
+    CgArgs& A = hA[m];
+    const Csr& Am = mem[m].A;
+    const Precond* p = mem[m].pc;
+    A.n = n;
+    A.R = R;
+    A.row_ptr = Am.row_ptr;
+    A.col = Am.col;
+    A.val = Am.val;
+    A.X = X + m * NR;
+    A.Rr = Rr + m * NR;
+    A.P = Pp + m * NR;
+    A.Q = Q + m * NR;
+    A.V = V ? V + m * NR : nullptr;
+    A.sched = s.sched;
+    A.part = part + (size_t)m * nb * R;
+    A.part2 = part2 + (size_t)m * nb * R;
+    A.partg = partg ? partg + (size_t)m * nb * n1 * R : nullptr;
+    A.g = g ? g + (size_t)m * n1 * R : nullptr;
+    A.gp = gp ? gp + (size_t)m * n1 * R : nullptr;
+    A.n1 = n1;
+    A.use_pc = use_pc ? 1 : 0;
+    A.lowrank_op = use_lr ? 1 : 0;
+    A.F = n1 > 0 ? p->F : nullptr;
+    A.Sinv = use_pc ? p->Sinv : nullptr;
+    A.inv_c = use_pc ? 1.0 / p->c : 1.0;
+    A.sqrt_c = use_pc ? std::sqrt(p->c) : 1.0;
+    A.nb = nb;
+    A.max_iter = max_iter;
+    A.rtol2 = rtol * rtol;
+    char* mb = sb + sbytes * m;
+    A.st.rz = reinterpret_cast<double*>(mb);
+    A.st.rz0 = A.st.rz + 2 * (size_t)R;
+    A.st.bnorm2 = A.st.rz0 + R;
+    A.st.rr_last = A.st.bnorm2 + R;
+    int32_t* ib = reinterpret_cast<int32_t*>(A.st.rr_last + R);
+    A.st.act = ib;
+    A.st.failed = ib + 2 * (size_t)R;
+    A.st.iters = A.st.failed + R;
+    A.st.done = A.st.iters + R;
+    A.st.not_spd = A.st.done + 1;
+    A.st.it = A.st.not_spd + 1;
+    A.st.hist_a = ha + (size_t)m * max_iter * R;
+    A.st.hist_b = hb + (size_t)m * max_iter * R;
+  }
+  CgArgs* dA = c->get<CgArgs>(S_CG_ARGS, B);
+  SDGP_HIP(hipMemcpyAsync(dA, hA.data(), B * sizeof(CgArgs), hipMemcpyHostToDevice, c->stream));
   {
     const int64_t tot = (int64_t)NR;
-    const int64_t g = (tot + 255) / 256;
-    require(g < 0x7fffffff, "n*R too large");
-    k_cg_init<<<(unsigned)g, 256, 0, c->stream>>>(A, ys, s.perm, kind, seed, dense_rhs);
+    const int64_t gx = (tot + 255) / 256;
+    require(gx < 0x7fffffff, "n*R too large");
+    k_cg_init<<<dim3((unsigned)gx, 1, B), 256, 0, c->stream>>>(dA, ys, s.perm, kind, seed, dense_rhs);
     SDGP_CHECK_LAUNCH();
   }
-  dim3 grid(nb, chunks);
+  dim3 grid(nb, chunks, B);
   switch (NI) {
-    case 0: launch_cg_init<0>(c, A, grid, chunks); break;
-    case 8: launch_cg_init<8>(c, A, grid, chunks); break;
-    case 16: launch_cg_init<16>(c, A, grid, chunks); break;
-    case 32: launch_cg_init<32>(c, A, grid, chunks); break;
-    default: launch_cg_init<64>(c, A, grid, chunks); break;
+    case 0: launch_cg_init<0>(c->stream, dA, hA[0], grid, chunks, B); break;
+    case 8: launch_cg_init<8>(c->stream, dA, hA[0], grid, chunks, B); break;
+    case 16: launch_cg_init<16>(c->stream, dA, hA[0], grid, chunks, B); break;
+    case 32: launch_cg_init<32>(c->stream, dA, hA[0], grid, chunks, B); break;
+    default: launch_cg_init<64>(c->stream, dA, hA[0], grid, chunks, B); break;
   }
-  // iterate; poll the done flag now and then
-  int it = 0;
-  int check = 8;
-  int32_t flags[2] = {0, 0};
+  // iterate; poll the per-member flags now and then
+  std::vector<int32_t> flags((size_t)3 * B);
+  auto poll = [&](hipStream_t st) -> bool {
+    for (int m = 0; m < B; ++m)
+      SDGP_HIP(hipMemcpyAsync(&flags[3 * m], hA[m].st.done, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    SDGP_HIP(hipStreamSynchronize(st));
+    for (int m = 0; m < B; ++m)
+      if (flags[3 * m] == 0 && flags[3 * m + 2] < max_iter) return false;
+    return true;
+  };
   c->spmm_events.clear();
-  while (it < max_iter) {
-    const int upto = std::min(max_iter, it + check);
-    for (; it < upto; ++it) {
-      switch (NI) {
-        case 0: launch_cg_iteration<0>(c, A, grid, chunks, it); break;
-        case 8: launch_cg_iteration<8>(c, A, grid, chunks, it); break;
-        case 16: launch_cg_iteration<16>(c, A, grid, chunks, it); break;
-        case 32: launch_cg_iteration<32>(c, A, grid, chunks, it); break;
-        default: launch_cg_iteration<64>(c, A, grid, chunks, it); break;
-      }
+  int launched = 0;
+  if (use_graph) {
+    // capture k iterations once and replay them: the iteration counters live
+    // on the device, so every replay advances the solve; kernels of members
+    // that are done, or past max_iter, return at once
+    const int k = 8;
+    hipStream_t gs = c->graph_stream();
+    hipEvent_t ready = c->event();
+    SDGP_HIP(hipEventRecord(ready, c->stream));
+    SDGP_HIP(hipStreamWaitEvent(gs, ready, 0));
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    SDGP_HIP(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
+    for (int q = 0; q < k; ++q) cg_iteration(NI, gs, dA, hA[0], grid, chunks, B, nullptr);
+    SDGP_HIP(hipStreamEndCapture(gs, &graph));
+    hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (ie != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      throw Error(SDGP_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
     }
-    SDGP_HIP(hipMemcpyAsync(flags, A.st.done, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
-    SDGP_HIP(hipStreamSynchronize(c->stream));
-    if (flags[0] || flags[1]) break;
-    check = std::min(check * 2, 64);
+    int every = 1;
+    bool fin = false;
+    while (!fin && launched < max_iter) {
+      for (int q = 0; q < every && launched < max_iter; ++q) {
+        SDGP_HIP(hipGraphLaunch(exec, gs));
+        launched += k;
+      }
+      fin = poll(gs);
+      every = std::min(every * 2, 8);
+    }
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    hipEvent_t back = c->event();
+    SDGP_HIP(hipEventRecord(back, gs));
+    SDGP_HIP(hipStreamWaitEvent(c->stream, back, 0));
+  } else {
+    int check = 8;
+    bool fin = false;
+    while (!fin && launched < max_iter) {
+      const int upto = std::min(max_iter, launched + check);
+      for (; launched < upto; ++launched) cg_iteration(NI, c->stream, dA, hA[0], grid, chunks, B, c);
+      fin = poll(c->stream);
+      check = std::min(check * 2, 64);
+    }
   }
-  CgResult res;
-  res.R = R;
-  res.X = A.X;
-  res.V = A.V;
-  res.rz0 = A.st.rz0;
-  res.hist_a = A.st.hist_a;
-  res.hist_b = A.st.hist_b;
-  res.col_iters = A.st.iters;
-  res.not_spd = flags[1] != 0;
-  res.logdetM = use_pc ? pc->logdetM : 0.0;
-  std::vector<int32_t> its(R);
-  std::vector<double> bn(R);
-  std::vector<int32_t> actv(2 * (size_t)R);
-  SDGP_HIP(hipMemcpyAsync(its.data(), A.st.iters, R * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
-  SDGP_HIP(hipMemcpyAsync(bn.data(), A.st.bnorm2, R * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-  SDGP_HIP(hipMemcpyAsync(actv.data(), A.st.act, 2 * R * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+  // results
+  std::vector<CgResult> out(B);
+  std::vector<int32_t> its((size_t)R * B), actv((size_t)2 * R * B);
+  std::vector<double> bn((size_t)R * B), rl((size_t)R * B);
+  for (int m = 0; m < B; ++m) {
+    SDGP_HIP(hipMemcpyAsync(&its[(size_t)m * R], hA[m].st.iters, R * sizeof(int32_t), hipMemcpyDeviceToHost,
+                            c->stream));
+    SDGP_HIP(hipMemcpyAsync(&actv[(size_t)2 * m * R], hA[m].st.act, 2 * R * sizeof(int32_t),
+                            hipMemcpyDeviceToHost, c->stream));
+    SDGP_HIP(hipMemcpyAsync(&bn[(size_t)m * R], hA[m].st.bnorm2, R * sizeof(double), hipMemcpyDeviceToHost,
+                            c->stream));
+    SDGP_HIP(hipMemcpyAsync(&rl[(size_t)m * R], hA[m].st.rr_last, R * sizeof(double), hipMemcpyDeviceToHost,
+                            c->stream));
+    SDGP_HIP(hipMemcpyAsync(&flags[3 * m], hA[m].st.done, 3 * sizeof(int32_t), hipMemcpyDeviceToHost,
+                            c->stream));
+  }
   SDGP_HIP(hipStreamSynchronize(c->stream));
-  const int executed = flags[0] > 0 ? flags[0] : it;
-  const int lastpar = executed & 1;  // parity holding the latest state
-  bool conv = true;
-  for (int r = 0; r < R; ++r)
-    if (actv[lastpar * R + r]) conv = false;
-  // recursively updated residuals at each column's last iteration
-  std::vector<double> rl(R);
-  SDGP_HIP(hipMemcpyAsync(rl.data(), A.st.rr_last, R * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-  SDGP_HIP(hipStreamSynchronize(c->stream));
-  res.iters = executed;
-  res.iters_y = its[0];
-  res.relres_max = 0.0;
-  for (int r = 0; r < R; ++r)
-    if (bn[r] > 0.0) res.relres_max = std::max(res.relres_max, std::sqrt(rl[r] / bn[r]));
-  res.converged = conv && !res.not_spd;
+  for (int m = 0; m < B; ++m) {
+    CgResult& res = out[m];
+    const CgArgs& A = hA[m];
+    res.R = R;
+    res.X = A.X;
+    res.V = A.V;
+    res.rz0 = A.st.rz0;
+    res.hist_a = A.st.hist_a;
+    res.hist_b = A.st.hist_b;
+    res.col_iters = A.st.iters;
+    res.not_spd = flags[3 * m + 1] != 0;
+    res.logdetM = use_pc ? mem[m].pc->logdetM : 0.0;
+    const int executed = flags[3 * m] > 0 ? flags[3 * m] : flags[3 * m + 2];
+    const int lastpar = executed & 1;  // parity holding the latest state
+    bool conv = true;
+    for (int r = 0; r < R; ++r)
+      if (actv[(size_t)2 * m * R + lastpar * R + r]) conv = false;
+    res.iters = executed;
+    res.iters_y = its[(size_t)m * R];
+    res.relres_max = 0.0;
+    for (int r = 0; r < R; ++r) {
+      const double b2 = bn[(size_t)m * R + r];
+      if (b2 > 0.0) res.relres_max = std::max(res.relres_max, std::sqrt(rl[(size_t)m * R + r] / b2));
+    }
+    res.converged = conv && !res.not_spd;
+  }
+  return out;
+}
+
+CgResult block_cg(Ctx* c, const Csr& Am, const Sorted& s, const double* ys, int kind, int P, uint64_t seed,
+                  double rtol, int max_iter, const double* dense_rhs, int dense_R, const Precond* pc,
+                  bool keep_v, PhaseTimer* t) {
   (void)t;
-  return res;
+  std::vector<CgMember> mem(1);
+  mem[0].A = Am;
+  mem[0].pc = pc;
+  return block_cg_multi(c, mem, s, ys, kind, P, seed, rtol, max_iter, dense_rhs, dense_R, keep_v,
+                        c->use_graph)[0];
 }
 
 namespace {
