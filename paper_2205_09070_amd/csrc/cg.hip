@@ -1,0 +1,1224 @@
+// Block conjugate gradients on [y, z_1..z_P] (Section 2.5) for gfx950.
+//
+// Vector-block layout ("slab layout"): column 0 (y, or the first dense
+// column) is a plain vector of ny = round_up(n, 32) doubles; columns
+// 1..R-1 are packed in slabs of 32 columns, slab s being a row-major
+// [n][32] array at offset ny + s*n*32.  Slab columns past R-1 are padding
+// and stay zero.  A slab row is 256 bytes, i.e. two whole cache lines.
+//
+// SpMM (the hot loop): a 16-lane group handles one matrix row, lane j
+// holding slab columns 2j and 2j+1 (one 16-byte load per gathered
+// neighbour row), so a wavefront carries four rows at once.  The row's
+// (column, value) pairs are loaded 16 at a time, one per lane, and
+// broadcast inside each group of 16 lanes with a DPP row broadcast.
+// Column 0 is gathered lane-parallel: each lane multiplies its own entry's
+// value by y[col] and the 16 partial sums are reduced at the row's end.
+// Rows are visited in a Morton order of the cell grid, each XCD taking a
+// contiguous eighth of that order (workgroups are dealt to the 8 XCDs
+// round-robin), which keeps the gathered rows in the XCD's own L2.
+//
+// Reductions are deterministic: every block writes one partial per column
+// into part[column][block]; a small kernel sums each column's partials in
+// a fixed order.  No atomics take part in any sum.
+#include <algorithm>
+#include <cmath>
+#include <utility>
+#include <vector>
+
+#include "kernel_math.hpp"
+#include "sdgp_internal.hpp"
+
+namespace sdgp {
+
+namespace {
+
+constexpr int kT = 256;          // threads per block
+constexpr int kTile = 16;        // rows per block tile (4 waves x 4 groups of 16 lanes)
+constexpr int kSlab = 32;        // columns per slab
+constexpr int kMaxNbs = 32768;   // SpMM blocks
+constexpr int kMaxNbu = 2048;    // blocks of the streaming update kernels
+
+struct CgState {
+  double* rz;       // [2][R] parity buffers of r.z (r.r unpreconditioned)
+  double* rz0;      // [R] b^T M^{-1} b (b^T b unpreconditioned): SLQ weight
+  int32_t* act;     // [2][R] active flags
+  int32_t* failed;  // [R] p^T A p <= 0 met
+  double* bnorm2;   // [R]
+  double* rr_last;  // [R] |r|^2 at each column's last iteration
+  int32_t* iters;   // [R]
+  int32_t* done;    // [1] executed iterations once every column stopped
+  int32_t* not_spd; // [1]
+  int32_t* it;      // [1] iteration counter (advanced by k_cg_check)
+  double* hist_a;   // [max_iter][R]
+  double* hist_b;   // [max_iter][R]
+};
+
+struct CgArgs {
+  int64_t n, ny;
+  int R, ns;                  // columns, slabs
+  const int64_t* row_ptr;
+  const int32_t* col;
+  const double* val;
+  double *X, *Rr, *P, *Q, *V; // slab layout (V: M^{-1} b, may be null)
+  const int32_t* sched;       // SpMM row order (may be null)
+  const double* F;            // [n][n1] sorted bump values
+  const double* Sinv;         // [n1][n1] (c I + F^T F)^{-1}
+  int n1;
+  int use_pc;                 // z = M^{-1} r, M = c I + F F^T
+  int lowrank_op;             // operator K_core + F F^T (F F^T applied on the fly)
+  double inv_c, sqrt_c;
+  int nbs, nbu;               // blocks of the SpMM / update kernels
+  int max_iter;
+  double rtol2;
+  double* s_part;             // [R][nbs] p.(A p) partials of the SpMM
+  double* s_red;              // [R]
+  double* u_part;             // [(1+n1) R][nbu]: r.r, then F^T r (row R + i R + c)
+  double* u_red;              // [(1+n1) R]
+  double* p_part;             // [n1 R][nbu] F^T p (row i R + c)
+  double* p_red;              // [n1 R]
+  CgState st;
+};
+
+__device__ __forceinline__ bool stopped(const CgArgs& A) { return *A.st.done || *A.st.it >= A.max_iter; }
+
+// ------------------------------------------------------------ SpMM core
+template <int u>
+__device__ __forceinline__ int bcast16_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0x150 + u, 0xF, 0xF, false);  // row_newbcast:u
+}
+template <int u>
+__device__ __forceinline__ double bcast16_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = bcast16_i<u>((int)(b & 0xffffffffll));
+  const int hi = bcast16_i<u>((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <int H, int... us>
+__device__ __forceinline__ void gather8(int cj, double vj, const double* __restrict__ Xs, int64_t ld,
+                                        double& ax, double& ay, double& bx, double& by,
+                                        std::integer_sequence<int, us...>) {
+  double vv[8];
+  double2 xv[8];
+  ((vv[us] = bcast16_d<H + us>(vj),
+    xv[us] = *reinterpret_cast<const double2*>(Xs + (int64_t)(uint32_t)bcast16_i<H + us>(cj) * ld)), ...);
+#pragma unroll
+  for (int u = 0; u < 8; u += 2) {
+    ax += vv[u] * xv[u].x;
+    ay += vv[u] * xv[u].y;
+    bx += vv[u + 1] * xv[u + 1].x;
+    by += vv[u + 1] * xv[u + 1].y;
+  }
+}
+
+// Row dot products of one matrix row (entries k0..k1) with the two slab
+// columns of the calling lane: q = sum_k val[k] * Xs[col[k] * ld + {0, 1}],
+// Xs pointing at the lane's first column.  With kY, yacc also receives the
+// lane's share of sum_k val[k] * ycol[col[k]] (entries kb + j).  Every lane
+// of the wavefront must call this together (DPP broadcasts); ``self`` is a
+// valid row index used for the padding entries.
+template <bool kY, bool kSlabs = true>
+__device__ __forceinline__ void slab_row(int64_t k0, int64_t k1, int32_t self, const int32_t* __restrict__ col,
+                                         const double* __restrict__ val, const double* __restrict__ Xs,
+                                         int64_t ld, const double* __restrict__ ycol, double2& q, double& yacc) {
+  const int j = lane_id() & 15;
+  double ax = 0.0, ay = 0.0, bx = 0.0, by = 0.0;
+  for (int64_t kb = k0; __any(kb < k1); kb += 16) {
+    const int64_t k = kb + j;
+    const bool in = k < k1;
+    const int cj = in ? col[k] : self;
+    const double vj = in ? val[k] : 0.0;
+    if constexpr (kY) yacc += vj * ycol[cj];
+    if constexpr (kSlabs) {
+      gather8<0>(cj, vj, Xs, ld, ax, ay, bx, by, std::make_integer_sequence<int, 8>{});
+      gather8<8>(cj, vj, Xs, ld, ax, ay, bx, by, std::make_integer_sequence<int, 8>{});
+    }
+  }
+  q.x = ax + bx;
+  q.y = ay + by;
+}
+
+// Sum over the 16 lanes of a DPP row; lane 0 of the row holds the sum.
+__device__ __forceinline__ double row16_sum(double v) {
+  v += __shfl_xor(v, 8, 16);
+  v += __shfl_xor(v, 4, 16);
+  v += __shfl_xor(v, 2, 16);
+  v += __shfl_xor(v, 1, 16);
+  return v;
+}
+
+// Block sums of per-thread (2-column) values over the 16 row slots of a
+// tile: red[(w*4+g)*32 + col] in LDS, thread t < 32 adds in fixed order.
+__device__ __forceinline__ double tile_colsum(double* red, double v0, double v1) {
+  const int lane = lane_id(), g = lane >> 4, j = lane & 15, w = threadIdx.x >> 6;
+  __syncthreads();
+  red[(w * 4 + g) * kSlab + 2 * j] = v0;
+  red[(w * 4 + g) * kSlab + 2 * j + 1] = v1;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x < kSlab)
+    for (int q = 0; q < kTile; ++q) s += red[q * kSlab + threadIdx.x];
+  return s;
+}
+
+// Block sum of one value per thread (fixed order); valid in thread 0.
+__device__ __forceinline__ double block_sum(double* red, double v) {
+  __syncthreads();
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = kT / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  return red[0];
+}
+
+// Q = A P on the slabs (grid y = slab) and on column 0 (slab-0 blocks);
+// per-block partials of p.q.  With the factored operator A = K_core + F F^T
+// this computes K_core P; the F F^T part is added by the update kernel.
+// kSlabs = false: column 0 only (no slabs; grid y = 1).
+template <bool kSlabs>
+__global__ __launch_bounds__(kT) void k_cg_spmm(const CgArgs* __restrict__ AA) {
+  const CgArgs& A = AA[blockIdx.z];
+  if (stopped(A)) return;
+  __shared__ double red[kTile * kSlab];
+  __shared__ double redy[kTile];
+  const int lane = lane_id(), g = lane >> 4, j = lane & 15, w = threadIdx.x >> 6;
+  const int s = blockIdx.y;
+  const int64_t n = A.n;
+  const int64_t so = A.ny + (int64_t)s * n * kSlab + 2 * j;
+  const double* Ps = A.P + so;
+  double* Qs = A.Q + so;
+  const int xcd = blockIdx.x & 7;
+  const int64_t bi = blockIdx.x >> 3, nbx = gridDim.x >> 3;
+  const int64_t nx = (n + 7) >> 3, lo = xcd * nx, hi = min(n, lo + nx);
+  double pq0 = 0.0, pq1 = 0.0, pqy = 0.0;
+  for (int64_t pb = lo + bi * kTile + w * 4; pb < hi; pb += nbx * kTile) {
+    const int64_t p = pb + g;
+    const bool live = p < hi;
+    const int64_t a = live ? (A.sched ? (int64_t)A.sched[p] : p) : 0;
+    const int64_t k0 = live ? A.row_ptr[a] : 0, k1 = live ? A.row_ptr[a + 1] : 0;
+    double2 q;
+    double yacc = 0.0;
+    if (!kSlabs) slab_row<true, false>(k0, k1, (int32_t)a, A.col, A.val, Ps, kSlab, A.P, q, yacc);
+    else if (s == 0) slab_row<true>(k0, k1, (int32_t)a, A.col, A.val, Ps, kSlab, A.P, q, yacc);
+    else slab_row<false>(k0, k1, (int32_t)a, A.col, A.val, Ps, kSlab, nullptr, q, yacc);
+    if (s == 0) yacc = row16_sum(yacc);
+    if (live) {
+      if (kSlabs) {
+        *reinterpret_cast<double2*>(Qs + a * kSlab) = q;
+        const double2 pv = *reinterpret_cast<const double2*>(Ps + a * kSlab);
+        pq0 += pv.x * q.x;
+        pq1 += pv.y * q.y;
+      }
+      if (s == 0 && j == 0) {
+        A.Q[a] = yacc;
+        pqy += A.P[a] * yacc;
+      }
+    }
+  }
+  if (kSlabs) {
+    const double t = tile_colsum(red, pq0, pq1);
+    if (threadIdx.x < kSlab) {
+      const int rc = 1 + s * kSlab + threadIdx.x;
+      if (rc < A.R) A.s_part[(int64_t)rc * A.nbs + blockIdx.x] = t;
+    }
+  }
+  if (s == 0) {
+    __syncthreads();
+    if (j == 0) redy[w * 4 + g] = pqy;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double ty = 0.0;
+      for (int q = 0; q < kTile; ++q) ty += redy[q];
+      A.s_part[blockIdx.x] = ty;
+    }
+  }
+}
+
+// out[c] = sum_b part[c][b] in a fixed order.  which: 0 SpMM partials,
+// 1 update partials (r.r and F^T r), 2 F^T p partials.
+__global__ __launch_bounds__(kT) void k_cg_colsum(const CgArgs* __restrict__ AA, int which) {
+  const CgArgs& A = AA[blockIdx.z];
+  if (stopped(A)) return;
+  __shared__ double red[kT];
+  const double* part;
+  double* out;
+  int nparts, ncols;
+  if (which == 0) { part = A.s_part; out = A.s_red; nparts = A.nbs; ncols = A.R; }
+  else if (which == 1) { part = A.u_part; out = A.u_red; nparts = A.nbu; ncols = (1 + (A.use_pc ? A.n1 : 0)) * A.R; }
+  else { part = A.p_part; out = A.p_red; nparts = A.nbu; ncols = A.n1 * A.R; }
+  const int c = blockIdx.x;
+  if (c >= ncols) return;
+  const double* pc = part + (int64_t)c * nparts;
+  double v = 0.0;
+  for (int b = threadIdx.x; b < nparts; b += kT) v += pc[b];
+  v = block_sum(red, v);
+  if (threadIdx.x == 0) out[c] = v;
+}
+
+// ------------------------------------------------------------ updates
+// Per-thread column handling of the streaming kernels.  Slab blocks
+// (blockIdx.y < ns): rows a = 16 t + 4 w + g of tiles t = blockIdx.x +
+// k nbu, lane j holding slab columns 2j, 2j+1.  Column-0 blocks
+// (blockIdx.y == ns): one row per thread, a = 256 t + threadIdx.x.
+
+// ------------------------------------------------------------ F^T v
+// Slab blocks accumulate F^T v (v = r, p or z: the n1 x 32 block of the
+// slab's columns) on the FP64 matrix cores: per step the wavefront's four
+// rows are the K = 4 dimension of v_mfma_f64_16x16x4f64 with
+//   A[i][k] = F[a_k][16 mt + i]   (lane 16 k + i),
+//   B[k][c] = v[a_k][2 c + par]   (lane 16 k + c; par = even / odd column),
+// so lane (g, j) supplies exactly its own row's F value and its own two
+// columns.  The 16 x 16 result keeps D[4 q + g][j] in lane (g, j),
+// register q (checked on gfx950).  Column-0 blocks (one row per thread)
+// accumulate in scalars.
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+template <int NT>
+__device__ __forceinline__ void ft_step(const double* f, double v0, double v1, d4 (*acc)[2]) {
+#pragma unroll
+  for (int mt = 0; mt < NT; ++mt) {
+    acc[mt][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(f[mt], v0, acc[mt][0], 0, 0, 0);
+    acc[mt][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(f[mt], v1, acc[mt][1], 0, 0, 0);
+  }
+}
+
+// F values of the calling lane for row a (a < 0: zeros): f[mt] = F[a][16 mt + j].
+template <int NT>
+__device__ __forceinline__ void load_f(const CgArgs& A, int64_t a, double* f) {
+  const int j = lane_id() & 15;
+#pragma unroll
+  for (int mt = 0; mt < NT; ++mt) {
+    const int i = 16 * mt + j;
+    f[mt] = (a >= 0 && i < A.n1) ? A.F[a * (int64_t)A.n1 + i] : 0.0;
+  }
+}
+
+// sum_i F[a][i] w[i][cl] with the row's F values spread over the 16 lanes
+// of the group (f from load_f) and w in LDS (stride kSlab).  Every lane of
+// the wavefront must call this together (DPP broadcasts).
+template <int H, int... us>
+__device__ __forceinline__ double fdot16(double f, int n1i, const double* w, int cl,
+                                         std::integer_sequence<int, us...>) {
+  double s = 0.0;
+  ((s += (H + us < n1i) ? bcast16_d<us>(f) * w[(H + us) * kSlab + cl] : 0.0), ...);
+  return s;
+}
+template <int NT>
+__device__ __forceinline__ double frow_bc(const double* f, int n1, const double* w, int cl) {
+  double s = 0.0;
+  for (int mt = 0; mt < NT && 16 * mt < n1; ++mt) {
+    if (mt == 0) s += fdot16<0>(f[0], n1, w, cl, std::make_integer_sequence<int, 16>{});
+    else if (mt == 1) s += fdot16<16>(f[1], n1, w, cl, std::make_integer_sequence<int, 16>{});
+    else if (mt == 2) s += fdot16<32>(f[2], n1, w, cl, std::make_integer_sequence<int, 16>{});
+    else s += fdot16<48>(f[3], n1, w, cl, std::make_integer_sequence<int, 16>{});
+  }
+  return s;
+}
+
+// Block sums of the wavefronts' F^T v tiles into part rows base + i R + rc
+// (slab blocks).  red: at least 4 * 512 doubles of LDS.
+template <int NT>
+__device__ void put_ft_partials(const CgArgs& A, double* red, d4 (*acc)[2], double* part, int64_t base) {
+  const int lane = lane_id(), g = lane >> 4, j = lane & 15, w = threadIdx.x >> 6;
+  const int s = blockIdx.y;
+#pragma unroll
+  for (int mt = 0; mt < NT; ++mt) {
+    if (16 * mt >= A.n1) continue;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      red[w * 512 + (4 * q + g) * kSlab + 2 * j] = acc[mt][0][q];
+      red[w * 512 + (4 * q + g) * kSlab + 2 * j + 1] = acc[mt][1][q];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 512; e += kT) {
+      const int i = 16 * mt + (e >> 5);
+      const int rc = 1 + s * kSlab + (e & 31);
+      const double t = red[e] + red[512 + e] + red[1024 + e] + red[1536 + e];
+      if (i < A.n1 && rc < A.R) part[(base + (int64_t)i * A.R + rc) * A.nbu + blockIdx.x] = t;
+    }
+  }
+}
+
+// Column-0 block sums of scalar F^T v accumulators into part rows base + i R.
+template <int NI>
+__device__ void put_fty_partials(const CgArgs& A, double* red, const double* gy, double* part, int64_t base) {
+#pragma unroll
+  for (int i = 0; i < (NI > 0 ? NI : 1); ++i) {
+    if (i >= A.n1) continue;
+    const double t = block_sum(red, gy[i]);
+    if (threadIdx.x == 0) part[(base + (int64_t)i * A.R) * A.nbu + blockIdx.x] = t;
+  }
+}
+
+// Per-column scalars are computed once per block into LDS by the column's
+// owner thread (slab blocks: thread cl < 32 for column 1 + 32 s + cl;
+// column-0 blocks: thread 0); each thread then reads those of its own
+// columns (cl = 2j, 2j+1, or cl = 0).
+__device__ __forceinline__ bool is_ycol(const CgArgs& A) { return (int)blockIdx.y == A.ns; }
+__device__ __forceinline__ int col_of(const CgArgs& A, bool ycol, int cl) {
+  return ycol ? 0 : 1 + (int)blockIdx.y * kSlab + cl;
+}
+__device__ __forceinline__ int my_cl(bool ycol) { return ycol ? 0 : 2 * (lane_id() & 15); }
+
+// Row visited by step k of the calling thread (or -1 past the end).
+__device__ __forceinline__ int64_t thread_row(const CgArgs& A, bool ycol, int64_t k) {
+  if (ycol) {
+    const int64_t a = (blockIdx.x + k * (int64_t)A.nbu) * kT + threadIdx.x;
+    return a < A.n ? a : -1;
+  }
+  const int64_t t = blockIdx.x + k * (int64_t)A.nbu;
+  const int64_t a = t * kTile + (threadIdx.x >> 6) * 4 + (lane_id() >> 4);
+  return a < A.n ? a : -1;
+}
+// Steps of the calling block (uniform over the block).
+__device__ __forceinline__ int64_t thread_steps(const CgArgs& A, bool ycol) {
+  const int64_t per = ycol ? kT : kTile;
+  const int64_t tiles = (A.n + per - 1) / per;
+  return tiles > (int64_t)blockIdx.x ? (tiles - blockIdx.x + A.nbu - 1) / A.nbu : 0;
+}
+// Offset of the thread's (first) element in row a.
+__device__ __forceinline__ int64_t elem(const CgArgs& A, bool ycol, int64_t a) {
+  return ycol ? a : A.ny + (int64_t)blockIdx.y * A.n * kSlab + a * kSlab + 2 * (lane_id() & 15);
+}
+
+// u = S^{-1} g for column rc (g = F^T r, from u_red) into us[i * kSlab]
+// (stride kSlab); returns g.u.
+template <int NI>
+__device__ __forceinline__ double small_solve(const CgArgs& A, int rc, double* us) {
+  double gv[NI > 0 ? NI : 1];
+#pragma unroll
+  for (int i = 0; i < (NI > 0 ? NI : 1); ++i) gv[i] = i < A.n1 ? A.u_red[(int64_t)A.R + (int64_t)i * A.R + rc] : 0.0;
+  double gu = 0.0;
+  for (int i = 0; i < A.n1; ++i) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < (NI > 0 ? NI : 1); ++k)
+      if (k < A.n1) s += A.Sinv[i * A.n1 + k] * gv[k];
+    us[i * kSlab] = s;
+    gu += gv[i] * s;
+  }
+  return gu;
+}
+
+// sum_i F[a][i] w[i][0] for a column-0 thread's own row.
+template <int NI>
+__device__ __forceinline__ double frow_dot(const double* __restrict__ Fa, int n1, const double* w) {
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < (NI > 0 ? NI : 1); ++i)
+    if (i < n1) s += Fa[i] * w[i * kSlab];
+  return s;
+}
+
+constexpr int kRed = 4 * 512;   // LDS doubles for the block reductions
+
+// alpha = r.z / p.A p (p.A p = p.K_core p + |F^T p|^2 with the factored
+// operator); x += alpha p; r -= alpha A p; partials of r.r and F^T r.
+template <int NI>
+__global__ __launch_bounds__(kT) void k_cg_update_xr(const CgArgs* __restrict__ AA) {
+  constexpr int NT = (NI + 15) / 16;
+  const CgArgs& A = AA[blockIdx.z];
+  if (stopped(A)) return;
+  __shared__ double red[kRed];
+  __shared__ double s_alpha[kSlab];
+  __shared__ int s_act[kSlab];
+  __shared__ double s_gp[(NI > 0 ? NI : 1) * kSlab];
+  const int it = *A.st.it;
+  const int par = it & 1;
+  const bool ycol = is_ycol(A);
+  const bool lr = NI > 0 && A.lowrank_op;
+  const bool pc = NI > 0 && A.use_pc;
+  if ((int)threadIdx.x < (ycol ? 1 : kSlab)) {
+    const int cl = threadIdx.x;
+    const int rc = col_of(A, ycol, cl);
+    double alpha = 0.0;
+    int act = 0;
+    if (rc < A.R) {
+      const bool was = A.st.act[par * A.R + rc] != 0;
+      double d = A.s_red[rc];
+      if (lr)
+        for (int i = 0; i < A.n1; ++i) {
+          const double gi = A.p_red[(int64_t)i * A.R + rc];
+          s_gp[i * kSlab + cl] = gi;
+          d += gi * gi;
+        }
+      if (was) {
+        if (d > 0.0 && isfinite(d)) {
+          alpha = A.st.rz[par * A.R + rc] / d;
+          act = 1;
+        }
+        if (blockIdx.x == 0) {
+          A.st.hist_a[(int64_t)it * A.R + rc] = alpha;
+          if (!act) {
+            A.st.failed[rc] = 1;
+            *A.st.not_spd = 1;
+          }
+        }
+      }
+    } else if (lr) {
+      for (int i = 0; i < A.n1; ++i) s_gp[i * kSlab + cl] = 0.0;
+    }
+    s_alpha[cl] = alpha;
+    s_act[cl] = act;
+  }
+  __syncthreads();
+  const int64_t steps = thread_steps(A, ycol);
+  if (ycol) {
+    const double al = s_alpha[0];
+    double rr = 0.0;
+    double gy[NI > 0 ? NI : 1];
+#pragma unroll
+    for (int i = 0; i < (NI > 0 ? NI : 1); ++i) gy[i] = 0.0;
+    if (s_act[0])
+      for (int64_t k = 0; k < steps; ++k) {
+        const int64_t a = thread_row(A, true, k);
+        if (a < 0) continue;
+        const double* Fa = A.F + a * (int64_t)A.n1;
+        double q = A.Q[a];
+        if (lr) q += frow_dot<NI>(Fa, A.n1, s_gp);
+        A.X[a] += al * A.P[a];
+        const double r = A.Rr[a] - al * q;
+        A.Rr[a] = r;
+        rr += r * r;
+        if (pc) {
+#pragma unroll
+          for (int i = 0; i < (NI > 0 ? NI : 1); ++i)
+            if (i < A.n1) gy[i] += Fa[i] * r;
+        }
+      }
+    const double t = block_sum(red, rr);
+    if (threadIdx.x == 0) A.u_part[blockIdx.x] = t;
+    if (pc) put_fty_partials<NI>(A, red, gy, A.u_part, A.R);
+    return;
+  }
+  const int cl = my_cl(false);
+  const double al0 = s_alpha[cl], al1 = s_alpha[cl + 1];
+  const bool mine = s_act[cl] || s_act[cl + 1];
+  double rr0 = 0.0, rr1 = 0.0;
+  d4 acc[NT > 0 ? NT : 1][2];
+#pragma unroll
+  for (int mt = 0; mt < (NT > 0 ? NT : 1); ++mt) acc[mt][0] = acc[mt][1] = d4{0.0, 0.0, 0.0, 0.0};
+  if (__any(mine)) {
+    for (int64_t k = 0; k < steps; ++k) {
+      const int64_t a = thread_row(A, false, k);
+      double f[NT > 0 ? NT : 1];
+      if (NT > 0) load_f<NT>(A, a, f);
+      double c0 = 0.0, c1 = 0.0;
+      if (lr) {
+        c0 = frow_bc<NT>(f, A.n1, s_gp, cl);
+        c1 = frow_bc<NT>(f, A.n1, s_gp, cl + 1);
+      }
+      double2 r = {0.0, 0.0};
+      if (a >= 0) {
+        const int64_t o = elem(A, false, a);
+        double2 q = *reinterpret_cast<const double2*>(A.Q + o);
+        const double2 p = *reinterpret_cast<const double2*>(A.P + o);
+        double2 x = *reinterpret_cast<const double2*>(A.X + o);
+        r = *reinterpret_cast<const double2*>(A.Rr + o);
+        q.x += c0;
+        q.y += c1;
+        x.x += al0 * p.x;
+        x.y += al1 * p.y;
+        r.x -= al0 * q.x;
+        r.y -= al1 * q.y;
+        *reinterpret_cast<double2*>(A.X + o) = x;
+        *reinterpret_cast<double2*>(A.Rr + o) = r;
+        rr0 += r.x * r.x;
+        rr1 += r.y * r.y;
+      }
+      if (NT > 0 && pc) ft_step<NT>(f, r.x, r.y, acc);
+    }
+  }
+  const double t = tile_colsum(red, rr0, rr1);
+  if (threadIdx.x < kSlab) {
+    const int rc = 1 + (int)blockIdx.y * kSlab + (int)threadIdx.x;
+    if (rc < A.R) A.u_part[(int64_t)rc * A.nbu + blockIdx.x] = t;
+  }
+  if (NT > 0 && pc) put_ft_partials<NT>(A, red, acc, A.u_part, A.R);
+}
+
+// beta = r.z_new / r.z; convergence on |r|; p = z + beta p with
+// z = M^{-1} r = (r - F u) / c formed on the fly (r.z_new = (r.r - g.u)/c,
+// g = F^T r, u = (cI + F^T F)^{-1} g).  With the factored operator also
+// the partials of F^T p for the next iteration.
+template <int NI>
+__global__ __launch_bounds__(kT) void k_cg_update_p(const CgArgs* __restrict__ AA) {
+  constexpr int NT = (NI + 15) / 16;
+  const CgArgs& A = AA[blockIdx.z];
+  if (stopped(A)) return;
+  __shared__ double red[kRed];
+  __shared__ double s_beta[kSlab];
+  __shared__ int s_cont[kSlab];
+  __shared__ double s_u[(NI > 0 ? NI : 1) * kSlab];
+  const int it = *A.st.it;
+  const int par = it & 1, nxt = par ^ 1;
+  const bool ycol = is_ycol(A);
+  const bool lr = NI > 0 && A.lowrank_op;
+  const bool pc = NI > 0 && A.use_pc;
+  if ((int)threadIdx.x < (ycol ? 1 : kSlab)) {
+    const int cl = threadIdx.x;
+    const int rc = col_of(A, ycol, cl);
+    double beta = 0.0;
+    int cont = 0;
+    if (rc < A.R) {
+      const double rr_new = A.u_red[rc];
+      const double rz_new = pc ? (rr_new - small_solve<NI>(A, rc, s_u + cl)) * A.inv_c : rr_new;
+      const bool act = A.st.act[par * A.R + rc] != 0 && A.st.failed[rc] == 0;
+      const double rz_old = A.st.rz[par * A.R + rc];
+      if (act) {
+        beta = rz_new / rz_old;
+        cont = !(rr_new <= A.rtol2 * A.st.bnorm2[rc]) ? 1 : 0;
+      }
+      if (blockIdx.x == 0) {
+        A.st.rz[nxt * A.R + rc] = act ? rz_new : rz_old;
+        A.st.act[nxt * A.R + rc] = cont;
+        if (act) {
+          A.st.hist_b[(int64_t)it * A.R + rc] = beta;
+          A.st.iters[rc] += 1;
+          A.st.rr_last[rc] = rr_new;
+        }
+      }
+    } else if (pc) {
+      for (int i = 0; i < A.n1; ++i) s_u[i * kSlab + cl] = 0.0;
+    }
+    s_beta[cl] = beta;
+    s_cont[cl] = cont;
+  }
+  __syncthreads();
+  const int64_t steps = thread_steps(A, ycol);
+  if (ycol) {
+    const double be = s_beta[0];
+    double gy[NI > 0 ? NI : 1];
+#pragma unroll
+    for (int i = 0; i < (NI > 0 ? NI : 1); ++i) gy[i] = 0.0;
+    if (s_cont[0])
+      for (int64_t k = 0; k < steps; ++k) {
+        const int64_t a = thread_row(A, true, k);
+        if (a < 0) continue;
+        const double* Fa = A.F + a * (int64_t)A.n1;
+        const double r = A.Rr[a];
+        const double z = pc ? (r - frow_dot<NI>(Fa, A.n1, s_u)) * A.inv_c : r;
+        const double p = z + be * A.P[a];
+        A.P[a] = p;
+        if (lr) {
+#pragma unroll
+          for (int i = 0; i < (NI > 0 ? NI : 1); ++i)
+            if (i < A.n1) gy[i] += Fa[i] * p;
+        }
+      }
+    if (lr) put_fty_partials<NI>(A, red, gy, A.p_part, 0);
+    return;
+  }
+  const int cl = my_cl(false);
+  const double be0 = s_beta[cl], be1 = s_beta[cl + 1];
+  const bool c0 = s_cont[cl] != 0, c1 = s_cont[cl + 1] != 0;
+  d4 acc[NT > 0 ? NT : 1][2];
+#pragma unroll
+  for (int mt = 0; mt < (NT > 0 ? NT : 1); ++mt) acc[mt][0] = acc[mt][1] = d4{0.0, 0.0, 0.0, 0.0};
+  if (__any(c0 || c1)) {
+    for (int64_t k = 0; k < steps; ++k) {
+      const int64_t a = thread_row(A, false, k);
+      double f[NT > 0 ? NT : 1];
+      if (NT > 0) load_f<NT>(A, a, f);
+      double u0 = 0.0, u1 = 0.0;
+      if (pc) {
+        u0 = frow_bc<NT>(f, A.n1, s_u, cl);
+        u1 = frow_bc<NT>(f, A.n1, s_u, cl + 1);
+      }
+      double2 p = {0.0, 0.0};
+      if (a >= 0) {
+        const int64_t o = elem(A, false, a);
+        const double2 r = *reinterpret_cast<const double2*>(A.Rr + o);
+        p = *reinterpret_cast<const double2*>(A.P + o);
+        const double z0 = pc ? (r.x - u0) * A.inv_c : r.x;
+        const double z1 = pc ? (r.y - u1) * A.inv_c : r.y;
+        if (c0) p.x = z0 + be0 * p.x;
+        if (c1) p.y = z1 + be1 * p.y;
+        *reinterpret_cast<double2*>(A.P + o) = p;
+      }
+      if (NT > 0 && lr) ft_step<NT>(f, p.x, p.y, acc);
+    }
+  }
+  if (NT > 0 && lr) put_ft_partials<NT>(A, red, acc, A.p_part, 0);
+}
+
+// Records the executed iteration count in done when no column is active
+// and advances the iteration counter (one block per member).
+__global__ void k_cg_check(const CgArgs* __restrict__ AA) {
+  const CgArgs& A = AA[blockIdx.z];
+  if (stopped(A)) return;
+  const int it = *A.st.it;
+  const int nxt = (it & 1) ^ 1;
+  __shared__ int left;
+  if (threadIdx.x == 0) left = 0;
+  __syncthreads();
+  int mine = 0;
+  for (int r = threadIdx.x; r < A.R; r += blockDim.x) mine |= A.st.act[nxt * A.R + r];
+  if (mine) atomicOr(&left, 1);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (!left) *A.st.done = it + 1;
+    *A.st.it = it + 1;
+  }
+}
+
+// ------------------------------------------------------------ start
+// x = 0, r = b, p = 0 over the whole slab layout (padding included).
+// Column 0 is y (or the first dense column); probe p (column 1+p) is the
+// Rademacher vector w_p of caller row perm[a], or with the preconditioner
+// sqrt(c) w_p + F v_p (v_p: n1 Rademacher signs), whose covariance is M.
+__global__ void k_cg_start(const CgArgs* __restrict__ AA, const double* __restrict__ ys,
+                           const int32_t* __restrict__ perm, int kind, uint64_t seed,
+                           const double* __restrict__ dense) {
+  const CgArgs& A = AA[blockIdx.z];
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t n = A.n;
+  const int64_t tot = A.ny + (int64_t)A.ns * n * kSlab;
+  if (idx >= tot) return;
+  int64_t a;
+  int rc;
+  if (idx < A.ny) {
+    a = idx;
+    rc = 0;
+  } else {
+    const int64_t t = idx - A.ny;
+    const int64_t s = t / (n * kSlab);
+    const int64_t rem = t - s * n * kSlab;
+    a = rem >> 5;
+    rc = 1 + (int)(s * kSlab) + (int)(rem & 31);
+  }
+  double b = 0.0;
+  if (a < n && rc < A.R) {
+    if (kind == PK_DENSE) {
+      b = dense[a * A.R + rc];
+    } else if (rc == 0) {
+      b = ys[a];
+    } else if (kind == PK_IDENTITY) {
+      b = (perm[a] == rc - 1) ? 1.0 : 0.0;
+    } else {
+      const uint64_t pbase = (uint64_t)(rc - 1) << 32;
+      b = (splitmix64_at(seed, pbase + (uint64_t)perm[a] + 1ull) >> 63) ? -1.0 : 1.0;
+      if (A.use_pc) {
+        double fv = 0.0;
+        const double* Fa = A.F + a * (int64_t)A.n1;
+        for (int i = 0; i < A.n1; ++i) {
+          const double v = (splitmix64_at(seed, pbase + 0xFFFFFFFFull - (uint64_t)i) >> 63) ? -1.0 : 1.0;
+          fv += Fa[i] * v;
+        }
+        b = A.sqrt_c * b + fv;
+      }
+    }
+  }
+  A.X[idx] = 0.0;
+  A.Rr[idx] = b;
+  A.P[idx] = 0.0;
+}
+
+// Partials of b.b and F^T b.
+template <int NI>
+__global__ __launch_bounds__(kT) void k_cg_norm(const CgArgs* __restrict__ AA) {
+  constexpr int NT = (NI + 15) / 16;
+  const CgArgs& A = AA[blockIdx.z];
+  __shared__ double red[kRed];
+  const bool ycol = is_ycol(A);
+  const bool pc = NI > 0 && A.use_pc;
+  const int64_t steps = thread_steps(A, ycol);
+  if (ycol) {
+    double rr = 0.0;
+    double gy[NI > 0 ? NI : 1];
+#pragma unroll
+    for (int i = 0; i < (NI > 0 ? NI : 1); ++i) gy[i] = 0.0;
+    for (int64_t k = 0; k < steps; ++k) {
+      const int64_t a = thread_row(A, true, k);
+      if (a < 0) continue;
+      const double r = A.Rr[a];
+      rr += r * r;
+      if (pc) {
+        const double* Fa = A.F + a * (int64_t)A.n1;
+#pragma unroll
+        for (int i = 0; i < (NI > 0 ? NI : 1); ++i)
+          if (i < A.n1) gy[i] += Fa[i] * r;
+      }
+    }
+    const double t = block_sum(red, rr);
+    if (threadIdx.x == 0) A.u_part[blockIdx.x] = t;
+    if (pc) put_fty_partials<NI>(A, red, gy, A.u_part, A.R);
+    return;
+  }
+  double rr0 = 0.0, rr1 = 0.0;
+  d4 acc[NT > 0 ? NT : 1][2];
+#pragma unroll
+  for (int mt = 0; mt < (NT > 0 ? NT : 1); ++mt) acc[mt][0] = acc[mt][1] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int64_t k = 0; k < steps; ++k) {
+    const int64_t a = thread_row(A, false, k);
+    double2 r = {0.0, 0.0};
+    if (a >= 0) {
+      r = *reinterpret_cast<const double2*>(A.Rr + elem(A, false, a));
+      rr0 += r.x * r.x;
+      rr1 += r.y * r.y;
+    }
+    if (NT > 0 && pc) {
+      double f[NT > 0 ? NT : 1];
+      load_f<NT>(A, a, f);
+      ft_step<NT>(f, r.x, r.y, acc);
+    }
+  }
+  const double t = tile_colsum(red, rr0, rr1);
+  if (threadIdx.x < kSlab) {
+    const int rc = 1 + (int)blockIdx.y * kSlab + (int)threadIdx.x;
+    if (rc < A.R) A.u_part[(int64_t)rc * A.nbu + blockIdx.x] = t;
+  }
+  if (NT > 0 && pc) put_ft_partials<NT>(A, red, acc, A.u_part, A.R);
+}
+
+// Initial state: p = z0 = M^{-1} b (b when unpreconditioned), V = z0,
+// rz0 = b.z0, bnorm2 = b.b; with the factored operator the partials of
+// F^T p.
+template <int NI>
+__global__ __launch_bounds__(kT) void k_cg_init_fin(const CgArgs* __restrict__ AA) {
+  constexpr int NT = (NI + 15) / 16;
+  const CgArgs& A = AA[blockIdx.z];
+  __shared__ double red[kRed];
+  __shared__ double s_u[(NI > 0 ? NI : 1) * kSlab];
+  const bool ycol = is_ycol(A);
+  const bool lr = NI > 0 && A.lowrank_op;
+  const bool pc = NI > 0 && A.use_pc;
+  if ((int)threadIdx.x < (ycol ? 1 : kSlab)) {
+    const int cl = threadIdx.x;
+    const int rc = col_of(A, ycol, cl);
+    if (rc < A.R) {
+      const double bb = A.u_red[rc];
+      const double rz0 = pc ? (bb - small_solve<NI>(A, rc, s_u + cl)) * A.inv_c : bb;
+      if (blockIdx.x == 0) {
+        A.st.bnorm2[rc] = bb;
+        A.st.rr_last[rc] = bb;
+        A.st.rz[rc] = rz0;
+        A.st.rz[A.R + rc] = rz0;
+        A.st.rz0[rc] = rz0;
+        A.st.act[rc] = bb > 0.0 ? 1 : 0;
+        A.st.act[A.R + rc] = 0;
+        A.st.failed[rc] = 0;
+        A.st.iters[rc] = 0;
+      }
+    } else if (pc) {
+      for (int i = 0; i < A.n1; ++i) s_u[i * kSlab + cl] = 0.0;
+    }
+  }
+  __syncthreads();
+  const int64_t steps = thread_steps(A, ycol);
+  if (ycol) {
+    double gy[NI > 0 ? NI : 1];
+#pragma unroll
+    for (int i = 0; i < (NI > 0 ? NI : 1); ++i) gy[i] = 0.0;
+    for (int64_t k = 0; k < steps; ++k) {
+      const int64_t a = thread_row(A, true, k);
+      if (a < 0) continue;
+      const double* Fa = A.F + a * (int64_t)A.n1;
+      const double r = A.Rr[a];
+      const double z = pc ? (r - frow_dot<NI>(Fa, A.n1, s_u)) * A.inv_c : r;
+      A.P[a] = z;
+      if (A.V) A.V[a] = z;
+      if (lr) {
+#pragma unroll
+        for (int i = 0; i < (NI > 0 ? NI : 1); ++i)
+          if (i < A.n1) gy[i] += Fa[i] * z;
+      }
+    }
+    if (lr) put_fty_partials<NI>(A, red, gy, A.p_part, 0);
+    return;
+  }
+  const int cl = my_cl(false);
+  d4 acc[NT > 0 ? NT : 1][2];
+#pragma unroll
+  for (int mt = 0; mt < (NT > 0 ? NT : 1); ++mt) acc[mt][0] = acc[mt][1] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int64_t k = 0; k < steps; ++k) {
+    const int64_t a = thread_row(A, false, k);
+    double f[NT > 0 ? NT : 1];
+    if (NT > 0) load_f<NT>(A, a, f);
+    double u0 = 0.0, u1 = 0.0;
+    if (pc) {
+      u0 = frow_bc<NT>(f, A.n1, s_u, cl);
+      u1 = frow_bc<NT>(f, A.n1, s_u, cl + 1);
+    }
+    double2 z = {0.0, 0.0};
+    if (a >= 0) {
+      const int64_t o = elem(A, false, a);
+      const double2 r = *reinterpret_cast<const double2*>(A.Rr + o);
+      z.x = pc ? (r.x - u0) * A.inv_c : r.x;
+      z.y = pc ? (r.y - u1) * A.inv_c : r.y;
+      *reinterpret_cast<double2*>(A.P + o) = z;
+      if (A.V) *reinterpret_cast<double2*>(A.V + o) = z;
+    }
+    if (NT > 0 && lr) ft_step<NT>(f, z.x, z.y, acc);
+  }
+  if (NT > 0 && lr) put_ft_partials<NT>(A, red, acc, A.p_part, 0);
+}
+
+// dst[a][rc] = src(a, rc): slab layout to row-major [n][R].
+__global__ void k_cg_unpack(const CgArgs* __restrict__ AA, int which) {
+  const CgArgs& A = AA[blockIdx.z];
+  const double* src = which == 0 ? A.X : A.V;
+  double* dst = which == 0 ? A.P : A.Q;
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= A.n * (int64_t)A.R) return;
+  const int64_t a = idx / A.R;
+  const int rc = (int)(idx - a * A.R);
+  dst[idx] = rc == 0 ? src[a] : src[A.ny + (int64_t)((rc - 1) >> 5) * A.n * kSlab + a * kSlab + ((rc - 1) & 31)];
+}
+
+// ------------------------------------------------------------ launches
+struct Launch {
+  int nbs, nbu, ns, R, n1;
+  bool use_pc, lowrank;
+  int B;
+};
+
+template <int NI>
+void launch_iteration(hipStream_t st, const CgArgs* dA, const Launch& L, Ctx* c) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (c != nullptr && c->timing) {
+    e0 = c->event();
+    SDGP_HIP(hipEventRecord(e0, st));
+  }
+  if (L.ns > 0) k_cg_spmm<true><<<dim3(L.nbs, L.ns, L.B), kT, 0, st>>>(dA);
+  else k_cg_spmm<false><<<dim3(L.nbs, 1, L.B), kT, 0, st>>>(dA);
+  SDGP_CHECK_LAUNCH();
+  if (c != nullptr && c->timing) {
+    e1 = c->event();
+    SDGP_HIP(hipEventRecord(e1, st));
+    c->spmm_events.push_back({e0, e1});
+  }
+  k_cg_colsum<<<dim3(L.R, 1, L.B), kT, 0, st>>>(dA, 0);
+  SDGP_CHECK_LAUNCH();
+  k_cg_update_xr<NI><<<dim3(L.nbu, L.ns + 1, L.B), kT, 0, st>>>(dA);
+  SDGP_CHECK_LAUNCH();
+  k_cg_colsum<<<dim3((1 + (L.use_pc ? L.n1 : 0)) * L.R, 1, L.B), kT, 0, st>>>(dA, 1);
+  SDGP_CHECK_LAUNCH();
+  k_cg_update_p<NI><<<dim3(L.nbu, L.ns + 1, L.B), kT, 0, st>>>(dA);
+  SDGP_CHECK_LAUNCH();
+  if (L.lowrank) {
+    k_cg_colsum<<<dim3(L.n1 * L.R, 1, L.B), kT, 0, st>>>(dA, 2);
+    SDGP_CHECK_LAUNCH();
+  }
+  k_cg_check<<<dim3(1, 1, L.B), 256, 0, st>>>(dA);
+  SDGP_CHECK_LAUNCH();
+}
+
+template <int NI>
+void launch_start(hipStream_t st, const CgArgs* dA, const Launch& L) {
+  k_cg_norm<NI><<<dim3(L.nbu, L.ns + 1, L.B), kT, 0, st>>>(dA);
+  SDGP_CHECK_LAUNCH();
+  k_cg_colsum<<<dim3((1 + (L.use_pc ? L.n1 : 0)) * L.R, 1, L.B), kT, 0, st>>>(dA, 1);
+  SDGP_CHECK_LAUNCH();
+  k_cg_init_fin<NI><<<dim3(L.nbu, L.ns + 1, L.B), kT, 0, st>>>(dA);
+  SDGP_CHECK_LAUNCH();
+  if (L.lowrank) {
+    k_cg_colsum<<<dim3(L.n1 * L.R, 1, L.B), kT, 0, st>>>(dA, 2);
+    SDGP_CHECK_LAUNCH();
+  }
+}
+
+void cg_iteration(int NI, hipStream_t st, const CgArgs* dA, const Launch& L, Ctx* c) {
+  switch (NI) {
+    case 0: launch_iteration<0>(st, dA, L, c); break;
+    case 8: launch_iteration<8>(st, dA, L, c); break;
+    case 16: launch_iteration<16>(st, dA, L, c); break;
+    case 32: launch_iteration<32>(st, dA, L, c); break;
+    default: launch_iteration<64>(st, dA, L, c); break;
+  }
+}
+
+void cg_start(int NI, hipStream_t st, const CgArgs* dA, const Launch& L) {
+  switch (NI) {
+    case 0: launch_start<0>(st, dA, L); break;
+    case 8: launch_start<8>(st, dA, L); break;
+    case 16: launch_start<16>(st, dA, L); break;
+    case 32: launch_start<32>(st, dA, L); break;
+    default: launch_start<64>(st, dA, L); break;
+  }
+}
+
+int64_t round8(int64_t v) { return (v + 7) / 8 * 8; }
+
+}  // namespace
+
+std::vector<CgResult> block_cg_multi(Ctx* c, const std::vector<CgMember>& mem, const Sorted& s, const double* ys,
+                                     int kind, int P, uint64_t seed, double rtol, int max_iter,
+                                     const double* dense_rhs, int dense_R, bool keep_v, bool use_graph) {
+  const int B = (int)mem.size();
+  require(B >= 1 && B <= 65535, "1..65535 members");
+  const int64_t n = s.n;
+  require(n >= 1, "no points");
+  int R;
+  if (kind == PK_DENSE) R = dense_R;
+  else if (kind == PK_IDENTITY) R = (int)(1 + n);
+  else if (kind == PK_NONE) R = 1;
+  else R = 1 + P;
+  require(R >= 1, "no right-hand sides");
+  require(max_iter >= 1, "cg_max_iter must be >= 1");
+  require(rtol > 0.0 && std::isfinite(rtol), "cg_rtol must be > 0");
+  require(kind != PK_DENSE || B == 1, "dense right-hand sides take one member");
+  require(n <= 0x7fffffffLL, "n must fit a 32-bit column index");
+  const Precond* pc0 = mem[0].pc;
+  const bool use_pc = pc0 != nullptr && pc0->n1 > 0 && pc0->apply;
+  const bool use_lr = pc0 != nullptr && pc0->n1 > 0 && pc0->lowrank_op;
+  const int n1 = (use_pc || use_lr) ? pc0->n1 : 0;
+  for (int m = 0; m < B; ++m) {
+    const Precond* p = mem[m].pc;
+    const bool up = p != nullptr && p->n1 > 0 && p->apply;
+    const bool ul = p != nullptr && p->n1 > 0 && p->lowrank_op;
+    require(up == use_pc && ul == use_lr && (!(up || ul) || p->n1 == n1), "members must share the solver form");
+    require(mem[m].A.n == n, "members must share the point set");
+  }
+  require(n1 <= 64, "at most 64 bump functions");
+  require((R - 1 + kSlab - 1) / kSlab + 1 <= 65535, "too many right-hand sides");
+  const int NI = n1 == 0 ? 0 : (n1 <= 8 ? 8 : (n1 <= 16 ? 16 : (n1 <= 32 ? 32 : 64)));
+  const int ns = (R - 1 + kSlab - 1) / kSlab;
+  const int64_t ny = (n + kSlab - 1) / kSlab * kSlab;
+  const size_t NV = (size_t)ny + (size_t)ns * n * kSlab;   // doubles per vector block
+  require(NV >= (size_t)n * R, "layout");
+  const int64_t tiles = (n + kTile - 1) / kTile;
+  const int nbs = (int)std::min<int64_t>(kMaxNbs, round8(tiles));
+  const int nbu = (int)std::min<int64_t>(kMaxNbu, round8(tiles));
+  const int nu = 1 + (use_pc ? n1 : 0);
+  double* X = c->get<double>(S_CG_X, NV * B);
+  double* Rr = c->get<double>(S_CG_R, NV * B);
+  double* Pp = c->get<double>(S_CG_P, NV * B);
+  double* Q = c->get<double>(S_CG_Q, NV * B);
+  double* V = (use_pc && keep_v) ? c->get<double>(S_CG_V, NV * B) : nullptr;
+  double* s_part = c->get<double>(S_CG_PART, (size_t)R * nbs * B);
+  double* s_red = c->get<double>(S_CG_SRED, (size_t)R * B);
+  double* u_part = c->get<double>(S_CG_PART2, (size_t)nu * R * nbu * B);
+  double* u_red = c->get<double>(S_CG_G, (size_t)nu * R * B);
+  double* p_part = use_lr ? c->get<double>(S_CG_PARTG, (size_t)n1 * R * nbu * B) : nullptr;
+  double* p_red = use_lr ? c->get<double>(S_CG_GP, (size_t)n1 * R * B) : nullptr;
+  double* ha = c->get<double>(S_CG_HIST_A, (size_t)max_iter * R * B);
+  double* hb = c->get<double>(S_CG_HIST_B, (size_t)max_iter * R * B);
+  // per-member state block: doubles rz[2R], rz0[R], bnorm2[R], rr_last[R];
+  // ints act[2R], failed[R], iters[R], done, not_spd, it
+  const size_t sbytes = ((5 * (size_t)R) * 8 + (4 * (size_t)R + 3) * 4 + 255) / 256 * 256;
+  char* sb = c->get<char>(S_CG_STATE, sbytes * B);
+  SDGP_HIP(hipMemsetAsync(sb, 0, sbytes * B, c->stream));
+  std::vector<CgArgs> hA(B);
+  for (int m = 0; m < B; ++m) {
+    CgArgs& A = hA[m];
+    const Csr& Am = mem[m].A;
+    const Precond* p = mem[m].pc;
+    A.n = n;
+    A.ny = ny;
+    A.R = R;
+    A.ns = ns;
+    A.row_ptr = Am.row_ptr;
+    A.col = Am.col;
+    A.val = Am.val;
+    A.X = X + m * NV;
+    A.Rr = Rr + m * NV;
+    A.P = Pp + m * NV;
+    A.Q = Q + m * NV;
+    A.V = V ? V + m * NV : nullptr;
+    A.sched = s.sched;
+    A.F = n1 > 0 ? p->F : nullptr;
+    A.Sinv = use_pc ? p->Sinv : nullptr;
+    A.n1 = n1;
+    A.use_pc = use_pc ? 1 : 0;
+    A.lowrank_op = use_lr ? 1 : 0;
+    A.inv_c = use_pc ? 1.0 / p->c : 1.0;
+    A.sqrt_c = use_pc ? std::sqrt(p->c) : 1.0;
+    A.nbs = nbs;
+    A.nbu = nbu;
+    A.max_iter = max_iter;
+    A.rtol2 = rtol * rtol;
+    A.s_part = s_part + (size_t)m * R * nbs;
+    A.s_red = s_red + (size_t)m * R;
+    A.u_part = u_part + (size_t)m * nu * R * nbu;
+    A.u_red = u_red + (size_t)m * nu * R;
+    A.p_part = p_part ? p_part + (size_t)m * n1 * R * nbu : nullptr;
+    A.p_red = p_red ? p_red + (size_t)m * n1 * R : nullptr;
+    char* mb = sb + sbytes * m;
+    A.st.rz = reinterpret_cast<double*>(mb);
+    A.st.rz0 = A.st.rz + 2 * (size_t)R;
+    A.st.bnorm2 = A.st.rz0 + R;
+    A.st.rr_last = A.st.bnorm2 + R;
+    int32_t* ib = reinterpret_cast<int32_t*>(A.st.rr_last + R);
+    A.st.act = ib;
+    A.st.failed = ib + 2 * (size_t)R;
+    A.st.iters = A.st.failed + R;
+    A.st.done = A.st.iters + R;
+    A.st.not_spd = A.st.done + 1;
+    A.st.it = A.st.not_spd + 1;
+    A.st.hist_a = ha + (size_t)m * max_iter * R;
+    A.st.hist_b = hb + (size_t)m * max_iter * R;
+  }
+  CgArgs* dA = c->get<CgArgs>(S_CG_ARGS, B);
+  SDGP_HIP(hipMemcpyAsync(dA, hA.data(), B * sizeof(CgArgs), hipMemcpyHostToDevice, c->stream));
+  Launch L{nbs, nbu, ns, R, n1, use_pc, use_lr, B};
+  {
+    const int64_t gx = ((int64_t)NV + 255) / 256;
+    require(gx < 0x7fffffff, "n*R too large");
+    k_cg_start<<<dim3((unsigned)gx, 1, B), 256, 0, c->stream>>>(dA, ys, s.perm, kind, seed, dense_rhs);
+    SDGP_CHECK_LAUNCH();
+  }
+  cg_start(NI, c->stream, dA, L);
+  // iterate; poll the per-member flags now and then
+  std::vector<int32_t> flags((size_t)3 * B);
+  auto poll = [&](hipStream_t st) -> bool {
+    for (int m = 0; m < B; ++m)
+      SDGP_HIP(hipMemcpyAsync(&flags[3 * m], hA[m].st.done, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    SDGP_HIP(hipStreamSynchronize(st));
+    for (int m = 0; m < B; ++m)
+      if (flags[3 * m] == 0 && flags[3 * m + 2] < max_iter) return false;
+    return true;
+  };
+  c->spmm_events.clear();
+  int launched = 0;
+  if (use_graph) {
+    // capture k iterations once and replay them: the iteration counters live
+    // on the device, so every replay advances the solve; kernels of members
+    // that are done, or past max_iter, return at once
+    const int k = 8;
+    hipStream_t gs = c->graph_stream();
+    hipEvent_t ready = c->event();
+    SDGP_HIP(hipEventRecord(ready, c->stream));
+    SDGP_HIP(hipStreamWaitEvent(gs, ready, 0));
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    SDGP_HIP(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
+    for (int q = 0; q < k; ++q) cg_iteration(NI, gs, dA, L, nullptr);
+    SDGP_HIP(hipStreamEndCapture(gs, &graph));
+    hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (ie != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      throw Error(SDGP_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+    }
+    int every = 1;
+    bool fin = false;
+    while (!fin && launched < max_iter) {
+      for (int q = 0; q < every && launched < max_iter; ++q) {
+        SDGP_HIP(hipGraphLaunch(exec, gs));
+        launched += k;
+      }
+      fin = poll(gs);
+      every = std::min(every * 2, 8);
+    }
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    hipEvent_t back = c->event();
+    SDGP_HIP(hipEventRecord(back, gs));
+    SDGP_HIP(hipStreamWaitEvent(c->stream, back, 0));
+  } else {
+    int check = 8;
+    bool fin = false;
+    while (!fin && launched < max_iter) {
+      const int upto = std::min(max_iter, launched + check);
+      for (; launched < upto; ++launched) cg_iteration(NI, c->stream, dA, L, c);
+      fin = poll(c->stream);
+      check = std::min(check * 2, 64);
+    }
+  }
+  // solutions (and M^{-1} b) back to row-major [n][R], into the P and Q
+  // storage that the iteration no longer needs
+  {
+    const int64_t gx = ((int64_t)n * R + 255) / 256;
+    require(gx < 0x7fffffff, "n*R too large");
+    k_cg_unpack<<<dim3((unsigned)gx, 1, B), 256, 0, c->stream>>>(dA, 0);
+    SDGP_CHECK_LAUNCH();
+    if (V) {
+      k_cg_unpack<<<dim3((unsigned)gx, 1, B), 256, 0, c->stream>>>(dA, 1);
+      SDGP_CHECK_LAUNCH();
+    }
+  }
+  // results
+  std::vector<CgResult> out(B);
+  std::vector<int32_t> its((size_t)R * B), actv((size_t)2 * R * B);
+  std::vector<double> bn((size_t)R * B), rl((size_t)R * B);
+  for (int m = 0; m < B; ++m) {
+    SDGP_HIP(hipMemcpyAsync(&its[(size_t)m * R], hA[m].st.iters, R * sizeof(int32_t), hipMemcpyDeviceToHost,
+                            c->stream));
+    SDGP_HIP(hipMemcpyAsync(&actv[(size_t)2 * m * R], hA[m].st.act, 2 * R * sizeof(int32_t),
+                            hipMemcpyDeviceToHost, c->stream));
+    SDGP_HIP(hipMemcpyAsync(&bn[(size_t)m * R], hA[m].st.bnorm2, R * sizeof(double), hipMemcpyDeviceToHost,
+                            c->stream));
+    SDGP_HIP(hipMemcpyAsync(&rl[(size_t)m * R], hA[m].st.rr_last, R * sizeof(double), hipMemcpyDeviceToHost,
+                            c->stream));
+    SDGP_HIP(hipMemcpyAsync(&flags[3 * m], hA[m].st.done, 3 * sizeof(int32_t), hipMemcpyDeviceToHost,
+                            c->stream));
+  }
+  SDGP_HIP(hipStreamSynchronize(c->stream));
+  for (int m = 0; m < B; ++m) {
+    CgResult& res = out[m];
+    const CgArgs& A = hA[m];
+    res.R = R;
+    res.X = A.P;
+    res.V = A.V ? A.Q : nullptr;
+    res.rz0 = A.st.rz0;
+    res.hist_a = A.st.hist_a;
+    res.hist_b = A.st.hist_b;
+    res.col_iters = A.st.iters;
+    res.not_spd = flags[3 * m + 1] != 0;
+    res.logdetM = use_pc ? mem[m].pc->logdetM : 0.0;
+    const int executed = flags[3 * m] > 0 ? flags[3 * m] : flags[3 * m + 2];
+    const int lastpar = executed & 1;  // parity holding the latest state
+    bool conv = true;
+    for (int r = 0; r < R; ++r)
+      if (actv[(size_t)2 * m * R + lastpar * R + r]) conv = false;
+    res.iters = executed;
+    res.iters_y = its[(size_t)m * R];
+    res.relres_max = 0.0;
+    for (int r = 0; r < R; ++r) {
+      const double b2 = bn[(size_t)m * R + r];
+      if (b2 > 0.0) res.relres_max = std::max(res.relres_max, std::sqrt(rl[(size_t)m * R + r] / b2));
+    }
+    res.converged = conv && !res.not_spd;
+  }
+  return out;
+}
+
+CgResult block_cg(Ctx* c, const Csr& Am, const Sorted& s, const double* ys, int kind, int P, uint64_t seed,
+                  double rtol, int max_iter, const double* dense_rhs, int dense_R, const Precond* pc,
+                  bool keep_v, PhaseTimer* t) {
+  (void)t;
+  std::vector<CgMember> mem(1);
+  mem[0].A = Am;
+  mem[0].pc = pc;
+  return block_cg_multi(c, mem, s, ys, kind, P, seed, rtol, max_iter, dense_rhs, dense_R, keep_v,
+                        c->use_graph)[0];
+}
+
+// Plain SpMM Y = A X for row-major X, Y [n][R] with R even (16-byte rows
+// of pairs): slabs of 32 columns over grid y, 16 lanes per row.
+namespace {
+__global__ __launch_bounds__(kT) void k_spmm_slab(int64_t n, const int64_t* __restrict__ row_ptr,
+                                                  const int32_t* __restrict__ col, const double* __restrict__ val,
+                                                  const double* __restrict__ X, int R, double* __restrict__ Y) {
+  const int lane = lane_id(), g = lane >> 4, j = lane & 15, w = threadIdx.x >> 6;
+  const int c0 = (int)blockIdx.y * kSlab + 2 * j;
+  const int cc = c0 + 1 < R ? c0 : R - 2;   // lanes past the last column read a valid pair
+  const int xcd = blockIdx.x & 7;
+  const int64_t bi = blockIdx.x >> 3, nbx = gridDim.x >> 3;
+  const int64_t nx = (n + 7) >> 3, lo = xcd * nx, hi = min(n, lo + nx);
+  for (int64_t pb = lo + bi * kTile + w * 4; pb < hi; pb += nbx * kTile) {
+    const int64_t a = pb + g;
+    const bool live = a < hi;
+    const int64_t k0 = live ? row_ptr[a] : 0, k1 = live ? row_ptr[a + 1] : 0;
+    double2 q;
+    double unused = 0.0;
+    slab_row<false>(k0, k1, live ? (int32_t)a : 0, col, val, X + cc, R, nullptr, q, unused);
+    if (live && c0 + 1 < R) *reinterpret_cast<double2*>(Y + a * R + c0) = q;
+  }
+}
+}  // namespace
+
+void spmm_slab(Ctx* c, const Csr& A, const double* X, int R, double* Y) {
+  require(R >= 2 && R % 2 == 0, "slab SpMM needs an even column count");
+  require(A.n <= 0x7fffffffLL, "n must fit a 32-bit column index");
+  const int64_t tiles = (A.n + kTile - 1) / kTile;
+  const int nb = (int)std::min<int64_t>(kMaxNbs, round8(tiles));
+  const int ns = (R + kSlab - 1) / kSlab;
+  k_spmm_slab<<<dim3(nb, ns), kT, 0, c->stream>>>(A.n, A.row_ptr, A.col, A.val, X, R, Y);
+  SDGP_CHECK_LAUNCH();
+}
+
+}  // namespace sdgp

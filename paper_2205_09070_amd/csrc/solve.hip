@@ -1,16 +1,12 @@
-// Iterative solves on the sparse covariance (Section 2.5): SpMM, block
-// conjugate gradients on [y, z_1..z_P], and stochastic Lanczos quadrature of
-// ln det A from the CG coefficients, for gfx950.
+// Solver helpers on the sparse covariance (Section 2.5): SpMV / SpMM,
+// dot products, the low-rank preconditioner, the posterior variance and
+// Taylor log-det drivers, and stochastic Lanczos quadrature of ln det A
+// from the CG coefficients, for gfx950.  The block CG itself is in cg.hip.
 //
-// Layout: every vector block is row-major [n][R] so one wavefront handles one
-// row and its 64 lanes hold 64 consecutive right-hand sides: a gathered
-// neighbour row X[b, :] is one coalesced load.  CSR entries of a row are
-// fetched 64 at a time by the lanes and broadcast with readlane.
-//
-// Reductions are deterministic: each block writes per-column partial sums;
-// the consumer kernel of the next phase re-reduces all partials of its
-// column chunk in a fixed order inside every block (so every block obtains
-// bit-identical scalars without atomics or grid-wide barriers).
+// Caller-facing SpMM on row-major [n][R] blocks: R == 1 takes the SpMV
+// kernel (16 lanes per row), even R the 32-column slab kernel of cg.hip,
+// odd R a one-wavefront-per-row kernel whose 64 lanes hold 64 consecutive
+// columns.  Reductions are deterministic (fixed-order block partials).
 #include <algorithm>
 #include <atomic>
 #include <cmath>
@@ -23,9 +19,6 @@
 namespace sdgp {
 
 namespace {
-
-constexpr int kCgBlock = 1024;             // 16 wavefronts
-constexpr int kCgWaves = kCgBlock / kWave;
 
 // y = sum_k val[k] X[col[k], rc] over one CSR row (the calling wave's row).
 // The row's entries are loaded 64 at a time by the lanes and broadcast with
@@ -131,484 +124,6 @@ __global__ __launch_bounds__(256) void k_spmv(int64_t n, const int64_t* __restri
   }
 }
 
-struct CgState {
-  double* rz;       // [2][R] parity buffers of the CG scalar r.z (r.r unpreconditioned)
-  double* rz0;      // [R] b^T M^{-1} b (b^T b unpreconditioned): SLQ weight
-  int32_t* act;     // [2][R] active flags
-  int32_t* failed;  // [R] p^T A p <= 0 met
-  double* bnorm2;   // [R]
-  double* rr_last;  // [R] |r|^2 at each column's last iteration
-  int32_t* iters;   // [R]
-  int32_t* done;    // [1] executed iterations once every column stopped
-  int32_t* not_spd; // [1]
-  int32_t* it;      // [1] iteration counter (advanced by k_cg_check)
-  double* hist_a;   // [max_iter][R]
-  double* hist_b;   // [max_iter][R]
-};
-
-// Fixed-order reduction of per-block partials part[b*stride + rc] (b < nb)
-// for the 64-column chunk of this block into sh[0..63].  All blocks obtain
-// bit-identical values.
-__device__ void chunk_reduce(const double* __restrict__ part, int nb, int64_t stride, int R, double* sh,
-                             double* scratch) {
-  const int t = threadIdx.x;
-  const int l = t & 63, w = t >> 6;
-  const int rc = blockIdx.y * kWave + l;
-  double s = 0.0;
-  if (rc < R)
-    for (int b = w; b < nb; b += kCgWaves) s += part[(int64_t)b * stride + rc];
-  scratch[w * kWave + l] = s;
-  __syncthreads();
-  if (t < kWave) {
-    double tot = 0.0;
-    for (int q = 0; q < kCgWaves; ++q) tot += scratch[q * kWave + t];
-    sh[t] = tot;
-  }
-  __syncthreads();
-}
-
-// Block partial of per-lane values over the block's waves into
-// part[blockIdx.x*stride + rc].
-__device__ void block_partial(double v, double* scratch, double* part, int64_t stride, int R) {
-  const int t = threadIdx.x;
-  const int l = t & 63, w = t >> 6;
-  __syncthreads();
-  scratch[w * kWave + l] = v;
-  __syncthreads();
-  if (t < kWave) {
-    double tot = 0.0;
-    for (int q = 0; q < kCgWaves; ++q) tot += scratch[q * kWave + t];
-    const int rc = blockIdx.y * kWave + t;
-    if (rc < R) part[(int64_t)blockIdx.x * stride + rc] = tot;
-  }
-}
-
-struct CgArgs {
-  int64_t n;
-  int R;
-  const int64_t* row_ptr;
-  const int32_t* col;
-  const double* val;
-  double *X, *Rr, *P, *Q;
-  double* part;        // [nb][R] p.Ap partials (written by the SpMM, read by update_xr)
-  double* part2;       // [nb][R] r.r partials (written by update_xr / norm_part, read after)
-  double* partg;       // [nb][n1][R]  F^T p / F^T r partials (each reduced by its own launch)
-  double* g;           // [n1][R]
-  double* V;           // [n][R] M^{-1} b (preconditioned, may be null)
-  const int32_t* sched;  // row processing order for the SpMM (may be null)
-  const double* F;     // [n][n1] sorted bump values
-  const double* Sinv;  // [n1][n1] (c I + F^T F)^{-1}
-  int n1;
-  int use_pc;          // preconditioned: g = F^T r, z = M^{-1} r on the fly
-  int lowrank_op;      // operator K_core P + F (F^T P) (SUM combine)
-  double* gp;          // [n1][R] F^T p (lowrank_op)
-  double inv_c, sqrt_c;
-  int nb;
-  int max_iter;
-  CgState st;
-  double rtol2;
-};
-
-// Per-block partials of F^T v (v: this lane's column of the block's rows)
-// given per-lane accumulators acc[NI]: reduced 4 at a time through LDS.
-template <int NI>
-__device__ void block_partial_g(const double* acc, double* gs, const CgArgs& A, double* out) {
-  const int t = threadIdx.x;
-  const int l = t & 63, w = t >> 6;
-  const int rc = blockIdx.y * kWave + l;
-#pragma unroll
-  for (int i0 = 0; i0 < NI; i0 += 4) {
-    if (i0 >= A.n1) break;
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 4; ++q) gs[(q * kCgWaves + w) * kWave + l] = acc[i0 + q];
-    __syncthreads();
-    if (t < 4 * kWave) {
-      const int q = t >> 6;
-      const int i = i0 + q;
-      double tot = 0.0;
-      for (int ww = 0; ww < kCgWaves; ++ww) tot += gs[(q * kCgWaves + ww) * kWave + l];
-      if (i < A.n1 && rc < A.R) out[((int64_t)blockIdx.x * A.n1 + i) * A.R + rc] = tot;
-    }
-  }
-}
-
-// u = Sinv g for the block's 64 columns into us[i][l] (gs, us in LDS), then
-// gu[l] = g.u per column.  g is read from A.g.
-template <int NI>
-__device__ void solve_small(const CgArgs& A, double* gs, double* us, double* gu) {
-  const int t = threadIdx.x;
-  const int l = t & 63;
-  const int rc = blockIdx.y * kWave + l;
-  for (int idx = t; idx < A.n1 * kWave; idx += blockDim.x) {
-    const int i = idx >> 6, ll = idx & 63;
-    const int r = blockIdx.y * kWave + ll;
-    gs[i * kWave + ll] = r < A.R ? A.g[(int64_t)i * A.R + r] : 0.0;
-  }
-  __syncthreads();
-  for (int idx = t; idx < A.n1 * kWave; idx += blockDim.x) {
-    const int i = idx >> 6, ll = idx & 63;
-    double u = 0.0;
-    for (int j = 0; j < A.n1; ++j) u += A.Sinv[i * A.n1 + j] * gs[j * kWave + ll];
-    us[i * kWave + ll] = u;
-  }
-  __syncthreads();
-  if (t < kWave) {
-    double d = 0.0;
-    for (int i = 0; i < A.n1; ++i) d += gs[i * kWave + t] * us[i * kWave + t];
-    gu[t] = d;
-  }
-  __syncthreads();
-  (void)rc;
-}
-
-// z_a = M^{-1} r at row a, column lane: (r - F_a . u) / c.
-template <int NI>
-__device__ __forceinline__ double apply_prec(const CgArgs& A, int64_t a, double r, const double* us) {
-  if (NI == 0) return r;
-  const int lane = lane_id();
-  const double* Fa = A.F + a * (int64_t)A.n1;
-  double s = 0.0;
-#pragma unroll
-  for (int i = 0; i < NI; ++i)
-    if (i < A.n1) s += Fa[i] * us[i * kWave + lane];
-  return (r - s) * A.inv_c;
-}
-
-// Q = A P (with the factored operator: Q = K_core P, and F^T P partials),
-// partial p.q per column.
-template <int NI>
-__global__ __launch_bounds__(kCgBlock) void k_cg_spmm(const CgArgs* __restrict__ AA) {
-  const CgArgs& A = AA[blockIdx.z];
-  if (*A.st.done || *A.st.it >= A.max_iter) return;
-  __shared__ double scratch[kCgBlock];
-  __shared__ double gsh[NI > 0 ? 4 * kCgBlock : 1];
-  const int lane = lane_id();
-  const int rc = blockIdx.y * kWave + lane;
-  const int rcc = rc < A.R ? rc : A.R - 1;
-  const int64_t R = A.R;
-  double pq = 0.0;
-  double gacc[NI > 0 ? NI : 1];
-#pragma unroll
-  for (int i = 0; i < (NI > 0 ? NI : 1); ++i) gacc[i] = 0.0;
-  const bool lr = NI > 0 && A.lowrank_op;
-  for (RowSweep w(A.n, kCgWaves); w.a < w.hi; w.a += w.step) {
-    const int64_t a = A.sched ? (int64_t)A.sched[w.a] : w.a;
-    const double q = row_dot(A.row_ptr[a], A.row_ptr[a + 1], A.col, A.val, A.P + rcc, R);
-    if (rc < A.R) {
-      A.Q[a * R + rc] = q;
-      const double pa = A.P[a * R + rc];
-      pq += pa * q;
-      if (lr) {
-        const double* Fa = A.F + a * (int64_t)A.n1;
-#pragma unroll
-        for (int i = 0; i < (NI > 0 ? NI : 1); ++i)
-          if (i < A.n1) gacc[i] += Fa[i] * pa;
-      }
-    }
-  }
-  block_partial(pq, scratch, A.part, A.R, A.R);
-  if (lr) block_partial_g<NI>(gacc, gsh, A, A.partg);
-}
-
-// out[i][r] = sum_b partg[b][i][r] (fixed order); grid (n1, chunks).
-__global__ __launch_bounds__(kCgBlock) void k_cg_reduce_g(const CgArgs* __restrict__ AA, int which) {
-  const CgArgs& A = AA[blockIdx.z];
-  if (*A.st.done || *A.st.it >= A.max_iter) return;
-  double* __restrict__ out = which == 0 ? A.gp : A.g;
-  __shared__ double scratch[kCgBlock];
-  const int i = blockIdx.x;
-  const int t = threadIdx.x;
-  const int l = t & 63, w = t >> 6;
-  const int rc = blockIdx.y * kWave + l;
-  double s = 0.0;
-  if (rc < A.R)
-    for (int b = w; b < A.nb; b += kCgWaves) s += A.partg[((int64_t)b * A.n1 + i) * A.R + rc];
-  scratch[w * kWave + l] = s;
-  __syncthreads();
-  if (t < kWave && rc < A.R) {
-    double tot = 0.0;
-    for (int q = 0; q < kCgWaves; ++q) tot += scratch[q * kWave + t];
-    out[(int64_t)i * A.R + rc] = tot;
-  }
-}
-
-// One row of the x/r update (lane = column): returns the new residual.
-template <int NI>
-__device__ __forceinline__ void xr_row(const CgArgs& A, int64_t a, int rc, double alpha, const double* gpl,
-                                       double& rr, double* gacc) {
-  const int64_t o = a * (int64_t)A.R + rc;
-  double q = A.Q[o];
-  const double* Fa = A.F + a * (int64_t)A.n1;
-  if (NI > 0 && A.lowrank_op) {
-    double s = 0.0;
-#pragma unroll
-    for (int i = 0; i < (NI > 0 ? NI : 1); ++i)
-      if (i < A.n1) s += Fa[i] * gpl[i * kWave + (rc & 63)];
-    q += s;
-  }
-  A.X[o] += alpha * A.P[o];
-  const double r = A.Rr[o] - alpha * q;
-  A.Rr[o] = r;
-  rr += r * r;
-  if (NI > 0 && A.use_pc) {
-#pragma unroll
-    for (int i = 0; i < (NI > 0 ? NI : 1); ++i)
-      if (i < A.n1) gacc[i] += Fa[i] * r;
-  }
-}
-
-// alpha = r.z / p.A p; x += alpha p; r -= alpha A p; partials r.r and F^T r.
-// With the factored operator p.A p = p.(K_core p) + |F^T p|^2 and
-// A p = K_core p + F (F^T p) is completed here on the fly.
-template <int NI>
-__global__ __launch_bounds__(kCgBlock) void k_cg_update_xr(const CgArgs* __restrict__ AA) {
-  const CgArgs& A = AA[blockIdx.z];
-  if (*A.st.done) return;
-  const int it = *A.st.it;
-  if (it >= A.max_iter) return;
-  __shared__ double scratch[kCgBlock];
-  __shared__ double pAp[kWave];
-  __shared__ double gsh[NI > 0 ? 4 * kCgBlock : 1];
-  __shared__ double gpl[NI > 0 ? NI * kWave : 1];
-  chunk_reduce(A.part, A.nb, A.R, A.R, pAp, scratch);
-  const int lane = lane_id();
-  const int rc = blockIdx.y * kWave + lane;
-  if (NI > 0 && A.lowrank_op) {
-    for (int idx = threadIdx.x; idx < A.n1 * kWave; idx += blockDim.x) {
-      const int i = idx >> 6, ll = idx & 63;
-      const int r = blockIdx.y * kWave + ll;
-      gpl[i * kWave + ll] = r < A.R ? A.gp[(int64_t)i * A.R + r] : 0.0;
-    }
-    __syncthreads();
-    if (threadIdx.x < kWave) {
-      double gg = 0.0;
-      for (int i = 0; i < A.n1; ++i) gg += gpl[i * kWave + threadIdx.x] * gpl[i * kWave + threadIdx.x];
-      pAp[threadIdx.x] += gg;
-    }
-    __syncthreads();
-  }
-  const int par = it & 1;
-  double alpha = 0.0;
-  bool act = false;
-  if (rc < A.R) {
-    act = A.st.act[par * A.R + rc] != 0;
-    if (act) {
-      const double d = pAp[lane];
-      if (d > 0.0 && isfinite(d)) alpha = A.st.rz[par * A.R + rc] / d;
-      else act = false;
-    }
-  }
-  if (blockIdx.x == 0 && threadIdx.x < kWave && rc < A.R) {
-    const bool was = A.st.act[par * A.R + rc] != 0;
-    if (was) A.st.hist_a[(int64_t)it * A.R + rc] = alpha;
-    if (was && !act) { A.st.failed[rc] = 1; *A.st.not_spd = 1; }
-  }
-  const int64_t W = (int64_t)gridDim.x * kCgWaves;
-  double rr = 0.0;
-  double gacc[NI > 0 ? NI : 1];
-#pragma unroll
-  for (int i = 0; i < (NI > 0 ? NI : 1); ++i) gacc[i] = 0.0;
-  if (act) {
-    // two rows in flight per wave
-    int64_t a = blockIdx.x * (int64_t)kCgWaves + (threadIdx.x >> 6);
-    for (; a + W < A.n; a += 2 * W) {
-      xr_row<NI>(A, a, rc, alpha, gpl, rr, gacc);
-      xr_row<NI>(A, a + W, rc, alpha, gpl, rr, gacc);
-    }
-    if (a < A.n) xr_row<NI>(A, a, rc, alpha, gpl, rr, gacc);
-  }
-  block_partial(rr, scratch, A.part2, A.R, A.R);
-  if (NI > 0 && A.use_pc) block_partial_g<NI>(gacc, gsh, A, A.partg);
-}
-
-// beta = r.z_new / r.z; convergence on |r|; p = z + beta p with
-// z = M^{-1} r formed on the fly (r.z_new = (r.r - g.u)/c, g = F^T r,
-// u = (cI + F^T F)^{-1} g, so no extra pass is needed).
-template <int NI>
-__global__ __launch_bounds__(kCgBlock) void k_cg_update_p(const CgArgs* __restrict__ AA) {
-  const CgArgs& A = AA[blockIdx.z];
-  if (*A.st.done) return;
-  const int it = *A.st.it;
-  if (it >= A.max_iter) return;
-  __shared__ double scratch[kCgBlock];
-  __shared__ double rrn[kWave];
-  __shared__ double gu[kWave];
-  __shared__ double gs[NI > 0 ? NI * kWave : 1];
-  __shared__ double us[NI > 0 ? NI * kWave : 1];
-  chunk_reduce(A.part2, A.nb, A.R, A.R, rrn, scratch);
-  const bool pc = NI > 0 && A.use_pc;
-  if (pc) solve_small<NI>(A, gs, us, gu);
-  const int lane = lane_id();
-  const int rc = blockIdx.y * kWave + lane;
-  const int par = it & 1, nxt = par ^ 1;
-  double beta = 0.0;
-  bool cont = false;
-  bool act = false;
-  double rz_new = 0.0, rz_old = 0.0;
-  if (rc < A.R) {
-    act = A.st.act[par * A.R + rc] != 0 && A.st.failed[rc] == 0;
-    rz_old = A.st.rz[par * A.R + rc];
-    const double rr_new = rrn[lane];
-    rz_new = pc ? (rr_new - gu[lane]) * A.inv_c : rr_new;
-    if (act) {
-      beta = rz_new / rz_old;
-      cont = !(rr_new <= A.rtol2 * A.st.bnorm2[rc]);
-    }
-  }
-  if (blockIdx.x == 0 && threadIdx.x < kWave && rc < A.R) {
-    A.st.rz[nxt * A.R + rc] = act ? rz_new : rz_old;
-    A.st.act[nxt * A.R + rc] = cont ? 1 : 0;
-    if (act) {
-      A.st.hist_b[(int64_t)it * A.R + rc] = beta;
-      A.st.iters[rc] += 1;
-      A.st.rr_last[rc] = rrn[lane];
-    }
-  }
-  const int64_t R = A.R;
-  const int64_t W = (int64_t)gridDim.x * kCgWaves;
-  if (cont) {
-    int64_t a = blockIdx.x * (int64_t)kCgWaves + (threadIdx.x >> 6);
-    for (; a + W < A.n; a += 2 * W) {
-      const int64_t o0 = a * R + rc, o1 = (a + W) * R + rc;
-      const double r0 = A.Rr[o0], r1 = A.Rr[o1];
-      const double p0 = A.P[o0], p1 = A.P[o1];
-      const double z0 = pc ? apply_prec<NI>(A, a, r0, us) : r0;
-      const double z1 = pc ? apply_prec<NI>(A, a + W, r1, us) : r1;
-      A.P[o0] = z0 + beta * p0;
-      A.P[o1] = z1 + beta * p1;
-    }
-    if (a < A.n) {
-      const int64_t o = a * R + rc;
-      A.P[o] = (pc ? apply_prec<NI>(A, a, A.Rr[o], us) : A.Rr[o]) + beta * A.P[o];
-    }
-  }
-}
-
-// Records the executed iteration count in done when no column is active
-// (one block, after update_p).
-__global__ void k_cg_check(const CgArgs* __restrict__ AA) {
-  const CgArgs& A = AA[blockIdx.z];
-  if (*A.st.done) return;
-  const int it = *A.st.it;
-  if (it >= A.max_iter) return;
-  const int nxt = (it & 1) ^ 1;
-  __shared__ int left;
-  if (threadIdx.x == 0) left = 0;
-  __syncthreads();
-  int mine = 0;
-  for (int r = threadIdx.x; r < A.R; r += blockDim.x) mine |= A.st.act[nxt * A.R + r];
-  if (mine) atomicOr(&left, 1);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    if (!left) *A.st.done = it + 1;
-    *A.st.it = it + 1;
-  }
-}
-
-// Right-hand sides and x = 0, r = b.  Probe p (column 1+p) is the Rademacher
-// vector w_p of caller row perm[a], or with the preconditioner
-// sqrt(c) w_p + F v_p (v_p: n1 Rademacher signs), whose covariance is M.
-__global__ void k_cg_init(const CgArgs* __restrict__ AA, const double* __restrict__ ys,
-                          const int32_t* __restrict__ perm, int kind, uint64_t seed,
-                          const double* __restrict__ dense) {
-  const CgArgs& A = AA[blockIdx.z];
-  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const int64_t tot = A.n * (int64_t)A.R;
-  if (idx >= tot) return;
-  const int64_t a = idx / A.R;
-  const int r = (int)(idx % A.R);
-  double b;
-  if (kind == PK_DENSE) {
-    b = dense[idx];
-  } else if (r == 0) {
-    b = ys[a];
-  } else if (kind == PK_IDENTITY) {
-    b = (perm[a] == r - 1) ? 1.0 : 0.0;
-  } else {
-    const uint64_t pbase = (uint64_t)(r - 1) << 32;
-    b = (splitmix64_at(seed, pbase + (uint64_t)perm[a] + 1ull) >> 63) ? -1.0 : 1.0;
-    if (A.use_pc) {
-      double fv = 0.0;
-      const double* Fa = A.F + a * (int64_t)A.n1;
-      for (int i = 0; i < A.n1; ++i) {
-        const double v = (splitmix64_at(seed, pbase + 0xFFFFFFFFull - (uint64_t)i) >> 63) ? -1.0 : 1.0;
-        fv += Fa[i] * v;
-      }
-      b = A.sqrt_c * b + fv;
-    }
-  }
-  A.X[idx] = 0.0;
-  A.Rr[idx] = b;
-}
-
-// Partials of b.b and F^T b.
-template <int NI>
-__global__ __launch_bounds__(kCgBlock) void k_cg_norm_part(const CgArgs* __restrict__ AA) {
-  const CgArgs& A = AA[blockIdx.z];
-  __shared__ double scratch[kCgBlock];
-  __shared__ double gsh[NI > 0 ? 4 * kCgBlock : 1];
-  const int rc = blockIdx.y * kWave + lane_id();
-  const int64_t R = A.R;
-  const int64_t W = (int64_t)gridDim.x * kCgWaves;
-  double s = 0.0;
-  double gacc[NI > 0 ? NI : 1];
-#pragma unroll
-  for (int i = 0; i < (NI > 0 ? NI : 1); ++i) gacc[i] = 0.0;
-  if (rc < A.R)
-    for (int64_t a = blockIdx.x * (int64_t)kCgWaves + (threadIdx.x >> 6); a < A.n; a += W) {
-      const double v = A.Rr[a * R + rc];
-      s += v * v;
-      if (NI > 0 && A.use_pc) {
-        const double* Fa = A.F + a * (int64_t)A.n1;
-#pragma unroll
-        for (int i = 0; i < NI; ++i)
-          if (i < A.n1) gacc[i] += Fa[i] * v;
-      }
-    }
-  block_partial(s, scratch, A.part2, A.R, A.R);
-  if (NI > 0 && A.use_pc) block_partial_g<NI>(gacc, gsh, A, A.partg);
-}
-
-// Initial state: p = z0 = M^{-1} b (b when unpreconditioned), V = z0,
-// rz0 = b.z0, bnorm2 = b.b.
-template <int NI>
-__global__ __launch_bounds__(kCgBlock) void k_cg_init_fin(const CgArgs* __restrict__ AA) {
-  const CgArgs& A = AA[blockIdx.z];
-  __shared__ double scratch[kCgBlock];
-  __shared__ double nrm[kWave];
-  __shared__ double gu[kWave];
-  __shared__ double gs[NI > 0 ? NI * kWave : 1];
-  __shared__ double us[NI > 0 ? NI * kWave : 1];
-  chunk_reduce(A.part2, A.nb, A.R, A.R, nrm, scratch);
-  const bool pc = NI > 0 && A.use_pc;
-  if (pc) solve_small<NI>(A, gs, us, gu);
-  const int lane = lane_id();
-  const int rc = blockIdx.y * kWave + lane;
-  if (blockIdx.x == 0 && threadIdx.x < kWave && rc < A.R) {
-    const double bb = nrm[lane];
-    const double rz0 = pc ? (bb - gu[lane]) * A.inv_c : bb;
-    A.st.bnorm2[rc] = bb;
-    A.st.rr_last[rc] = bb;
-    A.st.rz[rc] = rz0;
-    A.st.rz[A.R + rc] = rz0;
-    A.st.rz0[rc] = rz0;
-    A.st.act[rc] = bb > 0.0 ? 1 : 0;
-    A.st.act[A.R + rc] = 0;
-    A.st.failed[rc] = 0;
-    A.st.iters[rc] = 0;
-  }
-  const int64_t R = A.R;
-  const int64_t W = (int64_t)gridDim.x * kCgWaves;
-  if (rc < A.R)
-    for (int64_t a = blockIdx.x * (int64_t)kCgWaves + (threadIdx.x >> 6); a < A.n; a += W) {
-      const int64_t o = a * R + rc;
-      const double z = pc ? apply_prec<NI>(A, a, A.Rr[o], us) : A.Rr[o];
-      A.P[o] = z;
-      if (A.V) A.V[o] = z;
-    }
-}
-
 // ------------------------------------------------------------ utilities
 __global__ void k_dot_part(const double* __restrict__ a, int64_t sa, const double* __restrict__ b,
                            int64_t sb, int64_t n, double* __restrict__ part) {
@@ -662,8 +177,6 @@ __global__ void k_rowdot_chunk(const int64_t* __restrict__ rp, const int32_t* __
   if (lane_id() == 0) var[t] = kxx[t] - s;
 }
 
-// Blocks per column chunk for the CG kernels: about two 1024-thread blocks
-// per CU, a multiple of 8 (the XCD-aware row sweep needs it).
 // Gershgorin bound: per-block partial maxima of sum_b |A_ab| over rows.
 __global__ void k_rowabs_max(const int64_t* __restrict__ rp, const double* __restrict__ val, int64_t n,
                              double* __restrict__ part) {
@@ -713,14 +226,6 @@ __global__ void k_taylor_step(int64_t len, const double* __restrict__ Z, const d
     __syncthreads();
   }
   if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
-}
-
-inline int cg_nb(int64_t n, int R) {
-  const int chunks = (R + kWave - 1) / kWave;
-  int64_t nb = std::max<int64_t>(1, 512 / chunks);
-  nb = std::min<int64_t>(nb, (n + kCgWaves - 1) / kCgWaves);
-  nb = (nb + 7) / 8 * 8;
-  return (int)nb;
 }
 
 }  // namespace
@@ -795,6 +300,10 @@ void spmm(Ctx* c, const Csr& A, const double* X, int R, double* Y) {
     SDGP_CHECK_LAUNCH();
     return;
   }
+  if (R % 2 == 0 && (reinterpret_cast<uintptr_t>(X) % 16) == 0 && (reinterpret_cast<uintptr_t>(Y) % 16) == 0) {
+    spmm_slab(c, A, X, R, Y);
+    return;
+  }
   const int chunks = (R + kWave - 1) / kWave;
   int64_t blocks = std::min<int64_t>((A.n + 3) / 4, std::max<int64_t>(8, cu * 8 / chunks));
   blocks = std::max<int64_t>(8, (blocks + 7) / 8 * 8);
@@ -853,58 +362,6 @@ __global__ __launch_bounds__(256) void k_gram(const double* __restrict__ F, int6
   for (int q = 0; q < 16; ++q) {
     const int idx = threadIdx.x + q * 256;
     if (idx < np) part[(int64_t)blockIdx.x * np + idx] = acc[q];
-  }
-}
-
-// One CG iteration for every member (grid z = member).
-template <int NI>
-void launch_cg_iteration(hipStream_t st, const CgArgs* dA, const CgArgs& h0, dim3 grid, int chunks, int B,
-                         Ctx* c) {
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (c != nullptr && c->timing) { e0 = c->event(); SDGP_HIP(hipEventRecord(e0, st)); }
-  k_cg_spmm<NI><<<grid, kCgBlock, 0, st>>>(dA);
-  SDGP_CHECK_LAUNCH();
-  if (c != nullptr && c->timing) {
-    e1 = c->event();
-    SDGP_HIP(hipEventRecord(e1, st));
-    c->spmm_events.push_back({e0, e1});
-  }
-  if (NI > 0 && h0.lowrank_op) {
-    k_cg_reduce_g<<<dim3(h0.n1, chunks, B), kCgBlock, 0, st>>>(dA, 0);
-    SDGP_CHECK_LAUNCH();
-  }
-  k_cg_update_xr<NI><<<grid, kCgBlock, 0, st>>>(dA);
-  SDGP_CHECK_LAUNCH();
-  if (NI > 0 && h0.use_pc) {
-    k_cg_reduce_g<<<dim3(h0.n1, chunks, B), kCgBlock, 0, st>>>(dA, 1);
-    SDGP_CHECK_LAUNCH();
-  }
-  k_cg_update_p<NI><<<grid, kCgBlock, 0, st>>>(dA);
-  SDGP_CHECK_LAUNCH();
-  k_cg_check<<<dim3(1, 1, B), 256, 0, st>>>(dA);
-  SDGP_CHECK_LAUNCH();
-}
-
-template <int NI>
-void launch_cg_init(hipStream_t st, const CgArgs* dA, const CgArgs& h0, dim3 grid, int chunks, int B) {
-  k_cg_norm_part<NI><<<grid, kCgBlock, 0, st>>>(dA);
-  SDGP_CHECK_LAUNCH();
-  if (NI > 0 && h0.use_pc) {
-    k_cg_reduce_g<<<dim3(h0.n1, chunks, B), kCgBlock, 0, st>>>(dA, 1);
-    SDGP_CHECK_LAUNCH();
-  }
-  k_cg_init_fin<NI><<<grid, kCgBlock, 0, st>>>(dA);
-  SDGP_CHECK_LAUNCH();
-}
-
-void cg_iteration(int NI, hipStream_t st, const CgArgs* dA, const CgArgs& h0, dim3 grid, int chunks, int B,
-                  Ctx* c) {
-  switch (NI) {
-    case 0: launch_cg_iteration<0>(st, dA, h0, grid, chunks, B, c); break;
-    case 8: launch_cg_iteration<8>(st, dA, h0, grid, chunks, B, c); break;
-    case 16: launch_cg_iteration<16>(st, dA, h0, grid, chunks, B, c); break;
-    case 32: launch_cg_iteration<32>(st, dA, h0, grid, chunks, B, c); break;
-    default: launch_cg_iteration<64>(st, dA, h0, grid, chunks, B, c); break;
   }
 }
 
@@ -972,228 +429,6 @@ Precond lowrank_precond(Ctx* c, const Sorted& s, const KParams& kp, const Bumps&
   return pc;
 }
 
-std::vector<CgResult> block_cg_multi(Ctx* c, const std::vector<CgMember>& mem, const Sorted& s, const double* ys,
-                                     int kind, int P, uint64_t seed, double rtol, int max_iter,
-                                     const double* dense_rhs, int dense_R, bool keep_v, bool use_graph) {
-  const int B = (int)mem.size();
-  require(B >= 1 && B <= 65535, "1..65535 members");
-  const int64_t n = s.n;
-  int R;
-  if (kind == PK_DENSE) R = dense_R;
-  else if (kind == PK_IDENTITY) R = (int)(1 + n);
-  else if (kind == PK_NONE) R = 1;
-  else R = 1 + P;
-  require(R >= 1, "no right-hand sides");
-  require(max_iter >= 1, "cg_max_iter must be >= 1");
-  require(rtol > 0.0 && std::isfinite(rtol), "cg_rtol must be > 0");
-  require(kind != PK_DENSE || B == 1, "dense right-hand sides take one member");
-  const Precond* pc0 = mem[0].pc;
-  const bool use_pc = pc0 != nullptr && pc0->n1 > 0 && pc0->apply;
-  const bool use_lr = pc0 != nullptr && pc0->n1 > 0 && pc0->lowrank_op;
-  const int n1 = (use_pc || use_lr) ? pc0->n1 : 0;
-  for (int m = 0; m < B; ++m) {
-    const Precond* p = mem[m].pc;
-    const bool up = p != nullptr && p->n1 > 0 && p->apply;
-    const bool ul = p != nullptr && p->n1 > 0 && p->lowrank_op;
-    require(up == use_pc && ul == use_lr && (!(up || ul) || p->n1 == n1), "members must share the solver form");
-    require(mem[m].A.n == n, "members must share the point set");
-  }
-  const int NI = n1 == 0 ? 0 : (n1 <= 8 ? 8 : (n1 <= 16 ? 16 : (n1 <= 32 ? 32 : 64)));
-  const size_t NR = (size_t)n * R;
-  const int nb = cg_nb(n, R);
-  const int chunks = (R + kWave - 1) / kWave;
-  double* X = c->get<double>(S_CG_X, NR * B);
-  double* Rr = c->get<double>(S_CG_R, NR * B);
-  double* Pp = c->get<double>(S_CG_P, NR * B);
-  double* Q = c->get<double>(S_CG_Q, NR * B);
-  double* V = (use_pc && keep_v) ? c->get<double>(S_CG_V, NR * B) : nullptr;
-  double* part = c->get<double>(S_CG_PART, (size_t)nb * R * B);
-  double* part2 = c->get<double>(S_CG_PART2, (size_t)nb * R * B);
-  double* partg = n1 > 0 ? c->get<double>(S_CG_PARTG, (size_t)nb * n1 * R * B) : nullptr;
-  double* g = use_pc ? c->get<double>(S_CG_G, (size_t)n1 * R * B) : nullptr;
-  double* gp = use_lr ? c->get<double>(S_CG_GP, (size_t)n1 * R * B) : nullptr;
-  double* ha = c->get<double>(S_CG_HIST_A, (size_t)max_iter * R * B);
-  double* hb = c->get<double>(S_CG_HIST_B, (size_t)max_iter * R * B);
-  // per-member state block: doubles rz[2R], rz0[R], bnorm2[R], rr_last[R];
-  // ints act[2R], failed[R], iters[R], done, not_spd, it
-  const size_t sbytes = ((5 * (size_t)R) * 8 + (4 * (size_t)R + 3) * 4 + 255) / 256 * 256;
-  char* sb = c->get<char>(S_CG_STATE, sbytes * B);
-  SDGP_HIP(hipMemsetAsync(sb, 0, sbytes * B, c->stream));
-  std::vector<CgArgs> hA(B);
-  for (int m = 0; m < B; ++m) {
-    CgArgs& A = hA[m];
-    const Csr& Am = mem[m].A;
-    const Precond* p = mem[m].pc;
-    A.n = n;
-    A.R = R;
-    A.row_ptr = Am.row_ptr;
-    A.col = Am.col;
-    A.val = Am.val;
-    A.X = X + m * NR;
-    A.Rr = Rr + m * NR;
-    A.P = Pp + m * NR;
-    A.Q = Q + m * NR;
-    A.V = V ? V + m * NR : nullptr;
-    A.sched = s.sched;
-    A.part = part + (size_t)m * nb * R;
-    A.part2 = part2 + (size_t)m * nb * R;
-    A.partg = partg ? partg + (size_t)m * nb * n1 * R : nullptr;
-    A.g = g ? g + (size_t)m * n1 * R : nullptr;
-    A.gp = gp ? gp + (size_t)m * n1 * R : nullptr;
-    A.n1 = n1;
-    A.use_pc = use_pc ? 1 : 0;
-    A.lowrank_op = use_lr ? 1 : 0;
-    A.F = n1 > 0 ? p->F : nullptr;
-    A.Sinv = use_pc ? p->Sinv : nullptr;
-    A.inv_c = use_pc ? 1.0 / p->c : 1.0;
-    A.sqrt_c = use_pc ? std::sqrt(p->c) : 1.0;
-    A.nb = nb;
-    A.max_iter = max_iter;
-    A.rtol2 = rtol * rtol;
-    char* mb = sb + sbytes * m;
-    A.st.rz = reinterpret_cast<double*>(mb);
-    A.st.rz0 = A.st.rz + 2 * (size_t)R;
-    A.st.bnorm2 = A.st.rz0 + R;
-    A.st.rr_last = A.st.bnorm2 + R;
-    int32_t* ib = reinterpret_cast<int32_t*>(A.st.rr_last + R);
-    A.st.act = ib;
-    A.st.failed = ib + 2 * (size_t)R;
-    A.st.iters = A.st.failed + R;
-    A.st.done = A.st.iters + R;
-    A.st.not_spd = A.st.done + 1;
-    A.st.it = A.st.not_spd + 1;
-    A.st.hist_a = ha + (size_t)m * max_iter * R;
-    A.st.hist_b = hb + (size_t)m * max_iter * R;
-  }
-  CgArgs* dA = c->get<CgArgs>(S_CG_ARGS, B);
-  SDGP_HIP(hipMemcpyAsync(dA, hA.data(), B * sizeof(CgArgs), hipMemcpyHostToDevice, c->stream));
-  {
-    const int64_t tot = (int64_t)NR;
-    const int64_t gx = (tot + 255) / 256;
-    require(gx < 0x7fffffff, "n*R too large");
-    k_cg_init<<<dim3((unsigned)gx, 1, B), 256, 0, c->stream>>>(dA, ys, s.perm, kind, seed, dense_rhs);
-    SDGP_CHECK_LAUNCH();
-  }
-  dim3 grid(nb, chunks, B);
-  switch (NI) {
-    case 0: launch_cg_init<0>(c->stream, dA, hA[0], grid, chunks, B); break;
-    case 8: launch_cg_init<8>(c->stream, dA, hA[0], grid, chunks, B); break;
-    case 16: launch_cg_init<16>(c->stream, dA, hA[0], grid, chunks, B); break;
-    case 32: launch_cg_init<32>(c->stream, dA, hA[0], grid, chunks, B); break;
-    default: launch_cg_init<64>(c->stream, dA, hA[0], grid, chunks, B); break;
-  }
-  // iterate; poll the per-member flags now and then
-  std::vector<int32_t> flags((size_t)3 * B);
-  auto poll = [&](hipStream_t st) -> bool {
-    for (int m = 0; m < B; ++m)
-      SDGP_HIP(hipMemcpyAsync(&flags[3 * m], hA[m].st.done, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    SDGP_HIP(hipStreamSynchronize(st));
-    for (int m = 0; m < B; ++m)
-      if (flags[3 * m] == 0 && flags[3 * m + 2] < max_iter) return false;
-    return true;
-  };
-  c->spmm_events.clear();
-  int launched = 0;
-  if (use_graph) {
-    // capture k iterations once and replay them: the iteration counters live
-    // on the device, so every replay advances the solve; kernels of members
-    // that are done, or past max_iter, return at once
-    const int k = 8;
-    hipStream_t gs = c->graph_stream();
-    hipEvent_t ready = c->event();
-    SDGP_HIP(hipEventRecord(ready, c->stream));
-    SDGP_HIP(hipStreamWaitEvent(gs, ready, 0));
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    SDGP_HIP(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
-    for (int q = 0; q < k; ++q) cg_iteration(NI, gs, dA, hA[0], grid, chunks, B, nullptr);
-    SDGP_HIP(hipStreamEndCapture(gs, &graph));
-    hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    if (ie != hipSuccess) {
-      (void)hipGraphDestroy(graph);
-      throw Error(SDGP_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
-    }
-    int every = 1;
-    bool fin = false;
-    while (!fin && launched < max_iter) {
-      for (int q = 0; q < every && launched < max_iter; ++q) {
-        SDGP_HIP(hipGraphLaunch(exec, gs));
-        launched += k;
-      }
-      fin = poll(gs);
-      every = std::min(every * 2, 8);
-    }
-    (void)hipGraphExecDestroy(exec);
-    (void)hipGraphDestroy(graph);
-    hipEvent_t back = c->event();
-    SDGP_HIP(hipEventRecord(back, gs));
-    SDGP_HIP(hipStreamWaitEvent(c->stream, back, 0));
-  } else {
-    int check = 8;
-    bool fin = false;
-    while (!fin && launched < max_iter) {
-      const int upto = std::min(max_iter, launched + check);
-      for (; launched < upto; ++launched) cg_iteration(NI, c->stream, dA, hA[0], grid, chunks, B, c);
-      fin = poll(c->stream);
-      check = std::min(check * 2, 64);
-    }
-  }
-  // results
-  std::vector<CgResult> out(B);
-  std::vector<int32_t> its((size_t)R * B), actv((size_t)2 * R * B);
-  std::vector<double> bn((size_t)R * B), rl((size_t)R * B);
-  for (int m = 0; m < B; ++m) {
-    SDGP_HIP(hipMemcpyAsync(&its[(size_t)m * R], hA[m].st.iters, R * sizeof(int32_t), hipMemcpyDeviceToHost,
-                            c->stream));
-    SDGP_HIP(hipMemcpyAsync(&actv[(size_t)2 * m * R], hA[m].st.act, 2 * R * sizeof(int32_t),
-                            hipMemcpyDeviceToHost, c->stream));
-    SDGP_HIP(hipMemcpyAsync(&bn[(size_t)m * R], hA[m].st.bnorm2, R * sizeof(double), hipMemcpyDeviceToHost,
-                            c->stream));
-    SDGP_HIP(hipMemcpyAsync(&rl[(size_t)m * R], hA[m].st.rr_last, R * sizeof(double), hipMemcpyDeviceToHost,
-                            c->stream));
-    SDGP_HIP(hipMemcpyAsync(&flags[3 * m], hA[m].st.done, 3 * sizeof(int32_t), hipMemcpyDeviceToHost,
-                            c->stream));
-  }
-  SDGP_HIP(hipStreamSynchronize(c->stream));
-  for (int m = 0; m < B; ++m) {
-    CgResult& res = out[m];
-    const CgArgs& A = hA[m];
-    res.R = R;
-    res.X = A.X;
-    res.V = A.V;
-    res.rz0 = A.st.rz0;
-    res.hist_a = A.st.hist_a;
-    res.hist_b = A.st.hist_b;
-    res.col_iters = A.st.iters;
-    res.not_spd = flags[3 * m + 1] != 0;
-    res.logdetM = use_pc ? mem[m].pc->logdetM : 0.0;
-    const int executed = flags[3 * m] > 0 ? flags[3 * m] : flags[3 * m + 2];
-    const int lastpar = executed & 1;  // parity holding the latest state
-    bool conv = true;
-    for (int r = 0; r < R; ++r)
-      if (actv[(size_t)2 * m * R + lastpar * R + r]) conv = false;
-    res.iters = executed;
-    res.iters_y = its[(size_t)m * R];
-    res.relres_max = 0.0;
-    for (int r = 0; r < R; ++r) {
-      const double b2 = bn[(size_t)m * R + r];
-      if (b2 > 0.0) res.relres_max = std::max(res.relres_max, std::sqrt(rl[(size_t)m * R + r] / b2));
-    }
-    res.converged = conv && !res.not_spd;
-  }
-  return out;
-}
-
-CgResult block_cg(Ctx* c, const Csr& Am, const Sorted& s, const double* ys, int kind, int P, uint64_t seed,
-                  double rtol, int max_iter, const double* dense_rhs, int dense_R, const Precond* pc,
-                  bool keep_v, PhaseTimer* t) {
-  (void)t;
-  std::vector<CgMember> mem(1);
-  mem[0].A = Am;
-  mem[0].pc = pc;
-  return block_cg_multi(c, mem, s, ys, kind, P, seed, rtol, max_iter, dense_rhs, dense_R, keep_v,
-                        c->use_graph)[0];
-}
 
 namespace {
 
