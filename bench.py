@@ -46,6 +46,9 @@ def parse():
                    help="replay the CG iterations from a HIP graph (1; the SpMM is then not timed per launch)")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--spmv-reps", type=int, default=50)
+    p.add_argument("--copy-ref-mib", type=int, default=0,
+                   help="before the benchmark, copy a buffer of this many MiB three times (a plain device copy "
+                        "of known size, the reference that scales profiler byte counters)")
     return p.parse_args()
 
 
@@ -88,6 +91,13 @@ def main():
     n = w.x.shape[0]
     x = torch.from_numpy(w.x).to(dev)
     y = torch.from_numpy(w.y).to(dev)
+    if args.copy_ref_mib > 0:
+        src = torch.ones(args.copy_ref_mib << 17, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     pc = sd.PRECOND_LOWRANK if args.precond == "lowrank" else sd.PRECOND_NONE
     op = sd.OPERATOR_FACTORED if args.operator == "factored" else sd.OPERATOR_ASSEMBLED
     est = sd.estimator(probes=args.probes, seed=1, cg_rtol=args.rtol, cg_max_iter=20000, precond=pc,

@@ -118,35 +118,26 @@ __device__ __forceinline__ uint64_t spread_bits(uint64_t v, int dim, int nb) {
   return out;
 }
 
-__global__ void k_cell_morton(Grid g, uint64_t* __restrict__ keys, int32_t* __restrict__ ids) {
-  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (c >= g.n_cells) return;
-  int64_t r = c;
+struct MortonQ {
+  int dim, bits;
+  double lo[kMaxDim], scale[kMaxDim];
+};
+
+// Morton key of sorted point s: its quantised coordinates, bits interleaved.
+__global__ void k_point_morton(const double4* __restrict__ xs, int64_t n, MortonQ q, uint64_t* __restrict__ keys,
+                               int32_t* __restrict__ ids) {
+  const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const double4 p = xs[s];
+  const double xk[4] = {p.x, p.y, p.z, p.w};
+  const double top = (double)((1 << q.bits) - 1);
   uint64_t key = 0;
-  const int nb = 64 / g.dim;
-  for (int k = 0; k < g.dim; ++k) {
-    const uint64_t ck = (uint64_t)(r % g.G[k]);
-    r /= g.G[k];
-    key |= spread_bits(ck, g.dim, nb) << k;
+  for (int k = 0; k < q.dim; ++k) {
+    const double t = fmin(fmax((xk[k] - q.lo[k]) * q.scale[k], 0.0), top);
+    key |= spread_bits((uint64_t)t, q.dim, q.bits) << k;
   }
-  keys[c] = key;
-  ids[c] = (int32_t)c;
-}
-
-__global__ void k_cell_sizes(const int32_t* __restrict__ order, const int32_t* __restrict__ cell_start,
-                             int64_t n_cells, int32_t* __restrict__ sz) {
-  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (k < n_cells) sz[k] = cell_start[order[k] + 1] - cell_start[order[k]];
-  if (k == 0) sz[n_cells] = 0;
-}
-
-__global__ void k_fill_sched(const int32_t* __restrict__ order, const int32_t* __restrict__ off,
-                             const int32_t* __restrict__ cell_start, int64_t n_cells, int32_t* __restrict__ sched) {
-  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (k >= n_cells) return;
-  const int32_t c = order[k];
-  const int32_t s0 = cell_start[c], s1 = cell_start[c + 1];
-  for (int32_t j = s0; j < s1; ++j) sched[off[k] + (j - s0)] = j;
+  keys[s] = key;
+  ids[s] = (int32_t)s;
 }
 
 // ------------------------------------------------------------ bump values
@@ -678,30 +669,31 @@ Sorted order_points(Ctx* c, const double* x, int64_t n, int dim, double r_cell) 
   double4* xs = c->get<double4>(S_XS, n);
   k_gather_points<<<grid_for(n, kBlock), kBlock, 0, c->stream>>>(x, perm, n, dim, xs);
   SDGP_CHECK_LAUNCH();
-  // Morton schedule of the cells
+  // Row schedule: the sorted points in Morton (Z-curve) order of their
+  // coordinates quantised to 2^mb steps per axis; consecutive schedule
+  // positions are spatial neighbours at every scale, so a window of rows in
+  // flight gathers from a compact neighbourhood.
   {
-    const int64_t nc = g.n_cells;
-    uint64_t* mk = c->get<uint64_t>(S_MORTON_KEYS, nc);
-    uint64_t* mk2 = c->get<uint64_t>(S_MORTON_KEYS2, nc);
-    int32_t* ids = c->get<int32_t>(S_MORTON_IDS, nc);
-    int32_t* order = c->get<int32_t>(S_MORTON_ORDER, nc);
-    k_cell_morton<<<grid_for(nc, kBlock), kBlock, 0, c->stream>>>(g, mk, ids);
+    MortonQ mq;
+    mq.dim = dim;
+    mq.bits = std::min(16, 62 / dim);
+    const double steps = (double)((1 << mq.bits) - 1);
+    for (int k = 0; k < kMaxDim; ++k) {
+      mq.lo[k] = k < dim ? lo[k] : 0.0;
+      const double ext = k < dim ? hi[k] - lo[k] : 0.0;
+      mq.scale[k] = ext > 0.0 ? steps / ext : 0.0;
+    }
+    uint64_t* mk = c->get<uint64_t>(S_MORTON_KEYS, n);
+    uint64_t* mk2 = c->get<uint64_t>(S_MORTON_KEYS2, n);
+    int32_t* ids = c->get<int32_t>(S_MORTON_IDS, n);
+    int32_t* sched = c->get<int32_t>(S_SCHED, n);
+    k_point_morton<<<grid_for(n, kBlock), kBlock, 0, c->stream>>>(xs, n, mq, mk, ids);
     SDGP_CHECK_LAUNCH();
     size_t tb2 = 0;
-    SDGP_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tb2, mk, mk2, ids, order, (int)nc, 0, 64, c->stream));
+    const int kbits = mq.bits * dim;
+    SDGP_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tb2, mk, mk2, ids, sched, (int)n, 0, kbits, c->stream));
     void* tmp2 = c->get<char>(S_SORT_TMP, tb2);
-    SDGP_HIP(hipcub::DeviceRadixSort::SortPairs(tmp2, tb2, mk, mk2, ids, order, (int)nc, 0, 64, c->stream));
-    int32_t* sz = c->get<int32_t>(S_MORTON_SZ, nc + 1);
-    int32_t* off = c->get<int32_t>(S_MORTON_OFF, nc + 1);
-    k_cell_sizes<<<grid_for(nc, kBlock), kBlock, 0, c->stream>>>(order, cell_start, nc, sz);
-    SDGP_CHECK_LAUNCH();
-    tb2 = 0;
-    SDGP_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tb2, sz, off, (int)(nc + 1), c->stream));
-    tmp2 = c->get<char>(S_SORT_TMP, tb2);
-    SDGP_HIP(hipcub::DeviceScan::ExclusiveSum(tmp2, tb2, sz, off, (int)(nc + 1), c->stream));
-    int32_t* sched = c->get<int32_t>(S_SCHED, n);
-    k_fill_sched<<<grid_for(nc, kBlock), kBlock, 0, c->stream>>>(order, off, cell_start, nc, sched);
-    SDGP_CHECK_LAUNCH();
+    SDGP_HIP(hipcub::DeviceRadixSort::SortPairs(tmp2, tb2, mk, mk2, ids, sched, (int)n, 0, kbits, c->stream));
     s.sched = sched;
   }
   s.perm = perm;

@@ -81,6 +81,38 @@ struct CgArgs {
 
 __device__ __forceinline__ bool stopped(const CgArgs& A) { return *A.st.done || *A.st.it >= A.max_iter; }
 
+// The CG kernels read their arrays through pointers held in device memory
+// (one argument block per member), which the compiler cannot prove to be
+// global; these casts let it emit global (not flat) memory instructions.
+#define GL __attribute__((address_space(1)))
+typedef double dv2 __attribute__((ext_vector_type(2)));
+struct Gv {
+  const GL int64_t* row_ptr;
+  const GL int32_t* col;
+  const GL double* val;
+  GL double *X, *Rr, *P, *Q, *V;
+  const GL int32_t* sched;
+  const GL double* F;
+  GL double *s_part, *u_part, *p_part;
+};
+__device__ __forceinline__ Gv gview(const CgArgs& A) {
+  Gv g;
+  g.row_ptr = (const GL int64_t*)A.row_ptr;
+  g.col = (const GL int32_t*)A.col;
+  g.val = (const GL double*)A.val;
+  g.X = (GL double*)A.X;
+  g.Rr = (GL double*)A.Rr;
+  g.P = (GL double*)A.P;
+  g.Q = (GL double*)A.Q;
+  g.V = (GL double*)A.V;
+  g.sched = (const GL int32_t*)A.sched;
+  g.F = (const GL double*)A.F;
+  g.s_part = (GL double*)A.s_part;
+  g.u_part = (GL double*)A.u_part;
+  g.p_part = (GL double*)A.p_part;
+  return g;
+}
+
 // ------------------------------------------------------------ SpMM core
 template <int u>
 __device__ __forceinline__ int bcast16_i(int v) {
@@ -94,48 +126,59 @@ __device__ __forceinline__ double bcast16_d(double v) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-template <int H, int... us>
-__device__ __forceinline__ void gather8(int cj, double vj, const double* __restrict__ Xs, int64_t ld,
-                                        double& ax, double& ay, double& bx, double& by,
-                                        std::integer_sequence<int, us...>) {
-  double vv[8];
-  double2 xv[8];
-  ((vv[us] = bcast16_d<H + us>(vj),
-    xv[us] = *reinterpret_cast<const double2*>(Xs + (int64_t)(uint32_t)bcast16_i<H + us>(cj) * ld)), ...);
+// 16 gathers of the calling lane's two slab columns, all issued before any
+// product is summed; acc[0..7]: four accumulator pairs (entry u feeds pair
+// u % 4).
+template <int... us>
+__device__ __forceinline__ void gather16(int cj, double vj, const GL double* __restrict__ Xs, int64_t ld,
+                                         double* acc, std::integer_sequence<int, us...>) {
+  double vv[16];
+  dv2 xv[16];
+  ((vv[us] = bcast16_d<us>(vj),
+    xv[us] = *reinterpret_cast<const GL dv2*>(Xs + (int64_t)(uint32_t)bcast16_i<us>(cj) * ld)), ...);
 #pragma unroll
-  for (int u = 0; u < 8; u += 2) {
-    ax += vv[u] * xv[u].x;
-    ay += vv[u] * xv[u].y;
-    bx += vv[u + 1] * xv[u + 1].x;
-    by += vv[u + 1] * xv[u + 1].y;
+  for (int u = 0; u < 16; u += 4) {
+    acc[0] += vv[u] * xv[u].x;
+    acc[1] += vv[u] * xv[u].y;
+    acc[2] += vv[u + 1] * xv[u + 1].x;
+    acc[3] += vv[u + 1] * xv[u + 1].y;
+    acc[4] += vv[u + 2] * xv[u + 2].x;
+    acc[5] += vv[u + 2] * xv[u + 2].y;
+    acc[6] += vv[u + 3] * xv[u + 3].x;
+    acc[7] += vv[u + 3] * xv[u + 3].y;
   }
 }
 
 // Row dot products of one matrix row (entries k0..k1) with the two slab
 // columns of the calling lane: q = sum_k val[k] * Xs[col[k] * ld + {0, 1}],
 // Xs pointing at the lane's first column.  With kY, yacc also receives the
-// lane's share of sum_k val[k] * ycol[col[k]] (entries kb + j).  Every lane
-// of the wavefront must call this together (DPP broadcasts); ``self`` is a
-// valid row index used for the padding entries.
+// lane's share of sum_k val[k] * ycol[col[k]] (entries kb + j).  The next
+// 16 (column, value) pairs are loaded while the current 16 gathers are in
+// flight.  Every lane of the wavefront must call this together (DPP
+// broadcasts); ``self`` is a valid row index used for the padding entries.
 template <bool kY, bool kSlabs = true>
-__device__ __forceinline__ void slab_row(int64_t k0, int64_t k1, int32_t self, const int32_t* __restrict__ col,
-                                         const double* __restrict__ val, const double* __restrict__ Xs,
-                                         int64_t ld, const double* __restrict__ ycol, double2& q, double& yacc) {
+__device__ __forceinline__ void slab_row(int64_t k0, int64_t k1, int32_t self, const GL int32_t* __restrict__ col,
+                                         const GL double* __restrict__ val, const GL double* __restrict__ Xs,
+                                         int64_t ld, const GL double* __restrict__ ycol, dv2& q, double& yacc) {
   const int j = lane_id() & 15;
-  double ax = 0.0, ay = 0.0, bx = 0.0, by = 0.0;
-  for (int64_t kb = k0; __any(kb < k1); kb += 16) {
-    const int64_t k = kb + j;
-    const bool in = k < k1;
-    const int cj = in ? col[k] : self;
-    const double vj = in ? val[k] : 0.0;
+  double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int64_t kb = k0;
+  bool in = kb + j < k1;
+  int cj = in ? col[kb + j] : self;
+  double vj = in ? val[kb + j] : 0.0;
+  while (__any(kb < k1)) {
+    const int64_t kn = kb + 16 + j;
+    const bool inn = kn < k1;
+    const int cn = inn ? col[kn] : self;
+    const double vn = inn ? val[kn] : 0.0;
     if constexpr (kY) yacc += vj * ycol[cj];
-    if constexpr (kSlabs) {
-      gather8<0>(cj, vj, Xs, ld, ax, ay, bx, by, std::make_integer_sequence<int, 8>{});
-      gather8<8>(cj, vj, Xs, ld, ax, ay, bx, by, std::make_integer_sequence<int, 8>{});
-    }
+    if constexpr (kSlabs) gather16(cj, vj, Xs, ld, acc, std::make_integer_sequence<int, 16>{});
+    cj = cn;
+    vj = vn;
+    kb += 16;
   }
-  q.x = ax + bx;
-  q.y = ay + by;
+  q.x = (acc[0] + acc[2]) + (acc[4] + acc[6]);
+  q.y = (acc[1] + acc[3]) + (acc[5] + acc[7]);
 }
 
 // Sum over the 16 lanes of a DPP row; lane 0 of the row holds the sum.
@@ -173,22 +216,25 @@ __device__ __forceinline__ double block_sum(double* red, double v) {
   return red[0];
 }
 
-// Q = A P on the slabs (grid y = slab) and on column 0 (slab-0 blocks);
-// per-block partials of p.q.  With the factored operator A = K_core + F F^T
+// Q = A P, per-block partials of p.q.  kMode 1: slab 0 and column 0
+// together (grid y = 1); kMode 2: slabs 1.. (grid y = ns - 1); kMode 0:
+// column 0 only (no slabs).  With the factored operator A = K_core + F F^T
 // this computes K_core P; the F F^T part is added by the update kernel.
-// kSlabs = false: column 0 only (no slabs; grid y = 1).
-template <bool kSlabs>
+template <int kMode>
 __global__ __launch_bounds__(kT) void k_cg_spmm(const CgArgs* __restrict__ AA) {
   const CgArgs& A = AA[blockIdx.z];
+  const Gv G = gview(A);
   if (stopped(A)) return;
+  constexpr bool kY = kMode != 2;
+  constexpr bool kSlabs = kMode != 0;
   __shared__ double red[kTile * kSlab];
   __shared__ double redy[kTile];
   const int lane = lane_id(), g = lane >> 4, j = lane & 15, w = threadIdx.x >> 6;
-  const int s = blockIdx.y;
+  const int s = kMode == 2 ? (int)blockIdx.y + 1 : 0;
   const int64_t n = A.n;
   const int64_t so = A.ny + (int64_t)s * n * kSlab + 2 * j;
-  const double* Ps = A.P + so;
-  double* Qs = A.Q + so;
+  const GL double* Ps = G.P + so;
+  GL double* Qs = G.Q + so;
   const int xcd = blockIdx.x & 7;
   const int64_t bi = blockIdx.x >> 3, nbx = gridDim.x >> 3;
   const int64_t nx = (n + 7) >> 3, lo = xcd * nx, hi = min(n, lo + nx);
@@ -196,24 +242,22 @@ __global__ __launch_bounds__(kT) void k_cg_spmm(const CgArgs* __restrict__ AA) {
   for (int64_t pb = lo + bi * kTile + w * 4; pb < hi; pb += nbx * kTile) {
     const int64_t p = pb + g;
     const bool live = p < hi;
-    const int64_t a = live ? (A.sched ? (int64_t)A.sched[p] : p) : 0;
-    const int64_t k0 = live ? A.row_ptr[a] : 0, k1 = live ? A.row_ptr[a + 1] : 0;
-    double2 q;
+    const int64_t a = live ? (G.sched ? (int64_t)G.sched[p] : p) : 0;
+    const int64_t k0 = live ? G.row_ptr[a] : 0, k1 = live ? G.row_ptr[a + 1] : 0;
+    dv2 q;
     double yacc = 0.0;
-    if (!kSlabs) slab_row<true, false>(k0, k1, (int32_t)a, A.col, A.val, Ps, kSlab, A.P, q, yacc);
-    else if (s == 0) slab_row<true>(k0, k1, (int32_t)a, A.col, A.val, Ps, kSlab, A.P, q, yacc);
-    else slab_row<false>(k0, k1, (int32_t)a, A.col, A.val, Ps, kSlab, nullptr, q, yacc);
-    if (s == 0) yacc = row16_sum(yacc);
+    slab_row<kY, kSlabs>(k0, k1, (int32_t)a, G.col, G.val, Ps, kSlab, G.P, q, yacc);
+    if (kY) yacc = row16_sum(yacc);
     if (live) {
       if (kSlabs) {
-        *reinterpret_cast<double2*>(Qs + a * kSlab) = q;
-        const double2 pv = *reinterpret_cast<const double2*>(Ps + a * kSlab);
+        *reinterpret_cast<GL dv2*>(Qs + a * kSlab) = q;
+        const dv2 pv = *reinterpret_cast<const GL dv2*>(Ps + a * kSlab);
         pq0 += pv.x * q.x;
         pq1 += pv.y * q.y;
       }
-      if (s == 0 && j == 0) {
-        A.Q[a] = yacc;
-        pqy += A.P[a] * yacc;
+      if (kY && j == 0) {
+        G.Q[a] = yacc;
+        pqy += G.P[a] * yacc;
       }
     }
   }
@@ -221,17 +265,17 @@ __global__ __launch_bounds__(kT) void k_cg_spmm(const CgArgs* __restrict__ AA) {
     const double t = tile_colsum(red, pq0, pq1);
     if (threadIdx.x < kSlab) {
       const int rc = 1 + s * kSlab + threadIdx.x;
-      if (rc < A.R) A.s_part[(int64_t)rc * A.nbs + blockIdx.x] = t;
+      if (rc < A.R) G.s_part[(int64_t)rc * A.nbs + blockIdx.x] = t;
     }
   }
-  if (s == 0) {
+  if (kY) {
     __syncthreads();
     if (j == 0) redy[w * 4 + g] = pqy;
     __syncthreads();
     if (threadIdx.x == 0) {
       double ty = 0.0;
       for (int q = 0; q < kTile; ++q) ty += redy[q];
-      A.s_part[blockIdx.x] = ty;
+      G.s_part[blockIdx.x] = ty;
     }
   }
 }
@@ -240,17 +284,18 @@ __global__ __launch_bounds__(kT) void k_cg_spmm(const CgArgs* __restrict__ AA) {
 // 1 update partials (r.r and F^T r), 2 F^T p partials.
 __global__ __launch_bounds__(kT) void k_cg_colsum(const CgArgs* __restrict__ AA, int which) {
   const CgArgs& A = AA[blockIdx.z];
+  const Gv G = gview(A);
   if (stopped(A)) return;
   __shared__ double red[kT];
-  const double* part;
+  const GL double* part;
   double* out;
   int nparts, ncols;
-  if (which == 0) { part = A.s_part; out = A.s_red; nparts = A.nbs; ncols = A.R; }
-  else if (which == 1) { part = A.u_part; out = A.u_red; nparts = A.nbu; ncols = (1 + (A.use_pc ? A.n1 : 0)) * A.R; }
-  else { part = A.p_part; out = A.p_red; nparts = A.nbu; ncols = A.n1 * A.R; }
+  if (which == 0) { part = G.s_part; out = A.s_red; nparts = A.nbs; ncols = A.R; }
+  else if (which == 1) { part = G.u_part; out = A.u_red; nparts = A.nbu; ncols = (1 + (A.use_pc ? A.n1 : 0)) * A.R; }
+  else { part = G.p_part; out = A.p_red; nparts = A.nbu; ncols = A.n1 * A.R; }
   const int c = blockIdx.x;
   if (c >= ncols) return;
-  const double* pc = part + (int64_t)c * nparts;
+  const GL double* pc = part + (int64_t)c * nparts;
   double v = 0.0;
   for (int b = threadIdx.x; b < nparts; b += kT) v += pc[b];
   v = block_sum(red, v);
@@ -287,11 +332,12 @@ __device__ __forceinline__ void ft_step(const double* f, double v0, double v1, d
 // F values of the calling lane for row a (a < 0: zeros): f[mt] = F[a][16 mt + j].
 template <int NT>
 __device__ __forceinline__ void load_f(const CgArgs& A, int64_t a, double* f) {
+  const GL double* F = (const GL double*)A.F;
   const int j = lane_id() & 15;
 #pragma unroll
   for (int mt = 0; mt < NT; ++mt) {
     const int i = 16 * mt + j;
-    f[mt] = (a >= 0 && i < A.n1) ? A.F[a * (int64_t)A.n1 + i] : 0.0;
+    f[mt] = (a >= 0 && i < A.n1) ? F[a * (int64_t)A.n1 + i] : 0.0;
   }
 }
 
@@ -320,7 +366,7 @@ __device__ __forceinline__ double frow_bc(const double* f, int n1, const double*
 // Block sums of the wavefronts' F^T v tiles into part rows base + i R + rc
 // (slab blocks).  red: at least 4 * 512 doubles of LDS.
 template <int NT>
-__device__ void put_ft_partials(const CgArgs& A, double* red, d4 (*acc)[2], double* part, int64_t base) {
+__device__ void put_ft_partials(const CgArgs& A, double* red, d4 (*acc)[2], GL double* part, int64_t base) {
   const int lane = lane_id(), g = lane >> 4, j = lane & 15, w = threadIdx.x >> 6;
   const int s = blockIdx.y;
 #pragma unroll
@@ -344,7 +390,7 @@ __device__ void put_ft_partials(const CgArgs& A, double* red, d4 (*acc)[2], doub
 
 // Column-0 block sums of scalar F^T v accumulators into part rows base + i R.
 template <int NI>
-__device__ void put_fty_partials(const CgArgs& A, double* red, const double* gy, double* part, int64_t base) {
+__device__ void put_fty_partials(const CgArgs& A, double* red, const double* gy, GL double* part, int64_t base) {
 #pragma unroll
   for (int i = 0; i < (NI > 0 ? NI : 1); ++i) {
     if (i >= A.n1) continue;
@@ -405,7 +451,7 @@ __device__ __forceinline__ double small_solve(const CgArgs& A, int rc, double* u
 
 // sum_i F[a][i] w[i][0] for a column-0 thread's own row.
 template <int NI>
-__device__ __forceinline__ double frow_dot(const double* __restrict__ Fa, int n1, const double* w) {
+__device__ __forceinline__ double frow_dot(const GL double* __restrict__ Fa, int n1, const double* w) {
   double s = 0.0;
 #pragma unroll
   for (int i = 0; i < (NI > 0 ? NI : 1); ++i)
@@ -421,6 +467,7 @@ template <int NI>
 __global__ __launch_bounds__(kT) void k_cg_update_xr(const CgArgs* __restrict__ AA) {
   constexpr int NT = (NI + 15) / 16;
   const CgArgs& A = AA[blockIdx.z];
+  const Gv G = gview(A);
   if (stopped(A)) return;
   __shared__ double red[kRed];
   __shared__ double s_alpha[kSlab];
@@ -476,12 +523,12 @@ __global__ __launch_bounds__(kT) void k_cg_update_xr(const CgArgs* __restrict__ 
       for (int64_t k = 0; k < steps; ++k) {
         const int64_t a = thread_row(A, true, k);
         if (a < 0) continue;
-        const double* Fa = A.F + a * (int64_t)A.n1;
-        double q = A.Q[a];
+        const GL double* Fa = G.F + a * (int64_t)A.n1;
+        double q = G.Q[a];
         if (lr) q += frow_dot<NI>(Fa, A.n1, s_gp);
-        A.X[a] += al * A.P[a];
-        const double r = A.Rr[a] - al * q;
-        A.Rr[a] = r;
+        G.X[a] += al * G.P[a];
+        const double r = G.Rr[a] - al * q;
+        G.Rr[a] = r;
         rr += r * r;
         if (pc) {
 #pragma unroll
@@ -490,8 +537,8 @@ __global__ __launch_bounds__(kT) void k_cg_update_xr(const CgArgs* __restrict__ 
         }
       }
     const double t = block_sum(red, rr);
-    if (threadIdx.x == 0) A.u_part[blockIdx.x] = t;
-    if (pc) put_fty_partials<NI>(A, red, gy, A.u_part, A.R);
+    if (threadIdx.x == 0) G.u_part[blockIdx.x] = t;
+    if (pc) put_fty_partials<NI>(A, red, gy, G.u_part, A.R);
     return;
   }
   const int cl = my_cl(false);
@@ -511,21 +558,21 @@ __global__ __launch_bounds__(kT) void k_cg_update_xr(const CgArgs* __restrict__ 
         c0 = frow_bc<NT>(f, A.n1, s_gp, cl);
         c1 = frow_bc<NT>(f, A.n1, s_gp, cl + 1);
       }
-      double2 r = {0.0, 0.0};
+      dv2 r = {0.0, 0.0};
       if (a >= 0) {
         const int64_t o = elem(A, false, a);
-        double2 q = *reinterpret_cast<const double2*>(A.Q + o);
-        const double2 p = *reinterpret_cast<const double2*>(A.P + o);
-        double2 x = *reinterpret_cast<const double2*>(A.X + o);
-        r = *reinterpret_cast<const double2*>(A.Rr + o);
+        dv2 q = *reinterpret_cast<const GL dv2*>(G.Q + o);
+        const dv2 p = *reinterpret_cast<const GL dv2*>(G.P + o);
+        dv2 x = *reinterpret_cast<const GL dv2*>(G.X + o);
+        r = *reinterpret_cast<const GL dv2*>(G.Rr + o);
         q.x += c0;
         q.y += c1;
         x.x += al0 * p.x;
         x.y += al1 * p.y;
         r.x -= al0 * q.x;
         r.y -= al1 * q.y;
-        *reinterpret_cast<double2*>(A.X + o) = x;
-        *reinterpret_cast<double2*>(A.Rr + o) = r;
+        *reinterpret_cast<GL dv2*>(G.X + o) = x;
+        *reinterpret_cast<GL dv2*>(G.Rr + o) = r;
         rr0 += r.x * r.x;
         rr1 += r.y * r.y;
       }
@@ -535,9 +582,9 @@ __global__ __launch_bounds__(kT) void k_cg_update_xr(const CgArgs* __restrict__ 
   const double t = tile_colsum(red, rr0, rr1);
   if (threadIdx.x < kSlab) {
     const int rc = 1 + (int)blockIdx.y * kSlab + (int)threadIdx.x;
-    if (rc < A.R) A.u_part[(int64_t)rc * A.nbu + blockIdx.x] = t;
+    if (rc < A.R) G.u_part[(int64_t)rc * A.nbu + blockIdx.x] = t;
   }
-  if (NT > 0 && pc) put_ft_partials<NT>(A, red, acc, A.u_part, A.R);
+  if (NT > 0 && pc) put_ft_partials<NT>(A, red, acc, G.u_part, A.R);
 }
 
 // beta = r.z_new / r.z; convergence on |r|; p = z + beta p with
@@ -548,6 +595,7 @@ template <int NI>
 __global__ __launch_bounds__(kT) void k_cg_update_p(const CgArgs* __restrict__ AA) {
   constexpr int NT = (NI + 15) / 16;
   const CgArgs& A = AA[blockIdx.z];
+  const Gv G = gview(A);
   if (stopped(A)) return;
   __shared__ double red[kRed];
   __shared__ double s_beta[kSlab];
@@ -598,18 +646,18 @@ __global__ __launch_bounds__(kT) void k_cg_update_p(const CgArgs* __restrict__ A
       for (int64_t k = 0; k < steps; ++k) {
         const int64_t a = thread_row(A, true, k);
         if (a < 0) continue;
-        const double* Fa = A.F + a * (int64_t)A.n1;
-        const double r = A.Rr[a];
+        const GL double* Fa = G.F + a * (int64_t)A.n1;
+        const double r = G.Rr[a];
         const double z = pc ? (r - frow_dot<NI>(Fa, A.n1, s_u)) * A.inv_c : r;
-        const double p = z + be * A.P[a];
-        A.P[a] = p;
+        const double p = z + be * G.P[a];
+        G.P[a] = p;
         if (lr) {
 #pragma unroll
           for (int i = 0; i < (NI > 0 ? NI : 1); ++i)
             if (i < A.n1) gy[i] += Fa[i] * p;
         }
       }
-    if (lr) put_fty_partials<NI>(A, red, gy, A.p_part, 0);
+    if (lr) put_fty_partials<NI>(A, red, gy, G.p_part, 0);
     return;
   }
   const int cl = my_cl(false);
@@ -628,27 +676,28 @@ __global__ __launch_bounds__(kT) void k_cg_update_p(const CgArgs* __restrict__ A
         u0 = frow_bc<NT>(f, A.n1, s_u, cl);
         u1 = frow_bc<NT>(f, A.n1, s_u, cl + 1);
       }
-      double2 p = {0.0, 0.0};
+      dv2 p = {0.0, 0.0};
       if (a >= 0) {
         const int64_t o = elem(A, false, a);
-        const double2 r = *reinterpret_cast<const double2*>(A.Rr + o);
-        p = *reinterpret_cast<const double2*>(A.P + o);
+        const dv2 r = *reinterpret_cast<const GL dv2*>(G.Rr + o);
+        p = *reinterpret_cast<const GL dv2*>(G.P + o);
         const double z0 = pc ? (r.x - u0) * A.inv_c : r.x;
         const double z1 = pc ? (r.y - u1) * A.inv_c : r.y;
         if (c0) p.x = z0 + be0 * p.x;
         if (c1) p.y = z1 + be1 * p.y;
-        *reinterpret_cast<double2*>(A.P + o) = p;
+        *reinterpret_cast<GL dv2*>(G.P + o) = p;
       }
       if (NT > 0 && lr) ft_step<NT>(f, p.x, p.y, acc);
     }
   }
-  if (NT > 0 && lr) put_ft_partials<NT>(A, red, acc, A.p_part, 0);
+  if (NT > 0 && lr) put_ft_partials<NT>(A, red, acc, G.p_part, 0);
 }
 
 // Records the executed iteration count in done when no column is active
 // and advances the iteration counter (one block per member).
 __global__ void k_cg_check(const CgArgs* __restrict__ AA) {
   const CgArgs& A = AA[blockIdx.z];
+  const Gv G = gview(A);
   if (stopped(A)) return;
   const int it = *A.st.it;
   const int nxt = (it & 1) ^ 1;
@@ -674,6 +723,7 @@ __global__ void k_cg_start(const CgArgs* __restrict__ AA, const double* __restri
                            const int32_t* __restrict__ perm, int kind, uint64_t seed,
                            const double* __restrict__ dense) {
   const CgArgs& A = AA[blockIdx.z];
+  const Gv G = gview(A);
   const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int64_t n = A.n;
   const int64_t tot = A.ny + (int64_t)A.ns * n * kSlab;
@@ -703,7 +753,7 @@ __global__ void k_cg_start(const CgArgs* __restrict__ AA, const double* __restri
       b = (splitmix64_at(seed, pbase + (uint64_t)perm[a] + 1ull) >> 63) ? -1.0 : 1.0;
       if (A.use_pc) {
         double fv = 0.0;
-        const double* Fa = A.F + a * (int64_t)A.n1;
+        const GL double* Fa = G.F + a * (int64_t)A.n1;
         for (int i = 0; i < A.n1; ++i) {
           const double v = (splitmix64_at(seed, pbase + 0xFFFFFFFFull - (uint64_t)i) >> 63) ? -1.0 : 1.0;
           fv += Fa[i] * v;
@@ -712,9 +762,9 @@ __global__ void k_cg_start(const CgArgs* __restrict__ AA, const double* __restri
       }
     }
   }
-  A.X[idx] = 0.0;
-  A.Rr[idx] = b;
-  A.P[idx] = 0.0;
+  G.X[idx] = 0.0;
+  G.Rr[idx] = b;
+  G.P[idx] = 0.0;
 }
 
 // Partials of b.b and F^T b.
@@ -722,6 +772,7 @@ template <int NI>
 __global__ __launch_bounds__(kT) void k_cg_norm(const CgArgs* __restrict__ AA) {
   constexpr int NT = (NI + 15) / 16;
   const CgArgs& A = AA[blockIdx.z];
+  const Gv G = gview(A);
   __shared__ double red[kRed];
   const bool ycol = is_ycol(A);
   const bool pc = NI > 0 && A.use_pc;
@@ -734,18 +785,18 @@ __global__ __launch_bounds__(kT) void k_cg_norm(const CgArgs* __restrict__ AA) {
     for (int64_t k = 0; k < steps; ++k) {
       const int64_t a = thread_row(A, true, k);
       if (a < 0) continue;
-      const double r = A.Rr[a];
+      const double r = G.Rr[a];
       rr += r * r;
       if (pc) {
-        const double* Fa = A.F + a * (int64_t)A.n1;
+        const GL double* Fa = G.F + a * (int64_t)A.n1;
 #pragma unroll
         for (int i = 0; i < (NI > 0 ? NI : 1); ++i)
           if (i < A.n1) gy[i] += Fa[i] * r;
       }
     }
     const double t = block_sum(red, rr);
-    if (threadIdx.x == 0) A.u_part[blockIdx.x] = t;
-    if (pc) put_fty_partials<NI>(A, red, gy, A.u_part, A.R);
+    if (threadIdx.x == 0) G.u_part[blockIdx.x] = t;
+    if (pc) put_fty_partials<NI>(A, red, gy, G.u_part, A.R);
     return;
   }
   double rr0 = 0.0, rr1 = 0.0;
@@ -754,9 +805,9 @@ __global__ __launch_bounds__(kT) void k_cg_norm(const CgArgs* __restrict__ AA) {
   for (int mt = 0; mt < (NT > 0 ? NT : 1); ++mt) acc[mt][0] = acc[mt][1] = d4{0.0, 0.0, 0.0, 0.0};
   for (int64_t k = 0; k < steps; ++k) {
     const int64_t a = thread_row(A, false, k);
-    double2 r = {0.0, 0.0};
+    dv2 r = {0.0, 0.0};
     if (a >= 0) {
-      r = *reinterpret_cast<const double2*>(A.Rr + elem(A, false, a));
+      r = *reinterpret_cast<const GL dv2*>(G.Rr + elem(A, false, a));
       rr0 += r.x * r.x;
       rr1 += r.y * r.y;
     }
@@ -769,9 +820,9 @@ __global__ __launch_bounds__(kT) void k_cg_norm(const CgArgs* __restrict__ AA) {
   const double t = tile_colsum(red, rr0, rr1);
   if (threadIdx.x < kSlab) {
     const int rc = 1 + (int)blockIdx.y * kSlab + (int)threadIdx.x;
-    if (rc < A.R) A.u_part[(int64_t)rc * A.nbu + blockIdx.x] = t;
+    if (rc < A.R) G.u_part[(int64_t)rc * A.nbu + blockIdx.x] = t;
   }
-  if (NT > 0 && pc) put_ft_partials<NT>(A, red, acc, A.u_part, A.R);
+  if (NT > 0 && pc) put_ft_partials<NT>(A, red, acc, G.u_part, A.R);
 }
 
 // Initial state: p = z0 = M^{-1} b (b when unpreconditioned), V = z0,
@@ -781,6 +832,7 @@ template <int NI>
 __global__ __launch_bounds__(kT) void k_cg_init_fin(const CgArgs* __restrict__ AA) {
   constexpr int NT = (NI + 15) / 16;
   const CgArgs& A = AA[blockIdx.z];
+  const Gv G = gview(A);
   __shared__ double red[kRed];
   __shared__ double s_u[(NI > 0 ? NI : 1) * kSlab];
   const bool ycol = is_ycol(A);
@@ -816,18 +868,18 @@ __global__ __launch_bounds__(kT) void k_cg_init_fin(const CgArgs* __restrict__ A
     for (int64_t k = 0; k < steps; ++k) {
       const int64_t a = thread_row(A, true, k);
       if (a < 0) continue;
-      const double* Fa = A.F + a * (int64_t)A.n1;
-      const double r = A.Rr[a];
+      const GL double* Fa = G.F + a * (int64_t)A.n1;
+      const double r = G.Rr[a];
       const double z = pc ? (r - frow_dot<NI>(Fa, A.n1, s_u)) * A.inv_c : r;
-      A.P[a] = z;
-      if (A.V) A.V[a] = z;
+      G.P[a] = z;
+      if (G.V) G.V[a] = z;
       if (lr) {
 #pragma unroll
         for (int i = 0; i < (NI > 0 ? NI : 1); ++i)
           if (i < A.n1) gy[i] += Fa[i] * z;
       }
     }
-    if (lr) put_fty_partials<NI>(A, red, gy, A.p_part, 0);
+    if (lr) put_fty_partials<NI>(A, red, gy, G.p_part, 0);
     return;
   }
   const int cl = my_cl(false);
@@ -843,25 +895,26 @@ __global__ __launch_bounds__(kT) void k_cg_init_fin(const CgArgs* __restrict__ A
       u0 = frow_bc<NT>(f, A.n1, s_u, cl);
       u1 = frow_bc<NT>(f, A.n1, s_u, cl + 1);
     }
-    double2 z = {0.0, 0.0};
+    dv2 z = {0.0, 0.0};
     if (a >= 0) {
       const int64_t o = elem(A, false, a);
-      const double2 r = *reinterpret_cast<const double2*>(A.Rr + o);
+      const dv2 r = *reinterpret_cast<const GL dv2*>(G.Rr + o);
       z.x = pc ? (r.x - u0) * A.inv_c : r.x;
       z.y = pc ? (r.y - u1) * A.inv_c : r.y;
-      *reinterpret_cast<double2*>(A.P + o) = z;
-      if (A.V) *reinterpret_cast<double2*>(A.V + o) = z;
+      *reinterpret_cast<GL dv2*>(G.P + o) = z;
+      if (G.V) *reinterpret_cast<GL dv2*>(G.V + o) = z;
     }
     if (NT > 0 && lr) ft_step<NT>(f, z.x, z.y, acc);
   }
-  if (NT > 0 && lr) put_ft_partials<NT>(A, red, acc, A.p_part, 0);
+  if (NT > 0 && lr) put_ft_partials<NT>(A, red, acc, G.p_part, 0);
 }
 
 // dst[a][rc] = src(a, rc): slab layout to row-major [n][R].
 __global__ void k_cg_unpack(const CgArgs* __restrict__ AA, int which) {
   const CgArgs& A = AA[blockIdx.z];
-  const double* src = which == 0 ? A.X : A.V;
-  double* dst = which == 0 ? A.P : A.Q;
+  const Gv G = gview(A);
+  const GL double* src = which == 0 ? G.X : G.V;
+  GL double* dst = which == 0 ? G.P : G.Q;
   const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (idx >= A.n * (int64_t)A.R) return;
   const int64_t a = idx / A.R;
@@ -883,8 +936,15 @@ void launch_iteration(hipStream_t st, const CgArgs* dA, const Launch& L, Ctx* c)
     e0 = c->event();
     SDGP_HIP(hipEventRecord(e0, st));
   }
-  if (L.ns > 0) k_cg_spmm<true><<<dim3(L.nbs, L.ns, L.B), kT, 0, st>>>(dA);
-  else k_cg_spmm<false><<<dim3(L.nbs, 1, L.B), kT, 0, st>>>(dA);
+  if (L.ns == 0) {
+    k_cg_spmm<0><<<dim3(L.nbs, 1, L.B), kT, 0, st>>>(dA);
+  } else {
+    k_cg_spmm<1><<<dim3(L.nbs, 1, L.B), kT, 0, st>>>(dA);
+    if (L.ns > 1) {
+      SDGP_CHECK_LAUNCH();
+      k_cg_spmm<2><<<dim3(L.nbs, L.ns - 1, L.B), kT, 0, st>>>(dA);
+    }
+  }
   SDGP_CHECK_LAUNCH();
   if (c != nullptr && c->timing) {
     e1 = c->event();
@@ -1203,10 +1263,11 @@ __global__ __launch_bounds__(kT) void k_spmm_slab(int64_t n, const int64_t* __re
     const int64_t a = pb + g;
     const bool live = a < hi;
     const int64_t k0 = live ? row_ptr[a] : 0, k1 = live ? row_ptr[a + 1] : 0;
-    double2 q;
+    dv2 q;
     double unused = 0.0;
-    slab_row<false>(k0, k1, live ? (int32_t)a : 0, col, val, X + cc, R, nullptr, q, unused);
-    if (live && c0 + 1 < R) *reinterpret_cast<double2*>(Y + a * R + c0) = q;
+    slab_row<false>(k0, k1, live ? (int32_t)a : 0, (const GL int32_t*)col, (const GL double*)val,
+                    (const GL double*)(X + cc), R, nullptr, q, unused);
+    if (live && c0 + 1 < R) *reinterpret_cast<dv2*>(Y + a * R + c0) = q;
   }
 }
 }  // namespace

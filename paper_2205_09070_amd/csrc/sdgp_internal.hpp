@@ -146,7 +146,7 @@ struct Sorted {
   double4* xs;          // sorted coordinates (padded to 4)
   int32_t* cell_start;  // [n_cells + 1]
   int32_t* cell_of;     // sorted position -> cell (the sorted keys)
-  int32_t* sched;       // processing order of rows (cells in Morton order)
+  int32_t* sched;       // processing order of rows (points in Morton order)
 };
 
 struct Bumps {
