@@ -15,6 +15,7 @@ rate on a bounded sample of the same workload (CPU).
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
 """
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -40,16 +41,42 @@ def parse():
     p.add_argument("--rtol", type=float, default=1e-10)
     p.add_argument("--precond", choices=["lowrank", "none"], default="lowrank",
                    help="CG preconditioner (low-rank bump part of the SUM kernel, or none)")
-    p.add_argument("--operator", choices=["assembled", "factored"], default="assembled",
+    p.add_argument("--operator", choices=["assembled", "factored"], default="factored",
                    help="CG operator: the fully assembled sparse K, or K_core (sparse) + F F^T")
     p.add_argument("--graph", type=int, default=0,
                    help="replay the CG iterations from a HIP graph (1; the SpMM is then not timed per launch)")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--spmv-reps", type=int, default=50)
+    p.add_argument("--population", type=int, default=0, metavar="B",
+                   help="instead of the N=1M line, time a population of B hyperparameter vectors on a shared "
+                        "N=200,000 point set: one batched call against B sequential calls")
+    p.add_argument("--pop-n", type=int, default=200_000)
     p.add_argument("--copy-ref-mib", type=int, default=0,
                    help="before the benchmark, copy a buffer of this many MiB three times (a plain device copy "
                         "of known size, the reference that scales profiler byte counters)")
     return p.parse_args()
+
+
+def spmm_traffic(operator):
+    """HBM bytes per CG SpMM launch (GB) from the committed counter summary,
+    or None when the CG source has changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "cg_kernels_uniform3d_n1000000.txt")
+    src = os.path.join(ROOT, "paper_2205_09070_amd", "csrc", "cg.hip")
+    try:
+        lines = open(path).read().splitlines()
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    want, tr = None, None
+    for line in lines:
+        p = line.split()
+        if line.startswith("source_sha256 cg.hip"):
+            want = p[2]
+        if line.startswith("traffic_gb_per_launch k_cg_spmm %s " % operator):
+            tr = {"GB_per_launch": float(p[3]), "fetch_GB": float(p[5]), "write_GB": float(p[7])}
+    if want != digest:
+        return None
+    return tr
 
 
 def cpu_baseline(w):
@@ -72,6 +99,60 @@ def cpu_baseline(w):
             "sample_evals_per_s": 1.0 / dt, "sample_points": ns}
 
 
+def population(args, sd, wl, torch):
+    """Batched population evaluation (one sdgp_lml_grad_batched call, CG
+    iterations replayed from a HIP graph) against one sdgp_lml_grad call per
+    member, on the same device, inputs resident in HBM."""
+    dev = torch.device("cuda", 0)
+    B = args.population
+    w, H = wl.population_3d(n=args.pop_n, members=B)
+    x = torch.from_numpy(w.x).to(dev)
+    y = torch.from_numpy(w.y).to(dev)
+    pc = sd.PRECOND_LOWRANK if args.precond == "lowrank" else sd.PRECOND_NONE
+    op = sd.OPERATOR_FACTORED if args.operator == "factored" else sd.OPERATOR_ASSEMBLED
+    est = sd.estimator(probes=args.probes, seed=1, cg_rtol=args.rtol, cg_max_iter=20000, precond=pc,
+                       operator_form=op)
+    ctx = sd.Context(0)
+    print("population: N=%d B=%d" % (w.x.shape[0], B), file=sys.stderr, flush=True)
+    # warm-up: one member each way
+    ctx.lml_grad(w.desc, x, y, H[0], est)
+    ctx.set_option("graph", 1)
+    ctx.lml_grad_batched(w.desc, x, y, H[:1], est)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    vb, gb, st, infos = ctx.lml_grad_batched(w.desc, x, y, H, est)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    print("batched: %.2f s" % tb, file=sys.stderr, flush=True)
+    ctx.set_option("graph", 0)
+    vs = np.zeros(B)
+    its = []
+    t0 = time.perf_counter()
+    for m in range(B):
+        vs[m], _, info = ctx.lml_grad(w.desc, x, y, H[m], est)
+        its.append(info.cg_iters)
+        print("  member %d: nnz/row %.1f cg iters %d" % (m, info.nnz / w.x.shape[0], info.cg_iters),
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    print("sequential: %.2f s" % ts, file=sys.stderr, flush=True)
+    rel = float(np.max(np.abs(vb - vs) / np.abs(vs)))
+    nnz = [int(i.nnz) for i in infos]
+    out = {"metric": "population LML+grad evals/s (N=%d, B=%d, FP64)" % (w.x.shape[0], B),
+           "value": B / tb, "unit": "evals/s", "n_gpus": 1, "higher_is_better": True,
+           "batched_evals_per_s": B / tb, "sequential_evals_per_s": B / ts, "speedup": ts / tb,
+           "batched_s": tb, "sequential_s": ts, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "population3d_n%d_b%d: shared uniform [0,1)^3 points, per-member core radius "
+                                  "(0.75 rho^2)^(1/3) with rho ~ U(0.005, 0.02), 8x4 shared bumps with per-member "
+                                  "heights ~ U(0, 1), SUM combine, %d probes, CG rtol %g, preconditioner %s, "
+                                  "operator %s" % (w.x.shape[0], B, args.probes, args.rtol, args.precond,
+                                                   args.operator)},
+           "member_status": [int(v) for v in st], "cg_iters": its,
+           "nnz_per_row": [v / w.x.shape[0] for v in nnz],
+           "max_rel_diff_batched_vs_sequential": rel}
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -86,6 +167,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py: no GPU", file=sys.stderr)
         sys.exit(1)
+    if args.population > 0:
+        population(args, sd, wl, torch)
+        return
     dev = torch.device("cuda", 0)
     w = wl.uniform3d_1m()
     n = w.x.shape[0]
@@ -135,13 +219,22 @@ def main():
     # entry, 8 B row pointer per row), P read once, Q written once
     spmm_bytes = 12.0 * nnz + 8.0 * (n + 1) + 2.0 * 8.0 * n * R
     spmm_gbps = spmm_bytes / (spmm_avg_ms * 1e-3) / 1e9
-    # plain SpMV (R = 1) on the assembled matrix in the solver's order
-    rp, col, vv, perm = ctx.kernel_assemble(w.desc, x, w.h, add_noise=True, sorted_order=True)
+    # full sparse covariance (all bump terms) in the solver's order: its
+    # assembly rate and a plain SpMV (R = 1) on it
+    s = ctx.stream
+    full_nnz = ctx.kernel_nnz(w.desc, x, w.h)
+    ctx.kernel_assemble(w.desc, x, w.h, add_noise=True, sorted_order=True, nnz=full_nnz)
+    ea0 = torch.cuda.Event(enable_timing=True)
+    ea1 = torch.cuda.Event(enable_timing=True)
+    ea0.record(s)
+    rp, col, vv, perm = ctx.kernel_assemble(w.desc, x, w.h, add_noise=True, sorted_order=True, nnz=full_nnz)
+    ea1.record(s)
+    ea1.synchronize()
+    full_asm_ms = ea0.elapsed_time(ea1)
     xv = torch.randn(n, dtype=torch.float64, device=dev)
     yv = torch.empty_like(xv)
     for _ in range(3):
         ctx.csr_spmm(rp, col, vv, xv, out=yv)
-    s = ctx.stream
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(s)
@@ -179,12 +272,17 @@ def main():
         "cg_iters": infos[-1]["cg_iters"],
         "phase_ms": {"order": ms[0], "bump": ms[1], "prune": ms[2], "count": ms[3], "fill": ms[4],
                      "cg": ms[5], "slq": ms[6], "adjoint": ms[7]},
-        "assembly_nnz_per_s": nnz / (asm_ms * 1e-3),
+        "assembly_nnz_per_s": spmv_nnz / (full_asm_ms * 1e-3),
+        "assembly": {"matrix": "full K + noise", "nnz": int(spmv_nnz), "ms": full_asm_ms,
+                     "note": "one sdgp_kernel_assemble_sorted call: order + bump + prune + count + fill"},
+        "solver_matrix_assembly_ms": asm_ms,
         "spmv": {"ms": spmv_ms, "GBps": spmv_gbps, "frac_hbm": spmv_gbps / HBM_PEAK_GBPS, "bytes": spmv_bytes,
                  "matrix": "full assembled K + noise (%d nnz)" % spmv_nnz},
         "roofline": {"kernel": "k_cg_spmm (CG SpMM, %d right-hand sides)" % R, "bound": "hbm",
                      "achieved": spmm_gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": spmm_gbps / HBM_PEAK_GBPS, "traffic": None,
+                     "frac": spmm_gbps / HBM_PEAK_GBPS,
+                     "traffic": (spmm_traffic(args.operator) or {}).get("GB_per_launch"),
+                     "traffic_unit": "GB per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE x1, copy-scaled)",
                      "avg_launch_ms": spmm_avg_ms, "launches": spmm_launches,
                      "algorithmic_bytes_per_launch": spmm_bytes},
         "lml": val,

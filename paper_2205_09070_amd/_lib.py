@@ -219,15 +219,17 @@ class Context:
                                              C.byref(out)))
         return int(out.value)
 
-    def kernel_assemble(self, desc, x, h, add_noise=True, sorted_order=False):
+    def kernel_assemble(self, desc, x, h, add_noise=True, sorted_order=False, nnz=None):
         """Returns (row_ptr, col, val) device tensors (and perm when
-        sorted_order)."""
+        sorted_order).  nnz: the stored count if already known (sizes the
+        outputs without a counting call)."""
         import torch
         x = _dev_f64(x)
         hh = self._h(h)
         d = desc_of(desc)
         n = x.shape[0]
-        nnz = self.kernel_nnz(desc, x, hh)
+        if nnz is None:
+            nnz = self.kernel_nnz(desc, x, hh)
         dev = x.device
         row_ptr = torch.empty(n + 1, dtype=torch.int64, device=dev)
         col = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)

@@ -367,76 +367,92 @@ struct RowArgs {
   const int32_t* cell_of;
   const int32_t* iv_ptr;
   const int2* iv;
+  const int32_t* sched;  // row visiting order (Morton), may be null
   int64_t n;
   int dim, n1, core, ell, combine, add_noise;
   int core_only;   // keep only the core part (+ diagonal), values without B
   double sigma2, r_core, rc2, noise;
 };
 
-// One wavefront per row.  kFill == false: count kept columns (and the
-// candidates examined); kFill == true: write them at row_ptr[a].
+// One wavefront per row, persistent: the waves of the grid sweep the rows in
+// schedule (Morton) order, each XCD taking a contiguous eighth of the
+// schedule (workgroups are dealt to the XCDs round-robin; gridDim.x is a
+// multiple of 8) so the candidate points of neighbouring rows stay in its
+// L2.  kFill == false: count kept columns (and the candidates examined, one
+// atomic per wave); kFill == true: write them at row_ptr[a].
 template <bool kFill>
 __global__ __launch_bounds__(kBlock) void k_rows(RowArgs A, int64_t* __restrict__ row_nnz,
                                                  unsigned long long* __restrict__ cand_total,
                                                  const int64_t* __restrict__ row_ptr,
                                                  int32_t* __restrict__ col, double* __restrict__ val) {
-  const int64_t a = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
-  if (a >= A.n) return;
   const int lane = lane_id();
-  const double4 xa = A.xs[a];
-  const uint64_t Ma = A.M[a];
-  const int32_t cell = A.cell_of[a];
-  const int32_t i0 = A.iv_ptr[cell], i1 = A.iv_ptr[cell + 1];
-  const double* Fa = A.F + a * (int64_t)A.n1;
-  int64_t pos = kFill ? row_ptr[a] : 0;
-  int64_t cnt = 0, cand = 0;
-  for (int32_t q = i0; q < i1; ++q) {
-    const int2 r = A.iv[q];
-    cand += r.y - r.x;
-    for (int32_t b0 = r.x; b0 < r.y; b0 += kWave) {
-      const int32_t b = b0 + lane;
-      bool keep = false;
-      double d2 = 0.0;
-      uint64_t mm = 0;
-      bool core = false;
-      if (b < r.y) {
-        const double4 xb = A.xs[b];
-        d2 = dist2(xa, xb, A.dim);
-        core = d2 < A.rc2;
-        mm = Ma & A.M[b];
-        const bool bump = mm != 0;
-        keep = (b == a) || (A.core_only ? core : (A.combine == 0 ? (core && bump) : (core || bump)));
-        if (A.core_only) mm = 0;
-      }
-      const uint64_t bal = ballot64(keep);
-      if (kFill) {
-        if (keep) {
-          double psi = 0.0;
-          if (core) psi = core_psi(sqrt(d2) / A.r_core, A.core, A.ell);
-          double B = 0.0;
-          const double* Fb = A.F + (int64_t)b * A.n1;
-          uint64_t t = mm;
-          while (t) {
-            const int i = __builtin_ctzll(t);
-            t &= t - 1;
-            B += Fa[i] * Fb[i];
-          }
-          double kv = A.combine == 0 ? A.sigma2 * psi * B : A.sigma2 * psi + B;
-          if (b == a && A.add_noise) kv += A.noise;
-          const int64_t o = pos + lanes_below(bal);
-          col[o] = b;
-          val[o] = kv;
+  const int wpb = kBlock / kWave;
+  const int xcd = blockIdx.x & 7;
+  const int64_t bi = blockIdx.x >> 3, nbx = gridDim.x >> 3;
+  const int64_t nx = (A.n + 7) >> 3, lo = xcd * nx, hi = min(A.n, lo + nx);
+  int64_t cand = 0;
+  for (int64_t p = lo + bi * wpb + (threadIdx.x >> 6); p < hi; p += nbx * wpb) {
+    const int64_t a = A.sched ? (int64_t)A.sched[p] : p;
+    const double4 xa = A.xs[a];
+    const uint64_t Ma = A.M[a];
+    const int32_t cell = A.cell_of[a];
+    const int32_t i0 = A.iv_ptr[cell], i1 = A.iv_ptr[cell + 1];
+    const double* Fa = A.F + a * (int64_t)A.n1;
+    int64_t pos = kFill ? row_ptr[a] : 0;
+    int64_t cnt = 0;
+    for (int32_t q = i0; q < i1; ++q) {
+      const int2 r = A.iv[q];
+      cand += r.y - r.x;
+      for (int32_t b0 = r.x; b0 < r.y; b0 += kWave) {
+        const int32_t b = b0 + lane;
+        bool keep = false;
+        double d2 = 0.0;
+        uint64_t mm = 0;
+        bool core = false;
+        if (b < r.y) {
+          const double4 xb = A.xs[b];
+          d2 = dist2(xa, xb, A.dim);
+          core = d2 < A.rc2;
+          mm = Ma & A.M[b];
+          const bool bump = mm != 0;
+          keep = (b == a) || (A.core_only ? core : (A.combine == 0 ? (core && bump) : (core || bump)));
+          if (A.core_only) mm = 0;
         }
-        pos += __popcll(bal);
-      } else {
-        cnt += __popcll(bal);
+        const uint64_t bal = ballot64(keep);
+        if (kFill) {
+          if (keep) {
+            double psi = 0.0;
+            if (core) psi = core_psi(sqrt(d2) / A.r_core, A.core, A.ell);
+            double B = 0.0;
+            const double* Fb = A.F + (int64_t)b * A.n1;
+            uint64_t t = mm;
+            while (t) {
+              const int i = __builtin_ctzll(t);
+              t &= t - 1;
+              B += Fa[i] * Fb[i];
+            }
+            double kv = A.combine == 0 ? A.sigma2 * psi * B : A.sigma2 * psi + B;
+            if (b == a && A.add_noise) kv += A.noise;
+            const int64_t o = pos + lanes_below(bal);
+            col[o] = b;
+            val[o] = kv;
+          }
+          pos += __popcll(bal);
+        } else {
+          cnt += __popcll(bal);
+        }
       }
     }
+    if (!kFill && lane == 0) row_nnz[a] = cnt;
   }
-  if (!kFill && lane == 0) {
-    row_nnz[a] = cnt;
-    atomicAdd(cand_total, (unsigned long long)cand);
-  }
+  if (!kFill && lane == 0 && cand > 0) atomicAdd(cand_total, (unsigned long long)cand);
+}
+
+// Blocks of the persistent row sweeps: about 32 waves per CU, a multiple of 8.
+static unsigned row_blocks(const Ctx* c, int64_t n) {
+  const int64_t want = std::max<int64_t>(8, (int64_t)c->cu_count * 32 / (kBlock / kWave));
+  const int64_t need = (n + kBlock / kWave - 1) / (kBlock / kWave);
+  return (unsigned)((std::min(want, need) + 7) / 8 * 8);
 }
 
 // ------------------------------------------------------- cross covariance
@@ -776,6 +792,7 @@ static RowArgs row_args(const Sorted& s, const KParams& kp, const Bumps& b, cons
                         const int2* iv, bool add_noise, bool core_only) {
   RowArgs A;
   A.xs = s.xs; A.M = b.M; A.F = b.F; A.cell_of = s.cell_of; A.iv_ptr = iv_ptr; A.iv = iv;
+  A.sched = s.sched;
   A.n = s.n; A.dim = kp.dim; A.n1 = kp.n1; A.core = kp.core; A.ell = kp.dim / 2 + 2;
   A.combine = kp.combine; A.add_noise = add_noise ? 1 : 0; A.core_only = core_only ? 1 : 0;
   A.sigma2 = kp.sigma2; A.r_core = kp.r_core; A.rc2 = kp.rc2; A.noise = kp.noise;
@@ -790,8 +807,8 @@ Csr assemble_sorted(Ctx* c, const Sorted& s, const KParams& kp, const Bumps& b, 
   unsigned long long* cand = c->get<unsigned long long>(S_COUNTER, 4);
   SDGP_HIP(hipMemsetAsync(cand, 0, sizeof(unsigned long long), c->stream));
   SDGP_HIP(hipMemsetAsync(row_nnz + n, 0, sizeof(int64_t), c->stream));
-  const int rows_per_block = kBlock / kWave;
-  k_rows<false><<<grid_for(n, rows_per_block), kBlock, 0, c->stream>>>(A, row_nnz, cand, nullptr, nullptr, nullptr);
+  const unsigned rb = row_blocks(c, n);
+  k_rows<false><<<rb, kBlock, 0, c->stream>>>(A, row_nnz, cand, nullptr, nullptr, nullptr);
   SDGP_CHECK_LAUNCH();
   int64_t* row_ptr = c->get<int64_t>(S_ROW_PTR, n + 1);
   size_t tb = 0;
@@ -807,7 +824,7 @@ Csr assemble_sorted(Ctx* c, const Sorted& s, const KParams& kp, const Bumps& b, 
   if (t) t->mark(4);
   int32_t* col = c->get<int32_t>(S_COL, nnz);
   double* val = c->get<double>(S_VAL, nnz);
-  k_rows<true><<<grid_for(n, rows_per_block), kBlock, 0, c->stream>>>(A, nullptr, nullptr, row_ptr, col, val);
+  k_rows<true><<<rb, kBlock, 0, c->stream>>>(A, nullptr, nullptr, row_ptr, col, val);
   SDGP_CHECK_LAUNCH();
   Csr k;
   k.n = n; k.nnz = nnz; k.row_ptr = row_ptr; k.col = col; k.val = val;

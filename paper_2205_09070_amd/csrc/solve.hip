@@ -87,39 +87,44 @@ __global__ __launch_bounds__(256) void k_spmm(int64_t n, const int64_t* __restri
   }
 }
 
-// SpMV (one right-hand side): 16 lanes per row, 4 rows per wave; each lane
-// first loads up to 8 of its row's (column, value) pairs, then issues the 8
-// gathers together (two round trips per 128 entries instead of sixteen).
+// SpMV (one right-hand side): 32 lanes per row, 8 rows per 256-thread block;
+// each lane loads 4 of its row's (column, value) pairs (stride 32) and then
+// issues their 4 gathers together.  Rows are dealt XCD-aware as in RowSweep;
+// many small blocks (about four row groups each) keep the tail short.
+constexpr int kSpmvLanes = 32;
+constexpr int kSpmvU = 4;
 __global__ __launch_bounds__(256) void k_spmv(int64_t n, const int64_t* __restrict__ row_ptr,
                                               const int32_t* __restrict__ col, const double* __restrict__ val,
                                               const double* __restrict__ x, double* __restrict__ y) {
-  const int sub = threadIdx.x & 15;
+  constexpr int G = 256 / kSpmvLanes;
+  const int sub = threadIdx.x & (kSpmvLanes - 1);
+  const int r = threadIdx.x / kSpmvLanes;
   const int xcd = blockIdx.x & 7;
   const int64_t bi = blockIdx.x >> 3, nbx = gridDim.x >> 3;
   const int64_t nx = (n + 7) >> 3, lo = xcd * nx, hi = min(n, lo + nx);
-  const int64_t groups = blockDim.x >> 4;
-  for (int64_t a = lo + bi * groups + (threadIdx.x >> 4); a - (threadIdx.x >> 4) < hi; a += nbx * groups) {
+  for (int64_t base = lo + bi * G; base < hi; base += nbx * G) {
+    const int64_t a = base + r;
     double acc = 0.0;
     if (a < hi) {
       const int64_t k1 = row_ptr[a + 1];
-      for (int64_t k0 = row_ptr[a] + sub; k0 < k1; k0 += 16 * 8) {
-        int cj[8];
-        double vj[8];
+      for (int64_t k0 = row_ptr[a] + sub; k0 < k1; k0 += kSpmvLanes * kSpmvU) {
+        int cj[kSpmvU];
+        double vj[kSpmvU];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int64_t k = k0 + 16 * u;
+        for (int u = 0; u < kSpmvU; ++u) {
+          const int64_t k = k0 + kSpmvLanes * u;
           cj[u] = k < k1 ? col[k] : 0;
           vj[u] = k < k1 ? val[k] : 0.0;
         }
-        double xv[8];
+        double xv[kSpmvU];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) xv[u] = x[cj[u]];
+        for (int u = 0; u < kSpmvU; ++u) xv[u] = x[cj[u]];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) acc += vj[u] * xv[u];
+        for (int u = 0; u < kSpmvU; ++u) acc += vj[u] * xv[u];
       }
     }
 #pragma unroll
-    for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 16);
+    for (int o = kSpmvLanes / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kSpmvLanes);
     if (a < hi && sub == 0) y[a] = acc;
   }
 }
@@ -293,8 +298,8 @@ void spmm(Ctx* c, const Csr& A, const double* X, int R, double* Y) {
   require(R >= 1 && R <= (1 << 20), "R must be in 1..2^20");
   const int64_t cu = std::max(8, c->cu_count);
   if (R == 1) {
-    // 16 rows per 256-thread block; about 8 blocks per CU in flight
-    int64_t blocks = std::min<int64_t>((A.n + 15) / 16, cu * 8);
+    // 8 rows per block step, up to 32768 blocks
+    int64_t blocks = std::min<int64_t>((A.n + 7) / 8, 32768);
     blocks = std::max<int64_t>(8, (blocks + 7) / 8 * 8);
     k_spmv<<<(unsigned)blocks, 256, 0, c->stream>>>(A.n, A.row_ptr, A.col, A.val, X, Y);
     SDGP_CHECK_LAUNCH();
