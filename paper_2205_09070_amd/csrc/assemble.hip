@@ -374,12 +374,12 @@ struct RowArgs {
   double sigma2, r_core, rc2, noise;
 };
 
-// One wavefront per row, persistent: the waves of the grid sweep the rows in
-// schedule (Morton) order, each XCD taking a contiguous eighth of the
-// schedule (workgroups are dealt to the XCDs round-robin; gridDim.x is a
-// multiple of 8) so the candidate points of neighbouring rows stay in its
-// L2.  kFill == false: count kept columns (and the candidates examined, one
-// atomic per wave); kFill == true: write them at row_ptr[a].
+// One wavefront per row, persistent: the waves of the grid sweep the rows
+// (in schedule order when one is given, else storage order), each XCD
+// taking a contiguous eighth (workgroups are dealt to the XCDs round-robin;
+// gridDim.x is a multiple of 8) so the candidate points of neighbouring rows
+// stay in its L2.  kFill == false: count kept columns (and the candidates
+// examined, one atomic per wave); kFill == true: write them at row_ptr[a].
 template <bool kFill>
 __global__ __launch_bounds__(kBlock) void k_rows(RowArgs A, int64_t* __restrict__ row_nnz,
                                                  unsigned long long* __restrict__ cand_total,
@@ -792,7 +792,7 @@ static RowArgs row_args(const Sorted& s, const KParams& kp, const Bumps& b, cons
                         const int2* iv, bool add_noise, bool core_only) {
   RowArgs A;
   A.xs = s.xs; A.M = b.M; A.F = b.F; A.cell_of = s.cell_of; A.iv_ptr = iv_ptr; A.iv = iv;
-  A.sched = s.sched;
+  A.sched = nullptr;  // storage order: the fill then writes the CSR arrays front to back
   A.n = s.n; A.dim = kp.dim; A.n1 = kp.n1; A.core = kp.core; A.ell = kp.dim / 2 + 2;
   A.combine = kp.combine; A.add_noise = add_noise ? 1 : 0; A.core_only = core_only ? 1 : 0;
   A.sigma2 = kp.sigma2; A.r_core = kp.r_core; A.rc2 = kp.rc2; A.noise = kp.noise;
@@ -824,7 +824,9 @@ Csr assemble_sorted(Ctx* c, const Sorted& s, const KParams& kp, const Bumps& b, 
   if (t) t->mark(4);
   int32_t* col = c->get<int32_t>(S_COL, nnz);
   double* val = c->get<double>(S_VAL, nnz);
-  k_rows<true><<<rb, kBlock, 0, c->stream>>>(A, nullptr, nullptr, row_ptr, col, val);
+  // the fill runs one row per wavefront (no persistence: measured faster)
+  const unsigned fb = (unsigned)(((n + kBlock / kWave - 1) / (kBlock / kWave) + 7) / 8 * 8);
+  k_rows<true><<<fb, kBlock, 0, c->stream>>>(A, nullptr, nullptr, row_ptr, col, val);
   SDGP_CHECK_LAUNCH();
   Csr k;
   k.n = n; k.nnz = nnz; k.row_ptr = row_ptr; k.col = col; k.val = val;

@@ -74,6 +74,7 @@ struct CgArgs {
   double* s_red;              // [R]
   double* u_part;             // [(1+n1) R][nbu]: r.r, then F^T r (row R + i R + c)
   double* u_red;              // [(1+n1) R]
+  double* w_red;              // [(n1+1) R]: u = S^{-1} g (row i R + c), then g.u (row n1 R + c)
   double* p_part;             // [n1 R][nbu] F^T p (row i R + c)
   double* p_red;              // [n1 R]
   CgState st;
@@ -280,13 +281,15 @@ __global__ __launch_bounds__(kT) void k_cg_spmm(const CgArgs* __restrict__ AA) {
   }
 }
 
-// out[c] = sum_b part[c][b] in a fixed order.  which: 0 SpMM partials,
-// 1 update partials (r.r and F^T r), 2 F^T p partials.
-__global__ __launch_bounds__(kT) void k_cg_colsum(const CgArgs* __restrict__ AA, int which) {
+// out[c] = sum_b part[c][b] in a fixed order (one 1024-thread block per
+// column).  which: 0 SpMM partials, 1 update partials (r.r and F^T r),
+// 2 F^T p partials.
+constexpr int kSumT = 1024;
+__global__ __launch_bounds__(kSumT) void k_cg_colsum(const CgArgs* __restrict__ AA, int which) {
   const CgArgs& A = AA[blockIdx.z];
-  const Gv G = gview(A);
   if (stopped(A)) return;
-  __shared__ double red[kT];
+  const Gv G = gview(A);
+  __shared__ double red[kSumT];
   const GL double* part;
   double* out;
   int nparts, ncols;
@@ -296,10 +299,48 @@ __global__ __launch_bounds__(kT) void k_cg_colsum(const CgArgs* __restrict__ AA,
   const int c = blockIdx.x;
   if (c >= ncols) return;
   const GL double* pc = part + (int64_t)c * nparts;
-  double v = 0.0;
-  for (int b = threadIdx.x; b < nparts; b += kT) v += pc[b];
-  v = block_sum(red, v);
-  if (threadIdx.x == 0) out[c] = v;
+  double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
+  int b = threadIdx.x;
+  for (; b + 3 * kSumT < nparts; b += 4 * kSumT) {
+    v0 += pc[b];
+    v1 += pc[b + kSumT];
+    v2 += pc[b + 2 * kSumT];
+    v3 += pc[b + 3 * kSumT];
+  }
+  for (; b < nparts; b += kSumT) v0 += pc[b];
+  red[threadIdx.x] = (v0 + v1) + (v2 + v3);
+  __syncthreads();
+  for (int o = kSumT / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[c] = red[0];
+}
+
+// Preconditioner coefficients per column (one 64-thread block per column):
+// u = S^{-1} g with g = F^T r from u_red, and g.u, each sum in a fixed order.
+__global__ __launch_bounds__(64) void k_cg_small_solve(const CgArgs* __restrict__ AA) {
+  const CgArgs& A = AA[blockIdx.z];
+  if (stopped(A)) return;
+  const int rc = blockIdx.x;
+  if (rc >= A.R) return;
+  __shared__ double gs[64];
+  __shared__ double gu[64];
+  const int i = threadIdx.x;
+  const int n1 = A.n1;
+  gs[i] = i < n1 ? A.u_red[(int64_t)A.R + (int64_t)i * A.R + rc] : 0.0;
+  __syncthreads();
+  double u = 0.0;
+  if (i < n1)
+    for (int k = 0; k < n1; ++k) u += A.Sinv[i * n1 + k] * gs[k];
+  if (i < n1) A.w_red[(int64_t)i * A.R + rc] = u;
+  gu[i] = i < n1 ? gs[i] * u : 0.0;
+  __syncthreads();
+  if (i == 0) {
+    double t = 0.0;
+    for (int k = 0; k < n1; ++k) t += gu[k];
+    A.w_red[(int64_t)n1 * A.R + rc] = t;
+  }
 }
 
 // ------------------------------------------------------------ updates
@@ -430,23 +471,12 @@ __device__ __forceinline__ int64_t elem(const CgArgs& A, bool ycol, int64_t a) {
   return ycol ? a : A.ny + (int64_t)blockIdx.y * A.n * kSlab + a * kSlab + 2 * (lane_id() & 15);
 }
 
-// u = S^{-1} g for column rc (g = F^T r, from u_red) into us[i * kSlab]
+// u = S^{-1} g of column rc (from k_cg_small_solve) into us[i * kSlab]
 // (stride kSlab); returns g.u.
 template <int NI>
-__device__ __forceinline__ double small_solve(const CgArgs& A, int rc, double* us) {
-  double gv[NI > 0 ? NI : 1];
-#pragma unroll
-  for (int i = 0; i < (NI > 0 ? NI : 1); ++i) gv[i] = i < A.n1 ? A.u_red[(int64_t)A.R + (int64_t)i * A.R + rc] : 0.0;
-  double gu = 0.0;
-  for (int i = 0; i < A.n1; ++i) {
-    double s = 0.0;
-#pragma unroll
-    for (int k = 0; k < (NI > 0 ? NI : 1); ++k)
-      if (k < A.n1) s += A.Sinv[i * A.n1 + k] * gv[k];
-    us[i * kSlab] = s;
-    gu += gv[i] * s;
-  }
-  return gu;
+__device__ __forceinline__ double coef_u(const CgArgs& A, int rc, double* us) {
+  for (int i = 0; i < A.n1; ++i) us[i * kSlab] = A.w_red[(int64_t)i * A.R + rc];
+  return A.w_red[(int64_t)A.n1 * A.R + rc];
 }
 
 // sum_i F[a][i] w[i][0] for a column-0 thread's own row.
@@ -613,7 +643,7 @@ __global__ __launch_bounds__(kT) void k_cg_update_p(const CgArgs* __restrict__ A
     int cont = 0;
     if (rc < A.R) {
       const double rr_new = A.u_red[rc];
-      const double rz_new = pc ? (rr_new - small_solve<NI>(A, rc, s_u + cl)) * A.inv_c : rr_new;
+      const double rz_new = pc ? (rr_new - coef_u<NI>(A, rc, s_u + cl)) * A.inv_c : rr_new;
       const bool act = A.st.act[par * A.R + rc] != 0 && A.st.failed[rc] == 0;
       const double rz_old = A.st.rz[par * A.R + rc];
       if (act) {
@@ -843,7 +873,7 @@ __global__ __launch_bounds__(kT) void k_cg_init_fin(const CgArgs* __restrict__ A
     const int rc = col_of(A, ycol, cl);
     if (rc < A.R) {
       const double bb = A.u_red[rc];
-      const double rz0 = pc ? (bb - small_solve<NI>(A, rc, s_u + cl)) * A.inv_c : bb;
+      const double rz0 = pc ? (bb - coef_u<NI>(A, rc, s_u + cl)) * A.inv_c : bb;
       if (blockIdx.x == 0) {
         A.st.bnorm2[rc] = bb;
         A.st.rr_last[rc] = bb;
@@ -951,16 +981,20 @@ void launch_iteration(hipStream_t st, const CgArgs* dA, const Launch& L, Ctx* c)
     SDGP_HIP(hipEventRecord(e1, st));
     c->spmm_events.push_back({e0, e1});
   }
-  k_cg_colsum<<<dim3(L.R, 1, L.B), kT, 0, st>>>(dA, 0);
+  k_cg_colsum<<<dim3(L.R, 1, L.B), kSumT, 0, st>>>(dA, 0);
   SDGP_CHECK_LAUNCH();
   k_cg_update_xr<NI><<<dim3(L.nbu, L.ns + 1, L.B), kT, 0, st>>>(dA);
   SDGP_CHECK_LAUNCH();
-  k_cg_colsum<<<dim3((1 + (L.use_pc ? L.n1 : 0)) * L.R, 1, L.B), kT, 0, st>>>(dA, 1);
+  k_cg_colsum<<<dim3((1 + (L.use_pc ? L.n1 : 0)) * L.R, 1, L.B), kSumT, 0, st>>>(dA, 1);
   SDGP_CHECK_LAUNCH();
+  if (L.use_pc) {
+    k_cg_small_solve<<<dim3(L.R, 1, L.B), 64, 0, st>>>(dA);
+    SDGP_CHECK_LAUNCH();
+  }
   k_cg_update_p<NI><<<dim3(L.nbu, L.ns + 1, L.B), kT, 0, st>>>(dA);
   SDGP_CHECK_LAUNCH();
   if (L.lowrank) {
-    k_cg_colsum<<<dim3(L.n1 * L.R, 1, L.B), kT, 0, st>>>(dA, 2);
+    k_cg_colsum<<<dim3(L.n1 * L.R, 1, L.B), kSumT, 0, st>>>(dA, 2);
     SDGP_CHECK_LAUNCH();
   }
   k_cg_check<<<dim3(1, 1, L.B), 256, 0, st>>>(dA);
@@ -971,12 +1005,16 @@ template <int NI>
 void launch_start(hipStream_t st, const CgArgs* dA, const Launch& L) {
   k_cg_norm<NI><<<dim3(L.nbu, L.ns + 1, L.B), kT, 0, st>>>(dA);
   SDGP_CHECK_LAUNCH();
-  k_cg_colsum<<<dim3((1 + (L.use_pc ? L.n1 : 0)) * L.R, 1, L.B), kT, 0, st>>>(dA, 1);
+  k_cg_colsum<<<dim3((1 + (L.use_pc ? L.n1 : 0)) * L.R, 1, L.B), kSumT, 0, st>>>(dA, 1);
   SDGP_CHECK_LAUNCH();
+  if (L.use_pc) {
+    k_cg_small_solve<<<dim3(L.R, 1, L.B), 64, 0, st>>>(dA);
+    SDGP_CHECK_LAUNCH();
+  }
   k_cg_init_fin<NI><<<dim3(L.nbu, L.ns + 1, L.B), kT, 0, st>>>(dA);
   SDGP_CHECK_LAUNCH();
   if (L.lowrank) {
-    k_cg_colsum<<<dim3(L.n1 * L.R, 1, L.B), kT, 0, st>>>(dA, 2);
+    k_cg_colsum<<<dim3(L.n1 * L.R, 1, L.B), kSumT, 0, st>>>(dA, 2);
     SDGP_CHECK_LAUNCH();
   }
 }
@@ -1053,6 +1091,7 @@ std::vector<CgResult> block_cg_multi(Ctx* c, const std::vector<CgMember>& mem, c
   double* s_red = c->get<double>(S_CG_SRED, (size_t)R * B);
   double* u_part = c->get<double>(S_CG_PART2, (size_t)nu * R * nbu * B);
   double* u_red = c->get<double>(S_CG_G, (size_t)nu * R * B);
+  double* w_red = use_pc ? c->get<double>(S_CG_WRED, (size_t)(n1 + 1) * R * B) : nullptr;
   double* p_part = use_lr ? c->get<double>(S_CG_PARTG, (size_t)n1 * R * nbu * B) : nullptr;
   double* p_red = use_lr ? c->get<double>(S_CG_GP, (size_t)n1 * R * B) : nullptr;
   double* ha = c->get<double>(S_CG_HIST_A, (size_t)max_iter * R * B);
@@ -1095,6 +1134,7 @@ std::vector<CgResult> block_cg_multi(Ctx* c, const std::vector<CgMember>& mem, c
     A.s_red = s_red + (size_t)m * R;
     A.u_part = u_part + (size_t)m * nu * R * nbu;
     A.u_red = u_red + (size_t)m * nu * R;
+    A.w_red = w_red ? w_red + (size_t)m * (n1 + 1) * R : nullptr;
     A.p_part = p_part ? p_part + (size_t)m * n1 * R * nbu : nullptr;
     A.p_red = p_red ? p_red + (size_t)m * n1 * R : nullptr;
     char* mb = sb + sbytes * m;

@@ -91,12 +91,12 @@ def test_spmm_matches_dense_product():
     gu.need_gpu()
     import torch
     w = wl.random_small(900, 2, 2, 2, 1, per_row=20.0)
-    gu.log("spmm R in (1, 5, 64, 70)")
+    gu.log("spmm R in (1, 2, 5, 34, 64, 70)")
     c = gu.ctx()
     rp, col, val = c.kernel_assemble(w.desc, gu.dev(w.x), w.h)
     _, _, _, S = gu.csr_to_host(rp, col, val, w.x.shape[0])
     rng = np.random.default_rng(0)
-    for R in (1, 5, 64, 70):
+    for R in (1, 2, 5, 34, 64, 70):
         X = rng.standard_normal((w.x.shape[0], R))
         Y = c.csr_spmm(rp, col, val, gu.dev(X if R > 1 else X[:, 0]))
         ref = S @ (X if R > 1 else X[:, 0])
