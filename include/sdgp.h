@@ -264,6 +264,64 @@ sdgp_status sdgp_sparsity_bound(const sdgp_kernel_desc* desc, const double* h,
 sdgp_status sdgp_sparsity_objective(double lml, double s, double requirement,
                                     double* augmented_out, int32_t* feasible_out);
 
+/* ------------------------------------------------------------------------
+ * Training driver over the batched path: differential evolution
+ * (DE/rand/1/bin of Storn and Price, J. Global Optim. 11, 1997), the
+ * derivative-free population search over hyperparameters for which the
+ * batched evaluation is built (the paper maximises the LML derivative-free,
+ * by MCMC: Sections 2.5 and 3).
+ * Random numbers: the SplitMix64 counter generator of sdgp_estimator, with
+ * stream keys derived from (seed, generation, member, draw); deterministic.
+ * ------------------------------------------------------------------------ */
+
+/* Fitness used by sdgp_train_de. */
+typedef enum {
+  SDGP_DE_LML = 0,          /* ln L */
+  SDGP_DE_AUGMENTED = 1,    /* the augmented objective of sdgp_sparsity_objective */
+  SDGP_DE_CONSTRAINED = 2   /* ln L when the sparsity bound s(h) < requirement, else -inf */
+} sdgp_de_objective;
+
+typedef struct {
+  int32_t generations;      /* >= 0 */
+  double F;                 /* differential weight, (0, 2] */
+  double CR;                /* crossover probability, [0, 1] */
+  uint64_t seed;
+  int32_t objective;        /* sdgp_de_objective */
+  double requirement;       /* sparsity requirement (objectives 1, 2) */
+  double domain_volume;     /* V_X of sdgp_sparsity_bound (objectives 1, 2) */
+} sdgp_de_options;
+
+/* Trial vectors of one DE generation: for member m of the population H
+ * (host, B x nh, row-major) pick r1, r2, r3 distinct and != m, a forced
+ * component jrand, and set T[m][j] = H[r1][j] + F (H[r2][j] - H[r3][j]) where
+ * u_j < CR or j == jrand, else H[m][j].  A component outside [lo[j], hi[j]]
+ * is redrawn uniformly between the violated bound and H[m][j]; components
+ * with lo[j] == hi[j] stay fixed.  Needs B >= 4, lo <= H <= hi.  Host only;
+ * T: host, B x nh.  INVALID_ARG on bad sizes, bounds or F / CR. */
+sdgp_status sdgp_de_trials(int32_t B, int32_t nh, const double* H, const double* lo,
+                           const double* hi, double F, double CR, uint64_t seed,
+                           uint64_t generation, double* T);
+
+/* Selection: row m of H and fit[m] take T[m] and ft[m] when ft[m] >= fit[m]
+ * (a NaN trial fitness never wins; a NaN incumbent always loses to a
+ * number).  replaced_out (host, may be NULL) receives the count.  Host
+ * only. */
+sdgp_status sdgp_de_select(int32_t B, int32_t nh, double* H, double* fit, const double* T,
+                           const double* ft, int32_t* replaced_out);
+
+/* Runs opt->generations DE generations on the device path: the initial
+ * population H and every generation's trials are evaluated with one batched
+ * evaluation each (sdgp_lml_grad_batched semantics; a member whose
+ * evaluation fails gets fitness -inf), then selected.  H (host, B x nh) is
+ * updated in place; fit (host, B) receives the final fitness;
+ * history (host, generations + 1, may be NULL) the best fitness after the
+ * initial evaluation and after each generation.  x, y: device, as in
+ * sdgp_lml. */
+sdgp_status sdgp_train_de(sdgp_ctx* ctx, const sdgp_kernel_desc* desc, const double* x,
+                          const double* y, int64_t n, double* H, int32_t B, const double* lo,
+                          const double* hi, const sdgp_estimator* est,
+                          const sdgp_de_options* opt, double* fit, double* history);
+
 #ifdef __cplusplus
 }
 #endif

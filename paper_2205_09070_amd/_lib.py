@@ -26,6 +26,7 @@ COMBINE_PRODUCT, COMBINE_SUM = 0, 1
 PROBE_RADEMACHER, PROBE_IDENTITY = 0, 2
 PRECOND_NONE, PRECOND_LOWRANK = 0, 1
 OPERATOR_ASSEMBLED, OPERATOR_FACTORED = 0, 1
+DE_LML, DE_AUGMENTED, DE_CONSTRAINED = 0, 1, 2
 
 
 class KernelDesc(C.Structure):
@@ -50,6 +51,11 @@ class Info(C.Structure):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "ms"}
         d["ms"] = list(self.ms)
         return d
+
+
+class DeOptions(C.Structure):
+    _fields_ = [("generations", C.c_int32), ("F", C.c_double), ("CR", C.c_double), ("seed", C.c_uint64),
+                ("objective", C.c_int32), ("requirement", C.c_double), ("domain_volume", C.c_double)]
 
 
 class SdgpError(RuntimeError):
@@ -86,6 +92,10 @@ _SIGS = {
                                  C.POINTER(D), C.POINTER(D)]),
     "sdgp_sparsity_bound": (I32, [C.POINTER(KernelDesc), VP, D, C.POINTER(D)]),
     "sdgp_sparsity_objective": (I32, [D, D, D, C.POINTER(D), C.POINTER(I32)]),
+    "sdgp_de_trials": (I32, [I32, I32, VP, VP, VP, D, D, C.c_uint64, C.c_uint64, VP]),
+    "sdgp_de_select": (I32, [I32, I32, VP, VP, VP, VP, C.POINTER(I32)]),
+    "sdgp_train_de": (I32, [VP, C.POINTER(KernelDesc), VP, VP, I64, VP, I32, VP, VP, C.POINTER(Estimator),
+                            C.POINTER(DeOptions), VP, VP]),
 }
 
 
@@ -110,6 +120,36 @@ def sparsity_objective(lml, s, requirement):
     if st != OK:
         raise SdgpError(st, "sdgp_sparsity_objective failed")
     return float(a.value), bool(f.value)
+
+
+def _f64(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def de_trials(H, lo, hi, F=0.7, CR=0.9, seed=0, generation=1):
+    """Trial vectors of one differential-evolution generation (host-only
+    library call); H: (B, nh)."""
+    lib = load()
+    H, lo, hi = _f64(H), _f64(lo), _f64(hi)
+    B, nh = H.shape
+    T = np.empty_like(H)
+    st = lib.sdgp_de_trials(B, nh, H.ctypes.data, lo.ctypes.data, hi.ctypes.data, float(F), float(CR),
+                            int(seed), int(generation), T.ctypes.data)
+    if st != OK:
+        raise SdgpError(st, "sdgp_de_trials failed")
+    return T
+
+
+def de_select(H, fit, T, ft):
+    """Selection step; returns (H, fit, replaced) (new arrays)."""
+    lib = load()
+    H, fit, T, ft = _f64(H).copy(), _f64(fit).copy(), _f64(T), _f64(ft)
+    B, nh = H.shape
+    rep = I32(0)
+    st = lib.sdgp_de_select(B, nh, H.ctypes.data, fit.ctypes.data, T.ctypes.data, ft.ctypes.data, C.byref(rep))
+    if st != OK:
+        raise SdgpError(st, "sdgp_de_select failed")
+    return H, fit, int(rep.value)
 
 
 def header_functions() -> list:
@@ -296,6 +336,25 @@ class Context:
                                                    _hptr(H), B, C.byref(e), _hptr(v), _hptr(g), _hptr(ms),
                                                    C.cast(infos, VP)))
         return v, g, ms, list(infos)
+
+    def train_de(self, desc, x, y, H, lo, hi, est=None, generations=10, F=0.7, CR=0.9, seed=0,
+                 objective=DE_LML, requirement=1.0, domain_volume=1.0):
+        """Differential evolution over the population H (B, nh) with one
+        batched evaluation per generation; returns (H, fit, history)."""
+        x, y = _dev_f64(x), _dev_f64(y)
+        H = _f64(H).copy()
+        lo, hi = _f64(lo), _f64(hi)
+        B, nh = H.shape
+        d = desc_of(desc)
+        e = est or estimator()
+        o = DeOptions(int(generations), float(F), float(CR), int(seed), int(objective), float(requirement),
+                      float(domain_volume))
+        fit = np.zeros(B)
+        hist = np.zeros(int(generations) + 1)
+        self._check(self.lib.sdgp_train_de(self.h, C.byref(d), _ptr(x), _ptr(y), x.shape[0], H.ctypes.data, B,
+                                           lo.ctypes.data, hi.ctypes.data, C.byref(e), C.byref(o),
+                                           fit.ctypes.data, hist.ctypes.data))
+        return H, fit, hist
 
     def logdet_taylor(self, desc, x, h, probes=32, terms=50, seed=0):
         """Randomised Taylor-series log-det; returns (logdet, alpha)."""

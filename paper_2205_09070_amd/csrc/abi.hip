@@ -533,4 +533,78 @@ sdgp_status sdgp_sparsity_objective(double lml, double s, double requirement, do
   return SDGP_OK;
 }
 
+sdgp_status sdgp_de_trials(int32_t B, int32_t nh, const double* H, const double* lo, const double* hi, double F,
+                           double CR, uint64_t seed, uint64_t generation, double* T) {
+  try {
+    de_trials(B, nh, H, lo, hi, F, CR, seed, generation, T);
+    return SDGP_OK;
+  } catch (const Error& e) {
+    return (sdgp_status)e.code;
+  }
+}
+
+sdgp_status sdgp_de_select(int32_t B, int32_t nh, double* H, double* fit, const double* T, const double* ft,
+                           int32_t* replaced_out) {
+  try {
+    const int32_t r = de_select(B, nh, H, fit, T, ft);
+    if (replaced_out) *replaced_out = r;
+    return SDGP_OK;
+  } catch (const Error& e) {
+    return (sdgp_status)e.code;
+  }
+}
+
+sdgp_status sdgp_train_de(sdgp_ctx* ctx, const sdgp_kernel_desc* desc, const double* x, const double* y, int64_t n,
+                          double* H, int32_t B, const double* lo, const double* hi, const sdgp_estimator* est,
+                          const sdgp_de_options* opt, double* fit, double* history) {
+  return guarded(ctx, [&] {
+    require(desc && x && y && H && lo && hi && est && opt && fit, "NULL argument");
+    require(opt->generations >= 0, "generations must be >= 0");
+    require(opt->objective >= SDGP_DE_LML && opt->objective <= SDGP_DE_CONSTRAINED, "unknown objective");
+    const int64_t nh = sdgp_num_hyper(desc);
+    require(nh > 0, "invalid kernel descriptor");
+    require(B >= 4, "differential evolution needs at least 4 members");
+    const size_t BN = (size_t)B * nh;
+    std::vector<double> T(BN), grad(BN), val(B), ft(B);
+    std::vector<int32_t> st(B);
+    // fitness of a population: one batched evaluation, failures -> -inf
+    auto evaluate = [&](const double* P, double* out) {
+      const sdgp_status s = sdgp_lml_grad_batched(ctx, desc, x, y, n, P, B, est, val.data(), grad.data(),
+                                                  st.data(), nullptr);
+      if (s != SDGP_OK) throw Error(s, std::string("batched evaluation failed: ") + ctx->err);
+      for (int32_t m = 0; m < B; ++m) {
+        double f = -INFINITY;
+        if (st[m] == SDGP_OK && std::isfinite(val[m])) {
+          f = val[m];
+          if (opt->objective != SDGP_DE_LML) {
+            double sp = 0.0, aug = 0.0;
+            int32_t feas = 0;
+            if (sdgp_sparsity_bound(desc, P + (size_t)m * nh, opt->domain_volume, &sp) != SDGP_OK ||
+                sdgp_sparsity_objective(val[m], sp, opt->requirement, &aug, &feas) != SDGP_OK)
+              f = -INFINITY;
+            else if (opt->objective == SDGP_DE_AUGMENTED)
+              f = aug;
+            else
+              f = feas ? val[m] : -INFINITY;
+          }
+        }
+        out[m] = f;
+      }
+    };
+    auto best = [&]() {
+      double b = -INFINITY;
+      for (int32_t m = 0; m < B; ++m) b = std::max(b, fit[m]);
+      return b;
+    };
+    evaluate(H, fit);
+    if (history) history[0] = best();
+    for (int32_t gnr = 1; gnr <= opt->generations; ++gnr) {
+      de_trials(B, (int32_t)nh, H, lo, hi, opt->F, opt->CR, opt->seed, (uint64_t)gnr, T.data());
+      evaluate(T.data(), ft.data());
+      de_select(B, (int32_t)nh, H, fit, T.data(), ft.data());
+      if (history) history[gnr] = best();
+    }
+  });
+}
+
 }  // extern "C"

@@ -244,6 +244,11 @@ void spmm(Ctx* c, const Csr& A, const double* X, int R, double* Y);
 void spmm_slab(Ctx* c, const Csr& A, const double* X, int R, double* Y);
 // Randomised Taylor-series log-det (Boutsidis et al. 2017) on A.
 double logdet_taylor(Ctx* c, const Csr& A, const Sorted& s, int P, int terms, uint64_t seed, double* alpha_out);
+// Differential evolution (host): trial vectors of one generation, selection
+// (returns the number of members replaced).
+void de_trials(int32_t B, int32_t nh, const double* H, const double* lo, const double* hi, double F, double CR,
+               uint64_t seed, uint64_t generation, double* T);
+int32_t de_select(int32_t B, int32_t nh, double* H, double* fit, const double* T, const double* ft);
 // Stochastic Lanczos quadrature from CG coefficients of columns 1..R-1.
 void slq_from_cg(Ctx* c, const CgResult& cg, int kind, int P, int64_t n,
                  int lanczos_steps, double* logdet, double* stderr_out,
