@@ -147,11 +147,15 @@ void sdgp_destroy(sdgp_ctx* ctx);
 const char* sdgp_last_error(const sdgp_ctx* ctx);
 /* Enable (1) or disable (0) per-phase and per-SpMM-launch HIP-event timing. */
 sdgp_status sdgp_set_timing(sdgp_ctx* ctx, int enable);
-/* Context options: "timing" (0/1, as sdgp_set_timing) and "graph" (0/1):
+/* Context options: "timing" (0/1, as sdgp_set_timing); "graph" (0/1):
  * run the CG iterations as a captured hipGraph of 8 iterations replayed
  * until every column (and every population member) has converged; the
  * iteration counters live on the device, so replays past convergence or
- * past cg_max_iter do nothing.  Results are bitwise identical either way. */
+ * past cg_max_iter do nothing; "staged_spmm" (0/1, default 0): with at most
+ * 33 right-hand sides the CG SpMM stages each 64-row block's neighbour rows
+ * in LDS (lists built once per solve).  "timing" and "graph" leave the
+ * results bitwise unchanged; "staged_spmm" changes only the blocking of the
+ * p.Ap partial sums (agreement to rounding).  Unknown names: INVALID_ARG. */
 sdgp_status sdgp_set_option(sdgp_ctx* ctx, const char* name, int64_t value);
 
 /* 2 + n1*n2*(3+dim) + 1, or -1 for an invalid descriptor. */

@@ -450,6 +450,7 @@ sdgp_status sdgp_set_option(sdgp_ctx* ctx, const char* name, int64_t value) {
   const std::string k(name);
   if (k == "timing") { ctx->timing = value != 0; return SDGP_OK; }
   if (k == "graph") { ctx->use_graph = value != 0; return SDGP_OK; }
+  if (k == "staged_spmm") { ctx->staged_spmm = value != 0; return SDGP_OK; }
   ctx->err = "unknown option '" + k + "'";
   return SDGP_ERR_INVALID_ARG;
 }

@@ -74,7 +74,7 @@ enum Slot {
   S_RED_PART, S_RED_OUT, S_X0S, S_MISC, S_POST, S_COUNTER,
   S_CG_V, S_CG_PART2, S_CG_ARGS, S_CG_PARTG, S_CG_G, S_CG_GP, S_PC_PART, S_PC_SINV, S_LR_PART, S_LR_FX, S_LR_FV,
   S_MORTON_KEYS, S_MORTON_KEYS2, S_MORTON_IDS, S_MORTON_ORDER, S_MORTON_SZ, S_MORTON_OFF, S_SCHED,
-  S_CG_SRED, S_CG_WRED, S_QF, S_QM, S_KXX, S_QIV_CNT, S_QIV_PTR, S_QIV, S_QROW_NNZ, S_QROW_PTR, S_QCOL, S_QVAL,
+  S_CG_SRED, S_CG_WRED, S_CG_LNB, S_CG_LCNT, S_CG_LSLOT, S_QF, S_QM, S_KXX, S_QIV_CNT, S_QIV_PTR, S_QIV, S_QROW_NNZ, S_QROW_PTR, S_QCOL, S_QVAL,
   S_NUM
 };
 
@@ -89,6 +89,7 @@ struct Ctx {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> spmm_events;
   int cu_count = 256;
   bool use_graph = false;        // replay captured CG iterations (hipGraph)
+  bool staged_spmm = false;      // neighbourhood-staged CG SpMM when R <= 33 (opt-in)
   std::vector<DevBuf> member_bufs;  // per-member storage of the population path
   hipStream_t gstream = nullptr; // private default-priority stream for graph capture
   hipStream_t graph_stream() {
