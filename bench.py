@@ -28,6 +28,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "LML+grad evals/s at N=1M (FP64); assembly nnz/s; SpMV GB/s vs HBM peak"
+METRIC_5M = "LML+grad evals/s at N=5M, 4-D space-time (FP64); assembly nnz/s; SpMV GB/s vs HBM peak"
 HBM_PEAK_GBPS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 
@@ -47,6 +48,10 @@ def parse():
                    help="replay the CG iterations from a HIP graph (1; the SpMM is then not timed per launch)")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--spmv-reps", type=int, default=50)
+    p.add_argument("--workload", choices=["uniform3d_n1000000", "spacetime4d_n5000000"],
+                   default="uniform3d_n1000000",
+                   help="uniform3d_n1000000: 1M points in the unit cube (the headline); spacetime4d_n5000000: "
+                        "5M space-time points in 4-D with 32x8 bumps")
     p.add_argument("--population", type=int, default=0, metavar="B",
                    help="instead of the N=1M line, time a population of B hyperparameter vectors on a shared "
                         "N=200,000 point set: one batched call against B sequential calls")
@@ -84,7 +89,8 @@ def cpu_baseline(w):
     window of the same point set (same density, kernel and hyperparameters),
     scaled to N by the oracle's O(N^3) cost."""
     from oracle import gp
-    side = 0.12
+    d = w.x.shape[1]
+    side = (1712.0 / w.x.shape[0]) ** (1.0 / d)
     m = np.all(w.x < side, axis=1)
     xs, ys = w.x[m], w.y[m]
     ns = xs.shape[0]
@@ -94,8 +100,8 @@ def cpu_baseline(w):
     n = w.x.shape[0]
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": (1.0 / dt) * (ns / n) ** 3, "unit": "evals/s", "cores": threads, "kind": "oracle",
-            "sample": "dense FP64 oracle LML+gradient on the %d points of the [0,%.2f)^3 window of the "
-                      "same 1M-point set (%.2f s); value scaled to N=%d by (n/N)^3" % (ns, side, dt, n),
+            "sample": "dense FP64 oracle LML+gradient on the %d points of the [0,%.3f)^%d window of the "
+                      "same point set (%.2f s); value scaled to N=%d by (n/N)^3" % (ns, side, d, dt, n),
             "sample_evals_per_s": 1.0 / dt, "sample_points": ns}
 
 
@@ -171,7 +177,14 @@ def main():
         population(args, sd, wl, torch)
         return
     dev = torch.device("cuda", 0)
-    w = wl.uniform3d_1m()
+    if args.workload == "spacetime4d_n5000000":
+        w = wl.spacetime_4d()
+        wdesc = ("spacetime4d_n5000000: 5,000,000 points, x1..x3 uniform in [0,1), x4 on 365 time steps, "
+                 "Wendland C2 core (l=4, ~50 core neighbours/row) + 32x8 bump functions, SUM combine")
+    else:
+        w = wl.uniform3d_1m()
+        wdesc = ("uniform3d_n1000000: 1,000,000 points uniform in [0,1)^3, Wendland C2 core "
+                 "(~60 core neighbours/row) + 16x4 bump functions, SUM combine")
     n = w.x.shape[0]
     x = torch.from_numpy(w.x).to(dev)
     y = torch.from_numpy(w.y).to(dev)
@@ -247,7 +260,7 @@ def main():
     spmv_bytes = 12.0 * spmv_nnz + 8.0 * (n + 1) + 8.0 * n + 8.0 * n
     spmv_gbps = spmv_bytes / (spmv_ms * 1e-3) / 1e9
     out = {
-        "metric": METRIC,
+        "metric": METRIC if args.workload == "uniform3d_n1000000" else METRIC_5M,
         "value": value,
         "unit": "evals/s",
         "n_gpus": 1,
@@ -259,11 +272,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "uniform3d_n1000000: 1,000,000 points uniform in [0,1)^3, Wendland C2 core "
-                               "(~60 core neighbours/row) + 16x4 bump functions, SUM combine, "
-                               "%d Rademacher probes, CG rtol %g, preconditioner %s, operator %s"
+        "config": {"workload": wdesc + ", %d Rademacher probes, CG rtol %g, preconditioner %s, operator %s"
                                % (args.probes, args.rtol, args.precond, args.operator),
-                   "points": n, "dim": 3, "n1": w.desc.n1, "n2": w.desc.n2, "n_hyper": int(len(w.h)),
+                   "points": n, "dim": int(w.desc.dim), "n1": w.desc.n1, "n2": w.desc.n2, "n_hyper": int(len(w.h)),
                    "probes": args.probes, "cg_rtol": args.rtol, "precond": args.precond,
                    "operator": args.operator, "graph": bool(args.graph)},
         "nnz": int(nnz),
@@ -281,7 +292,8 @@ def main():
         "roofline": {"kernel": "k_cg_spmm (CG SpMM, %d right-hand sides)" % R, "bound": "hbm",
                      "achieved": spmm_gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": spmm_gbps / HBM_PEAK_GBPS,
-                     "traffic": (spmm_traffic(args.operator) or {}).get("GB_per_launch"),
+                     "traffic": ((spmm_traffic(args.operator) or {}).get("GB_per_launch")
+                                 if args.workload == "uniform3d_n1000000" else None),
                      "traffic_unit": "GB per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE x1, copy-scaled)",
                      "avg_launch_ms": spmm_avg_ms, "launches": spmm_launches,
                      "algorithmic_bytes_per_launch": spmm_bytes},

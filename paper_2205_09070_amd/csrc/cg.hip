@@ -1422,22 +1422,37 @@ std::vector<CgResult> block_cg_multi(Ctx* c, const std::vector<CgMember>& mem, c
     SDGP_CHECK_LAUNCH();
   }
   cg_start(NI, c->stream, dA, L);
-  // iterate; poll the per-member flags now and then
+  // iterate; poll the per-member flags now and then.  Members that have
+  // stopped leave the launch grid (grid z covers the active members only).
   std::vector<int32_t> flags((size_t)3 * B);
-  auto poll = [&](hipStream_t st) -> bool {
-    for (int m = 0; m < B; ++m)
+  std::vector<int> active(B);
+  for (int m = 0; m < B; ++m) active[m] = m;
+  std::vector<CgArgs> hAct;
+  auto poll = [&](hipStream_t st) -> bool {  // true when the active set shrank
+    for (int m : active)
       SDGP_HIP(hipMemcpyAsync(&flags[3 * m], hA[m].st.done, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     SDGP_HIP(hipStreamSynchronize(st));
-    for (int m = 0; m < B; ++m)
-      if (flags[3 * m] == 0 && flags[3 * m + 2] < max_iter) return false;
+    std::vector<int> still;
+    for (int m : active)
+      if (flags[3 * m] == 0 && flags[3 * m + 2] < max_iter) still.push_back(m);
+    if (still.size() == active.size()) return false;
+    active.swap(still);
+    if (!active.empty()) {
+      hAct.clear();
+      for (int m : active) hAct.push_back(hA[m]);
+      SDGP_HIP(hipMemcpyAsync(dA, hAct.data(), hAct.size() * sizeof(CgArgs), hipMemcpyHostToDevice, st));
+      SDGP_HIP(hipStreamSynchronize(st));
+      L.B = (int)active.size();
+    }
     return true;
   };
   c->spmm_events.clear();
   int launched = 0;
   if (use_graph) {
-    // capture k iterations once and replay them: the iteration counters live
-    // on the device, so every replay advances the solve; kernels of members
-    // that are done, or past max_iter, return at once
+    // capture k iterations and replay them: the iteration counters live on
+    // the device, so every replay advances the solve; kernels of members
+    // that are done, or past max_iter, return at once.  The graph is
+    // captured again whenever the active set shrinks.
     const int k = 8;
     hipStream_t gs = c->graph_stream();
     hipEvent_t ready = c->event();
@@ -1445,38 +1460,49 @@ std::vector<CgResult> block_cg_multi(Ctx* c, const std::vector<CgMember>& mem, c
     SDGP_HIP(hipStreamWaitEvent(gs, ready, 0));
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    SDGP_HIP(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
-    for (int q = 0; q < k; ++q) cg_iteration(NI, gs, dA, L, nullptr);
-    SDGP_HIP(hipStreamEndCapture(gs, &graph));
-    hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    if (ie != hipSuccess) {
-      (void)hipGraphDestroy(graph);
-      throw Error(SDGP_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
-    }
+    auto capture = [&]() {
+      if (exec) (void)hipGraphExecDestroy(exec);
+      if (graph) (void)hipGraphDestroy(graph);
+      exec = nullptr;
+      graph = nullptr;
+      SDGP_HIP(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
+      for (int q = 0; q < k; ++q) cg_iteration(NI, gs, dA, L, nullptr);
+      SDGP_HIP(hipStreamEndCapture(gs, &graph));
+      hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      if (ie != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        graph = nullptr;
+        throw Error(SDGP_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+      }
+    };
+    capture();
     int every = 1;
-    bool fin = false;
-    while (!fin && launched < max_iter) {
+    while (!active.empty() && launched < max_iter) {
       for (int q = 0; q < every && launched < max_iter; ++q) {
         SDGP_HIP(hipGraphLaunch(exec, gs));
         launched += k;
       }
-      fin = poll(gs);
+      if (poll(gs) && !active.empty()) capture();
       every = std::min(every * 2, 8);
     }
-    (void)hipGraphExecDestroy(exec);
-    (void)hipGraphDestroy(graph);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
     hipEvent_t back = c->event();
     SDGP_HIP(hipEventRecord(back, gs));
     SDGP_HIP(hipStreamWaitEvent(c->stream, back, 0));
   } else {
     int check = 8;
-    bool fin = false;
-    while (!fin && launched < max_iter) {
+    while (!active.empty() && launched < max_iter) {
       const int upto = std::min(max_iter, launched + check);
       for (; launched < upto; ++launched) cg_iteration(NI, c->stream, dA, L, c);
-      fin = poll(c->stream);
+      poll(c->stream);
       check = std::min(check * 2, 64);
     }
+  }
+  // every member's arguments again, for the unpack
+  if (L.B != B) {
+    SDGP_HIP(hipMemcpyAsync(dA, hA.data(), B * sizeof(CgArgs), hipMemcpyHostToDevice, c->stream));
+    L.B = B;
   }
   // solutions (and M^{-1} b) back to row-major [n][R], into the P and Q
   // storage that the iteration no longer needs
