@@ -153,9 +153,13 @@ sdgp_status sdgp_set_timing(sdgp_ctx* ctx, int enable);
  * iteration counters live on the device, so replays past convergence or
  * past cg_max_iter do nothing; "staged_spmm" (0/1, default 0): with at most
  * 33 right-hand sides the CG SpMM stages each 64-row block's neighbour rows
- * in LDS (lists built once per solve).  "timing" and "graph" leave the
- * results bitwise unchanged; "staged_spmm" changes only the blocking of the
- * p.Ap partial sums (agreement to rounding).  Unknown names: INVALID_ARG. */
+ * in LDS (lists built once per solve); "fw_mfma" (-1 default = 1, 0, 1):
+ * the preconditioner / factored-operator products
+ * F w of the CG update kernels per 16-row tile on the matrix cores instead
+ * of per-row broadcasts.  "timing" and "graph" leave the
+ * results bitwise unchanged; "staged_spmm" and "fw_mfma" change only the
+ * order of floating-point sums (agreement to rounding).  Unknown names or
+ * values: INVALID_ARG. */
 sdgp_status sdgp_set_option(sdgp_ctx* ctx, const char* name, int64_t value);
 
 /* 2 + n1*n2*(3+dim) + 1, or -1 for an invalid descriptor. */

@@ -662,15 +662,75 @@ __device__ void put_ft_partials(const CgArgs& A, double* red, d4 (*acc)[2], GL d
   }
 }
 
-// Column-0 block sums of scalar F^T v accumulators into part rows base + i R.
+// Column-0 block sums: v0 (when has0) into part row row0, and the scalar
+// F^T v accumulators gy[i] into part rows base + i R (when hasg); wavefront
+// sums by DPP butterflies, then the four wavefronts in LDS (fixed order).
 template <int NI>
-__device__ void put_fty_partials(const CgArgs& A, double* red, const double* gy, GL double* part, int64_t base) {
-#pragma unroll
-  for (int i = 0; i < (NI > 0 ? NI : 1); ++i) {
-    if (i >= A.n1) continue;
-    const double t = block_sum(red, gy[i]);
-    if (threadIdx.x == 0) part[(base + (int64_t)i * A.R) * A.nbu + blockIdx.x] = t;
+__device__ void put_y_partials(const CgArgs& A, double* red, bool has0, double v0, int64_t row0, bool hasg,
+                               const double* gy, GL double* part, int64_t base) {
+  constexpr int NV = (NI > 0 ? NI : 1) + 1;
+  const int w = threadIdx.x >> 6, lane = lane_id();
+  __syncthreads();
+  if (has0) {
+    const double t = wave_sum(v0);
+    if (lane == 0) red[w * NV] = t;
   }
+  if (hasg) {
+#pragma unroll
+    for (int i = 0; i < (NI > 0 ? NI : 1); ++i) {
+      if (i >= A.n1) continue;
+      const double t = wave_sum(gy[i]);
+      if (lane == 0) red[w * NV + 1 + i] = t;
+    }
+  }
+  __syncthreads();
+  const int nv = hasg ? 1 + A.n1 : 1;
+  for (int v = threadIdx.x; v < nv; v += kT) {
+    if (v == 0 && !has0) continue;
+    const double t = (red[v] + red[NV + v]) + (red[2 * NV + v] + red[3 * NV + v]);
+    const int64_t row = v == 0 ? row0 : base + (int64_t)(v - 1) * A.R;
+    part[row * A.nbu + blockIdx.x] = t;
+  }
+}
+
+// F w for the wavefront's 16-row tile on the matrix cores (used with many
+// bump functions, where the per-row broadcast products cost more): with
+// rows base .. base+15 and K = 4 bump indices per instruction,
+//   A[m][k] = F[base + m][4 s + k]   (lane 16 k + m),
+//   B[k][c] = w[4 s + k][2 c + par]  (lane 16 k + c; w in LDS, stride kSlab),
+// so D[4 q + g][j] (lane (g, j), register q) is the product for the row the
+// lane owns at step q, even column (de) / odd column (dd).
+template <int NS>
+__device__ __forceinline__ void fw_tile(const GL double* __restrict__ F, int n1, int64_t n, int64_t base,
+                                        const double* w, d4& de, d4& dd) {
+  const int g = lane_id() >> 4, j = lane_id() & 15;
+  const int64_t row = base + j;
+  de = d4{0.0, 0.0, 0.0, 0.0};
+  dd = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int i = 4 * s + g;
+    const bool ok = i < n1;
+    const double fa = (row < n && ok) ? F[row * n1 + i] : 0.0;
+    const double b0 = ok ? w[i * kSlab + 2 * j] : 0.0;
+    const double b1 = ok ? w[i * kSlab + 2 * j + 1] : 0.0;
+    de = __builtin_amdgcn_mfma_f64_16x16x4f64(fa, b0, de, 0, 0, 0);
+    dd = __builtin_amdgcn_mfma_f64_16x16x4f64(fa, b1, dd, 0, 0, 0);
+  }
+}
+__device__ __forceinline__ double pick4(const d4& v, int q) {
+  return q == 0 ? v[0] : (q == 1 ? v[1] : (q == 2 ? v[2] : v[3]));
+}
+// Slab blocks with 16-row wavefront tiles: block steps and the wavefront's
+// first row at step k.
+constexpr int kWaveRows = 16;
+constexpr int kBlockRows = 4 * kWaveRows;
+__device__ __forceinline__ int64_t tile_steps(const CgArgs& A) {
+  const int64_t tiles = (A.n + kBlockRows - 1) / kBlockRows;
+  return tiles > (int64_t)blockIdx.x ? (tiles - blockIdx.x + A.nbu - 1) / A.nbu : 0;
+}
+__device__ __forceinline__ int64_t wave_base(const CgArgs& A, int64_t k) {
+  return (blockIdx.x + k * (int64_t)A.nbu) * kBlockRows + (threadIdx.x >> 6) * kWaveRows;
 }
 
 // Per-column scalars are computed once per block into LDS by the column's
@@ -726,7 +786,7 @@ constexpr int kRed = 4 * 512;   // LDS doubles for the block reductions
 
 // alpha = r.z / p.A p (p.A p = p.K_core p + |F^T p|^2 with the factored
 // operator); x += alpha p; r -= alpha A p; partials of r.r and F^T r.
-template <int NI>
+template <int NI, int FW>
 __global__ __launch_bounds__(kT) void k_cg_update_xr(const CgArgs* __restrict__ AA) {
   constexpr int NT = (NI + 15) / 16;
   const CgArgs& A = AA[blockIdx.z];
@@ -799,9 +859,7 @@ __global__ __launch_bounds__(kT) void k_cg_update_xr(const CgArgs* __restrict__ 
             if (i < A.n1) gy[i] += Fa[i] * r;
         }
       }
-    const double t = block_sum(red, rr);
-    if (threadIdx.x == 0) G.u_part[blockIdx.x] = t;
-    if (pc) put_fty_partials<NI>(A, red, gy, G.u_part, A.R);
+    put_y_partials<NI>(A, red, true, rr, 0, pc, gy, G.u_part, A.R);
     return;
   }
   const int cl = my_cl(false);
@@ -811,7 +869,45 @@ __global__ __launch_bounds__(kT) void k_cg_update_xr(const CgArgs* __restrict__ 
   d4 acc[NT > 0 ? NT : 1][2];
 #pragma unroll
   for (int mt = 0; mt < (NT > 0 ? NT : 1); ++mt) acc[mt][0] = acc[mt][1] = d4{0.0, 0.0, 0.0, 0.0};
-  if (__any(mine)) {
+  if (FW == 1 && __any(mine)) {
+    // F (F^T p) per 16-row wavefront tile on the matrix cores
+    constexpr int NS = (NI + 3) / 4;
+    const int g = lane_id() >> 4;
+    const int64_t nst = tile_steps(A);
+    for (int64_t k = 0; k < nst; ++k) {
+      const int64_t base = wave_base(A, k);
+      if (base >= A.n) break;                       // uniform over the wavefront
+      d4 ce = {0.0, 0.0, 0.0, 0.0}, cd = {0.0, 0.0, 0.0, 0.0};
+      if (NS > 0 && lr) fw_tile<NS>(G.F, A.n1, A.n, base, s_gp, ce, cd);
+#pragma unroll 1
+      for (int st = 0; st < 4; ++st) {
+        const int64_t a = base + 4 * st + g;
+        dv2 r = {0.0, 0.0};
+        if (a < A.n) {
+          const int64_t o = elem(A, false, a);
+          dv2 q = *reinterpret_cast<const GL dv2*>(G.Q + o);
+          const dv2 p = *reinterpret_cast<const GL dv2*>(G.P + o);
+          dv2 x = *reinterpret_cast<const GL dv2*>(G.X + o);
+          r = *reinterpret_cast<const GL dv2*>(G.Rr + o);
+          q.x += pick4(ce, st);
+          q.y += pick4(cd, st);
+          x.x += al0 * p.x;
+          x.y += al1 * p.y;
+          r.x -= al0 * q.x;
+          r.y -= al1 * q.y;
+          *reinterpret_cast<GL dv2*>(G.X + o) = x;
+          *reinterpret_cast<GL dv2*>(G.Rr + o) = r;
+          rr0 += r.x * r.x;
+          rr1 += r.y * r.y;
+        }
+        if (NT > 0 && pc) {
+          double f[NT > 0 ? NT : 1];
+          load_f<NT>(A, a < A.n ? a : -1, f);
+          ft_step<NT>(f, r.x, r.y, acc);
+        }
+      }
+    }
+  } else if (FW == 0 && __any(mine)) {
     for (int64_t k = 0; k < steps; ++k) {
       const int64_t a = thread_row(A, false, k);
       double f[NT > 0 ? NT : 1];
@@ -854,7 +950,7 @@ __global__ __launch_bounds__(kT) void k_cg_update_xr(const CgArgs* __restrict__ 
 // z = M^{-1} r = (r - F u) / c formed on the fly (r.z_new = (r.r - g.u)/c,
 // g = F^T r, u = (cI + F^T F)^{-1} g).  With the factored operator also
 // the partials of F^T p for the next iteration.
-template <int NI>
+template <int NI, int FW>
 __global__ __launch_bounds__(kT) void k_cg_update_p(const CgArgs* __restrict__ AA) {
   constexpr int NT = (NI + 15) / 16;
   const CgArgs& A = AA[blockIdx.z];
@@ -920,7 +1016,7 @@ __global__ __launch_bounds__(kT) void k_cg_update_p(const CgArgs* __restrict__ A
             if (i < A.n1) gy[i] += Fa[i] * p;
         }
       }
-    if (lr) put_fty_partials<NI>(A, red, gy, G.p_part, 0);
+    if (lr) put_y_partials<NI>(A, red, false, 0.0, 0, true, gy, G.p_part, 0);
     return;
   }
   const int cl = my_cl(false);
@@ -929,7 +1025,38 @@ __global__ __launch_bounds__(kT) void k_cg_update_p(const CgArgs* __restrict__ A
   d4 acc[NT > 0 ? NT : 1][2];
 #pragma unroll
   for (int mt = 0; mt < (NT > 0 ? NT : 1); ++mt) acc[mt][0] = acc[mt][1] = d4{0.0, 0.0, 0.0, 0.0};
-  if (__any(c0 || c1)) {
+  if (FW == 1 && __any(c0 || c1)) {
+    // F u per 16-row wavefront tile on the matrix cores
+    constexpr int NS = (NI + 3) / 4;
+    const int g = lane_id() >> 4;
+    const int64_t nst = tile_steps(A);
+    for (int64_t k = 0; k < nst; ++k) {
+      const int64_t base = wave_base(A, k);
+      if (base >= A.n) break;                       // uniform over the wavefront
+      d4 ue = {0.0, 0.0, 0.0, 0.0}, ud = {0.0, 0.0, 0.0, 0.0};
+      if (NS > 0 && pc) fw_tile<NS>(G.F, A.n1, A.n, base, s_u, ue, ud);
+#pragma unroll 1
+      for (int st = 0; st < 4; ++st) {
+        const int64_t a = base + 4 * st + g;
+        dv2 p = {0.0, 0.0};
+        if (a < A.n) {
+          const int64_t o = elem(A, false, a);
+          const dv2 r = *reinterpret_cast<const GL dv2*>(G.Rr + o);
+          p = *reinterpret_cast<const GL dv2*>(G.P + o);
+          const double z0 = pc ? (r.x - pick4(ue, st)) * A.inv_c : r.x;
+          const double z1 = pc ? (r.y - pick4(ud, st)) * A.inv_c : r.y;
+          if (c0) p.x = z0 + be0 * p.x;
+          if (c1) p.y = z1 + be1 * p.y;
+          *reinterpret_cast<GL dv2*>(G.P + o) = p;
+        }
+        if (NT > 0 && lr) {
+          double f[NT > 0 ? NT : 1];
+          load_f<NT>(A, a < A.n ? a : -1, f);
+          ft_step<NT>(f, p.x, p.y, acc);
+        }
+      }
+    }
+  } else if (FW == 0 && __any(c0 || c1)) {
     for (int64_t k = 0; k < steps; ++k) {
       const int64_t a = thread_row(A, false, k);
       double f[NT > 0 ? NT : 1];
@@ -1057,9 +1184,7 @@ __global__ __launch_bounds__(kT) void k_cg_norm(const CgArgs* __restrict__ AA) {
           if (i < A.n1) gy[i] += Fa[i] * r;
       }
     }
-    const double t = block_sum(red, rr);
-    if (threadIdx.x == 0) G.u_part[blockIdx.x] = t;
-    if (pc) put_fty_partials<NI>(A, red, gy, G.u_part, A.R);
+    put_y_partials<NI>(A, red, true, rr, 0, pc, gy, G.u_part, A.R);
     return;
   }
   double rr0 = 0.0, rr1 = 0.0;
@@ -1142,7 +1267,7 @@ __global__ __launch_bounds__(kT) void k_cg_init_fin(const CgArgs* __restrict__ A
           if (i < A.n1) gy[i] += Fa[i] * z;
       }
     }
-    if (lr) put_fty_partials<NI>(A, red, gy, G.p_part, 0);
+    if (lr) put_y_partials<NI>(A, red, false, 0.0, 0, true, gy, G.p_part, 0);
     return;
   }
   const int cl = my_cl(false);
@@ -1191,6 +1316,7 @@ struct Launch {
   bool use_pc, lowrank;
   int B;
   bool staged;  // neighbourhood-staged SpMM (ns == 1)
+  bool fw;      // F w products of the update kernels on the matrix cores
 };
 
 template <int NI>
@@ -1219,7 +1345,8 @@ void launch_iteration(hipStream_t st, const CgArgs* dA, const Launch& L, Ctx* c)
   }
   k_cg_colsum<<<dim3(L.R, 1, L.B), kSumT, 0, st>>>(dA, 0);
   SDGP_CHECK_LAUNCH();
-  k_cg_update_xr<NI><<<dim3(L.nbu, L.ns + 1, L.B), kT, 0, st>>>(dA);
+  if (L.fw) k_cg_update_xr<NI, 1><<<dim3(L.nbu, L.ns + 1, L.B), kT, 0, st>>>(dA);
+  else k_cg_update_xr<NI, 0><<<dim3(L.nbu, L.ns + 1, L.B), kT, 0, st>>>(dA);
   SDGP_CHECK_LAUNCH();
   k_cg_colsum<<<dim3((1 + (L.use_pc ? L.n1 : 0)) * L.R, 1, L.B), kSumT, 0, st>>>(dA, 1);
   SDGP_CHECK_LAUNCH();
@@ -1227,7 +1354,8 @@ void launch_iteration(hipStream_t st, const CgArgs* dA, const Launch& L, Ctx* c)
     k_cg_small_solve<<<dim3(L.R, 1, L.B), 64, 0, st>>>(dA);
     SDGP_CHECK_LAUNCH();
   }
-  k_cg_update_p<NI><<<dim3(L.nbu, L.ns + 1, L.B), kT, 0, st>>>(dA);
+  if (L.fw) k_cg_update_p<NI, 1><<<dim3(L.nbu, L.ns + 1, L.B), kT, 0, st>>>(dA);
+  else k_cg_update_p<NI, 0><<<dim3(L.nbu, L.ns + 1, L.B), kT, 0, st>>>(dA);
   SDGP_CHECK_LAUNCH();
   if (L.lowrank) {
     k_cg_colsum<<<dim3(L.n1 * L.R, 1, L.B), kSumT, 0, st>>>(dA, 2);
@@ -1414,7 +1542,10 @@ std::vector<CgResult> block_cg_multi(Ctx* c, const std::vector<CgMember>& mem, c
   }
   CgArgs* dA = c->get<CgArgs>(S_CG_ARGS, B);
   SDGP_HIP(hipMemcpyAsync(dA, hA.data(), B * sizeof(CgArgs), hipMemcpyHostToDevice, c->stream));
-  Launch L{nbs, nbu, ns, R, n1, use_pc, use_lr, B, staged};
+  // F w products on the matrix cores (measured faster at 16 and at 32 bump
+  // functions); context option "fw_mfma": -1 automatic, 0 broadcasts, 1 cores
+  const bool fw = c->fw_mfma < 0 ? n1 > 0 : c->fw_mfma > 0;
+  Launch L{nbs, nbu, ns, R, n1, use_pc, use_lr, B, staged, fw};
   {
     const int64_t gx = ((int64_t)NV + 255) / 256;
     require(gx < 0x7fffffff, "n*R too large");

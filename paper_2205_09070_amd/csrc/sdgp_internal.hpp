@@ -90,6 +90,7 @@ struct Ctx {
   int cu_count = 256;
   bool use_graph = false;        // replay captured CG iterations (hipGraph)
   bool staged_spmm = false;      // neighbourhood-staged CG SpMM when R <= 33 (opt-in)
+  int fw_mfma = -1;              // F w products on the matrix cores: -1 auto, 0 off, 1 on
   std::vector<DevBuf> member_bufs;  // per-member storage of the population path
   hipStream_t gstream = nullptr; // private default-priority stream for graph capture
   hipStream_t graph_stream() {

@@ -281,3 +281,26 @@ def test_staged_spmm_matches_global_gathers(operator, per_row):
     assert abs(i1.cg_iters - i0.cg_iters) <= 2
     assert abs(v1 - v0) <= 1e-10 * abs(v0)
     assert gu.grad_close(g1, g0, rel=1e-8).all()
+
+
+@pytest.mark.parametrize("n1,operator", [(6, 1), (20, 1), (20, 0)], ids=["n1=6-factored", "n1=20-factored",
+                                                                       "n1=20-assembled"])
+def test_update_products_on_matrix_cores_match_broadcasts(n1, operator):
+    """The F w products of the CG update kernels per 16-row tile on the
+    matrix cores (fw_mfma = 1) agree to rounding with the per-row broadcast
+    form (fw_mfma = 0)."""
+    gu.need_gpu()
+    import paper_2205_09070_amd as sd
+    w = wl.random_small(3000, 3, n1, 2, 21, per_row=15.0, noise_var=1e-3)
+    gu.log("fw_mfma n1=%d operator=%d" % (n1, operator))
+    est = sd.estimator(probes=12, seed=6, cg_rtol=1e-11, cg_max_iter=5000, precond=1, operator_form=operator)
+    c = gu.ctx()
+    x, y = gu.dev(w.x), gu.dev(w.y)
+    c.set_option("fw_mfma", 1)
+    v1, g1, i1 = c.lml_grad(w.desc, x, y, w.h, est)
+    c.set_option("fw_mfma", 0)
+    v0, g0, i0 = c.lml_grad(w.desc, x, y, w.h, est)
+    c.set_option("fw_mfma", -1)
+    assert abs(i1.cg_iters - i0.cg_iters) <= 2
+    assert abs(v1 - v0) <= 1e-10 * abs(v0)
+    assert gu.grad_close(g1, g0, rel=1e-8).all()
