@@ -365,70 +365,115 @@ struct RowArgs {
   const uint64_t* M;
   const double* F;
   const int32_t* cell_of;
+  const int32_t* cell_start;
   const int32_t* iv_ptr;
   const int2* iv;
-  const int32_t* sched;  // row visiting order (Morton), may be null
   int64_t n;
   int dim, n1, core, ell, combine, add_noise;
   int core_only;   // keep only the core part (+ diagonal), values without B
   double sigma2, r_core, rc2, noise;
 };
 
-// One wavefront per row, persistent: the waves of the grid sweep the rows
-// (in schedule order when one is given, else storage order), each XCD
-// taking a contiguous eighth (workgroups are dealt to the XCDs round-robin;
-// gridDim.x is a multiple of 8) so the candidate points of neighbouring rows
-// stay in its L2.  kFill == false: count kept columns (and the candidates
-// examined, one atomic per wave); kFill == true: write them at row_ptr[a].
+// Count / fill with LDS-staged point tiles: one workgroup per cell.  All rows
+// of a cell share the cell's candidate intervals, so the candidates' points
+// and bump masks are staged in LDS once per chunk of 512 candidates and every
+// row of the cell (one wavefront per row, rows dealt to the four wavefronts)
+// tests them from there: a candidate point is read from memory once per cell
+// instead of once per row.  Columns stay ascending (chunks follow the sorted
+// disjoint intervals); each row's output position persists in LDS across
+// chunks.  Cells with more than 1024 rows are processed in row groups.
+constexpr int kCC = 512;      // staged candidates per chunk
+constexpr int kCRows = 1024;  // rows per row group
+constexpr int kCSeg = 64;     // interval pieces per chunk
+
 template <bool kFill>
-__global__ __launch_bounds__(kBlock) void k_rows(RowArgs A, int64_t* __restrict__ row_nnz,
-                                                 unsigned long long* __restrict__ cand_total,
-                                                 const int64_t* __restrict__ row_ptr,
-                                                 int32_t* __restrict__ col, double* __restrict__ val) {
-  const int lane = lane_id();
-  const int wpb = kBlock / kWave;
-  const int xcd = blockIdx.x & 7;
-  const int64_t bi = blockIdx.x >> 3, nbx = gridDim.x >> 3;
-  const int64_t nx = (A.n + 7) >> 3, lo = xcd * nx, hi = min(A.n, lo + nx);
-  int64_t cand = 0;
-  for (int64_t p = lo + bi * wpb + (threadIdx.x >> 6); p < hi; p += nbx * wpb) {
-    const int64_t a = A.sched ? (int64_t)A.sched[p] : p;
-    const double4 xa = A.xs[a];
-    const uint64_t Ma = A.M[a];
-    const int32_t cell = A.cell_of[a];
-    const int32_t i0 = A.iv_ptr[cell], i1 = A.iv_ptr[cell + 1];
-    const double* Fa = A.F + a * (int64_t)A.n1;
-    int64_t pos = kFill ? row_ptr[a] : 0;
-    int64_t cnt = 0;
-    for (int32_t q = i0; q < i1; ++q) {
-      const int2 r = A.iv[q];
-      cand += r.y - r.x;
-      for (int32_t b0 = r.x; b0 < r.y; b0 += kWave) {
-        const int32_t b = b0 + lane;
-        bool keep = false;
-        double d2 = 0.0;
-        uint64_t mm = 0;
-        bool core = false;
-        if (b < r.y) {
-          const double4 xb = A.xs[b];
-          d2 = dist2(xa, xb, A.dim);
-          core = d2 < A.rc2;
-          mm = Ma & A.M[b];
-          const bool bump = mm != 0;
-          keep = (b == a) || (A.core_only ? core : (A.combine == 0 ? (core && bump) : (core || bump)));
-          if (A.core_only) mm = 0;
+__global__ __launch_bounds__(kBlock) void k_cell_rows(RowArgs A, int64_t* __restrict__ row_nnz,
+                                                      unsigned long long* __restrict__ cand_total,
+                                                      const int64_t* __restrict__ row_ptr,
+                                                      int32_t* __restrict__ col, double* __restrict__ val) {
+  __shared__ double4 sx[kCC];
+  __shared__ uint64_t sm[kCC];
+  __shared__ int32_t sb[kCC];
+  __shared__ int64_t spos[kCRows];
+  __shared__ int32_t seg_b[kCSeg];
+  __shared__ int32_t seg_off[kCSeg + 1];
+  __shared__ int32_t st_q, st_o, st_n, st_fill;
+  const int64_t c = blockIdx.x;
+  const int32_t r0 = A.cell_start[c], r1 = A.cell_start[c + 1];
+  if (r1 <= r0) return;                       // uniform: empty cell
+  const int32_t i0 = A.iv_ptr[c], i1 = A.iv_ptr[c + 1];
+  const int t = threadIdx.x, lane = lane_id(), w = t >> 6;
+  constexpr int kWaves = kBlock / kWave;
+  for (int32_t g0 = r0; g0 < r1; g0 += kCRows) {
+    const int nr = min(r1 - g0, kCRows);
+    for (int r = t; r < nr; r += kBlock) spos[r] = kFill ? row_ptr[g0 + r] : 0;
+    if (t == 0) { st_q = i0; st_o = 0; }
+    __syncthreads();
+    for (;;) {
+      if (t == 0) {  // next chunk: pieces of the remaining intervals, up to kCC candidates
+        int q = st_q, o = st_o, filled = 0, ns = 0;
+        while (q < i1 && filled < kCC && ns < kCSeg) {
+          const int2 iv = A.iv[q];
+          const int len = iv.y - iv.x - o;
+          const int take = min(len, kCC - filled);
+          seg_b[ns] = iv.x + o;
+          seg_off[ns] = filled;
+          ++ns;
+          filled += take;
+          if (take == len) { ++q; o = 0; } else { o += take; }
         }
-        const uint64_t bal = ballot64(keep);
-        if (kFill) {
-          if (keep) {
+        seg_off[ns] = filled;
+        st_n = ns;
+        st_fill = filled;
+        st_q = q;
+        st_o = o;
+      }
+      __syncthreads();
+      const int filled = st_fill, ns = st_n;
+      if (filled == 0) break;                 // uniform
+      for (int k = t; k < filled; k += kBlock) {
+        int lo = 0, hi = ns;                  // seg_off[lo] <= k < seg_off[hi]
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (seg_off[mid] <= k) lo = mid; else hi = mid;
+        }
+        const int32_t b = seg_b[lo] + (k - seg_off[lo]);
+        sx[k] = A.xs[b];
+        sm[k] = A.M[b];
+        sb[k] = b;
+      }
+      __syncthreads();
+      for (int r = w; r < nr; r += kWaves) {
+        const int64_t a = (int64_t)g0 + r;
+        const double4 xa = A.xs[a];
+        const uint64_t Ma = A.M[a];
+        const double* Fa = A.F + a * (int64_t)A.n1;
+        int64_t pos = spos[r];
+        for (int k0 = 0; k0 < filled; k0 += kWave) {
+          const int k = k0 + lane;
+          bool keep = false, core = false;
+          double d2 = 0.0;
+          uint64_t mm = 0;
+          int32_t b = 0;
+          if (k < filled) {
+            b = sb[k];
+            d2 = dist2(xa, sx[k], A.dim);
+            core = d2 < A.rc2;
+            mm = Ma & sm[k];
+            const bool bump = mm != 0;
+            keep = (b == a) || (A.core_only ? core : (A.combine == 0 ? (core && bump) : (core || bump)));
+            if (A.core_only) mm = 0;
+          }
+          const uint64_t bal = ballot64(keep);
+          if (kFill && keep) {
             double psi = 0.0;
             if (core) psi = core_psi(sqrt(d2) / A.r_core, A.core, A.ell);
             double B = 0.0;
             const double* Fb = A.F + (int64_t)b * A.n1;
-            uint64_t t = mm;
-            while (t) {
-              const int i = __builtin_ctzll(t);
-              t &= t - 1;
+            uint64_t tm = mm;
+            while (tm) {
+              const int i = __builtin_ctzll(tm);
+              tm &= tm - 1;
               B += Fa[i] * Fb[i];
             }
             double kv = A.combine == 0 ? A.sigma2 * psi * B : A.sigma2 * psi + B;
@@ -438,22 +483,22 @@ __global__ __launch_bounds__(kBlock) void k_rows(RowArgs A, int64_t* __restrict_
             val[o] = kv;
           }
           pos += __popcll(bal);
-        } else {
-          cnt += __popcll(bal);
         }
+        if (lane == 0) spos[r] = pos;
       }
+      __syncthreads();
     }
-    if (!kFill && lane == 0) row_nnz[a] = cnt;
+    if (!kFill)
+      for (int r = t; r < nr; r += kBlock) row_nnz[g0 + r] = spos[r];
+    __syncthreads();
   }
-  if (!kFill && lane == 0 && cand > 0) atomicAdd(cand_total, (unsigned long long)cand);
+  if (!kFill && t == 0) {
+    unsigned long long cnt = 0;
+    for (int32_t q = i0; q < i1; ++q) cnt += (unsigned long long)(A.iv[q].y - A.iv[q].x);
+    atomicAdd(cand_total, cnt * (unsigned long long)(r1 - r0));
+  }
 }
 
-// Blocks of the persistent row sweeps: about 32 waves per CU, a multiple of 8.
-static unsigned row_blocks(const Ctx* c, int64_t n) {
-  const int64_t want = std::max<int64_t>(8, (int64_t)c->cu_count * 32 / (kBlock / kWave));
-  const int64_t need = (n + kBlock / kWave - 1) / (kBlock / kWave);
-  return (unsigned)((std::min(want, need) + 7) / 8 * 8);
-}
 
 // ------------------------------------------------------- cross covariance
 // Rows are test points (caller order), columns sorted training points; the
@@ -791,8 +836,8 @@ void prune(Ctx* c, const Sorted& s, const KParams& kp, const Bumps& b, int32_t**
 static RowArgs row_args(const Sorted& s, const KParams& kp, const Bumps& b, const int32_t* iv_ptr,
                         const int2* iv, bool add_noise, bool core_only) {
   RowArgs A;
-  A.xs = s.xs; A.M = b.M; A.F = b.F; A.cell_of = s.cell_of; A.iv_ptr = iv_ptr; A.iv = iv;
-  A.sched = nullptr;  // storage order: the fill then writes the CSR arrays front to back
+  A.xs = s.xs; A.M = b.M; A.F = b.F; A.cell_of = s.cell_of; A.cell_start = s.cell_start;
+  A.iv_ptr = iv_ptr; A.iv = iv;
   A.n = s.n; A.dim = kp.dim; A.n1 = kp.n1; A.core = kp.core; A.ell = kp.dim / 2 + 2;
   A.combine = kp.combine; A.add_noise = add_noise ? 1 : 0; A.core_only = core_only ? 1 : 0;
   A.sigma2 = kp.sigma2; A.r_core = kp.r_core; A.rc2 = kp.rc2; A.noise = kp.noise;
@@ -807,8 +852,9 @@ Csr assemble_sorted(Ctx* c, const Sorted& s, const KParams& kp, const Bumps& b, 
   unsigned long long* cand = c->get<unsigned long long>(S_COUNTER, 4);
   SDGP_HIP(hipMemsetAsync(cand, 0, sizeof(unsigned long long), c->stream));
   SDGP_HIP(hipMemsetAsync(row_nnz + n, 0, sizeof(int64_t), c->stream));
-  const unsigned rb = row_blocks(c, n);
-  k_rows<false><<<rb, kBlock, 0, c->stream>>>(A, row_nnz, cand, nullptr, nullptr, nullptr);
+  const int64_t ncell = s.grid.n_cells;
+  require(ncell < 0x7fffffff, "too many cells");
+  k_cell_rows<false><<<(unsigned)ncell, kBlock, 0, c->stream>>>(A, row_nnz, cand, nullptr, nullptr, nullptr);
   SDGP_CHECK_LAUNCH();
   int64_t* row_ptr = c->get<int64_t>(S_ROW_PTR, n + 1);
   size_t tb = 0;
@@ -824,9 +870,7 @@ Csr assemble_sorted(Ctx* c, const Sorted& s, const KParams& kp, const Bumps& b, 
   if (t) t->mark(4);
   int32_t* col = c->get<int32_t>(S_COL, nnz);
   double* val = c->get<double>(S_VAL, nnz);
-  // the fill runs one row per wavefront (no persistence: measured faster)
-  const unsigned fb = (unsigned)(((n + kBlock / kWave - 1) / (kBlock / kWave) + 7) / 8 * 8);
-  k_rows<true><<<fb, kBlock, 0, c->stream>>>(A, nullptr, nullptr, row_ptr, col, val);
+  k_cell_rows<true><<<(unsigned)ncell, kBlock, 0, c->stream>>>(A, nullptr, nullptr, row_ptr, col, val);
   SDGP_CHECK_LAUNCH();
   Csr k;
   k.n = n; k.nnz = nnz; k.row_ptr = row_ptr; k.col = col; k.val = val;
