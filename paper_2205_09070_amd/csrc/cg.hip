@@ -38,6 +38,7 @@ namespace {
 constexpr int kT = 256;          // threads per block
 constexpr int kTile = 16;        // rows per block tile (4 waves x 4 groups of 16 lanes)
 constexpr int kSlab = 32;        // columns per slab
+constexpr int kSC = kSlab + 1;   // LDS stride of per-column values (slab columns + column 0)
 constexpr int kMaxNbs = 32768;   // SpMM blocks
 constexpr int kMaxNbu = 2048;    // blocks of the streaming update kernels
 constexpr int kLRows = 64;       // rows per block of the staged SpMM
@@ -622,7 +623,7 @@ template <int H, int... us>
 __device__ __forceinline__ double fdot16(double f, int n1i, const double* w, int cl,
                                          std::integer_sequence<int, us...>) {
   double s = 0.0;
-  ((s += (H + us < n1i) ? bcast16_d<us>(f) * w[(H + us) * kSlab + cl] : 0.0), ...);
+  ((s += (H + us < n1i) ? bcast16_d<us>(f) * w[(H + us) * kSC + cl] : 0.0), ...);
   return s;
 }
 template <int NT>
@@ -712,12 +713,67 @@ __device__ __forceinline__ void fw_tile(const GL double* __restrict__ F, int n1,
     const int i = 4 * s + g;
     const bool ok = i < n1;
     const double fa = (row < n && ok) ? F[row * n1 + i] : 0.0;
-    const double b0 = ok ? w[i * kSlab + 2 * j] : 0.0;
-    const double b1 = ok ? w[i * kSlab + 2 * j + 1] : 0.0;
+    const double b0 = ok ? w[i * kSC + 2 * j] : 0.0;
+    const double b1 = ok ? w[i * kSC + 2 * j + 1] : 0.0;
     de = __builtin_amdgcn_mfma_f64_16x16x4f64(fa, b0, de, 0, 0, 0);
     dd = __builtin_amdgcn_mfma_f64_16x16x4f64(fa, b1, dd, 0, 0, 0);
   }
 }
+// fw_tile plus, when yfold, the column-0 product in lanes j == 0:
+// dy[q] of lane (g, 0) = sum_i F[base + 4q + g][i] w[i][kSlab].
+template <int NS>
+__device__ __forceinline__ void fw_tile_y(const GL double* __restrict__ F, int n1, int64_t n, int64_t base,
+                                          const double* w, bool yfold, d4& de, d4& dd, d4& dy) {
+  const int g = lane_id() >> 4, j = lane_id() & 15;
+  const int64_t row = base + j;
+  de = d4{0.0, 0.0, 0.0, 0.0};
+  dd = d4{0.0, 0.0, 0.0, 0.0};
+  dy = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int i = 4 * s + g;
+    const bool ok = i < n1;
+    const double fa = (row < n && ok) ? F[row * n1 + i] : 0.0;
+    const double b0 = ok ? w[i * kSC + 2 * j] : 0.0;
+    const double b1 = ok ? w[i * kSC + 2 * j + 1] : 0.0;
+    de = __builtin_amdgcn_mfma_f64_16x16x4f64(fa, b0, de, 0, 0, 0);
+    dd = __builtin_amdgcn_mfma_f64_16x16x4f64(fa, b1, dd, 0, 0, 0);
+    if (yfold) {
+      const double by = (ok && j == 0) ? w[i * kSC + kSlab] : 0.0;
+      dy = __builtin_amdgcn_mfma_f64_16x16x4f64(fa, by, dy, 0, 0, 0);
+    }
+  }
+}
+// Column-0 partials of a yfold block: v (nonzero in lanes j == 0 only) into
+// part row row0, and the column-0 F^T tile accumulators acc_y (D[i][0] in
+// lanes j == 0) into part rows base + i R.
+template <int NT>
+__device__ void put_yfold_partials(const CgArgs& A, double* red, bool has0, double v, int64_t row0, bool hasg,
+                                   const d4* acc_y, GL double* part, int64_t base) {
+  const int lane = lane_id(), g = lane >> 4, j = lane & 15, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (j == 0) {
+    red[w * 4 + g] = v;
+    if (hasg) {
+#pragma unroll
+      for (int mt = 0; mt < NT; ++mt)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) red[64 + w * 64 + 16 * mt + 4 * q + g] = acc_y[mt][q];
+    }
+  }
+  __syncthreads();
+  if (has0 && threadIdx.x == 0) {
+    double t = 0.0;
+    for (int k = 0; k < 16; ++k) t += red[k];
+    part[row0 * A.nbu + blockIdx.x] = t;
+  }
+  if (hasg)
+    for (int i = threadIdx.x; i < A.n1; i += kT) {
+      const double t = (red[64 + i] + red[128 + i]) + (red[192 + i] + red[256 + i]);
+      part[(base + (int64_t)i * A.R) * A.nbu + blockIdx.x] = t;
+    }
+}
+
 __device__ __forceinline__ double pick4(const d4& v, int q) {
   return q == 0 ? v[0] : (q == 1 ? v[1] : (q == 2 ? v[2] : v[3]));
 }
@@ -739,7 +795,7 @@ __device__ __forceinline__ int64_t wave_base(const CgArgs& A, int64_t k) {
 // columns (cl = 2j, 2j+1, or cl = 0).
 __device__ __forceinline__ bool is_ycol(const CgArgs& A) { return (int)blockIdx.y == A.ns; }
 __device__ __forceinline__ int col_of(const CgArgs& A, bool ycol, int cl) {
-  return ycol ? 0 : 1 + (int)blockIdx.y * kSlab + cl;
+  return (ycol || cl == kSlab) ? 0 : 1 + (int)blockIdx.y * kSlab + cl;   // cl == kSlab: column 0
 }
 __device__ __forceinline__ int my_cl(bool ycol) { return ycol ? 0 : 2 * (lane_id() & 15); }
 
@@ -764,11 +820,11 @@ __device__ __forceinline__ int64_t elem(const CgArgs& A, bool ycol, int64_t a) {
   return ycol ? a : A.ny + (int64_t)blockIdx.y * A.n * kSlab + a * kSlab + 2 * (lane_id() & 15);
 }
 
-// u = S^{-1} g of column rc (from k_cg_small_solve) into us[i * kSlab]
+// u = S^{-1} g of column rc (from k_cg_small_solve) into us[i * kSC]
 // (stride kSlab); returns g.u.
 template <int NI>
 __device__ __forceinline__ double coef_u(const CgArgs& A, int rc, double* us) {
-  for (int i = 0; i < A.n1; ++i) us[i * kSlab] = A.w_red[(int64_t)i * A.R + rc];
+  for (int i = 0; i < A.n1; ++i) us[i * kSC] = A.w_red[(int64_t)i * A.R + rc];
   return A.w_red[(int64_t)A.n1 * A.R + rc];
 }
 
@@ -778,7 +834,7 @@ __device__ __forceinline__ double frow_dot(const GL double* __restrict__ Fa, int
   double s = 0.0;
 #pragma unroll
   for (int i = 0; i < (NI > 0 ? NI : 1); ++i)
-    if (i < n1) s += Fa[i] * w[i * kSlab];
+    if (i < n1) s += Fa[i] * w[i * kSC];
   return s;
 }
 
@@ -793,15 +849,17 @@ __global__ __launch_bounds__(kT) void k_cg_update_xr(const CgArgs* __restrict__ 
   const Gv G = gview(A);
   if (stopped(A)) return;
   __shared__ double red[kRed];
-  __shared__ double s_alpha[kSlab];
-  __shared__ int s_act[kSlab];
-  __shared__ double s_gp[(NI > 0 ? NI : 1) * kSlab];
+  __shared__ double s_alpha[kSC];
+  __shared__ int s_act[kSC];
+  __shared__ double s_gp[(NI > 0 ? NI : 1) * kSC];
   const int it = *A.st.it;
   const int par = it & 1;
-  const bool ycol = is_ycol(A);
+  const bool ycol = FW == 0 && is_ycol(A);   // matrix-core launches have no column-0 blocks
   const bool lr = NI > 0 && A.lowrank_op;
   const bool pc = NI > 0 && A.use_pc;
-  if ((int)threadIdx.x < (ycol ? 1 : kSlab)) {
+  // matrix-core launches have no column-0 blocks: slab 0 also owns column 0
+  const bool yfold = FW == 1 && !ycol && blockIdx.y == 0;
+  if ((int)threadIdx.x < (ycol ? 1 : (yfold ? kSC : kSlab))) {
     const int cl = threadIdx.x;
     const int rc = col_of(A, ycol, cl);
     double alpha = 0.0;
@@ -812,7 +870,7 @@ __global__ __launch_bounds__(kT) void k_cg_update_xr(const CgArgs* __restrict__ 
       if (lr)
         for (int i = 0; i < A.n1; ++i) {
           const double gi = A.p_red[(int64_t)i * A.R + rc];
-          s_gp[i * kSlab + cl] = gi;
+          s_gp[i * kSC + cl] = gi;
           d += gi * gi;
         }
       if (was) {
@@ -829,7 +887,7 @@ __global__ __launch_bounds__(kT) void k_cg_update_xr(const CgArgs* __restrict__ 
         }
       }
     } else if (lr) {
-      for (int i = 0; i < A.n1; ++i) s_gp[i * kSlab + cl] = 0.0;
+      for (int i = 0; i < A.n1; ++i) s_gp[i * kSC + cl] = 0.0;
     }
     s_alpha[cl] = alpha;
     s_act[cl] = act;
@@ -864,7 +922,14 @@ __global__ __launch_bounds__(kT) void k_cg_update_xr(const CgArgs* __restrict__ 
   }
   const int cl = my_cl(false);
   const double al0 = s_alpha[cl], al1 = s_alpha[cl + 1];
-  const bool mine = s_act[cl] || s_act[cl + 1];
+  const int jl = lane_id() & 15;
+  const double aly = yfold ? s_alpha[kSlab] : 0.0;
+  const bool acty = yfold && s_act[kSlab] != 0;
+  const bool mine = s_act[cl] || s_act[cl + 1] || (acty && jl == 0);
+  double rry = 0.0;
+  d4 acc_y[NT > 0 ? NT : 1];
+#pragma unroll
+  for (int mt = 0; mt < (NT > 0 ? NT : 1); ++mt) acc_y[mt] = d4{0.0, 0.0, 0.0, 0.0};
   double rr0 = 0.0, rr1 = 0.0;
   d4 acc[NT > 0 ? NT : 1][2];
 #pragma unroll
@@ -877,11 +942,19 @@ __global__ __launch_bounds__(kT) void k_cg_update_xr(const CgArgs* __restrict__ 
     for (int64_t k = 0; k < nst; ++k) {
       const int64_t base = wave_base(A, k);
       if (base >= A.n) break;                       // uniform over the wavefront
-      d4 ce = {0.0, 0.0, 0.0, 0.0}, cd = {0.0, 0.0, 0.0, 0.0};
-      if (NS > 0 && lr) fw_tile<NS>(G.F, A.n1, A.n, base, s_gp, ce, cd);
+      d4 ce = {0.0, 0.0, 0.0, 0.0}, cd = {0.0, 0.0, 0.0, 0.0}, cy = {0.0, 0.0, 0.0, 0.0};
+      if (NS > 0 && lr) fw_tile_y<NS>(G.F, A.n1, A.n, base, s_gp, yfold, ce, cd, cy);
 #pragma unroll 1
       for (int st = 0; st < 4; ++st) {
         const int64_t a = base + 4 * st + g;
+        double ry = 0.0;
+        if (acty && jl == 0 && a < A.n) {          // column 0 of row a
+          const double qy = G.Q[a] + pick4(cy, st);
+          G.X[a] += aly * G.P[a];
+          ry = G.Rr[a] - aly * qy;
+          G.Rr[a] = ry;
+          rry += ry * ry;
+        }
         dv2 r = {0.0, 0.0};
         if (a < A.n) {
           const int64_t o = elem(A, false, a);
@@ -904,6 +977,10 @@ __global__ __launch_bounds__(kT) void k_cg_update_xr(const CgArgs* __restrict__ 
           double f[NT > 0 ? NT : 1];
           load_f<NT>(A, a < A.n ? a : -1, f);
           ft_step<NT>(f, r.x, r.y, acc);
+          if (yfold) {
+#pragma unroll
+            for (int mt = 0; mt < NT; ++mt) acc_y[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(f[mt], ry, acc_y[mt], 0, 0, 0);
+          }
         }
       }
     }
@@ -944,6 +1021,7 @@ __global__ __launch_bounds__(kT) void k_cg_update_xr(const CgArgs* __restrict__ 
     if (rc < A.R) G.u_part[(int64_t)rc * A.nbu + blockIdx.x] = t;
   }
   if (NT > 0 && pc) put_ft_partials<NT>(A, red, acc, G.u_part, A.R);
+  if (yfold) put_yfold_partials<(NT > 0 ? NT : 1)>(A, red, true, rry, 0, NT > 0 && pc, acc_y, G.u_part, A.R);
 }
 
 // beta = r.z_new / r.z; convergence on |r|; p = z + beta p with
@@ -957,15 +1035,17 @@ __global__ __launch_bounds__(kT) void k_cg_update_p(const CgArgs* __restrict__ A
   const Gv G = gview(A);
   if (stopped(A)) return;
   __shared__ double red[kRed];
-  __shared__ double s_beta[kSlab];
-  __shared__ int s_cont[kSlab];
-  __shared__ double s_u[(NI > 0 ? NI : 1) * kSlab];
+  __shared__ double s_beta[kSC];
+  __shared__ int s_cont[kSC];
+  __shared__ double s_u[(NI > 0 ? NI : 1) * kSC];
   const int it = *A.st.it;
   const int par = it & 1, nxt = par ^ 1;
-  const bool ycol = is_ycol(A);
+  const bool ycol = FW == 0 && is_ycol(A);   // matrix-core launches have no column-0 blocks
   const bool lr = NI > 0 && A.lowrank_op;
   const bool pc = NI > 0 && A.use_pc;
-  if ((int)threadIdx.x < (ycol ? 1 : kSlab)) {
+  // matrix-core launches have no column-0 blocks: slab 0 also owns column 0
+  const bool yfold = FW == 1 && !ycol && blockIdx.y == 0;
+  if ((int)threadIdx.x < (ycol ? 1 : (yfold ? kSC : kSlab))) {
     const int cl = threadIdx.x;
     const int rc = col_of(A, ycol, cl);
     double beta = 0.0;
@@ -989,7 +1069,7 @@ __global__ __launch_bounds__(kT) void k_cg_update_p(const CgArgs* __restrict__ A
         }
       }
     } else if (pc) {
-      for (int i = 0; i < A.n1; ++i) s_u[i * kSlab + cl] = 0.0;
+      for (int i = 0; i < A.n1; ++i) s_u[i * kSC + cl] = 0.0;
     }
     s_beta[cl] = beta;
     s_cont[cl] = cont;
@@ -1022,10 +1102,16 @@ __global__ __launch_bounds__(kT) void k_cg_update_p(const CgArgs* __restrict__ A
   const int cl = my_cl(false);
   const double be0 = s_beta[cl], be1 = s_beta[cl + 1];
   const bool c0 = s_cont[cl] != 0, c1 = s_cont[cl + 1] != 0;
+  const int jl = lane_id() & 15;
+  const double bey = yfold ? s_beta[kSlab] : 0.0;
+  const bool cy = yfold && s_cont[kSlab] != 0;
+  d4 acc_y[NT > 0 ? NT : 1];
+#pragma unroll
+  for (int mt = 0; mt < (NT > 0 ? NT : 1); ++mt) acc_y[mt] = d4{0.0, 0.0, 0.0, 0.0};
   d4 acc[NT > 0 ? NT : 1][2];
 #pragma unroll
   for (int mt = 0; mt < (NT > 0 ? NT : 1); ++mt) acc[mt][0] = acc[mt][1] = d4{0.0, 0.0, 0.0, 0.0};
-  if (FW == 1 && __any(c0 || c1)) {
+  if (FW == 1 && __any(c0 || c1 || (cy && jl == 0))) {
     // F u per 16-row wavefront tile on the matrix cores
     constexpr int NS = (NI + 3) / 4;
     const int g = lane_id() >> 4;
@@ -1033,11 +1119,21 @@ __global__ __launch_bounds__(kT) void k_cg_update_p(const CgArgs* __restrict__ A
     for (int64_t k = 0; k < nst; ++k) {
       const int64_t base = wave_base(A, k);
       if (base >= A.n) break;                       // uniform over the wavefront
-      d4 ue = {0.0, 0.0, 0.0, 0.0}, ud = {0.0, 0.0, 0.0, 0.0};
-      if (NS > 0 && pc) fw_tile<NS>(G.F, A.n1, A.n, base, s_u, ue, ud);
+      d4 ue = {0.0, 0.0, 0.0, 0.0}, ud = {0.0, 0.0, 0.0, 0.0}, uy = {0.0, 0.0, 0.0, 0.0};
+      if (NS > 0 && pc) fw_tile_y<NS>(G.F, A.n1, A.n, base, s_u, yfold, ue, ud, uy);
 #pragma unroll 1
       for (int st = 0; st < 4; ++st) {
         const int64_t a = base + 4 * st + g;
+        double py = 0.0;
+        if (yfold && jl == 0 && a < A.n) {         // column 0 of row a
+          py = G.P[a];
+          if (cy) {
+            const double ry = G.Rr[a];
+            const double zy = pc ? (ry - pick4(uy, st)) * A.inv_c : ry;
+            py = zy + bey * py;
+            G.P[a] = py;
+          }
+        }
         dv2 p = {0.0, 0.0};
         if (a < A.n) {
           const int64_t o = elem(A, false, a);
@@ -1053,6 +1149,10 @@ __global__ __launch_bounds__(kT) void k_cg_update_p(const CgArgs* __restrict__ A
           double f[NT > 0 ? NT : 1];
           load_f<NT>(A, a < A.n ? a : -1, f);
           ft_step<NT>(f, p.x, p.y, acc);
+          if (yfold) {
+#pragma unroll
+            for (int mt = 0; mt < NT; ++mt) acc_y[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(f[mt], py, acc_y[mt], 0, 0, 0);
+          }
         }
       }
     }
@@ -1081,6 +1181,7 @@ __global__ __launch_bounds__(kT) void k_cg_update_p(const CgArgs* __restrict__ A
     }
   }
   if (NT > 0 && lr) put_ft_partials<NT>(A, red, acc, G.p_part, 0);
+  if (yfold && NT > 0 && lr) put_yfold_partials<(NT > 0 ? NT : 1)>(A, red, false, 0.0, 0, true, acc_y, G.p_part, 0);
 }
 
 // Records the executed iteration count in done when no column is active
@@ -1222,7 +1323,7 @@ __global__ __launch_bounds__(kT) void k_cg_init_fin(const CgArgs* __restrict__ A
   const CgArgs& A = AA[blockIdx.z];
   const Gv G = gview(A);
   __shared__ double red[kRed];
-  __shared__ double s_u[(NI > 0 ? NI : 1) * kSlab];
+  __shared__ double s_u[(NI > 0 ? NI : 1) * kSC];
   const bool ycol = is_ycol(A);
   const bool lr = NI > 0 && A.lowrank_op;
   const bool pc = NI > 0 && A.use_pc;
@@ -1244,7 +1345,7 @@ __global__ __launch_bounds__(kT) void k_cg_init_fin(const CgArgs* __restrict__ A
         A.st.iters[rc] = 0;
       }
     } else if (pc) {
-      for (int i = 0; i < A.n1; ++i) s_u[i * kSlab + cl] = 0.0;
+      for (int i = 0; i < A.n1; ++i) s_u[i * kSC + cl] = 0.0;
     }
   }
   __syncthreads();
@@ -1345,7 +1446,7 @@ void launch_iteration(hipStream_t st, const CgArgs* dA, const Launch& L, Ctx* c)
   }
   k_cg_colsum<<<dim3(L.R, 1, L.B), kSumT, 0, st>>>(dA, 0);
   SDGP_CHECK_LAUNCH();
-  if (L.fw) k_cg_update_xr<NI, 1><<<dim3(L.nbu, L.ns + 1, L.B), kT, 0, st>>>(dA);
+  if (L.fw) k_cg_update_xr<NI, 1><<<dim3(L.nbu, L.ns, L.B), kT, 0, st>>>(dA);
   else k_cg_update_xr<NI, 0><<<dim3(L.nbu, L.ns + 1, L.B), kT, 0, st>>>(dA);
   SDGP_CHECK_LAUNCH();
   k_cg_colsum<<<dim3((1 + (L.use_pc ? L.n1 : 0)) * L.R, 1, L.B), kSumT, 0, st>>>(dA, 1);
@@ -1354,7 +1455,7 @@ void launch_iteration(hipStream_t st, const CgArgs* dA, const Launch& L, Ctx* c)
     k_cg_small_solve<<<dim3(L.R, 1, L.B), 64, 0, st>>>(dA);
     SDGP_CHECK_LAUNCH();
   }
-  if (L.fw) k_cg_update_p<NI, 1><<<dim3(L.nbu, L.ns + 1, L.B), kT, 0, st>>>(dA);
+  if (L.fw) k_cg_update_p<NI, 1><<<dim3(L.nbu, L.ns, L.B), kT, 0, st>>>(dA);
   else k_cg_update_p<NI, 0><<<dim3(L.nbu, L.ns + 1, L.B), kT, 0, st>>>(dA);
   SDGP_CHECK_LAUNCH();
   if (L.lowrank) {
@@ -1544,7 +1645,7 @@ std::vector<CgResult> block_cg_multi(Ctx* c, const std::vector<CgMember>& mem, c
   SDGP_HIP(hipMemcpyAsync(dA, hA.data(), B * sizeof(CgArgs), hipMemcpyHostToDevice, c->stream));
   // F w products on the matrix cores (measured faster at 16 and at 32 bump
   // functions); context option "fw_mfma": -1 automatic, 0 broadcasts, 1 cores
-  const bool fw = c->fw_mfma < 0 ? n1 > 0 : c->fw_mfma > 0;
+  const bool fw = ns > 0 && n1 > 0 && (c->fw_mfma < 0 || c->fw_mfma > 0);
   Launch L{nbs, nbu, ns, R, n1, use_pc, use_lr, B, staged, fw};
   {
     const int64_t gx = ((int64_t)NV + 255) / 256;
