@@ -841,7 +841,8 @@ __device__ __forceinline__ double frow_dot(const GL double* __restrict__ Fa, int
 constexpr int kRed = 4 * 512;   // LDS doubles for the block reductions
 
 // alpha = r.z / p.A p (p.A p = p.K_core p + |F^T p|^2 with the factored
-// operator); x += alpha p; r -= alpha A p; partials of r.r and F^T r.
+// operator); r -= alpha A p; partials of r.r and F^T r.  The solution
+// update x += alpha p is left to the p-update pass, which reads p anyway.
 template <int NI, int FW>
 __global__ __launch_bounds__(kT) void k_cg_update_xr(const CgArgs* __restrict__ AA) {
   constexpr int NT = (NI + 15) / 16;
@@ -907,7 +908,6 @@ __global__ __launch_bounds__(kT) void k_cg_update_xr(const CgArgs* __restrict__ 
         const GL double* Fa = G.F + a * (int64_t)A.n1;
         double q = G.Q[a];
         if (lr) q += frow_dot<NI>(Fa, A.n1, s_gp);
-        G.X[a] += al * G.P[a];
         const double r = G.Rr[a] - al * q;
         G.Rr[a] = r;
         rr += r * r;
@@ -950,7 +950,6 @@ __global__ __launch_bounds__(kT) void k_cg_update_xr(const CgArgs* __restrict__ 
         double ry = 0.0;
         if (acty && jl == 0 && a < A.n) {          // column 0 of row a
           const double qy = G.Q[a] + pick4(cy, st);
-          G.X[a] += aly * G.P[a];
           ry = G.Rr[a] - aly * qy;
           G.Rr[a] = ry;
           rry += ry * ry;
@@ -959,16 +958,11 @@ __global__ __launch_bounds__(kT) void k_cg_update_xr(const CgArgs* __restrict__ 
         if (a < A.n) {
           const int64_t o = elem(A, false, a);
           dv2 q = *reinterpret_cast<const GL dv2*>(G.Q + o);
-          const dv2 p = *reinterpret_cast<const GL dv2*>(G.P + o);
-          dv2 x = *reinterpret_cast<const GL dv2*>(G.X + o);
           r = *reinterpret_cast<const GL dv2*>(G.Rr + o);
           q.x += pick4(ce, st);
           q.y += pick4(cd, st);
-          x.x += al0 * p.x;
-          x.y += al1 * p.y;
           r.x -= al0 * q.x;
           r.y -= al1 * q.y;
-          *reinterpret_cast<GL dv2*>(G.X + o) = x;
           *reinterpret_cast<GL dv2*>(G.Rr + o) = r;
           rr0 += r.x * r.x;
           rr1 += r.y * r.y;
@@ -998,16 +992,11 @@ __global__ __launch_bounds__(kT) void k_cg_update_xr(const CgArgs* __restrict__ 
       if (a >= 0) {
         const int64_t o = elem(A, false, a);
         dv2 q = *reinterpret_cast<const GL dv2*>(G.Q + o);
-        const dv2 p = *reinterpret_cast<const GL dv2*>(G.P + o);
-        dv2 x = *reinterpret_cast<const GL dv2*>(G.X + o);
         r = *reinterpret_cast<const GL dv2*>(G.Rr + o);
         q.x += c0;
         q.y += c1;
-        x.x += al0 * p.x;
-        x.y += al1 * p.y;
         r.x -= al0 * q.x;
         r.y -= al1 * q.y;
-        *reinterpret_cast<GL dv2*>(G.X + o) = x;
         *reinterpret_cast<GL dv2*>(G.Rr + o) = r;
         rr0 += r.x * r.x;
         rr1 += r.y * r.y;
@@ -1024,6 +1013,7 @@ __global__ __launch_bounds__(kT) void k_cg_update_xr(const CgArgs* __restrict__ 
   if (yfold) put_yfold_partials<(NT > 0 ? NT : 1)>(A, red, true, rry, 0, NT > 0 && pc, acc_y, G.u_part, A.R);
 }
 
+// x += alpha p (with this iteration's p, before it is replaced);
 // beta = r.z_new / r.z; convergence on |r|; p = z + beta p with
 // z = M^{-1} r = (r - F u) / c formed on the fly (r.z_new = (r.r - g.u)/c,
 // g = F^T r, u = (cI + F^T F)^{-1} g).  With the factored operator also
@@ -1037,6 +1027,8 @@ __global__ __launch_bounds__(kT) void k_cg_update_p(const CgArgs* __restrict__ A
   __shared__ double red[kRed];
   __shared__ double s_beta[kSC];
   __shared__ int s_cont[kSC];
+  __shared__ double s_alpha[kSC];
+  __shared__ int s_xa[kSC];
   __shared__ double s_u[(NI > 0 ? NI : 1) * kSC];
   const int it = *A.st.it;
   const int par = it & 1, nxt = par ^ 1;
@@ -1048,14 +1040,16 @@ __global__ __launch_bounds__(kT) void k_cg_update_p(const CgArgs* __restrict__ A
   if ((int)threadIdx.x < (ycol ? 1 : (yfold ? kSC : kSlab))) {
     const int cl = threadIdx.x;
     const int rc = col_of(A, ycol, cl);
-    double beta = 0.0;
-    int cont = 0;
+    double beta = 0.0, alpha = 0.0;
+    int cont = 0, xa = 0;
     if (rc < A.R) {
       const double rr_new = A.u_red[rc];
       const double rz_new = pc ? (rr_new - coef_u<NI>(A, rc, s_u + cl)) * A.inv_c : rr_new;
       const bool act = A.st.act[par * A.R + rc] != 0 && A.st.failed[rc] == 0;
       const double rz_old = A.st.rz[par * A.R + rc];
       if (act) {
+        alpha = A.st.hist_a[(int64_t)it * A.R + rc];
+        xa = 1;
         beta = rz_new / rz_old;
         cont = !(rr_new <= A.rtol2 * A.st.bnorm2[rc]) ? 1 : 0;
       }
@@ -1073,6 +1067,8 @@ __global__ __launch_bounds__(kT) void k_cg_update_p(const CgArgs* __restrict__ A
     }
     s_beta[cl] = beta;
     s_cont[cl] = cont;
+    s_alpha[cl] = alpha;
+    s_xa[cl] = xa;
   }
   __syncthreads();
   const int64_t steps = thread_steps(A, ycol);
@@ -1081,14 +1077,19 @@ __global__ __launch_bounds__(kT) void k_cg_update_p(const CgArgs* __restrict__ A
     double gy[NI > 0 ? NI : 1];
 #pragma unroll
     for (int i = 0; i < (NI > 0 ? NI : 1); ++i) gy[i] = 0.0;
-    if (s_cont[0])
+    const bool cont = s_cont[0] != 0;
+    const double al = s_alpha[0];
+    if (s_xa[0])
       for (int64_t k = 0; k < steps; ++k) {
         const int64_t a = thread_row(A, true, k);
         if (a < 0) continue;
+        const double p_old = G.P[a];
+        G.X[a] += al * p_old;
+        if (!cont) continue;
         const GL double* Fa = G.F + a * (int64_t)A.n1;
         const double r = G.Rr[a];
         const double z = pc ? (r - frow_dot<NI>(Fa, A.n1, s_u)) * A.inv_c : r;
-        const double p = z + be * G.P[a];
+        const double p = z + be * p_old;
         G.P[a] = p;
         if (lr) {
 #pragma unroll
@@ -1102,16 +1103,20 @@ __global__ __launch_bounds__(kT) void k_cg_update_p(const CgArgs* __restrict__ A
   const int cl = my_cl(false);
   const double be0 = s_beta[cl], be1 = s_beta[cl + 1];
   const bool c0 = s_cont[cl] != 0, c1 = s_cont[cl + 1] != 0;
+  const double al0 = s_alpha[cl], al1 = s_alpha[cl + 1];
+  const bool xa = s_xa[cl] || s_xa[cl + 1];
   const int jl = lane_id() & 15;
   const double bey = yfold ? s_beta[kSlab] : 0.0;
   const bool cy = yfold && s_cont[kSlab] != 0;
+  const double aly = yfold ? s_alpha[kSlab] : 0.0;
+  const bool xay = yfold && s_xa[kSlab] != 0;
   d4 acc_y[NT > 0 ? NT : 1];
 #pragma unroll
   for (int mt = 0; mt < (NT > 0 ? NT : 1); ++mt) acc_y[mt] = d4{0.0, 0.0, 0.0, 0.0};
   d4 acc[NT > 0 ? NT : 1][2];
 #pragma unroll
   for (int mt = 0; mt < (NT > 0 ? NT : 1); ++mt) acc[mt][0] = acc[mt][1] = d4{0.0, 0.0, 0.0, 0.0};
-  if (FW == 1 && __any(c0 || c1 || (cy && jl == 0))) {
+  if (FW == 1 && __any(xa || (xay && jl == 0))) {
     // F u per 16-row wavefront tile on the matrix cores
     constexpr int NS = (NI + 3) / 4;
     const int g = lane_id() >> 4;
@@ -1127,6 +1132,7 @@ __global__ __launch_bounds__(kT) void k_cg_update_p(const CgArgs* __restrict__ A
         double py = 0.0;
         if (yfold && jl == 0 && a < A.n) {         // column 0 of row a
           py = G.P[a];
+          if (xay) G.X[a] += aly * py;
           if (cy) {
             const double ry = G.Rr[a];
             const double zy = pc ? (ry - pick4(uy, st)) * A.inv_c : ry;
@@ -1139,6 +1145,12 @@ __global__ __launch_bounds__(kT) void k_cg_update_p(const CgArgs* __restrict__ A
           const int64_t o = elem(A, false, a);
           const dv2 r = *reinterpret_cast<const GL dv2*>(G.Rr + o);
           p = *reinterpret_cast<const GL dv2*>(G.P + o);
+          if (xa) {
+            dv2 x = *reinterpret_cast<const GL dv2*>(G.X + o);
+            x.x += al0 * p.x;
+            x.y += al1 * p.y;
+            *reinterpret_cast<GL dv2*>(G.X + o) = x;
+          }
           const double z0 = pc ? (r.x - pick4(ue, st)) * A.inv_c : r.x;
           const double z1 = pc ? (r.y - pick4(ud, st)) * A.inv_c : r.y;
           if (c0) p.x = z0 + be0 * p.x;
@@ -1156,7 +1168,7 @@ __global__ __launch_bounds__(kT) void k_cg_update_p(const CgArgs* __restrict__ A
         }
       }
     }
-  } else if (FW == 0 && __any(c0 || c1)) {
+  } else if (FW == 0 && __any(xa)) {
     for (int64_t k = 0; k < steps; ++k) {
       const int64_t a = thread_row(A, false, k);
       double f[NT > 0 ? NT : 1];
@@ -1171,6 +1183,12 @@ __global__ __launch_bounds__(kT) void k_cg_update_p(const CgArgs* __restrict__ A
         const int64_t o = elem(A, false, a);
         const dv2 r = *reinterpret_cast<const GL dv2*>(G.Rr + o);
         p = *reinterpret_cast<const GL dv2*>(G.P + o);
+        if (xa) {
+          dv2 x = *reinterpret_cast<const GL dv2*>(G.X + o);
+          x.x += al0 * p.x;
+          x.y += al1 * p.y;
+          *reinterpret_cast<GL dv2*>(G.X + o) = x;
+        }
         const double z0 = pc ? (r.x - u0) * A.inv_c : r.x;
         const double z1 = pc ? (r.y - u1) * A.inv_c : r.y;
         if (c0) p.x = z0 + be0 * p.x;
