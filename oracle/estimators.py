@@ -222,3 +222,96 @@ def preconditioned_lml_grad(desc, h, x, y, seed: int, probes: int, m: int):
         tr = float(np.sum(W * (dA @ V))) / probes
         grad[idx] = 0.5 * float(alpha @ dA @ alpha) - 0.5 * tr
     return val, grad, logdet, se
+
+
+# ---------------------------------------------------------------------------
+# Block preconditioner (SUM combine).
+#
+# M = B + F F^T with B = blockdiag(B_t), where the row groups T_t (tiles)
+# partition the points and B_t = S[T_t, T_t] is the principal submatrix of
+# the solver's matrix S on the tile: S = K_core + noise_var I when the
+# solver applies the factored operator A = S + F F^T, S = A (the whole
+# covariance) otherwise.  Principal submatrices of an SPD matrix are SPD, so
+# M is SPD, and every statement of the low-rank section above holds with
+#     ln det M = sum_t ln det B_t + ln det(I_{n1} + F^T B^{-1} F)
+# (determinant lemma) and probes b_p = L w_p + F v_p, L = blockdiag(L_t),
+# B_t = L_t L_t^T (Cholesky with the tile's rows in the given order), w_p and
+# v_p the Rademacher vectors of the low-rank probes: Cov(b_p) = L L^T +
+# F F^T = M.  With singleton tiles B = c I and L = sqrt(c) I, which is the
+# low-rank preconditioner with identical probes.
+# ---------------------------------------------------------------------------
+
+def block_terms(desc, h, x, tiles, factored: bool = True):
+    """(blocks, F): blocks[t] = S[T_t, T_t] (tile rows in the given order)."""
+    if desc.combine != kn.COMBINE_SUM:
+        raise ValueError("the block preconditioner needs the SUM combine")
+    p = kn.unpack(desc, h)
+    x = np.asarray(x, dtype=np.float64)
+    F, _ = kn.bump_F(desc, h, x)
+    if factored:
+        psi = kn.core_matrix(desc, h, x, x)[0]
+        S = p["sigma2"] * psi + p["noise_var"] * np.eye(x.shape[0])
+    else:
+        S = kn.kernel_matrix(desc, h, x, add_noise=True)
+    blocks = [S[np.ix_(t, t)] for t in tiles]
+    return blocks, F
+
+
+def block_probes(seed: int, chols, tiles, F, probes: int):
+    """b_p = L w_p + F v_p for the tile Cholesky factors ``chols``."""
+    n, n1 = F.shape
+    W = rademacher(seed, n, probes)
+    V = lowrank_probe_signs(seed, n1, probes)
+    Bp = F @ V
+    for t, L in zip(tiles, chols):
+        Bp[t] += L @ W[t]
+    return Bp
+
+
+def block_preconditioned_lml_grad(desc, h, x, y, seed: int, probes: int, m: int, tiles,
+                                  factored: bool = True):
+    """LML and gradient with the block-preconditioned SLQ / Hutchinson
+    estimators (exact solves); tiles: list of caller-row index arrays that
+    partition the points.  Returns (lml, grad, logdet, logdet_se)."""
+    A = kn.kernel_matrix(desc, h, x, add_noise=True)
+    n = A.shape[0]
+    tiles = [np.asarray(t, dtype=np.int64) for t in tiles]
+    cover = np.sort(np.concatenate(tiles))
+    if not np.array_equal(cover, np.arange(n)):
+        raise ValueError("tiles must partition the rows")
+    blocks, F = block_terms(desc, h, x, tiles, factored)
+    chols = [np.linalg.cholesky(Bt) for Bt in blocks]
+    Bm = np.zeros((n, n))
+    for t, Bt in zip(tiles, blocks):
+        Bm[np.ix_(t, t)] = Bt
+    M = Bm + F @ F.T
+    logdetB = sum(2.0 * float(np.sum(np.log(np.diag(L)))) for L in chols)
+    n1 = F.shape[1]
+    if n1 > 0:
+        S = np.eye(n1) + F.T @ np.linalg.solve(Bm, F)
+        logdetM = logdetB + np.linalg.slogdet(S)[1]
+    else:
+        logdetM = logdetB
+    lam, U = np.linalg.eigh(M)
+    Mmh = (U / np.sqrt(lam)) @ U.T
+    Ah = Mmh @ A @ Mmh
+    Bp = block_probes(seed, chols, tiles, F, probes)
+    vals = np.empty(probes)
+    for p in range(probes):
+        u = Mmh @ Bp[:, p]
+        al, be = lanczos(Ah, u, m)
+        vals[p] = float(u @ u) * quad_log(al, be)
+    est = float(vals.mean())
+    se = float(vals.std(ddof=1) / np.sqrt(probes)) if probes > 1 else float("nan")
+    logdet = logdetM + est
+    cf = sla.cho_factor(A, lower=True)
+    y = np.asarray(y, dtype=np.float64)
+    alpha = sla.cho_solve(cf, y)
+    val = -0.5 * float(y @ alpha) - 0.5 * logdet
+    W = sla.cho_solve(cf, Bp)
+    V = np.linalg.solve(M, Bp)
+    grad = np.zeros(len(h))
+    for idx, dA in gp.dA_dtheta(desc, h, x):
+        tr = float(np.sum(W * (dA @ V))) / probes
+        grad[idx] = 0.5 * float(alpha @ dA @ alpha) - 0.5 * tr
+    return val, grad, logdet, se
