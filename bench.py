@@ -40,9 +40,8 @@ def parse():
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--probes", type=int, default=32)
     p.add_argument("--rtol", type=float, default=1e-10)
-    p.add_argument("--precond", choices=["block", "lowrank", "none"], default="lowrank",
-                   help="CG preconditioner: block (16-row Morton tiles of the core plus the low-rank bump "
-                        "part), lowrank (bump part only) or none")
+    p.add_argument("--precond", choices=["lowrank", "none"], default="lowrank",
+                   help="CG preconditioner (low-rank bump part of the SUM kernel, or none)")
     p.add_argument("--operator", choices=["assembled", "factored"], default="factored",
                    help="CG operator: the fully assembled sparse K, or K_core (sparse) + F F^T")
     p.add_argument("--graph", type=int, default=0,
@@ -117,7 +116,7 @@ def population(args, sd, wl, torch):
     w, H = wl.population_3d(n=args.pop_n, members=B)
     x = torch.from_numpy(w.x).to(dev)
     y = torch.from_numpy(w.y).to(dev)
-    pc = {"block": sd.PRECOND_BLOCK, "lowrank": sd.PRECOND_LOWRANK, "none": sd.PRECOND_NONE}[args.precond]
+    pc = sd.PRECOND_LOWRANK if args.precond == "lowrank" else sd.PRECOND_NONE
     op = sd.OPERATOR_FACTORED if args.operator == "factored" else sd.OPERATOR_ASSEMBLED
     est = sd.estimator(probes=args.probes, seed=1, cg_rtol=args.rtol, cg_max_iter=20000, precond=pc,
                        operator_form=op)
@@ -198,7 +197,7 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    pc = {"block": sd.PRECOND_BLOCK, "lowrank": sd.PRECOND_LOWRANK, "none": sd.PRECOND_NONE}[args.precond]
+    pc = sd.PRECOND_LOWRANK if args.precond == "lowrank" else sd.PRECOND_NONE
     op = sd.OPERATOR_FACTORED if args.operator == "factored" else sd.OPERATOR_ASSEMBLED
     est = sd.estimator(probes=args.probes, seed=1, cg_rtol=args.rtol, cg_max_iter=20000, precond=pc,
                        operator_form=op)

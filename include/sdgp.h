@@ -67,7 +67,7 @@ typedef enum {
 enum { SDGP_CORE_WENDLAND_C2 = 0, SDGP_CORE_KSTAT = 1 };
 enum { SDGP_COMBINE_PRODUCT = 0, SDGP_COMBINE_SUM = 1 };
 enum { SDGP_PROBE_RADEMACHER = 0, SDGP_PROBE_IDENTITY = 2 };
-enum { SDGP_PRECOND_NONE = 0, SDGP_PRECOND_LOWRANK = 1, SDGP_PRECOND_BLOCK = 2 };
+enum { SDGP_PRECOND_NONE = 0, SDGP_PRECOND_LOWRANK = 1 };
 enum { SDGP_OPERATOR_ASSEMBLED = 0, SDGP_OPERATOR_FACTORED = 1 };
 
 typedef struct {
@@ -100,22 +100,8 @@ typedef struct {
  * (A^{-1} b_p)^T dA (M^{-1} b_p).  Estimates stay unbiased; the CG needs far
  * fewer iterations when the bump functions hold many points.
  *
- * precond = SDGP_PRECOND_BLOCK (SUM combine, Rademacher probes only): the
- * same construction with M = B + F F^T, B the 16 x 16 diagonal blocks of
- * the CG matrix (the core part plus noise under the factored operator, K
- * otherwise) on tiles of 16 consecutive rows of the library's row schedule
- * (points in Morton order of their coordinates: compact groups).  M^{-1}
- * by the Woodbury identity through Y = B^{-1} F and I + F^T Y, ln det M =
- * sum of the blocks' log-dets + ln det(I + F^T Y), probes
- * b_p = L w_p + F v_p with B = L L^T blockwise (w_p, v_p as above).  The
- * blocks also precondition the core part, so the CG needs several times
- * fewer iterations than with c I + F F^T on dense point sets.  The batched
- * entry point and the posterior take the low-rank preconditioner instead.
- * In this version the option is rejected (SDGP_ERR_INVALID_ARG): its device
- * path is switched off until a memory fault it met is explained.
- *
  * operator_form = SDGP_OPERATOR_FACTORED (needs SUM, Rademacher probes and
- * the low-rank or block preconditioner): the CG and the adjoint use the exact
+ * the low-rank preconditioner): the CG and the adjoint use the exact
  * identity K = K_core + F F^T of the SUM combine -- the sparse matrix holds
  * only the core supports (and the diagonal), F (F^T P) is applied in the
  * solver's update pass, and the bump-parameter adjoint is formed from F^T X

@@ -11,7 +11,7 @@ include/sdgp.h; this package is its thin Python binding:
 from . import workloads  # noqa: F401
 from ._lib import (Context, SdgpError, estimator, exact_estimator, load,  # noqa: F401
                    CORE_KSTAT, CORE_WENDLAND_C2, COMBINE_PRODUCT, COMBINE_SUM,
-                   PROBE_IDENTITY, PROBE_RADEMACHER, PRECOND_BLOCK, PRECOND_LOWRANK, PRECOND_NONE,
+                   PROBE_IDENTITY, PROBE_RADEMACHER, PRECOND_LOWRANK, PRECOND_NONE,
                    OPERATOR_ASSEMBLED, OPERATOR_FACTORED, OK, INVALID_ARG, OOM, NOT_SPD,
                    NOT_CONVERGED, HIP, CAPACITY, DE_LML, DE_AUGMENTED, DE_CONSTRAINED, de_trials,
                    de_select)

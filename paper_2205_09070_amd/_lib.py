@@ -24,7 +24,7 @@ STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "OOM", 3: "NOT_SPD", 4: "NOT_CONVE
 CORE_WENDLAND_C2, CORE_KSTAT = 0, 1
 COMBINE_PRODUCT, COMBINE_SUM = 0, 1
 PROBE_RADEMACHER, PROBE_IDENTITY = 0, 2
-PRECOND_NONE, PRECOND_LOWRANK, PRECOND_BLOCK = 0, 1, 2
+PRECOND_NONE, PRECOND_LOWRANK = 0, 1
 OPERATOR_ASSEMBLED, OPERATOR_FACTORED = 0, 1
 DE_LML, DE_AUGMENTED, DE_CONSTRAINED = 0, 1, 2
 

@@ -82,17 +82,13 @@ void check_estimator(const sdgp_estimator* e, int64_t n) {
   require(e->cg_max_iter >= 1, "cg_max_iter must be >= 1");
   require(e->cg_rtol > 0.0 && std::isfinite(e->cg_rtol), "cg_rtol must be > 0");
   require(e->lanczos_steps >= 0, "lanczos_steps must be >= 0");
-  require(e->precond == SDGP_PRECOND_NONE || e->precond == SDGP_PRECOND_LOWRANK || e->precond == SDGP_PRECOND_BLOCK,
-          "unknown preconditioner");
+  require(e->precond == SDGP_PRECOND_NONE || e->precond == SDGP_PRECOND_LOWRANK, "unknown preconditioner");
   require(e->operator_form == SDGP_OPERATOR_ASSEMBLED || e->operator_form == SDGP_OPERATOR_FACTORED,
           "unknown operator form");
-  // The block preconditioner's device path is switched off until a memory
-  // fault met on the device is explained; the option is rejected.
-  require(e->precond != SDGP_PRECOND_BLOCK, "SDGP_PRECOND_BLOCK is not available in this version");
-  if (e->precond != SDGP_PRECOND_NONE)
-    require(e->kind == SDGP_PROBE_RADEMACHER, "the preconditioners need Rademacher probes");
+  if (e->precond == SDGP_PRECOND_LOWRANK)
+    require(e->kind == SDGP_PROBE_RADEMACHER, "the low-rank preconditioner needs Rademacher probes");
   if (e->operator_form == SDGP_OPERATOR_FACTORED)
-    require(e->precond != SDGP_PRECOND_NONE, "the factored operator needs a preconditioner");
+    require(e->precond == SDGP_PRECOND_LOWRANK, "the factored operator needs the low-rank preconditioner");
 }
 
 void finish_timing(Ctx* c, PhaseTimer& t, sdgp_info* info) {
@@ -126,10 +122,10 @@ sdgp_status evaluate(Ctx* c, const Sorted& s, const double* ys, const sdgp_kerne
   const int kind = e.kind == SDGP_PROBE_IDENTITY ? PK_IDENTITY : PK_RADEMACHER;
   const int P = kind == PK_IDENTITY ? (int)s.n : e.probes;
   Precond pc;
-  const bool use_pc = e.precond != SDGP_PRECOND_NONE;
+  const bool use_pc = e.precond == SDGP_PRECOND_LOWRANK;
   if (use_pc) {
-    require(d.combine == SDGP_COMBINE_SUM, "the preconditioners need the SUM combine");
-    pc = e.precond == SDGP_PRECOND_BLOCK ? block_precond(c, s, as.A, as.kp, as.b) : lowrank_precond(c, s, as.kp, as.b);
+    require(d.combine == SDGP_COMBINE_SUM, "the low-rank preconditioner needs the SUM combine");
+    pc = lowrank_precond(c, s, as.kp, as.b);
     pc.lowrank_op = factored ? 1 : 0;
   }
   CgResult cg = block_cg(c, as.A, s, ys, kind, P, e.seed, e.cg_rtol, e.cg_max_iter, nullptr, 0,
@@ -320,8 +316,7 @@ sdgp_status sdgp_lml_grad_batched(sdgp_ctx* ctx, const sdgp_kernel_desc* desc, c
     check_estimator(est, n);
     validate_shape(*desc, n);
     const bool factored = est->operator_form == SDGP_OPERATOR_FACTORED;
-    // the batched path preconditions with c I + F F^T (also for SDGP_PRECOND_BLOCK)
-    const bool use_pc = est->precond != SDGP_PRECOND_NONE;
+    const bool use_pc = est->precond == SDGP_PRECOND_LOWRANK;
     if (factored || use_pc) require(desc->combine == SDGP_COMBINE_SUM, "preconditioner/factored form need SUM");
     const int kind = est->kind == SDGP_PROBE_IDENTITY ? PK_IDENTITY : PK_RADEMACHER;
     const int P = kind == PK_IDENTITY ? (int)n : est->probes;
@@ -480,8 +475,7 @@ sdgp_status sdgp_posterior_mean_var(sdgp_ctx* ctx, const sdgp_kernel_desc* desc,
     double* kxx = nullptr;
     Csr K0 = assemble_cross(ctx, s, as.kp, as.b, x0, n0, h, &kxx);
     Precond pc;
-    // the posterior's solves take c I + F F^T for either preconditioner
-    const bool use_pc = est->precond != SDGP_PRECOND_NONE && desc->combine == SDGP_COMBINE_SUM;
+    const bool use_pc = est->precond == SDGP_PRECOND_LOWRANK && desc->combine == SDGP_COMBINE_SUM;
     if (use_pc) pc = lowrank_precond(ctx, s, as.kp, as.b);
     CgResult cg = block_cg(ctx, as.A, s, ys, PK_NONE, 0, 0, est->cg_rtol, est->cg_max_iter, nullptr, 0,
                            use_pc ? &pc : nullptr, false, nullptr);

@@ -92,16 +92,6 @@ struct CgArgs {
   const int32_t* lcnt;
   const uint16_t* lslot;
   int nlb;                    // 64-row blocks
-  // block preconditioner M = B + F F^T (16-row schedule tiles): B_t^{-1}
-  // and Cholesky factors per tile in matrix-core operand order, Y = B^{-1} F,
-  // T = B^{-1} r (slab layout); u_part/u_red hold nu row groups of R: r.r,
-  // then n1 of Y^T r (F^T r), then r.t (row group rt_base)
-  int block;
-  int nu, rt_base;
-  const double* Bt;
-  const double* Lt;
-  const double* Y;
-  double* T;
   CgState st;
 };
 
@@ -122,10 +112,6 @@ struct Gv {
   GL double *s_part, *u_part, *p_part;
   const GL int32_t* lnb;
   const GL uint16_t* lslot;
-  const GL double* Bt;
-  const GL double* Lt;
-  const GL double* Y;
-  GL double* T;
 };
 __device__ __forceinline__ Gv gview(const CgArgs& A) {
   Gv g;
@@ -144,10 +130,6 @@ __device__ __forceinline__ Gv gview(const CgArgs& A) {
   g.p_part = (GL double*)A.p_part;
   g.lnb = (const GL int32_t*)A.lnb;
   g.lslot = (const GL uint16_t*)A.lslot;
-  g.Bt = (const GL double*)A.Bt;
-  g.Lt = (const GL double*)A.Lt;
-  g.Y = (const GL double*)A.Y;
-  g.T = (GL double*)A.T;
   return g;
 }
 
@@ -546,7 +528,7 @@ __global__ __launch_bounds__(kSumT) void k_cg_colsum(const CgArgs* __restrict__ 
   double* out;
   int nparts, ncols;
   if (which == 0) { part = G.s_part; out = A.s_red; nparts = A.nbs; ncols = A.R; }
-  else if (which == 1) { part = G.u_part; out = A.u_red; nparts = A.nbu; ncols = A.nu * A.R; }
+  else if (which == 1) { part = G.u_part; out = A.u_red; nparts = A.nbu; ncols = (1 + (A.use_pc ? A.n1 : 0)) * A.R; }
   else { part = G.p_part; out = A.p_red; nparts = A.nbu; ncols = A.n1 * A.R; }
   const int c = blockIdx.x;
   if (c >= ncols) return;
@@ -1220,407 +1202,6 @@ __global__ __launch_bounds__(kT) void k_cg_update_p(const CgArgs* __restrict__ A
   if (yfold && NT > 0 && lr) put_yfold_partials<(NT > 0 ? NT : 1)>(A, red, false, 0.0, 0, true, acc_y, G.p_part, 0);
 }
 
-// ------------------------------------------------------------ block preconditioner
-// M = B + F F^T with B the 16 x 16 diagonal blocks on tiles of 16
-// consecutive schedule rows.  Each wavefront takes whole tiles: lane (g, j)
-// holds, at step st, the slab columns 2j, 2j+1 of the row at schedule
-// position base + 4 st + g, which is exactly the K = 4 operand slice of
-// v_mfma_f64_16x16x4f64 for the tile's product X_t R (X_t = B_t^{-1} or L_t
-// with A[i][k] = X_t[i][4 st + k] in lane 16 k + i), and the 16 x 16
-// result D[4 q + g][j] lands in the lane that owns that row at step q.
-// The slab-0 blocks also own column 0 (lanes j == 0).
-
-__device__ __forceinline__ int64_t sched_row(const Gv& G, int64_t n, int64_t p) {
-  return p < n ? (int64_t)G.sched[p] : -1;
-}
-
-// X_t R for the tile: r[st] the lane's two slab values at step st, r0[st]
-// its column-0 value (lanes j == 0 of slab-0 blocks).
-__device__ __forceinline__ void tile_apply(const GL double* __restrict__ xt, const dv2* r, const double* r0,
-                                           bool y0, d4& te, d4& td, d4& t0) {
-  const int lane = lane_id();
-  te = d4{0.0, 0.0, 0.0, 0.0};
-  td = d4{0.0, 0.0, 0.0, 0.0};
-  t0 = d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-  for (int st = 0; st < 4; ++st) {
-    const double a = xt[st * 64 + lane];
-    te = __builtin_amdgcn_mfma_f64_16x16x4f64(a, r[st].x, te, 0, 0, 0);
-    td = __builtin_amdgcn_mfma_f64_16x16x4f64(a, r[st].y, td, 0, 0, 0);
-    if (y0) t0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, r0[st], t0, 0, 0, 0);
-  }
-}
-
-// sum_i X[row][i] w[i][.] for the tile rows (X = F or Y; rowj: the row of
-// schedule position base + j for lane j, -1 for padding); layout as fw_tile_y.
-template <int NS>
-__device__ __forceinline__ void xw_rows(const GL double* __restrict__ X, int n1, int64_t rowj, const double* w,
-                                        bool y0, d4& de, d4& dd, d4& dy) {
-  const int g = lane_id() >> 4, j = lane_id() & 15;
-  de = d4{0.0, 0.0, 0.0, 0.0};
-  dd = d4{0.0, 0.0, 0.0, 0.0};
-  dy = d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-  for (int s = 0; s < NS; ++s) {
-    const int i = 4 * s + g;
-    const bool ok = i < n1;
-    const double fa = (rowj >= 0 && ok) ? X[rowj * n1 + i] : 0.0;
-    const double b0 = ok ? w[i * kSC + 2 * j] : 0.0;
-    const double b1 = ok ? w[i * kSC + 2 * j + 1] : 0.0;
-    de = __builtin_amdgcn_mfma_f64_16x16x4f64(fa, b0, de, 0, 0, 0);
-    dd = __builtin_amdgcn_mfma_f64_16x16x4f64(fa, b1, dd, 0, 0, 0);
-    if (y0) {
-      const double by = (ok && j == 0) ? w[i * kSC + kSlab] : 0.0;
-      dy = __builtin_amdgcn_mfma_f64_16x16x4f64(fa, by, dy, 0, 0, 0);
-    }
-  }
-}
-
-// Row values of X (F or Y) for the lane: f[mt] = X[a][16 mt + j].
-template <int NT>
-__device__ __forceinline__ void load_x(const GL double* __restrict__ X, int n1, int64_t a, double* f) {
-  const int j = lane_id() & 15;
-#pragma unroll
-  for (int mt = 0; mt < NT; ++mt) {
-    const int i = 16 * mt + j;
-    f[mt] = (a >= 0 && i < n1) ? X[a * (int64_t)n1 + i] : 0.0;
-  }
-}
-
-// Probes of the block preconditioner: column 1+p of R holds w_p from
-// k_cg_start; replace it by L w_p + F v_p per tile (v_p: the n1 Rademacher
-// signs of the low-rank preconditioner's probes), covariance B + F F^T.
-template <int NI>
-__global__ __launch_bounds__(kT) void k_blk_probe(const CgArgs* __restrict__ AA, uint64_t seed) {
-  constexpr int NS = (NI + 3) / 4;
-  const CgArgs& A = AA[blockIdx.z];
-  const Gv G = gview(A);
-  __shared__ double s_v[(NI > 0 ? NI : 1) * kSC];
-  for (int e = threadIdx.x; e < A.n1 * kSlab; e += kT) {
-    const int i = e / kSlab, cl = e % kSlab;
-    const int rc = 1 + (int)blockIdx.y * kSlab + cl;
-    double v = 0.0;
-    if (rc < A.R) {
-      const uint64_t pbase = (uint64_t)(rc - 1) << 32;
-      v = (splitmix64_at(seed, pbase + 0xFFFFFFFFull - (uint64_t)i) >> 63) ? -1.0 : 1.0;
-    }
-    s_v[i * kSC + cl] = v;
-  }
-  __syncthreads();
-  const int g = lane_id() >> 4, jl = lane_id() & 15;
-  const int64_t nst = tile_steps(A);
-  const double zero4[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int64_t k = 0; k < nst; ++k) {
-    const int64_t base = wave_base(A, k);
-    if (base >= A.n) break;                         // uniform over the wavefront
-    d4 fe = {0.0, 0.0, 0.0, 0.0}, fd = {0.0, 0.0, 0.0, 0.0}, fy;
-    if (NS > 0) xw_rows<NS>(G.F, A.n1, sched_row(G, A.n, base + jl), s_v, false, fe, fd, fy);
-    dv2 rv[4];
-#pragma unroll
-    for (int st = 0; st < 4; ++st) {
-      const int64_t a = sched_row(G, A.n, base + 4 * st + g);
-      rv[st] = a >= 0 ? *reinterpret_cast<const GL dv2*>(G.Rr + elem(A, false, a)) : dv2{0.0, 0.0};
-    }
-    d4 te, td, t0;
-    tile_apply(G.Lt + (base / kWaveRows) * 256, rv, zero4, false, te, td, t0);
-#pragma unroll
-    for (int st = 0; st < 4; ++st) {
-      const int64_t a = sched_row(G, A.n, base + 4 * st + g);
-      if (a >= 0)
-        *reinterpret_cast<GL dv2*>(G.Rr + elem(A, false, a)) = dv2{te[st] + pick4(fe, st), td[st] + pick4(fd, st)};
-    }
-  }
-}
-
-// r-pass of the block-preconditioned CG.  INIT (r = b, before the first
-// iteration): partials of b.b, Y^T b and b.t, t = B^{-1} b.  Otherwise:
-// alpha = r.z / p.A p; r -= alpha A p (A p = K_core p + F (F^T p) with the
-// factored operator); partials of r.r, Y^T r and r.t, t = B^{-1} r.
-template <int NI, bool INIT>
-__global__ __launch_bounds__(kT) void k_blk_xr(const CgArgs* __restrict__ AA) {
-  constexpr int NT = (NI + 15) / 16;
-  constexpr int NS = (NI + 3) / 4;
-  const CgArgs& A = AA[blockIdx.z];
-  const Gv G = gview(A);
-  if (!INIT && stopped(A)) return;
-  __shared__ double red[kRed];
-  __shared__ double s_alpha[kSC];
-  __shared__ int s_act[kSC];
-  __shared__ double s_gp[(NI > 0 ? NI : 1) * kSC];
-  const int it = INIT ? 0 : *A.st.it;
-  const int par = it & 1;
-  const bool lr = NI > 0 && A.lowrank_op;
-  const bool pc = NI > 0 && A.use_pc;
-  const bool yfold = blockIdx.y == 0;
-  if ((int)threadIdx.x < (yfold ? kSC : kSlab)) {
-    const int cl = threadIdx.x;
-    const int rc = col_of(A, false, cl);
-    double alpha = 0.0;
-    int act = INIT ? 1 : 0;
-    if (!INIT && rc < A.R) {
-      const bool was = A.st.act[par * A.R + rc] != 0;
-      double d = A.s_red[rc];
-      if (lr)
-        for (int i = 0; i < A.n1; ++i) {
-          const double gi = A.p_red[(int64_t)i * A.R + rc];
-          s_gp[i * kSC + cl] = gi;
-          d += gi * gi;
-        }
-      if (was) {
-        if (d > 0.0 && isfinite(d)) {
-          alpha = A.st.rz[par * A.R + rc] / d;
-          act = 1;
-        }
-        if (blockIdx.x == 0) {
-          A.st.hist_a[(int64_t)it * A.R + rc] = alpha;
-          if (!act) {
-            A.st.failed[rc] = 1;
-            *A.st.not_spd = 1;
-          }
-        }
-      }
-    } else if (!INIT && lr) {
-      for (int i = 0; i < A.n1; ++i) s_gp[i * kSC + cl] = 0.0;
-    }
-    s_alpha[cl] = alpha;
-    s_act[cl] = act;
-  }
-  __syncthreads();
-  const int cl = my_cl(false);
-  const int g = lane_id() >> 4, jl = lane_id() & 15;
-  const double al0 = s_alpha[cl], al1 = s_alpha[cl + 1];
-  const double aly = yfold ? s_alpha[kSlab] : 0.0;
-  const bool acty = !INIT && yfold && s_act[kSlab] != 0;
-  const bool mine = INIT || s_act[cl] || s_act[cl + 1] || (acty && jl == 0);
-  double rr0 = 0.0, rr1 = 0.0, rry = 0.0, rt0 = 0.0, rt1 = 0.0, rty = 0.0;
-  d4 acc_y[NT > 0 ? NT : 1];
-  d4 acc[NT > 0 ? NT : 1][2];
-#pragma unroll
-  for (int mt = 0; mt < (NT > 0 ? NT : 1); ++mt) acc_y[mt] = acc[mt][0] = acc[mt][1] = d4{0.0, 0.0, 0.0, 0.0};
-  if (__any(mine)) {
-    const int64_t nst = tile_steps(A);
-    for (int64_t k = 0; k < nst; ++k) {
-      const int64_t base = wave_base(A, k);
-      if (base >= A.n) break;                       // uniform over the wavefront
-      d4 ce = {0.0, 0.0, 0.0, 0.0}, cd = {0.0, 0.0, 0.0, 0.0}, cy = {0.0, 0.0, 0.0, 0.0};
-      if (!INIT && NS > 0 && lr) xw_rows<NS>(G.F, A.n1, sched_row(G, A.n, base + jl), s_gp, yfold, ce, cd, cy);
-      dv2 rv[4];
-      double r0v[4];
-#pragma unroll
-      for (int st = 0; st < 4; ++st) {
-        const int64_t a = sched_row(G, A.n, base + 4 * st + g);
-        double ry = 0.0;
-        if (yfold && jl == 0 && a >= 0) {           // column 0 of row a
-          ry = G.Rr[a];
-          if (acty) {
-            ry -= aly * (G.Q[a] + pick4(cy, st));
-            G.Rr[a] = ry;
-          }
-          if (INIT || acty) rry += ry * ry;
-        }
-        dv2 r = {0.0, 0.0};
-        if (a >= 0) {
-          const int64_t o = elem(A, false, a);
-          r = *reinterpret_cast<const GL dv2*>(G.Rr + o);
-          if (!INIT) {
-            dv2 q = *reinterpret_cast<const GL dv2*>(G.Q + o);
-            q.x += pick4(ce, st);
-            q.y += pick4(cd, st);
-            r.x -= al0 * q.x;
-            r.y -= al1 * q.y;
-            *reinterpret_cast<GL dv2*>(G.Rr + o) = r;
-          }
-          rr0 += r.x * r.x;
-          rr1 += r.y * r.y;
-        }
-        rv[st] = r;
-        r0v[st] = ry;
-        if (NT > 0 && pc) {
-          double f[NT > 0 ? NT : 1];
-          load_x<NT>(G.Y, A.n1, a, f);
-          ft_step<NT>(f, r.x, r.y, acc);
-          if (yfold) {
-#pragma unroll
-            for (int mt = 0; mt < NT; ++mt) acc_y[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(f[mt], ry, acc_y[mt], 0, 0, 0);
-          }
-        }
-      }
-      d4 te, td, t0;
-      tile_apply(G.Bt + (base / kWaveRows) * 256, rv, r0v, yfold, te, td, t0);
-#pragma unroll
-      for (int st = 0; st < 4; ++st) {
-        const int64_t a = sched_row(G, A.n, base + 4 * st + g);
-        if (a < 0) continue;
-        const dv2 t = {te[st], td[st]};
-        *reinterpret_cast<GL dv2*>(G.T + elem(A, false, a)) = t;
-        rt0 += rv[st].x * t.x;
-        rt1 += rv[st].y * t.y;
-        if (yfold && jl == 0) {
-          G.T[a] = t0[st];
-          rty += r0v[st] * t0[st];
-        }
-      }
-    }
-  }
-  double t = tile_colsum(red, rr0, rr1);
-  if (threadIdx.x < kSlab) {
-    const int rc = 1 + (int)blockIdx.y * kSlab + (int)threadIdx.x;
-    if (rc < A.R) G.u_part[(int64_t)rc * A.nbu + blockIdx.x] = t;
-  }
-  t = tile_colsum(red, rt0, rt1);
-  if (threadIdx.x < kSlab) {
-    const int rc = 1 + (int)blockIdx.y * kSlab + (int)threadIdx.x;
-    if (rc < A.R) G.u_part[((int64_t)A.rt_base * A.R + rc) * A.nbu + blockIdx.x] = t;
-  }
-  if (NT > 0 && pc) put_ft_partials<NT>(A, red, acc, G.u_part, A.R);
-  if (yfold) {
-    put_yfold_partials<(NT > 0 ? NT : 1)>(A, red, true, rry, 0, NT > 0 && pc, acc_y, G.u_part, A.R);
-    put_yfold_partials<(NT > 0 ? NT : 1)>(A, red, true, rty, (int64_t)A.rt_base * A.R, false, acc_y, G.u_part, 0);
-  }
-}
-
-// p-pass of the block-preconditioned CG: z = M^{-1} r = t - Y u
-// (u = S^{-1} Y^T r from k_cg_small_solve, t = B^{-1} r from the r-pass),
-// r.z = r.t - (Y^T r).u.  INIT: the initial state (p = z0, V = z0,
-// rz0 = b.z0, bnorm2 = b.b).  Otherwise: x += alpha p; beta = r.z_new / r.z;
-// convergence on |r|; p = z + beta p.  With the factored operator also the
-// partials of F^T p.
-template <int NI, bool INIT>
-__global__ __launch_bounds__(kT) void k_blk_p(const CgArgs* __restrict__ AA) {
-  constexpr int NT = (NI + 15) / 16;
-  constexpr int NS = (NI + 3) / 4;
-  const CgArgs& A = AA[blockIdx.z];
-  const Gv G = gview(A);
-  if (!INIT && stopped(A)) return;
-  __shared__ double red[kRed];
-  __shared__ double s_beta[kSC];
-  __shared__ int s_cont[kSC];
-  __shared__ double s_alpha[kSC];
-  __shared__ int s_xa[kSC];
-  __shared__ double s_u[(NI > 0 ? NI : 1) * kSC];
-  const int it = INIT ? 0 : *A.st.it;
-  const int par = it & 1, nxt = par ^ 1;
-  const bool lr = NI > 0 && A.lowrank_op;
-  const bool pc = NI > 0 && A.use_pc;
-  const bool yfold = blockIdx.y == 0;
-  if ((int)threadIdx.x < (yfold ? kSC : kSlab)) {
-    const int cl = threadIdx.x;
-    const int rc = col_of(A, false, cl);
-    double beta = 0.0, alpha = 0.0;
-    int cont = INIT ? 1 : 0, xa = 0;
-    if (rc < A.R) {
-      const double rr_new = A.u_red[rc];
-      const double rt_new = A.u_red[(int64_t)A.rt_base * A.R + rc];
-      const double rz_new = pc ? rt_new - coef_u<NI>(A, rc, s_u + cl) : rt_new;
-      if (INIT) {
-        if (blockIdx.x == 0) {
-          A.st.bnorm2[rc] = rr_new;
-          A.st.rr_last[rc] = rr_new;
-          A.st.rz[rc] = rz_new;
-          A.st.rz[A.R + rc] = rz_new;
-          A.st.rz0[rc] = rz_new;
-          A.st.act[rc] = rr_new > 0.0 ? 1 : 0;
-          A.st.act[A.R + rc] = 0;
-          A.st.failed[rc] = 0;
-          A.st.iters[rc] = 0;
-        }
-      } else {
-        const bool act = A.st.act[par * A.R + rc] != 0 && A.st.failed[rc] == 0;
-        const double rz_old = A.st.rz[par * A.R + rc];
-        if (act) {
-          alpha = A.st.hist_a[(int64_t)it * A.R + rc];
-          xa = 1;
-          beta = rz_new / rz_old;
-          cont = !(rr_new <= A.rtol2 * A.st.bnorm2[rc]) ? 1 : 0;
-        }
-        if (blockIdx.x == 0) {
-          A.st.rz[nxt * A.R + rc] = act ? rz_new : rz_old;
-          A.st.act[nxt * A.R + rc] = cont;
-          if (act) {
-            A.st.hist_b[(int64_t)it * A.R + rc] = beta;
-            A.st.iters[rc] += 1;
-            A.st.rr_last[rc] = rr_new;
-          }
-        }
-      }
-    } else if (pc) {
-      for (int i = 0; i < A.n1; ++i) s_u[i * kSC + cl] = 0.0;
-    }
-    s_beta[cl] = beta;
-    s_cont[cl] = cont;
-    s_alpha[cl] = alpha;
-    s_xa[cl] = xa;
-  }
-  __syncthreads();
-  const int cl = my_cl(false);
-  const int g = lane_id() >> 4, jl = lane_id() & 15;
-  const double be0 = s_beta[cl], be1 = s_beta[cl + 1];
-  const bool c0 = s_cont[cl] != 0, c1 = s_cont[cl + 1] != 0;
-  const double al0 = s_alpha[cl], al1 = s_alpha[cl + 1];
-  const bool xa = s_xa[cl] || s_xa[cl + 1];
-  const double bey = yfold ? s_beta[kSlab] : 0.0;
-  const bool cy = yfold && s_cont[kSlab] != 0;
-  const double aly = yfold ? s_alpha[kSlab] : 0.0;
-  const bool xay = yfold && s_xa[kSlab] != 0;
-  d4 acc_y[NT > 0 ? NT : 1];
-  d4 acc[NT > 0 ? NT : 1][2];
-#pragma unroll
-  for (int mt = 0; mt < (NT > 0 ? NT : 1); ++mt) acc_y[mt] = acc[mt][0] = acc[mt][1] = d4{0.0, 0.0, 0.0, 0.0};
-  if (__any(INIT || xa || c0 || c1 || ((xay || cy) && jl == 0))) {
-    const int64_t nst = tile_steps(A);
-    for (int64_t k = 0; k < nst; ++k) {
-      const int64_t base = wave_base(A, k);
-      if (base >= A.n) break;                       // uniform over the wavefront
-      d4 ue = {0.0, 0.0, 0.0, 0.0}, ud = {0.0, 0.0, 0.0, 0.0}, uy = {0.0, 0.0, 0.0, 0.0};
-      if (NS > 0 && pc) xw_rows<NS>(G.Y, A.n1, sched_row(G, A.n, base + jl), s_u, yfold, ue, ud, uy);
-#pragma unroll 1
-      for (int st = 0; st < 4; ++st) {
-        const int64_t a = sched_row(G, A.n, base + 4 * st + g);
-        double py = 0.0;
-        if (yfold && jl == 0 && a >= 0) {           // column 0 of row a
-          py = INIT ? 0.0 : G.P[a];
-          if (xay) G.X[a] += aly * py;
-          if (cy) {
-            const double zy = G.T[a] - (pc ? pick4(uy, st) : 0.0);
-            py = INIT ? zy : zy + bey * py;
-            G.P[a] = py;
-            if (INIT && G.V) G.V[a] = zy;
-          }
-        }
-        dv2 p = {0.0, 0.0};
-        if (a >= 0) {
-          const int64_t o = elem(A, false, a);
-          const dv2 t = *reinterpret_cast<const GL dv2*>(G.T + o);
-          if (!INIT) p = *reinterpret_cast<const GL dv2*>(G.P + o);
-          if (!INIT && xa) {
-            dv2 x = *reinterpret_cast<const GL dv2*>(G.X + o);
-            x.x += al0 * p.x;
-            x.y += al1 * p.y;
-            *reinterpret_cast<GL dv2*>(G.X + o) = x;
-          }
-          const double z0 = t.x - (pc ? pick4(ue, st) : 0.0);
-          const double z1 = t.y - (pc ? pick4(ud, st) : 0.0);
-          if (c0) p.x = INIT ? z0 : z0 + be0 * p.x;
-          if (c1) p.y = INIT ? z1 : z1 + be1 * p.y;
-          *reinterpret_cast<GL dv2*>(G.P + o) = p;
-          if (INIT && G.V) *reinterpret_cast<GL dv2*>(G.V + o) = dv2{z0, z1};
-        }
-        if (NT > 0 && lr) {
-          double f[NT > 0 ? NT : 1];
-          load_x<NT>(G.F, A.n1, a, f);
-          ft_step<NT>(f, p.x, p.y, acc);
-          if (yfold) {
-#pragma unroll
-            for (int mt = 0; mt < NT; ++mt) acc_y[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(f[mt], py, acc_y[mt], 0, 0, 0);
-          }
-        }
-      }
-    }
-  }
-  if (NT > 0 && lr) put_ft_partials<NT>(A, red, acc, G.p_part, 0);
-  if (yfold && NT > 0 && lr) put_yfold_partials<(NT > 0 ? NT : 1)>(A, red, false, 0.0, 0, true, acc_y, G.p_part, 0);
-}
-
 // Records the executed iteration count in done when no column is active
 // and advances the iteration counter (one block per member).
 __global__ void k_cg_check(const CgArgs* __restrict__ AA) {
@@ -1646,8 +1227,7 @@ __global__ void k_cg_check(const CgArgs* __restrict__ AA) {
 // x = 0, r = b, p = 0 over the whole slab layout (padding included).
 // Column 0 is y (or the first dense column); probe p (column 1+p) is the
 // Rademacher vector w_p of caller row perm[a], or with the preconditioner
-// sqrt(c) w_p + F v_p (v_p: n1 Rademacher signs), whose covariance is M;
-// with the block preconditioner w_p is left for k_blk_probe.
+// sqrt(c) w_p + F v_p (v_p: n1 Rademacher signs), whose covariance is M.
 __global__ void k_cg_start(const CgArgs* __restrict__ AA, const double* __restrict__ ys,
                            const int32_t* __restrict__ perm, int kind, uint64_t seed,
                            const double* __restrict__ dense) {
@@ -1680,7 +1260,7 @@ __global__ void k_cg_start(const CgArgs* __restrict__ AA, const double* __restri
     } else {
       const uint64_t pbase = (uint64_t)(rc - 1) << 32;
       b = (splitmix64_at(seed, pbase + (uint64_t)perm[a] + 1ull) >> 63) ? -1.0 : 1.0;
-      if (A.use_pc && !A.block) {
+      if (A.use_pc) {
         double fv = 0.0;
         const GL double* Fa = G.F + a * (int64_t)A.n1;
         for (int i = 0; i < A.n1; ++i) {
@@ -1856,9 +1436,6 @@ struct Launch {
   int B;
   bool staged;  // neighbourhood-staged SpMM (ns == 1)
   bool fw;      // F w products of the update kernels on the matrix cores
-  bool blk;     // block preconditioner (block kernels, ns >= 1)
-  int nu;       // row groups of the r-pass partials
-  uint64_t seed;
 };
 
 template <int NI>
@@ -1887,18 +1464,16 @@ void launch_iteration(hipStream_t st, const CgArgs* dA, const Launch& L, Ctx* c)
   }
   k_cg_colsum<<<dim3(L.R, 1, L.B), kSumT, 0, st>>>(dA, 0);
   SDGP_CHECK_LAUNCH();
-  if (L.blk) k_blk_xr<NI, false><<<dim3(L.nbu, L.ns, L.B), kT, 0, st>>>(dA);
-  else if (L.fw) k_cg_update_xr<NI, 1><<<dim3(L.nbu, L.ns, L.B), kT, 0, st>>>(dA);
+  if (L.fw) k_cg_update_xr<NI, 1><<<dim3(L.nbu, L.ns, L.B), kT, 0, st>>>(dA);
   else k_cg_update_xr<NI, 0><<<dim3(L.nbu, L.ns + 1, L.B), kT, 0, st>>>(dA);
   SDGP_CHECK_LAUNCH();
-  k_cg_colsum<<<dim3(L.nu * L.R, 1, L.B), kSumT, 0, st>>>(dA, 1);
+  k_cg_colsum<<<dim3((1 + (L.use_pc ? L.n1 : 0)) * L.R, 1, L.B), kSumT, 0, st>>>(dA, 1);
   SDGP_CHECK_LAUNCH();
   if (L.use_pc) {
     k_cg_small_solve<<<dim3(L.R, 1, L.B), 64, 0, st>>>(dA);
     SDGP_CHECK_LAUNCH();
   }
-  if (L.blk) k_blk_p<NI, false><<<dim3(L.nbu, L.ns, L.B), kT, 0, st>>>(dA);
-  else if (L.fw) k_cg_update_p<NI, 1><<<dim3(L.nbu, L.ns, L.B), kT, 0, st>>>(dA);
+  if (L.fw) k_cg_update_p<NI, 1><<<dim3(L.nbu, L.ns, L.B), kT, 0, st>>>(dA);
   else k_cg_update_p<NI, 0><<<dim3(L.nbu, L.ns + 1, L.B), kT, 0, st>>>(dA);
   SDGP_CHECK_LAUNCH();
   if (L.lowrank) {
@@ -1911,22 +1486,15 @@ void launch_iteration(hipStream_t st, const CgArgs* dA, const Launch& L, Ctx* c)
 
 template <int NI>
 void launch_start(hipStream_t st, const CgArgs* dA, const Launch& L) {
-  if (L.blk) {
-    k_blk_probe<NI><<<dim3(L.nbu, L.ns, L.B), kT, 0, st>>>(dA, L.seed);
-    SDGP_CHECK_LAUNCH();
-    k_blk_xr<NI, true><<<dim3(L.nbu, L.ns, L.B), kT, 0, st>>>(dA);
-  } else {
-    k_cg_norm<NI><<<dim3(L.nbu, L.ns + 1, L.B), kT, 0, st>>>(dA);
-  }
+  k_cg_norm<NI><<<dim3(L.nbu, L.ns + 1, L.B), kT, 0, st>>>(dA);
   SDGP_CHECK_LAUNCH();
-  k_cg_colsum<<<dim3(L.nu * L.R, 1, L.B), kSumT, 0, st>>>(dA, 1);
+  k_cg_colsum<<<dim3((1 + (L.use_pc ? L.n1 : 0)) * L.R, 1, L.B), kSumT, 0, st>>>(dA, 1);
   SDGP_CHECK_LAUNCH();
   if (L.use_pc) {
     k_cg_small_solve<<<dim3(L.R, 1, L.B), 64, 0, st>>>(dA);
     SDGP_CHECK_LAUNCH();
   }
-  if (L.blk) k_blk_p<NI, true><<<dim3(L.nbu, L.ns, L.B), kT, 0, st>>>(dA);
-  else k_cg_init_fin<NI><<<dim3(L.nbu, L.ns + 1, L.B), kT, 0, st>>>(dA);
+  k_cg_init_fin<NI><<<dim3(L.nbu, L.ns + 1, L.B), kT, 0, st>>>(dA);
   SDGP_CHECK_LAUNCH();
   if (L.lowrank) {
     k_cg_colsum<<<dim3(L.n1 * L.R, 1, L.B), kSumT, 0, st>>>(dA, 2);
@@ -1978,15 +1546,12 @@ std::vector<CgResult> block_cg_multi(Ctx* c, const std::vector<CgMember>& mem, c
   const Precond* pc0 = mem[0].pc;
   const bool use_pc = pc0 != nullptr && pc0->n1 > 0 && pc0->apply;
   const bool use_lr = pc0 != nullptr && pc0->n1 > 0 && pc0->lowrank_op;
-  const bool use_blk = pc0 != nullptr && pc0->block && pc0->apply;
   const int n1 = (use_pc || use_lr) ? pc0->n1 : 0;
   for (int m = 0; m < B; ++m) {
     const Precond* p = mem[m].pc;
     const bool up = p != nullptr && p->n1 > 0 && p->apply;
     const bool ul = p != nullptr && p->n1 > 0 && p->lowrank_op;
-    const bool ub = p != nullptr && p->block && p->apply;
-    require(up == use_pc && ul == use_lr && ub == use_blk && (!(up || ul) || p->n1 == n1),
-            "members must share the solver form");
+    require(up == use_pc && ul == use_lr && (!(up || ul) || p->n1 == n1), "members must share the solver form");
     require(mem[m].A.n == n, "members must share the point set");
   }
   require(n1 <= 64, "at most 64 bump functions");
@@ -2002,15 +1567,12 @@ std::vector<CgResult> block_cg_multi(Ctx* c, const std::vector<CgMember>& mem, c
   const int nbs = staged ? (int)round8(nlb) : (int)std::min<int64_t>(kMaxNbs, round8(tiles));
   const int nbu = (int)std::min<int64_t>(kMaxNbu, round8(tiles));
   require(!staged || nbs < 0x7fffffff, "too many row blocks");
-  require(!use_blk || (kind == PK_RADEMACHER && ns >= 1), "the block preconditioner needs Rademacher probes");
-  const int rt_base = 1 + (use_pc ? n1 : 0);
-  const int nu = rt_base + (use_blk ? 1 : 0);
+  const int nu = 1 + (use_pc ? n1 : 0);
   double* X = c->get<double>(S_CG_X, NV * B);
   double* Rr = c->get<double>(S_CG_R, NV * B);
   double* Pp = c->get<double>(S_CG_P, NV * B);
   double* Q = c->get<double>(S_CG_Q, NV * B);
-  double* V = ((use_pc || use_blk) && keep_v) ? c->get<double>(S_CG_V, NV * B) : nullptr;
-  double* T = use_blk ? c->get<double>(S_CG_T, NV * B) : nullptr;
+  double* V = (use_pc && keep_v) ? c->get<double>(S_CG_V, NV * B) : nullptr;
   double* s_part = c->get<double>(S_CG_PART, (size_t)R * nbs * B);
   double* s_red = c->get<double>(S_CG_SRED, (size_t)R * B);
   double* u_part = c->get<double>(S_CG_PART2, (size_t)nu * R * nbu * B);
@@ -2082,13 +1644,6 @@ std::vector<CgResult> block_cg_multi(Ctx* c, const std::vector<CgMember>& mem, c
     A.lcnt = staged ? lcnt + (size_t)m * nlb : nullptr;
     A.lslot = staged ? lslot + slot_off[m] : nullptr;
     A.nlb = (int)nlb;
-    A.block = use_blk ? 1 : 0;
-    A.nu = nu;
-    A.rt_base = rt_base;
-    A.Bt = use_blk ? p->Bt : nullptr;
-    A.Lt = use_blk ? p->Lt : nullptr;
-    A.Y = (use_blk && n1 > 0) ? p->Y : nullptr;
-    A.T = T ? T + m * NV : nullptr;
     char* mb = sb + sbytes * m;
     A.st.rz = reinterpret_cast<double*>(mb);
     A.st.rz0 = A.st.rz + 2 * (size_t)R;
@@ -2109,7 +1664,7 @@ std::vector<CgResult> block_cg_multi(Ctx* c, const std::vector<CgMember>& mem, c
   // F w products on the matrix cores (measured faster at 16 and at 32 bump
   // functions); context option "fw_mfma": -1 automatic, 0 broadcasts, 1 cores
   const bool fw = ns > 0 && n1 > 0 && (c->fw_mfma < 0 || c->fw_mfma > 0);
-  Launch L{nbs, nbu, ns, R, n1, use_pc, use_lr, B, staged, fw, use_blk, nu, seed};
+  Launch L{nbs, nbu, ns, R, n1, use_pc, use_lr, B, staged, fw};
   {
     const int64_t gx = ((int64_t)NV + 255) / 256;
     require(gx < 0x7fffffff, "n*R too large");
@@ -2239,7 +1794,7 @@ std::vector<CgResult> block_cg_multi(Ctx* c, const std::vector<CgMember>& mem, c
     res.hist_b = A.st.hist_b;
     res.col_iters = A.st.iters;
     res.not_spd = flags[3 * m + 1] != 0;
-    res.logdetM = (use_pc || use_blk) ? mem[m].pc->logdetM : 0.0;
+    res.logdetM = use_pc ? mem[m].pc->logdetM : 0.0;
     const int executed = flags[3 * m] > 0 ? flags[3 * m] : flags[3 * m + 2];
     const int lastpar = executed & 1;  // parity holding the latest state
     bool conv = true;

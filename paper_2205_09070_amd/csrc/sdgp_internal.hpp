@@ -74,7 +74,7 @@ enum Slot {
   S_RED_PART, S_RED_OUT, S_X0S, S_MISC, S_POST, S_COUNTER,
   S_CG_V, S_CG_PART2, S_CG_ARGS, S_CG_PARTG, S_CG_G, S_CG_GP, S_PC_PART, S_PC_SINV, S_LR_PART, S_LR_FX, S_LR_FV,
   S_MORTON_KEYS, S_MORTON_KEYS2, S_MORTON_IDS, S_MORTON_ORDER, S_MORTON_SZ, S_MORTON_OFF, S_SCHED,
-  S_CG_SRED, S_CG_WRED, S_CG_LNB, S_CG_LCNT, S_CG_LSLOT, S_CG_T, S_BP_POS, S_BP_BT, S_BP_LT, S_BP_Y, S_BP_LD, S_BP_BAD, S_QF, S_QM, S_KXX, S_QIV_CNT, S_QIV_PTR, S_QIV, S_QROW_NNZ, S_QROW_PTR, S_QCOL, S_QVAL,
+  S_CG_SRED, S_CG_WRED, S_CG_LNB, S_CG_LCNT, S_CG_LSLOT, S_QF, S_QM, S_KXX, S_QIV_CNT, S_QIV_PTR, S_QIV, S_QROW_NNZ, S_QROW_PTR, S_QCOL, S_QVAL,
   S_NUM
 };
 
@@ -194,12 +194,8 @@ Csr assemble_cross(Ctx* c, const Sorted& s, const KParams& kp, const Bumps& b,
 // ---------------------------------------------------------------------------
 // Solver (solve.hip)
 // ---------------------------------------------------------------------------
-// Preconditioners of the SUM combine (F: the sorted bump values).
-// Low-rank: M = c I + F F^T, Sinv = (c I + F^T F)^{-1}.
-// Block (block = 1): M = B + F F^T with B the 16 x 16 diagonal blocks of
-// the CG matrix on tiles of 16 consecutive schedule rows; Bt / Lt hold
-// B_t^{-1} and its Cholesky factor per tile in matrix-core operand order,
-// Y = B^{-1} F [n][n1], Sinv = (I + F^T Y)^{-1}.
+// Low-rank preconditioner M = c I + F F^T of the SUM combine (F: the sorted
+// bump values); Sinv = (c I + F^T F)^{-1} on the device.
 struct Precond {
   int apply = 1;        // precondition the CG with M
   int lowrank_op = 0;   // the CSR holds only the core part; A = K_core + F F^T
@@ -208,10 +204,6 @@ struct Precond {
   const double* Sinv = nullptr;
   double c = 1.0;
   double logdetM = 0.0;
-  int block = 0;
-  const double* Bt = nullptr;
-  const double* Lt = nullptr;
-  const double* Y = nullptr;
 };
 
 struct CgResult {
@@ -249,8 +241,6 @@ std::vector<CgResult> block_cg_multi(Ctx* c, const std::vector<CgMember>& mem, c
                                      int max_iter, const double* dense_rhs, int dense_R, bool keep_v,
                                      bool use_graph);
 Precond lowrank_precond(Ctx* c, const Sorted& s, const KParams& kp, const Bumps& b);
-// Block preconditioner built from the CG matrix A (precond.hip).
-Precond block_precond(Ctx* c, const Sorted& s, const Csr& A, const KParams& kp, const Bumps& b);
 void spmm(Ctx* c, const Csr& A, const double* X, int R, double* Y);
 // Y = A X for row-major [n][R] blocks with even R (16-byte aligned).
 void spmm_slab(Ctx* c, const Csr& A, const double* X, int R, double* Y);

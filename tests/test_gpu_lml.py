@@ -304,13 +304,3 @@ def test_update_products_on_matrix_cores_match_broadcasts(n1, operator):
     assert abs(i1.cg_iters - i0.cg_iters) <= 2
     assert abs(v1 - v0) <= 1e-10 * abs(v0)
     assert gu.grad_close(g1, g0, rel=1e-8).all()
-
-
-def test_block_preconditioner_option_is_rejected():
-    gu.need_gpu()
-    import paper_2205_09070_amd as sd
-    w = wl.random_small(300, 2, 2, 2, 1, combine=1, per_row=10.0)
-    c = gu.ctx()
-    with pytest.raises(sd.SdgpError) as e:
-        c.lml(w.desc, gu.dev(w.x), gu.dev(w.y), w.h, sd.estimator(probes=4, precond=sd.PRECOND_BLOCK))
-    assert e.value.status == sd.INVALID_ARG
