@@ -456,6 +456,11 @@ sdgp_status sdgp_set_option(sdgp_ctx* ctx, const char* name, int64_t value) {
     ctx->fw_mfma = (int)value;
     return SDGP_OK;
   }
+  if (k == "update_blocks") {
+    if (value < 0 || value > 65535) { ctx->err = "update_blocks must be 0 (default) .. 65535"; return SDGP_ERR_INVALID_ARG; }
+    ctx->update_blocks = (int)value;
+    return SDGP_OK;
+  }
   ctx->err = "unknown option '" + k + "'";
   return SDGP_ERR_INVALID_ARG;
 }

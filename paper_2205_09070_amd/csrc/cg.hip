@@ -40,7 +40,7 @@ constexpr int kTile = 16;        // rows per block tile (4 waves x 4 groups of 1
 constexpr int kSlab = 32;        // columns per slab
 constexpr int kSC = kSlab + 1;   // LDS stride of per-column values (slab columns + column 0)
 constexpr int kMaxNbs = 32768;   // SpMM blocks
-constexpr int kMaxNbu = 2048;    // blocks of the streaming update kernels
+constexpr int kMaxNbu = 1536;    // blocks of the update kernels: two rounds of the 768 that fit at 3 waves/SIMD
 constexpr int kLRows = 64;       // rows per block of the staged SpMM
 constexpr int kLMax = 512;       // staged neighbour rows per block (LDS: 512 x 264 B)
 constexpr int kLT = 512;         // threads per staged SpMM / build block
@@ -1565,7 +1565,8 @@ std::vector<CgResult> block_cg_multi(Ctx* c, const std::vector<CgMember>& mem, c
   const bool staged = c->staged_spmm && ns == 1;
   const int64_t nlb = (n + kLRows - 1) / kLRows;
   const int nbs = staged ? (int)round8(nlb) : (int)std::min<int64_t>(kMaxNbs, round8(tiles));
-  const int nbu = (int)std::min<int64_t>(kMaxNbu, round8(tiles));
+  const int64_t nbu_cap = c->update_blocks > 0 ? c->update_blocks : kMaxNbu;
+  const int nbu = (int)std::max<int64_t>(1, std::min<int64_t>(nbu_cap, round8(tiles)));
   require(!staged || nbs < 0x7fffffff, "too many row blocks");
   const int nu = 1 + (use_pc ? n1 : 0);
   double* X = c->get<double>(S_CG_X, NV * B);

@@ -91,6 +91,7 @@ struct Ctx {
   bool use_graph = false;        // replay captured CG iterations (hipGraph)
   bool staged_spmm = false;      // neighbourhood-staged CG SpMM when R <= 33 (opt-in)
   int fw_mfma = -1;              // F w products on the matrix cores: -1 auto, 0 off, 1 on
+  int update_blocks = 0;         // blocks of the CG update kernels (0: default cap)
   std::vector<DevBuf> member_bufs;  // per-member storage of the population path
   hipStream_t gstream = nullptr; // private default-priority stream for graph capture
   hipStream_t graph_stream() {
