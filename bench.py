@@ -46,6 +46,8 @@ def parse():
                    help="CG operator: the fully assembled sparse K, or K_core (sparse) + F F^T")
     p.add_argument("--graph", type=int, default=0,
                    help="replay the CG iterations from a HIP graph (1; the SpMM is then not timed per launch)")
+    p.add_argument("--spmm-blocks", type=int, default=0,
+                   help="grid size of the CG SpMM (multiple of 8; 0: library default)")
     p.add_argument("--update-blocks", type=int, default=0,
                    help="grid size of the CG update kernels (0: library default)")
     p.add_argument("--fw-mfma", type=int, default=-1, choices=[-1, 0, 1],
@@ -207,6 +209,7 @@ def main():
     ctx.set_option("graph", args.graph)
     ctx.set_option("fw_mfma", args.fw_mfma)
     ctx.set_option("update_blocks", args.update_blocks)
+    ctx.set_option("spmm_blocks", args.spmm_blocks)
     print("bench: N=%d dim=%d n1=%d n2=%d probes=%d" % (n, w.desc.dim, w.desc.n1, w.desc.n2, args.probes),
           file=sys.stderr, flush=True)
     for i in range(args.warmup):

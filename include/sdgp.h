@@ -156,10 +156,12 @@ sdgp_status sdgp_set_timing(sdgp_ctx* ctx, int enable);
  * in LDS (lists built once per solve); "fw_mfma" (-1 default = 1, 0, 1):
  * the preconditioner / factored-operator products
  * F w of the CG update kernels per 16-row tile on the matrix cores instead
- * of per-row broadcasts; "update_blocks" (0 default = 1536, or 1..65535):
- * the grid size of the CG update kernels (at most one block per 16 rows).
+ * of per-row broadcasts; "update_blocks" (0 default = 1024, or 1..65535):
+ * the grid size of the CG update kernels (at most one block per 16 rows);
+ * "spmm_blocks" (0 default = 32768, or a multiple of 8 up to 65535): the
+ * grid size of the CG SpMM (blocks are dealt to the 8 XCDs in turn).
  * "timing" and "graph" leave the results bitwise unchanged; "staged_spmm",
- * "fw_mfma" and "update_blocks" change only the order of floating-point sums
+ * "fw_mfma", "update_blocks" and "spmm_blocks" change only the order of floating-point sums
  * (agreement to rounding).  Unknown names or
  * values: INVALID_ARG. */
 sdgp_status sdgp_set_option(sdgp_ctx* ctx, const char* name, int64_t value);

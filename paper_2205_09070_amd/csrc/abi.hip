@@ -456,6 +456,14 @@ sdgp_status sdgp_set_option(sdgp_ctx* ctx, const char* name, int64_t value) {
     ctx->fw_mfma = (int)value;
     return SDGP_OK;
   }
+  if (k == "spmm_blocks") {
+    if (value < 0 || value > 65535 || value % 8 != 0) {
+      ctx->err = "spmm_blocks must be 0 (default) or a multiple of 8 up to 65535";
+      return SDGP_ERR_INVALID_ARG;
+    }
+    ctx->spmm_blocks = (int)value;
+    return SDGP_OK;
+  }
   if (k == "update_blocks") {
     if (value < 0 || value > 65535) { ctx->err = "update_blocks must be 0 (default) .. 65535"; return SDGP_ERR_INVALID_ARG; }
     ctx->update_blocks = (int)value;

@@ -40,7 +40,7 @@ constexpr int kTile = 16;        // rows per block tile (4 waves x 4 groups of 1
 constexpr int kSlab = 32;        // columns per slab
 constexpr int kSC = kSlab + 1;   // LDS stride of per-column values (slab columns + column 0)
 constexpr int kMaxNbs = 32768;   // SpMM blocks
-constexpr int kMaxNbu = 1536;    // blocks of the update kernels: two rounds of the 768 that fit at 3 waves/SIMD
+constexpr int kMaxNbu = 1024;    // blocks of the update kernels: the 1024 resident at 4 waves/SIMD (16 bumps)
 constexpr int kLRows = 64;       // rows per block of the staged SpMM
 constexpr int kLMax = 512;       // staged neighbour rows per block (LDS: 512 x 264 B)
 constexpr int kLT = 512;         // threads per staged SpMM / build block
@@ -844,7 +844,7 @@ constexpr int kRed = 4 * 512;   // LDS doubles for the block reductions
 // operator); r -= alpha A p; partials of r.r and F^T r.  The solution
 // update x += alpha p is left to the p-update pass, which reads p anyway.
 template <int NI, int FW>
-__global__ __launch_bounds__(kT) void k_cg_update_xr(const CgArgs* __restrict__ AA) {
+__global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(NI <= 16 ? 4 : 1))) void k_cg_update_xr(const CgArgs* __restrict__ AA) {
   constexpr int NT = (NI + 15) / 16;
   const CgArgs& A = AA[blockIdx.z];
   const Gv G = gview(A);
@@ -1019,7 +1019,7 @@ __global__ __launch_bounds__(kT) void k_cg_update_xr(const CgArgs* __restrict__ 
 // g = F^T r, u = (cI + F^T F)^{-1} g).  With the factored operator also
 // the partials of F^T p for the next iteration.
 template <int NI, int FW>
-__global__ __launch_bounds__(kT) void k_cg_update_p(const CgArgs* __restrict__ AA) {
+__global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(NI <= 16 ? 4 : 1))) void k_cg_update_p(const CgArgs* __restrict__ AA) {
   constexpr int NT = (NI + 15) / 16;
   const CgArgs& A = AA[blockIdx.z];
   const Gv G = gview(A);
@@ -1564,7 +1564,8 @@ std::vector<CgResult> block_cg_multi(Ctx* c, const std::vector<CgMember>& mem, c
   const int64_t tiles = (n + kTile - 1) / kTile;
   const bool staged = c->staged_spmm && ns == 1;
   const int64_t nlb = (n + kLRows - 1) / kLRows;
-  const int nbs = staged ? (int)round8(nlb) : (int)std::min<int64_t>(kMaxNbs, round8(tiles));
+  const int64_t nbs_cap = c->spmm_blocks > 0 ? c->spmm_blocks : kMaxNbs;
+  const int nbs = staged ? (int)round8(nlb) : (int)std::min<int64_t>(nbs_cap, round8(tiles));
   const int64_t nbu_cap = c->update_blocks > 0 ? c->update_blocks : kMaxNbu;
   const int nbu = (int)std::max<int64_t>(1, std::min<int64_t>(nbu_cap, round8(tiles)));
   require(!staged || nbs < 0x7fffffff, "too many row blocks");

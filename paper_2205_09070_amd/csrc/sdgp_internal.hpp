@@ -92,6 +92,7 @@ struct Ctx {
   bool staged_spmm = false;      // neighbourhood-staged CG SpMM when R <= 33 (opt-in)
   int fw_mfma = -1;              // F w products on the matrix cores: -1 auto, 0 off, 1 on
   int update_blocks = 0;         // blocks of the CG update kernels (0: default cap)
+  int spmm_blocks = 0;           // blocks of the CG SpMM (0: default cap; multiple of 8)
   std::vector<DevBuf> member_bufs;  // per-member storage of the population path
   hipStream_t gstream = nullptr; // private default-priority stream for graph capture
   hipStream_t graph_stream() {
