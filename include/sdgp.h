@@ -156,7 +156,8 @@ sdgp_status sdgp_set_timing(sdgp_ctx* ctx, int enable);
  * in LDS (lists built once per solve); "fw_mfma" (-1 default = 1, 0, 1):
  * the preconditioner / factored-operator products
  * F w of the CG update kernels per 16-row tile on the matrix cores instead
- * of per-row broadcasts; "update_blocks" (0 default = 1024, or 1..65535):
+ * of per-row broadcasts; "update_blocks" (0 default: one round of the
+ * blocks the GPU holds at once, from the kernels' occupancy; or 1..65535):
  * the grid size of the CG update kernels (at most one block per 16 rows);
  * "spmm_blocks" (0 default = 32768, or a multiple of 8 up to 65535): the
  * grid size of the CG SpMM (blocks are dealt to the 8 XCDs in turn).

@@ -40,7 +40,7 @@ constexpr int kTile = 16;        // rows per block tile (4 waves x 4 groups of 1
 constexpr int kSlab = 32;        // columns per slab
 constexpr int kSC = kSlab + 1;   // LDS stride of per-column values (slab columns + column 0)
 constexpr int kMaxNbs = 32768;   // SpMM blocks
-constexpr int kMaxNbu = 1024;    // blocks of the update kernels: the 1024 resident at 4 waves/SIMD (16 bumps)
+constexpr int kMaxNbu = 8192;    // upper bound on the update kernels' grid (default: one resident round)
 constexpr int kLRows = 64;       // rows per block of the staged SpMM
 constexpr int kLMax = 512;       // staged neighbour rows per block (LDS: 512 x 264 B)
 constexpr int kLT = 512;         // threads per staged SpMM / build block
@@ -844,7 +844,7 @@ constexpr int kRed = 4 * 512;   // LDS doubles for the block reductions
 // operator); r -= alpha A p; partials of r.r and F^T r.  The solution
 // update x += alpha p is left to the p-update pass, which reads p anyway.
 template <int NI, int FW>
-__global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(NI <= 16 ? 4 : 1))) void k_cg_update_xr(const CgArgs* __restrict__ AA) {
+__global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(NI <= 16 ? 4 : (NI <= 32 ? 3 : 1)))) void k_cg_update_xr(const CgArgs* __restrict__ AA) {
   constexpr int NT = (NI + 15) / 16;
   const CgArgs& A = AA[blockIdx.z];
   const Gv G = gview(A);
@@ -1019,7 +1019,7 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(NI <= 16 ? 4
 // g = F^T r, u = (cI + F^T F)^{-1} g).  With the factored operator also
 // the partials of F^T p for the next iteration.
 template <int NI, int FW>
-__global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(NI <= 16 ? 4 : 1))) void k_cg_update_p(const CgArgs* __restrict__ AA) {
+__global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(NI <= 16 ? 4 : (NI <= 32 ? 3 : 1)))) void k_cg_update_p(const CgArgs* __restrict__ AA) {
   constexpr int NT = (NI + 15) / 16;
   const CgArgs& A = AA[blockIdx.z];
   const Gv G = gview(A);
@@ -1524,6 +1524,26 @@ void cg_start(int NI, hipStream_t st, const CgArgs* dA, const Launch& L) {
 
 int64_t round8(int64_t v) { return (v + 7) / 8 * 8; }
 
+// Blocks of the update kernels resident per CU (the p-update needs at least
+// as many registers as the x/r-update); the default grid is one round of
+// them over the whole GPU.
+template <int NI>
+int update_blocks_per_cu(bool fw) {
+  int nb = 0;
+  const hipError_t e = fw ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_cg_update_p<NI, 1>, kT, 0)
+                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_cg_update_p<NI, 0>, kT, 0);
+  return (e == hipSuccess && nb > 0) ? nb : 2;
+}
+int update_blocks_per_cu(int NI, bool fw) {
+  switch (NI) {
+    case 0: return update_blocks_per_cu<0>(fw);
+    case 8: return update_blocks_per_cu<8>(fw);
+    case 16: return update_blocks_per_cu<16>(fw);
+    case 32: return update_blocks_per_cu<32>(fw);
+    default: return update_blocks_per_cu<64>(fw);
+  }
+}
+
 }  // namespace
 
 std::vector<CgResult> block_cg_multi(Ctx* c, const std::vector<CgMember>& mem, const Sorted& s, const double* ys,
@@ -1566,7 +1586,13 @@ std::vector<CgResult> block_cg_multi(Ctx* c, const std::vector<CgMember>& mem, c
   const int64_t nlb = (n + kLRows - 1) / kLRows;
   const int64_t nbs_cap = c->spmm_blocks > 0 ? c->spmm_blocks : kMaxNbs;
   const int nbs = staged ? (int)round8(nlb) : (int)std::min<int64_t>(nbs_cap, round8(tiles));
-  const int64_t nbu_cap = c->update_blocks > 0 ? c->update_blocks : kMaxNbu;
+  // F w products of the update kernels on the matrix cores (measured faster at
+  // 16 and at 32 bump functions); context option "fw_mfma": -1 automatic,
+  // 0 broadcasts, 1 cores
+  const bool fw = ns > 0 && n1 > 0 && (c->fw_mfma < 0 || c->fw_mfma > 0);
+  const int64_t nbu_cap = c->update_blocks > 0
+                              ? c->update_blocks
+                              : std::min<int64_t>(kMaxNbu, (int64_t)update_blocks_per_cu(NI, fw) * c->cu_count);
   const int nbu = (int)std::max<int64_t>(1, std::min<int64_t>(nbu_cap, round8(tiles)));
   require(!staged || nbs < 0x7fffffff, "too many row blocks");
   const int nu = 1 + (use_pc ? n1 : 0);
@@ -1663,9 +1689,6 @@ std::vector<CgResult> block_cg_multi(Ctx* c, const std::vector<CgMember>& mem, c
   }
   CgArgs* dA = c->get<CgArgs>(S_CG_ARGS, B);
   SDGP_HIP(hipMemcpyAsync(dA, hA.data(), B * sizeof(CgArgs), hipMemcpyHostToDevice, c->stream));
-  // F w products on the matrix cores (measured faster at 16 and at 32 bump
-  // functions); context option "fw_mfma": -1 automatic, 0 broadcasts, 1 cores
-  const bool fw = ns > 0 && n1 > 0 && (c->fw_mfma < 0 || c->fw_mfma > 0);
   Launch L{nbs, nbu, ns, R, n1, use_pc, use_lr, B, staged, fw};
   {
     const int64_t gx = ((int64_t)NV + 255) / 256;
