@@ -157,3 +157,67 @@ def test_assemble_rows_at_one_million_points_sampled():
     nnz = rp[-1]
     gu.log("  nnz=%d (%.1f per row)" % (nnz, nnz / n))
     assert 60 < nnz / n < 200
+
+
+def _membership_band(desc, h, x, eps=1e-9, chunk=100_000):
+    """(M_in, M_out)[a, i]: x_a inside some ball of bump function i with the
+    balls shrunk / grown by a relative eps (pairs between the two are
+    decided by rounding, and their bump values are ~0)."""
+    p = kn.unpack(desc, h)
+    n1 = max(desc.n1, 1)
+    m_in = np.zeros((x.shape[0], n1), dtype=bool)
+    m_out = np.zeros((x.shape[0], n1), dtype=bool)
+    r2 = p["r"] ** 2
+    for s in range(0, x.shape[0], chunk):
+        xc = x[s:s + chunk]
+        d2 = np.zeros((xc.shape[0], desc.n1, desc.n2))
+        for k in range(desc.dim):
+            d2 += (xc[:, k][:, None, None] - p["c"][None, :, :, k]) ** 2
+        q = d2 / r2[None]
+        m_in[s:s + chunk, :desc.n1] = (q < 1.0 - eps).any(axis=2)
+        m_out[s:s + chunk, :desc.n1] = (q < 1.0 + eps).any(axis=2)
+    return m_in, m_out
+
+
+@pytest.mark.parametrize("make", [wl.uniform3d_100k, wl.spacetime_4d], ids=["uniform3d_n100000", "spacetime4d_n5000000"])
+def test_assemble_rows_at_full_size_sampled(make):
+    """Full-size assembly of the 100,000-point 3-D workload (8x4 bumps, ~100
+    core entries per row) and of the 5,000,000-point 4-D space-time workload
+    (32x8 bumps): for sampled rows (random, inside bump balls, first and
+    last) the stored columns lie between the support predicate with the
+    radii shrunk and grown by 1e-9 (evaluated over every point), and every
+    stored value matches the oracle's kernel entry."""
+    gu.need_gpu()
+    w = make()
+    n = w.x.shape[0]
+    eps = 1e-9
+    gu.log("assemble sampled rows: %s n=%d" % (w.name, n))
+    m_in, m_out = _membership_band(w.desc, w.h, w.x, eps)
+    c = gu.ctx()
+    rp, col, val = c.kernel_assemble(w.desc, gu.dev(w.x), w.h)
+    rp = rp.cpu().numpy()
+    rng = np.random.default_rng(1)
+    in_bump = np.nonzero(m_in.any(axis=1))[0]
+    rows = np.concatenate([rng.choice(n, 16, replace=False), rng.choice(in_bump, 8, replace=False), [0, n - 1]])
+    p = kn.unpack(w.desc, w.h)
+    rc2 = p["r_core"] ** 2
+    inb = np.nonzero(m_out.any(axis=1))[0]      # the few points inside any (grown) ball
+    for a in rows:
+        lo, hi = rp[a], rp[a + 1]
+        gc = col[lo:hi].cpu().numpy()
+        gv = val[lo:hi].cpu().numpy()
+        assert np.all(np.diff(gc) > 0), "row %d columns not ascending" % a
+        d2 = kn.pair_d2(w.x[a:a + 1], w.x)[0]
+        pat_lo = d2 < rc2 * (1 - eps)
+        pat_hi = d2 < rc2 * (1 + eps)
+        pat_lo[inb] |= (m_in[a][None, :] & m_in[inb]).any(axis=1)
+        pat_hi[inb] |= (m_out[a][None, :] & m_out[inb]).any(axis=1)
+        pat_lo[a] = pat_hi[a] = True
+        got = np.zeros(n, dtype=bool)
+        got[gc] = True
+        assert not (pat_lo & ~got).any(), "row %d misses entries" % a
+        assert not (got & ~pat_hi).any(), "row %d stores entries outside the support" % a
+        krow = kn.kernel_cross(w.desc, w.h, w.x[a:a + 1], w.x[gc])[0]
+        krow[np.searchsorted(gc, a)] += p["noise_var"]
+        assert np.all(gu.check_k_entries(gv, krow, 2.0)), "row %d values" % a
+    gu.log("  nnz=%d (%.1f per row)" % (rp[-1], rp[-1] / n))
