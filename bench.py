@@ -96,7 +96,7 @@ def cpu_baseline(w):
     scaled to N by the oracle's O(N^3) cost."""
     from oracle import gp
     d = w.x.shape[1]
-    side = (2400.0 / w.x.shape[0]) ** (1.0 / d)   # about 10 s of oracle work on the host
+    side = (2800.0 / w.x.shape[0]) ** (1.0 / d)   # about 15 s of oracle work on the host
     m = np.all(w.x < side, axis=1)
     xs, ys = w.x[m], w.y[m]
     ns = xs.shape[0]
