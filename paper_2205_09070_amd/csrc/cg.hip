@@ -41,6 +41,7 @@ constexpr int kSlab = 32;        // columns per slab
 constexpr int kSC = kSlab + 1;   // LDS stride of per-column values (slab columns + column 0)
 constexpr int kMaxNbs = 32768;   // SpMM blocks
 constexpr int kMaxNbu = 8192;    // upper bound on the update kernels' grid (default: one resident round)
+constexpr int kGS = 2;           // row-steps whose loads the update passes issue together
 constexpr int kLRows = 64;       // rows per block of the staged SpMM
 constexpr int kLMax = 512;       // staged neighbour rows per block (LDS: 512 x 264 B)
 constexpr int kLT = 512;         // threads per staged SpMM / build block
@@ -102,6 +103,16 @@ __device__ __forceinline__ bool stopped(const CgArgs& A) { return *A.st.done || 
 // global; these casts let it emit global (not flat) memory instructions.
 #define GL __attribute__((address_space(1)))
 typedef double dv2 __attribute__((ext_vector_type(2)));
+
+// Slab vectors streamed through a pass (the SpMM output, the update passes'
+// vectors): every element is touched once per pass and not again until the
+// next pass, so these loads and stores carry the non-temporal hint.
+__device__ __forceinline__ dv2 ld_s(const GL double* p) {
+  return __builtin_nontemporal_load(reinterpret_cast<const GL dv2*>(p));
+}
+__device__ __forceinline__ void st_s(GL double* p, dv2 v) {
+  __builtin_nontemporal_store(v, reinterpret_cast<GL dv2*>(p));
+}
 struct Gv {
   const GL int64_t* row_ptr;
   const GL int32_t* col;
@@ -270,7 +281,7 @@ __global__ __launch_bounds__(kT) void k_cg_spmm(const CgArgs* __restrict__ AA) {
     if (kY) yacc = row16_sum(yacc);
     if (live) {
       if (kSlabs) {
-        *reinterpret_cast<GL dv2*>(Qs + a * kSlab) = q;
+        st_s(Qs + a * kSlab, q);
         const dv2 pv = *reinterpret_cast<const GL dv2*>(Ps + a * kSlab);
         pq0 += pv.x * q.x;
         pq1 += pv.y * q.y;
@@ -844,7 +855,7 @@ constexpr int kRed = 4 * 512;   // LDS doubles for the block reductions
 // operator); r -= alpha A p; partials of r.r and F^T r.  The solution
 // update x += alpha p is left to the p-update pass, which reads p anyway.
 template <int NI, int FW>
-__global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(NI <= 16 ? 4 : (NI <= 32 ? 3 : 1)))) void k_cg_update_xr(const CgArgs* __restrict__ AA) {
+__global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(NI <= 32 ? 3 : 1))) void k_cg_update_xr(const CgArgs* __restrict__ AA) {
   constexpr int NT = (NI + 15) / 16;
   const CgArgs& A = AA[blockIdx.z];
   const Gv G = gview(A);
@@ -944,36 +955,62 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(NI <= 16 ? 4
       if (base >= A.n) break;                       // uniform over the wavefront
       d4 ce = {0.0, 0.0, 0.0, 0.0}, cd = {0.0, 0.0, 0.0, 0.0}, cy = {0.0, 0.0, 0.0, 0.0};
       if (NS > 0 && lr) fw_tile_y<NS>(G.F, A.n1, A.n, base, s_gp, yfold, ce, cd, cy);
-#pragma unroll 1
-      for (int st = 0; st < 4; ++st) {
-        const int64_t a = base + 4 * st + g;
-        double ry = 0.0;
-        if (acty && jl == 0 && a < A.n) {          // column 0 of row a
-          const double qy = G.Q[a] + pick4(cy, st);
-          ry = G.Rr[a] - aly * qy;
-          G.Rr[a] = ry;
-          rry += ry * ry;
-        }
-        dv2 r = {0.0, 0.0};
-        if (a < A.n) {
-          const int64_t o = elem(A, false, a);
-          dv2 q = *reinterpret_cast<const GL dv2*>(G.Q + o);
-          r = *reinterpret_cast<const GL dv2*>(G.Rr + o);
-          q.x += pick4(ce, st);
-          q.y += pick4(cd, st);
-          r.x -= al0 * q.x;
-          r.y -= al1 * q.y;
-          *reinterpret_cast<GL dv2*>(G.Rr + o) = r;
-          rr0 += r.x * r.x;
-          rr1 += r.y * r.y;
-        }
-        if (NT > 0 && pc) {
-          double f[NT > 0 ? NT : 1];
-          load_f<NT>(A, a < A.n ? a : -1, f);
-          ft_step<NT>(f, r.x, r.y, acc);
-          if (yfold) {
+      // row-steps in pairs: both steps' loads before either step's stores,
+      // then the arithmetic in row-step order (as in the p-update pass)
 #pragma unroll
-            for (int mt = 0; mt < NT; ++mt) acc_y[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(f[mt], ry, acc_y[mt], 0, 0, 0);
+      for (int h = 0; h < 4 / kGS; ++h) {
+        int64_t ar[kGS];
+        bool in[kGS], iny[kGS];
+        dv2 qv[kGS], rv[kGS];
+        double qyv[kGS], ryv[kGS];
+        double f[kGS][NT > 0 ? NT : 1];
+#pragma unroll
+        for (int e = 0; e < kGS; ++e) {
+          const int64_t a = base + 4 * (kGS * h + e) + g;
+          ar[e] = a;
+          in[e] = a < A.n;
+          iny[e] = acty && jl == 0 && in[e];        // column 0 of row a
+          qyv[e] = iny[e] ? G.Q[a] : 0.0;
+          ryv[e] = iny[e] ? G.Rr[a] : 0.0;
+          qv[e] = rv[e] = dv2{0.0, 0.0};
+          if (in[e]) {
+            const int64_t o = elem(A, false, a);
+            qv[e] = ld_s(G.Q + o);
+            rv[e] = ld_s(G.Rr + o);
+          }
+          if (NT > 0 && pc) load_f<NT>(A, in[e] ? a : -1, f[e]);
+        }
+#pragma unroll
+        for (int e = 0; e < kGS; ++e) {
+          const int st = kGS * h + e;
+          const int64_t a = ar[e];
+          double ry = 0.0;
+          if (iny[e]) {
+            const double qy = qyv[e] + pick4(cy, st);
+            ry = ryv[e] - aly * qy;
+            G.Rr[a] = ry;
+            rry += ry * ry;
+          }
+          dv2 r = {0.0, 0.0};
+          if (in[e]) {
+            const int64_t o = elem(A, false, a);
+            dv2 q = qv[e];
+            r = rv[e];
+            q.x += pick4(ce, st);
+            q.y += pick4(cd, st);
+            r.x -= al0 * q.x;
+            r.y -= al1 * q.y;
+            st_s(G.Rr + o, r);
+            rr0 += r.x * r.x;
+            rr1 += r.y * r.y;
+          }
+          if (NT > 0 && pc) {
+            ft_step<NT>(f[e], r.x, r.y, acc);
+            if (yfold) {
+#pragma unroll
+              for (int mt = 0; mt < NT; ++mt)
+                acc_y[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(f[e][mt], ry, acc_y[mt], 0, 0, 0);
+            }
           }
         }
       }
@@ -991,13 +1028,13 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(NI <= 16 ? 4
       dv2 r = {0.0, 0.0};
       if (a >= 0) {
         const int64_t o = elem(A, false, a);
-        dv2 q = *reinterpret_cast<const GL dv2*>(G.Q + o);
-        r = *reinterpret_cast<const GL dv2*>(G.Rr + o);
+        dv2 q = ld_s(G.Q + o);
+        r = ld_s(G.Rr + o);
         q.x += c0;
         q.y += c1;
         r.x -= al0 * q.x;
         r.y -= al1 * q.y;
-        *reinterpret_cast<GL dv2*>(G.Rr + o) = r;
+        st_s(G.Rr + o, r);
         rr0 += r.x * r.x;
         rr1 += r.y * r.y;
       }
@@ -1019,7 +1056,7 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(NI <= 16 ? 4
 // g = F^T r, u = (cI + F^T F)^{-1} g).  With the factored operator also
 // the partials of F^T p for the next iteration.
 template <int NI, int FW>
-__global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(NI <= 16 ? 4 : (NI <= 32 ? 3 : 1)))) void k_cg_update_p(const CgArgs* __restrict__ AA) {
+__global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(NI <= 32 ? 3 : 1))) void k_cg_update_p(const CgArgs* __restrict__ AA) {
   constexpr int NT = (NI + 15) / 16;
   const CgArgs& A = AA[blockIdx.z];
   const Gv G = gview(A);
@@ -1126,44 +1163,72 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(NI <= 16 ? 4
       if (base >= A.n) break;                       // uniform over the wavefront
       d4 ue = {0.0, 0.0, 0.0, 0.0}, ud = {0.0, 0.0, 0.0, 0.0}, uy = {0.0, 0.0, 0.0, 0.0};
       if (NS > 0 && pc) fw_tile_y<NS>(G.F, A.n1, A.n, base, s_u, yfold, ue, ud, uy);
-#pragma unroll 1
-      for (int st = 0; st < 4; ++st) {
-        const int64_t a = base + 4 * st + g;
-        double py = 0.0;
-        if (yfold && jl == 0 && a < A.n) {         // column 0 of row a
-          py = G.P[a];
-          if (xay) G.X[a] += aly * py;
-          if (cy) {
-            const double ry = G.Rr[a];
-            const double zy = pc ? (ry - pick4(uy, st)) * A.inv_c : ry;
-            py = zy + bey * py;
-            G.P[a] = py;
-          }
-        }
-        dv2 p = {0.0, 0.0};
-        if (a < A.n) {
-          const int64_t o = elem(A, false, a);
-          const dv2 r = *reinterpret_cast<const GL dv2*>(G.Rr + o);
-          p = *reinterpret_cast<const GL dv2*>(G.P + o);
-          if (xa) {
-            dv2 x = *reinterpret_cast<const GL dv2*>(G.X + o);
-            x.x += al0 * p.x;
-            x.y += al1 * p.y;
-            *reinterpret_cast<GL dv2*>(G.X + o) = x;
-          }
-          const double z0 = pc ? (r.x - pick4(ue, st)) * A.inv_c : r.x;
-          const double z1 = pc ? (r.y - pick4(ud, st)) * A.inv_c : r.y;
-          if (c0) p.x = z0 + be0 * p.x;
-          if (c1) p.y = z1 + be1 * p.y;
-          *reinterpret_cast<GL dv2*>(G.P + o) = p;
-        }
-        if (NT > 0 && lr) {
-          double f[NT > 0 ? NT : 1];
-          load_f<NT>(A, a < A.n ? a : -1, f);
-          ft_step<NT>(f, p.x, p.y, acc);
-          if (yfold) {
+      // row-steps in pairs: both steps' loads are issued before either
+      // step's stores (the compiler cannot reorder them itself, not knowing
+      // that the rows differ), then the arithmetic in row-step order
 #pragma unroll
-            for (int mt = 0; mt < NT; ++mt) acc_y[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(f[mt], py, acc_y[mt], 0, 0, 0);
+      for (int h = 0; h < 4 / kGS; ++h) {
+        int64_t ar[kGS];
+        bool in[kGS], iny[kGS];
+        dv2 rv[kGS], pv[kGS], xv[kGS];
+        double pyv[kGS], xyv[kGS], ryv[kGS];
+        double f[kGS][NT > 0 ? NT : 1];
+#pragma unroll
+        for (int e = 0; e < kGS; ++e) {
+          const int64_t a = base + 4 * (kGS * h + e) + g;
+          ar[e] = a;
+          in[e] = a < A.n;
+          iny[e] = yfold && jl == 0 && in[e];       // column 0 of row a
+          pyv[e] = iny[e] ? G.P[a] : 0.0;
+          xyv[e] = (iny[e] && xay) ? G.X[a] : 0.0;
+          ryv[e] = (iny[e] && cy) ? G.Rr[a] : 0.0;
+          rv[e] = pv[e] = xv[e] = dv2{0.0, 0.0};
+          if (in[e]) {
+            const int64_t o = elem(A, false, a);
+            rv[e] = ld_s(G.Rr + o);
+            pv[e] = ld_s(G.P + o);
+            if (xa) xv[e] = ld_s(G.X + o);
+          }
+          if (NT > 0 && lr) load_f<NT>(A, in[e] ? a : -1, f[e]);
+        }
+#pragma unroll
+        for (int e = 0; e < kGS; ++e) {
+          const int st = kGS * h + e;
+          const int64_t a = ar[e];
+          double py = 0.0;
+          if (iny[e]) {
+            py = pyv[e];
+            if (xay) G.X[a] = xyv[e] + aly * py;
+            if (cy) {
+              const double zy = pc ? (ryv[e] - pick4(uy, st)) * A.inv_c : ryv[e];
+              py = zy + bey * py;
+              G.P[a] = py;
+            }
+          }
+          dv2 p = {0.0, 0.0};
+          if (in[e]) {
+            const int64_t o = elem(A, false, a);
+            const dv2 r = rv[e];
+            p = pv[e];
+            if (xa) {
+              dv2 x = xv[e];
+              x.x += al0 * p.x;
+              x.y += al1 * p.y;
+              st_s(G.X + o, x);
+            }
+            const double z0 = pc ? (r.x - pick4(ue, st)) * A.inv_c : r.x;
+            const double z1 = pc ? (r.y - pick4(ud, st)) * A.inv_c : r.y;
+            if (c0) p.x = z0 + be0 * p.x;
+            if (c1) p.y = z1 + be1 * p.y;
+            st_s(G.P + o, p);
+          }
+          if (NT > 0 && lr) {
+            ft_step<NT>(f[e], p.x, p.y, acc);
+            if (yfold) {
+#pragma unroll
+              for (int mt = 0; mt < NT; ++mt)
+                acc_y[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(f[e][mt], py, acc_y[mt], 0, 0, 0);
+            }
           }
         }
       }
@@ -1181,19 +1246,19 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(NI <= 16 ? 4
       dv2 p = {0.0, 0.0};
       if (a >= 0) {
         const int64_t o = elem(A, false, a);
-        const dv2 r = *reinterpret_cast<const GL dv2*>(G.Rr + o);
-        p = *reinterpret_cast<const GL dv2*>(G.P + o);
+        const dv2 r = ld_s(G.Rr + o);
+        p = ld_s(G.P + o);
         if (xa) {
-          dv2 x = *reinterpret_cast<const GL dv2*>(G.X + o);
+          dv2 x = ld_s(G.X + o);
           x.x += al0 * p.x;
           x.y += al1 * p.y;
-          *reinterpret_cast<GL dv2*>(G.X + o) = x;
+          st_s(G.X + o, x);
         }
         const double z0 = pc ? (r.x - u0) * A.inv_c : r.x;
         const double z1 = pc ? (r.y - u1) * A.inv_c : r.y;
         if (c0) p.x = z0 + be0 * p.x;
         if (c1) p.y = z1 + be1 * p.y;
-        *reinterpret_cast<GL dv2*>(G.P + o) = p;
+        st_s(G.P + o, p);
       }
       if (NT > 0 && lr) ft_step<NT>(f, p.x, p.y, acc);
     }
