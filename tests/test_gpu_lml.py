@@ -211,7 +211,7 @@ def test_preconditioned_posterior_matches():
     assert np.allclose(v.cpu().numpy(), v0, rtol=1e-7, atol=1e-10)
 
 
-@pytest.mark.parametrize("dim,n1", [(2, 3), (3, 12)])
+@pytest.mark.parametrize("dim,n1", [(2, 3), (3, 12), (3, 40)])
 def test_factored_operator_matches_oracle_and_assembled(dim, n1):
     gu.need_gpu()
     import paper_2205_09070_amd as sd
@@ -283,8 +283,9 @@ def test_staged_spmm_matches_global_gathers(operator, per_row):
     assert gu.grad_close(g1, g0, rel=1e-8).all()
 
 
-@pytest.mark.parametrize("n1,operator", [(6, 1), (20, 1), (20, 0)], ids=["n1=6-factored", "n1=20-factored",
-                                                                       "n1=20-assembled"])
+@pytest.mark.parametrize("n1,operator", [(6, 1), (20, 1), (20, 0), (40, 1), (64, 1)],
+                         ids=["n1=6-factored", "n1=20-factored", "n1=20-assembled", "n1=40-factored",
+                              "n1=64-factored"])
 def test_update_products_on_matrix_cores_match_broadcasts(n1, operator):
     """The F w products of the CG update kernels per 16-row tile on the
     matrix cores (fw_mfma = 1) agree to rounding with the per-row broadcast
