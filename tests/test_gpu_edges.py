@@ -1,0 +1,79 @@
+"""Edge cases of the LML path on the GPU, against the oracle.
+
+* No points: every entry point rejects n = 0 with INVALID_ARG before any
+  device work.
+* Tiny and ragged point counts (1, 2, 7, 17, 33: below one 16-row tile, one
+  tile plus a ragged tail, two tiles plus one row): exact mode (identity
+  probes) against the dense Cholesky oracle, for both combines; the
+  preconditioned estimator with the assembled and the factored operator
+  against the oracle's own estimator on the same probes; and a population of
+  one member against the single evaluation, bitwise."""
+import numpy as np
+import pytest
+
+from oracle import estimators as es
+from oracle import gp
+from paper_2205_09070_amd import workloads as wl
+from tests import gpu_util as gu
+
+pytestmark = pytest.mark.gpu
+
+TINY = [1, 2, 7, 17, 33]
+
+
+def _points(n, combine, seed):
+    w = wl.random_small(max(n, 2), 2, 2, 2, seed, combine=combine, per_row=8.0, noise_var=1e-2)
+    return w, w.x[:n].copy(), w.y[:n].copy()
+
+
+def test_no_points_rejected():
+    gu.need_gpu()
+    import paper_2205_09070_amd as sd
+    w, x, y = _points(5, 1, 3)
+    c = gu.ctx()
+    x0, y0 = gu.dev(x)[:0], gu.dev(y)[:0]
+    gu.log("n = 0 rejected")
+    for call in (lambda: c.lml(w.desc, x0, y0, w.h),
+                 lambda: c.lml_grad(w.desc, x0, y0, w.h),
+                 lambda: c.kernel_assemble(w.desc, x0, w.h),
+                 lambda: c.lml_grad_batched(w.desc, x0, y0, w.h[None, :])):
+        with pytest.raises(sd.SdgpError) as e:
+            call()
+        assert e.value.status == 1
+
+
+@pytest.mark.parametrize("combine", [0, 1], ids=["product", "sum"])
+@pytest.mark.parametrize("n", TINY)
+def test_tiny_exact_matches_oracle(n, combine):
+    gu.need_gpu()
+    import paper_2205_09070_amd as sd
+    w, x, y = _points(n, combine, 40 + n)
+    gu.log("tiny exact n=%d combine=%d" % (n, combine))
+    c = gu.ctx()
+    v, g, info = c.lml_grad(w.desc, gu.dev(x), gu.dev(y), w.h, sd.exact_estimator())
+    v0, g0 = gp.lml_grad(w.desc, w.h, x, y)
+    gu.log("  gpu %.15g oracle %.15g iters %d" % (v, v0, info.cg_iters))
+    assert abs(v - v0) <= gu.LML_REL * abs(v0) + 1e-12
+    assert gu.grad_close(g, g0).all()
+
+
+@pytest.mark.parametrize("operator", [0, 1], ids=["assembled", "factored"])
+@pytest.mark.parametrize("n", TINY)
+def test_tiny_preconditioned_matches_oracle_estimator(n, operator):
+    gu.need_gpu()
+    import paper_2205_09070_amd as sd
+    w, x, y = _points(n, 1, 60 + n)
+    P, seed = 4, 77
+    gu.log("tiny preconditioned n=%d operator=%d" % (n, operator))
+    c = gu.ctx()
+    est = sd.estimator(probes=P, seed=seed, cg_rtol=1e-12, cg_max_iter=1000, precond=sd.PRECOND_LOWRANK,
+                       operator_form=operator)
+    v, g, info = c.lml_grad(w.desc, gu.dev(x), gu.dev(y), w.h, est)
+    v0, g0, _, _ = es.preconditioned_lml_grad(w.desc, w.h, x, y, seed, P, 400)
+    gu.log("  gpu %.15g oracle %.15g iters %d" % (v, v0, info.cg_iters))
+    assert abs(v - v0) <= 1e-7 * abs(v0) + 1e-10
+    assert gu.grad_close(g, g0, rel=1e-6).all()
+    vb, gb, st, infos = c.lml_grad_batched(w.desc, gu.dev(x), gu.dev(y), w.h[None, :], est)
+    assert int(st[0]) == sd.OK
+    assert vb[0] == v
+    assert np.array_equal(gb[0], g)
