@@ -1,6 +1,7 @@
-"""Properties at the full 1,000,000-point 3-D workload, in the benchmark's
-launch configuration (factored operator, low-rank preconditioner, 32
-Rademacher probes, seed 1, CG rtol 1e-10): two evaluations are bitwise
+"""Properties at the full benchmark workloads (1,000,000 points in 3-D and
+5,000,000 space-time points in 4-D), in the benchmark's launch
+configuration (factored operator, low-rank preconditioner, 32 Rademacher
+probes, seed 1, CG rtol 1e-10): two evaluations are bitwise
 identical; the solve converged; the assembled operator (every entry of K
 stored, no F F^T term in the update kernels) gives the same y^T K^{-1} y
 within the bound the CG tolerance implies, and the same LML and gradient to
@@ -15,10 +16,11 @@ from tests import gpu_util as gu
 pytestmark = pytest.mark.gpu
 
 
-def test_full_size_bitwise_and_operator_forms_agree():
+@pytest.mark.parametrize("make", [wl.uniform3d_1m, wl.spacetime_4d], ids=["uniform3d_1m", "spacetime4d_5m"])
+def test_full_size_bitwise_and_operator_forms_agree(make):
     gu.need_gpu()
     import paper_2205_09070_amd as sd
-    w = wl.uniform3d_1m()
+    w = make()
     gu.log("full size: n=%d" % w.x.shape[0])
     c = gu.ctx()
     x, y = gu.dev(w.x), gu.dev(w.y)
