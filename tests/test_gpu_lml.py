@@ -232,6 +232,32 @@ def test_factored_operator_matches_oracle_and_assembled(dim, n1):
     assert gu.grad_close(gf, ga, rel=1e-8).all()
 
 
+def test_factored_operator_graph_replay_is_bitwise():
+    """CG iterations replayed from a HIP graph (8 per graph) give bitwise the
+    eager result with the factored operator, on repeated calls with other
+    stream work in between."""
+    gu.need_gpu()
+    import torch
+    import paper_2205_09070_amd as sd
+    w = wl.random_small(3000, 3, 12, 2, 44, combine=1, per_row=14.0, noise_var=1e-3)
+    gu.log("factored graph replay")
+    est = sd.estimator(probes=12, seed=8, cg_rtol=1e-11, cg_max_iter=5000, precond=sd.PRECOND_LOWRANK,
+                       operator_form=sd.OPERATOR_FACTORED)
+    c = gu.ctx()
+    x, y = gu.dev(w.x), gu.dev(w.y)
+    v0, g0, i0 = c.lml_grad(w.desc, x, y, w.h, est)
+    c.set_option("graph", 1)
+    junk = torch.randn(1 << 20, dtype=torch.float64, device="cuda:0")
+    for rep in range(3):
+        junk.mul_(1.0001).add_(1.0)
+        v1, g1, i1 = c.lml_grad(w.desc, x, y, w.h, est)
+        torch.cuda.synchronize()
+        gu.log("  replay %d: %.15g iters %d" % (rep, v1, i1.cg_iters))
+        assert v1 == v0 and np.array_equal(g1, g0)
+        assert i1.cg_iters == i0.cg_iters
+    c.set_option("graph", 0)
+
+
 def test_factored_operator_requires_preconditioner():
     gu.need_gpu()
     import paper_2205_09070_amd as sd
