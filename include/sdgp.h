@@ -153,7 +153,12 @@ sdgp_status sdgp_set_timing(sdgp_ctx* ctx, int enable);
  * iteration counters live on the device, so replays past convergence or
  * past cg_max_iter do nothing; "staged_spmm" (0/1, default 0): with at most
  * 33 right-hand sides the CG SpMM stages each 64-row block's neighbour rows
- * in LDS (lists built once per solve); "fw_mfma" (-1 default = 1, 0, 1):
+ * in LDS (lists built once per solve); "union_spmm" (0/1, default 1): the
+ * CG SpMM reads, for every 4 consecutive rows of its row order, one sorted
+ * list of the 4 rows' distinct columns with 4 values per entry (0 where a
+ * row lacks the column), so each neighbour row of P is gathered once for
+ * the 4 rows (lists built once per solve; ignored when "staged_spmm" is
+ * on); "fw_mfma" (-1 default = 1, 0, 1):
  * the preconditioner / factored-operator products
  * F w of the CG update kernels per 16-row tile on the matrix cores instead
  * of per-row broadcasts; "update_blocks" (0 default: one round of the
@@ -162,7 +167,8 @@ sdgp_status sdgp_set_timing(sdgp_ctx* ctx, int enable);
  * "spmm_blocks" (0 default = 32768, or a multiple of 8 up to 65535): the
  * grid size of the CG SpMM (blocks are dealt to the 8 XCDs in turn).
  * "timing" and "graph" leave the results bitwise unchanged; "staged_spmm",
- * "fw_mfma", "update_blocks" and "spmm_blocks" change only the order of floating-point sums
+ * "union_spmm", "fw_mfma", "update_blocks" and "spmm_blocks" change only the
+ * order of floating-point sums
  * (agreement to rounding).  Unknown names or
  * values: INVALID_ARG. */
 sdgp_status sdgp_set_option(sdgp_ctx* ctx, const char* name, int64_t value);

@@ -93,6 +93,13 @@ struct CgArgs {
   const int32_t* lcnt;
   const uint16_t* lslot;
   int nlb;                    // 64-row blocks
+  // 4-row union lists of the shared-gather SpMM: group q = schedule rows
+  // 4q .. 4q+3; entries urp[q] .. urp[q+1]-1 hold the group's distinct
+  // columns (ascending, ucol) and their 4 values (uval[4e + r] for row 4q+r,
+  // 0 where that row lacks the column)
+  const int64_t* urp;
+  const int32_t* ucol;
+  const double* uval;
   CgState st;
 };
 
@@ -298,6 +305,194 @@ __global__ __launch_bounds__(kT) void k_cg_spmm(const CgArgs* __restrict__ AA) {
       const int rc = 1 + s * kSlab + threadIdx.x;
       if (rc < A.R) G.s_part[(int64_t)rc * A.nbs + blockIdx.x] = t;
     }
+  }
+  if (kY) {
+    __syncthreads();
+    if (j == 0) redy[w * 4 + g] = pqy;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double ty = 0.0;
+      for (int q = 0; q < kTile; ++q) ty += redy[q];
+      G.s_part[blockIdx.x] = ty;
+    }
+  }
+}
+
+// ------------------------------------------------------- union-list SpMM
+// Lists of the shared-gather SpMM, built once per solve.  A group is four
+// consecutive rows of the row schedule (the four rows one wavefront of the
+// SpMM owns); its list is the merge of the four rows' ascending column lists.
+// One thread per group; k_union_count writes the list lengths, k_union_fill
+// (after a scan into urp) the columns and values.
+__device__ __forceinline__ void union_head(int64_t n, int64_t p, const int64_t* __restrict__ rp,
+                                           const int32_t* __restrict__ sched, int64_t& k, int64_t& e) {
+  k = e = 0;
+  if (p < n) {
+    const int64_t a = sched ? (int64_t)sched[p] : p;
+    k = rp[a];
+    e = rp[a + 1];
+  }
+}
+__device__ __forceinline__ int32_t head_col(int64_t k, int64_t e, const int32_t* __restrict__ col) {
+  return k < e ? col[k] : INT32_MAX;
+}
+__global__ __launch_bounds__(256) void k_union_count(int64_t n, int64_t ng, const int64_t* __restrict__ rp,
+                                                     const int32_t* __restrict__ col,
+                                                     const int32_t* __restrict__ sched, int32_t* __restrict__ cnt) {
+  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (q >= ng) return;
+  int64_t k0, e0, k1, e1, k2, e2, k3, e3;
+  union_head(n, 4 * q, rp, sched, k0, e0);
+  union_head(n, 4 * q + 1, rp, sched, k1, e1);
+  union_head(n, 4 * q + 2, rp, sched, k2, e2);
+  union_head(n, 4 * q + 3, rp, sched, k3, e3);
+  int32_t c = 0;
+  for (;;) {
+    const int32_t h0 = head_col(k0, e0, col), h1 = head_col(k1, e1, col);
+    const int32_t h2 = head_col(k2, e2, col), h3 = head_col(k3, e3, col);
+    const int32_t m = min(min(h0, h1), min(h2, h3));
+    if (m == INT32_MAX) break;
+    k0 += h0 == m;
+    k1 += h1 == m;
+    k2 += h2 == m;
+    k3 += h3 == m;
+    ++c;
+  }
+  cnt[q] = c;
+}
+__global__ __launch_bounds__(256) void k_union_fill(int64_t n, int64_t ng, const int64_t* __restrict__ rp,
+                                                    const int32_t* __restrict__ col, const double* __restrict__ val,
+                                                    const int32_t* __restrict__ sched, const int64_t* __restrict__ urp,
+                                                    int32_t* __restrict__ ucol, double* __restrict__ uval) {
+  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (q >= ng) return;
+  int64_t k0, e0, k1, e1, k2, e2, k3, e3;
+  union_head(n, 4 * q, rp, sched, k0, e0);
+  union_head(n, 4 * q + 1, rp, sched, k1, e1);
+  union_head(n, 4 * q + 2, rp, sched, k2, e2);
+  union_head(n, 4 * q + 3, rp, sched, k3, e3);
+  const int64_t u0 = urp[q], u1 = urp[q + 1];
+  for (int64_t u = u0; u < u1; ++u) {   // the merge yields exactly u1 - u0 entries (k_union_count)
+    const int32_t h0 = head_col(k0, e0, col), h1 = head_col(k1, e1, col);
+    const int32_t h2 = head_col(k2, e2, col), h3 = head_col(k3, e3, col);
+    const int32_t m = min(min(h0, h1), min(h2, h3));
+    if (m == INT32_MAX) break;
+    ucol[u] = m;
+    uval[4 * u + 0] = h0 == m ? val[k0++] : 0.0;
+    uval[4 * u + 1] = h1 == m ? val[k1++] : 0.0;
+    uval[4 * u + 2] = h2 == m ? val[k2++] : 0.0;
+    uval[4 * u + 3] = h3 == m ? val[k3++] : 0.0;
+  }
+}
+
+// One union entry for all four rows: the 16-lane group gathers the entry's
+// slab row once (lane j: columns 2j, 2j+1) and adds it, times each row's
+// value, into the four rows' accumulators.
+template <int u>
+__device__ __forceinline__ void union_step(int cj, const double* vr, const GL double* __restrict__ Xs,
+                                           double (*acc)[2]) {
+  const dv2 x = *reinterpret_cast<const GL dv2*>(Xs + (int64_t)(uint32_t)bcast16_i<u>(cj) * kSlab);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const double v = bcast16_d<u>(vr[r]);
+    acc[r][0] += v * x.x;
+    acc[r][1] += v * x.y;
+  }
+}
+template <int... us>
+__device__ __forceinline__ void union_batch(int cj, const double* vr, const GL double* __restrict__ Xs,
+                                            double (*acc)[2], std::integer_sequence<int, us...>) {
+  (union_step<us>(cj, vr, Xs, acc), ...);
+}
+
+// Q = A P over the union lists, per-block partials of p.q as in k_cg_spmm.
+// A wavefront owns the four rows of one group and walks the group's list 64
+// entries at a time (one entry per lane); each 16-lane group takes 16 of
+// them (row-broadcast of the entry's column and four values), so every
+// listed neighbour row is gathered once for the four rows.  The four groups'
+// partial sums are then added across the wavefront.  kMode 1: slab 0 and
+// column 0 (grid y = 1); kMode 2: slabs 1.. (grid y = ns - 1).  Groups are
+// dealt to the XCDs in contiguous runs (the XCD share rounded to whole
+// groups).
+template <int kMode>
+__global__ __launch_bounds__(kT) void k_cg_spmm_u(const CgArgs* __restrict__ AA) {
+  const CgArgs& A = AA[blockIdx.z];
+  const Gv G = gview(A);
+  if (stopped(A)) return;
+  constexpr bool kY = kMode == 1;
+  __shared__ double red[kTile * kSlab];
+  __shared__ double redy[kTile];
+  const GL int64_t* urp = (const GL int64_t*)A.urp;
+  const GL int32_t* ucol = (const GL int32_t*)A.ucol;
+  const GL dv2* uval = (const GL dv2*)A.uval;
+  const int lane = lane_id(), g = lane >> 4, j = lane & 15, w = threadIdx.x >> 6;
+  const int s = kMode == 2 ? (int)blockIdx.y + 1 : 0;
+  const int64_t n = A.n;
+  const int64_t so = A.ny + (int64_t)s * n * kSlab + 2 * j;
+  const GL double* Ps = G.P + so;
+  GL double* Qs = G.Q + so;
+  const int xcd = blockIdx.x & 7;
+  const int64_t bi = blockIdx.x >> 3, nbx = gridDim.x >> 3;
+  const int64_t nx = (((n + 7) >> 3) + 3) & ~(int64_t)3, lo = xcd * nx, hi = min(n, lo + nx);
+  double pq0 = 0.0, pq1 = 0.0, pqy = 0.0;
+  for (int64_t pb = lo + bi * kTile + w * 4; pb < hi; pb += nbx * kTile) {
+    const int64_t q = pb >> 2;                      // pb is a multiple of 4
+    const int64_t p = pb + g;
+    const bool live = p < hi;
+    const int64_t a = live ? (G.sched ? (int64_t)G.sched[p] : p) : 0;
+    const int32_t a0 = G.sched ? G.sched[pb] : (int32_t)pb;
+    const int64_t k0 = urp[q], k1 = urp[q + 1];
+    double acc[4][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+    double ya[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t kb = k0; kb < k1; kb += 64) {     // uniform over the wavefront
+      const int64_t k = kb + lane;
+      const bool in = k < k1;
+      const int cj = in ? ucol[k] : a0;
+      double vr[4] = {0.0, 0.0, 0.0, 0.0};
+      if (in) {
+        const dv2 v01 = uval[2 * k], v23 = uval[2 * k + 1];
+        vr[0] = v01.x;
+        vr[1] = v01.y;
+        vr[2] = v23.x;
+        vr[3] = v23.y;
+      }
+      if (kY) {
+        const double yv = G.P[cj];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) ya[r] += vr[r] * yv;
+      }
+      union_batch(cj, vr, Ps, acc, std::make_integer_sequence<int, 16>{});
+    }
+    // the four 16-lane groups' partial sums (lanes j, j+16, j+32, j+48)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      acc[r][0] += __shfl_xor(acc[r][0], 16);
+      acc[r][1] += __shfl_xor(acc[r][1], 16);
+      acc[r][0] += __shfl_xor(acc[r][0], 32);
+      acc[r][1] += __shfl_xor(acc[r][1], 32);
+      if (kY)
+        for (int o = 32; o > 0; o >>= 1) ya[r] += __shfl_xor(ya[r], o);
+    }
+    dv2 qv = {acc[0][0], acc[0][1]};
+    double yacc = ya[0];
+    if (g == 1) { qv = dv2{acc[1][0], acc[1][1]}; yacc = ya[1]; }
+    if (g == 2) { qv = dv2{acc[2][0], acc[2][1]}; yacc = ya[2]; }
+    if (g == 3) { qv = dv2{acc[3][0], acc[3][1]}; yacc = ya[3]; }
+    if (live) {
+      st_s(Qs + a * kSlab, qv);
+      const dv2 pv = *reinterpret_cast<const GL dv2*>(Ps + a * kSlab);
+      pq0 += pv.x * qv.x;
+      pq1 += pv.y * qv.y;
+      if (kY && j == 0) {
+        G.Q[a] = yacc;
+        pqy += G.P[a] * yacc;
+      }
+    }
+  }
+  const double t = tile_colsum(red, pq0, pq1);
+  if (threadIdx.x < kSlab) {
+    const int rc = 1 + s * kSlab + threadIdx.x;
+    if (rc < A.R) G.s_part[(int64_t)rc * A.nbs + blockIdx.x] = t;
   }
   if (kY) {
     __syncthreads();
@@ -1500,6 +1695,7 @@ struct Launch {
   bool use_pc, lowrank;
   int B;
   bool staged;  // neighbourhood-staged SpMM (ns == 1)
+  bool uni;     // SpMM over the 4-row union lists
   bool fw;      // F w products of the update kernels on the matrix cores
 };
 
@@ -1514,6 +1710,12 @@ void launch_iteration(hipStream_t st, const CgArgs* dA, const Launch& L, Ctx* c)
     k_cg_spmm_lds<<<dim3(L.nbs, 1, L.B), kLT, 0, st>>>(dA);
   } else if (L.ns == 0) {
     k_cg_spmm<0><<<dim3(L.nbs, 1, L.B), kT, 0, st>>>(dA);
+  } else if (L.uni) {
+    k_cg_spmm_u<1><<<dim3(L.nbs, 1, L.B), kT, 0, st>>>(dA);
+    if (L.ns > 1) {
+      SDGP_CHECK_LAUNCH();
+      k_cg_spmm_u<2><<<dim3(L.nbs, L.ns - 1, L.B), kT, 0, st>>>(dA);
+    }
   } else {
     k_cg_spmm<1><<<dim3(L.nbs, 1, L.B), kT, 0, st>>>(dA);
     if (L.ns > 1) {
@@ -1690,6 +1892,47 @@ std::vector<CgResult> block_cg_multi(Ctx* c, const std::vector<CgMember>& mem, c
       SDGP_CHECK_LAUNCH();
     }
   }
+  // 4-row union lists of the shared-gather SpMM (per member): lengths,
+  // exclusive scan on the host (once per solve), columns and values
+  const bool uni = !staged && ns > 0 && c->union_spmm;
+  const int64_t ng = (n + 3) / 4;
+  int64_t* urp = nullptr;
+  int32_t* ucol = nullptr;
+  double* uval = nullptr;
+  std::vector<int64_t> uoff(B + 1, 0);
+  if (uni) {
+    int32_t* ucnt = c->get<int32_t>(S_CG_UCNT, (size_t)ng * B);
+    const unsigned gb = (unsigned)((ng + 255) / 256);
+    for (int m = 0; m < B; ++m) {
+      k_union_count<<<gb, 256, 0, c->stream>>>(n, ng, mem[m].A.row_ptr, mem[m].A.col, s.sched,
+                                               ucnt + (size_t)m * ng);
+      SDGP_CHECK_LAUNCH();
+    }
+    std::vector<int32_t> hc((size_t)ng * B);
+    SDGP_HIP(hipMemcpyAsync(hc.data(), ucnt, hc.size() * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    SDGP_HIP(hipStreamSynchronize(c->stream));
+    std::vector<int64_t> hp((size_t)(ng + 1) * B);
+    for (int m = 0; m < B; ++m) {
+      int64_t acc = 0;
+      for (int64_t q = 0; q < ng; ++q) {
+        hp[(size_t)m * (ng + 1) + q] = acc;
+        acc += hc[(size_t)m * ng + q];
+      }
+      hp[(size_t)m * (ng + 1) + ng] = acc;
+      require(acc <= mem[m].A.nnz || mem[m].A.nnz < 0, "union lists longer than the matrix");
+      uoff[m + 1] = uoff[m] + acc;
+    }
+    urp = c->get<int64_t>(S_CG_UPTR, hp.size());
+    SDGP_HIP(hipMemcpyAsync(urp, hp.data(), hp.size() * sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
+    ucol = c->get<int32_t>(S_CG_UCOL, (size_t)std::max<int64_t>(uoff[B], 1));
+    uval = c->get<double>(S_CG_UVAL, (size_t)std::max<int64_t>(uoff[B], 1) * 4);
+    for (int m = 0; m < B; ++m) {
+      k_union_fill<<<gb, 256, 0, c->stream>>>(n, ng, mem[m].A.row_ptr, mem[m].A.col, mem[m].A.val, s.sched,
+                                              urp + (size_t)m * (ng + 1), ucol + uoff[m], uval + 4 * uoff[m]);
+      SDGP_CHECK_LAUNCH();
+    }
+    SDGP_HIP(hipStreamSynchronize(c->stream));   // hp is read by the copy above
+  }
   double* ha = c->get<double>(S_CG_HIST_A, (size_t)max_iter * R * B);
   double* hb = c->get<double>(S_CG_HIST_B, (size_t)max_iter * R * B);
   // per-member state block: doubles rz[2R], rz0[R], bnorm2[R], rr_last[R];
@@ -1737,6 +1980,9 @@ std::vector<CgResult> block_cg_multi(Ctx* c, const std::vector<CgMember>& mem, c
     A.lcnt = staged ? lcnt + (size_t)m * nlb : nullptr;
     A.lslot = staged ? lslot + slot_off[m] : nullptr;
     A.nlb = (int)nlb;
+    A.urp = uni ? urp + (size_t)m * (ng + 1) : nullptr;
+    A.ucol = uni ? ucol + uoff[m] : nullptr;
+    A.uval = uni ? uval + 4 * uoff[m] : nullptr;
     char* mb = sb + sbytes * m;
     A.st.rz = reinterpret_cast<double*>(mb);
     A.st.rz0 = A.st.rz + 2 * (size_t)R;
@@ -1754,7 +2000,7 @@ std::vector<CgResult> block_cg_multi(Ctx* c, const std::vector<CgMember>& mem, c
   }
   CgArgs* dA = c->get<CgArgs>(S_CG_ARGS, B);
   SDGP_HIP(hipMemcpyAsync(dA, hA.data(), B * sizeof(CgArgs), hipMemcpyHostToDevice, c->stream));
-  Launch L{nbs, nbu, ns, R, n1, use_pc, use_lr, B, staged, fw};
+  Launch L{nbs, nbu, ns, R, n1, use_pc, use_lr, B, staged, uni, fw};
   {
     const int64_t gx = ((int64_t)NV + 255) / 256;
     require(gx < 0x7fffffff, "n*R too large");

@@ -74,7 +74,7 @@ enum Slot {
   S_RED_PART, S_RED_OUT, S_X0S, S_MISC, S_POST, S_COUNTER,
   S_CG_V, S_CG_PART2, S_CG_ARGS, S_CG_PARTG, S_CG_G, S_CG_GP, S_PC_PART, S_PC_SINV, S_LR_PART, S_LR_FX, S_LR_FV,
   S_MORTON_KEYS, S_MORTON_KEYS2, S_MORTON_IDS, S_MORTON_ORDER, S_MORTON_SZ, S_MORTON_OFF, S_SCHED,
-  S_CG_SRED, S_CG_WRED, S_CG_LNB, S_CG_LCNT, S_CG_LSLOT, S_QF, S_QM, S_KXX, S_QIV_CNT, S_QIV_PTR, S_QIV, S_QROW_NNZ, S_QROW_PTR, S_QCOL, S_QVAL,
+  S_CG_SRED, S_CG_WRED, S_CG_LNB, S_CG_LCNT, S_CG_LSLOT, S_CG_UCNT, S_CG_UPTR, S_CG_UCOL, S_CG_UVAL, S_QF, S_QM, S_KXX, S_QIV_CNT, S_QIV_PTR, S_QIV, S_QROW_NNZ, S_QROW_PTR, S_QCOL, S_QVAL,
   S_NUM
 };
 
@@ -90,6 +90,7 @@ struct Ctx {
   int cu_count = 256;
   bool use_graph = false;        // replay captured CG iterations (hipGraph)
   bool staged_spmm = false;      // neighbourhood-staged CG SpMM when R <= 33 (opt-in)
+  bool union_spmm = true;        // CG SpMM over the 4-row union lists (shared gathers)
   int fw_mfma = -1;              // F w products on the matrix cores: -1 auto, 0 off, 1 on
   int update_blocks = 0;         // blocks of the CG update kernels (0: default cap)
   int spmm_blocks = 0;           // blocks of the CG SpMM (0: default cap; multiple of 8)
