@@ -298,7 +298,8 @@ def main():
         "solver_matrix_assembly_ms": asm_ms,
         "spmv": {"ms": spmv_ms, "GBps": spmv_gbps, "frac_hbm": spmv_gbps / HBM_PEAK_GBPS, "bytes": spmv_bytes,
                  "matrix": "full assembled K + noise (%d nnz)" % spmv_nnz},
-        "roofline": {"kernel": "k_cg_spmm (CG SpMM, %d right-hand sides)" % R, "bound": "hbm",
+        "roofline": {"kernel": "k_cg_spmm_u (CG SpMM over 4-row union lists, %d right-hand sides; "
+                               "algorithmic bytes of the CSR form)" % R, "bound": "hbm",
                      "achieved": spmm_gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": spmm_gbps / HBM_PEAK_GBPS,
                      "traffic": ((spmm_traffic(args.operator) or {}).get("GB_per_launch")
