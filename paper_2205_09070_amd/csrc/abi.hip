@@ -452,8 +452,8 @@ sdgp_status sdgp_set_option(sdgp_ctx* ctx, const char* name, int64_t value) {
   if (k == "graph") { ctx->use_graph = value != 0; return SDGP_OK; }
   if (k == "staged_spmm") { ctx->staged_spmm = value != 0; return SDGP_OK; }
   if (k == "union_spmm") {
-    if (value < 0 || value > 1) { ctx->err = "union_spmm must be 0 or 1"; return SDGP_ERR_INVALID_ARG; }
-    ctx->union_spmm = value != 0;
+    if (value < -1 || value > 1) { ctx->err = "union_spmm must be -1, 0 or 1"; return SDGP_ERR_INVALID_ARG; }
+    ctx->union_spmm = (int)value;
     return SDGP_OK;
   }
   if (k == "fw_mfma") {

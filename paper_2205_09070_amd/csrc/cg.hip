@@ -42,6 +42,7 @@ constexpr int kSC = kSlab + 1;   // LDS stride of per-column values (slab column
 constexpr int kMaxNbs = 32768;   // SpMM blocks
 constexpr int kMaxNbu = 8192;    // upper bound on the update kernels' grid (default: one resident round)
 constexpr int kGS = 2;           // row-steps whose loads the update passes issue together
+constexpr int64_t kUnionMinRows = 65536;  // union-list SpMM by default from this many rows
 constexpr int kLRows = 64;       // rows per block of the staged SpMM
 constexpr int kLMax = 512;       // staged neighbour rows per block (LDS: 512 x 264 B)
 constexpr int kLT = 512;         // threads per staged SpMM / build block
@@ -1894,7 +1895,9 @@ std::vector<CgResult> block_cg_multi(Ctx* c, const std::vector<CgMember>& mem, c
   }
   // 4-row union lists of the shared-gather SpMM (per member): lengths,
   // exclusive scan on the host (once per solve), columns and values
-  const bool uni = !staged && ns > 0 && c->union_spmm;
+  // (automatic from kUnionMinRows rows: below that, building the lists costs
+  // more than the solve saves)
+  const bool uni = !staged && ns > 0 && (c->union_spmm > 0 || (c->union_spmm < 0 && n >= kUnionMinRows));
   const int64_t ng = (n + 3) / 4;
   int64_t* urp = nullptr;
   int32_t* ucol = nullptr;

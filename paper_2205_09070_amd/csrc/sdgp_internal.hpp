@@ -90,7 +90,7 @@ struct Ctx {
   int cu_count = 256;
   bool use_graph = false;        // replay captured CG iterations (hipGraph)
   bool staged_spmm = false;      // neighbourhood-staged CG SpMM when R <= 33 (opt-in)
-  bool union_spmm = true;        // CG SpMM over the 4-row union lists (shared gathers)
+  int union_spmm = -1;           // CG SpMM over the 4-row union lists: -1 auto, 0 off, 1 on
   int fw_mfma = -1;              // F w products on the matrix cores: -1 auto, 0 off, 1 on
   int update_blocks = 0;         // blocks of the CG update kernels (0: default cap)
   int spmm_blocks = 0;           // blocks of the CG SpMM (0: default cap; multiple of 8)

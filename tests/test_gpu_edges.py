@@ -6,8 +6,9 @@
   tile plus a ragged tail, two tiles plus one row): exact mode (identity
   probes) against the dense Cholesky oracle, for both combines; the
   preconditioned estimator with the assembled and the factored operator
-  against the oracle's own estimator on the same probes; and a population of
-  one member against the single evaluation, bitwise."""
+  against the oracle's own estimator on the same probes, with the CSR and
+  with the union-list SpMM; and a population of one member against the
+  single evaluation, bitwise."""
 import numpy as np
 import pytest
 
@@ -77,3 +78,10 @@ def test_tiny_preconditioned_matches_oracle_estimator(n, operator):
     assert int(st[0]) == sd.OK
     assert vb[0] == v
     assert np.array_equal(gb[0], g)
+    # the union-list SpMM (automatic only from 65536 points) on the same
+    # tiny and ragged groups
+    c.set_option("union_spmm", 1)
+    vu, gu_, _ = c.lml_grad(w.desc, gu.dev(x), gu.dev(y), w.h, est)
+    c.set_option("union_spmm", -1)
+    assert abs(vu - v0) <= 1e-7 * abs(v0) + 1e-10
+    assert gu.grad_close(gu_, g0, rel=1e-6).all()

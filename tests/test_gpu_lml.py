@@ -235,9 +235,10 @@ def test_factored_operator_matches_oracle_and_assembled(dim, n1):
 @pytest.mark.parametrize("probes,operator,n", [(12, 1, 3001), (12, 0, 3001), (40, 1, 2999), (40, 0, 1203)],
                          ids=["1slab-factored", "1slab-assembled", "2slabs-factored", "2slabs-assembled"])
 def test_union_spmm_matches_csr_spmm(probes, operator, n):
-    """The CG SpMM over the 4-row union lists (default) agrees to rounding
-    with the CSR SpMM (union_spmm = 0), with one and with two slabs of
-    right-hand sides, on point counts that leave a ragged last group."""
+    """The CG SpMM over the 4-row union lists (union_spmm = 1; the default
+    from 65536 points) agrees to rounding with the CSR SpMM (union_spmm = 0),
+    with one and with two slabs of right-hand sides, on point counts that
+    leave a ragged last group."""
     gu.need_gpu()
     import paper_2205_09070_amd as sd
     w = wl.random_small(n, 3, 6, 2, 50 + probes, per_row=18.0, noise_var=1e-3)
@@ -249,7 +250,7 @@ def test_union_spmm_matches_csr_spmm(probes, operator, n):
     v1, g1, i1 = c.lml_grad(w.desc, x, y, w.h, est)
     c.set_option("union_spmm", 0)
     v0, g0, i0 = c.lml_grad(w.desc, x, y, w.h, est)
-    c.set_option("union_spmm", 1)
+    c.set_option("union_spmm", -1)
     gu.log("  union %.15g csr %.15g iters %d/%d" % (v1, v0, i1.cg_iters, i0.cg_iters))
     assert abs(i1.cg_iters - i0.cg_iters) <= 2
     assert abs(v1 - v0) <= 1e-10 * abs(v0)
