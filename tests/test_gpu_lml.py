@@ -151,6 +151,10 @@ def test_invalid_arguments_rejected():
         c.lml(w.desc, gu.dev(w.x), gu.dev(w.y), bad)
     with pytest.raises(sd.SdgpError):
         c.lml(w.desc, gu.dev(w.x), gu.dev(w.y), w.h, sd.estimator(probes=65))
+    for name, value in (("union_spmm", 2), ("fw_mfma", -2), ("spmm_blocks", 12), ("no_such_option", 1)):
+        with pytest.raises(sd.SdgpError) as e:
+            c.set_option(name, value)
+        assert e.value.status == 1
 
 
 def test_not_converged_reported():
