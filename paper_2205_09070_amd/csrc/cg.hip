@@ -390,9 +390,7 @@ __global__ __launch_bounds__(256) void k_union_fill(int64_t n, int64_t ng, const
 // slab row once (lane j: columns 2j, 2j+1) and adds it, times each row's
 // value, into the four rows' accumulators.
 template <int u>
-__device__ __forceinline__ void union_step(int cj, const double* vr, const GL double* __restrict__ Xs,
-                                           double (*acc)[2]) {
-  const dv2 x = *reinterpret_cast<const GL dv2*>(Xs + (int64_t)(uint32_t)bcast16_i<u>(cj) * kSlab);
+__device__ __forceinline__ void union_fma(const dv2& x, const double* vr, double (*acc)[2]) {
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const double v = bcast16_d<u>(vr[r]);
@@ -403,7 +401,10 @@ __device__ __forceinline__ void union_step(int cj, const double* vr, const GL do
 template <int... us>
 __device__ __forceinline__ void union_batch(int cj, const double* vr, const GL double* __restrict__ Xs,
                                             double (*acc)[2], std::integer_sequence<int, us...>) {
-  (union_step<us>(cj, vr, Xs, acc), ...);
+  // all 16 gathers in flight before the arithmetic
+  dv2 xv[16];
+  ((xv[us] = *reinterpret_cast<const GL dv2*>(Xs + (int64_t)(uint32_t)bcast16_i<us>(cj) * kSlab)), ...);
+  ((union_fma<us>(xv[us], vr, acc)), ...);
 }
 
 // Q = A P over the union lists, per-block partials of p.q as in k_cg_spmm.
