@@ -437,13 +437,25 @@ __global__ __launch_bounds__(kT) void k_cg_spmm_u(const CgArgs* __restrict__ AA)
   const int64_t bi = blockIdx.x >> 3, nbx = gridDim.x >> 3;
   const int64_t nx = (((n + 7) >> 3) + 3) & ~(int64_t)3, lo = xcd * nx, hi = min(n, lo + nx);
   double pq0 = 0.0, pq1 = 0.0, pqy = 0.0;
-  for (int64_t pb = lo + bi * kTile + w * 4; pb < hi; pb += nbx * kTile) {
-    const int64_t q = pb >> 2;                      // pb is a multiple of 4
+  const int64_t stride = nbx * kTile;
+  int64_t pb = lo + bi * kTile + w * 4;
+  // list bounds of the current group, those of the next one loaded a group ahead
+  int64_t k0 = 0, k1 = 0;
+  if (pb < hi) {
+    k0 = urp[pb >> 2];
+    k1 = urp[(pb >> 2) + 1];
+  }
+  for (; pb < hi; pb += stride) {
+    const int64_t pn = pb + stride;
+    int64_t k0n = 0, k1n = 0;
+    if (pn < hi) {
+      k0n = urp[pn >> 2];
+      k1n = urp[(pn >> 2) + 1];
+    }
     const int64_t p = pb + g;
     const bool live = p < hi;
     const int64_t a = live ? (G.sched ? (int64_t)G.sched[p] : p) : 0;
     const int32_t a0 = G.sched ? G.sched[pb] : (int32_t)pb;
-    const int64_t k0 = urp[q], k1 = urp[q + 1];
     double acc[4][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
     double ya[4] = {0.0, 0.0, 0.0, 0.0};
     for (int64_t kb = k0; kb < k1; kb += 64) {     // uniform over the wavefront
@@ -490,6 +502,8 @@ __global__ __launch_bounds__(kT) void k_cg_spmm_u(const CgArgs* __restrict__ AA)
         pqy += G.P[a] * yacc;
       }
     }
+    k0 = k0n;
+    k1 = k1n;
   }
   const double t = tile_colsum(red, pq0, pq1);
   if (threadIdx.x < kSlab) {
