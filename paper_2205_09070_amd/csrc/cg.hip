@@ -386,9 +386,9 @@ __global__ __launch_bounds__(256) void k_union_fill(int64_t n, int64_t ng, const
   }
 }
 
-// One union entry for all four rows: the 16-lane group gathers the entry's
-// slab row once (lane j: columns 2j, 2j+1) and adds it, times each row's
-// value, into the four rows' accumulators.
+// One union entry for all four rows: the entry's gathered slab row (lane j:
+// columns 2j, 2j+1), times each row's value (row-broadcast from the lane
+// holding the entry), is added into the four rows' accumulators.
 template <int u>
 __device__ __forceinline__ void union_fma(const dv2& x, const double* vr, double (*acc)[2]) {
 #pragma unroll
@@ -415,7 +415,8 @@ __device__ __forceinline__ void union_batch(int cj, const double* vr, const GL d
 // partial sums are then added across the wavefront.  kMode 1: slab 0 and
 // column 0 (grid y = 1); kMode 2: slabs 1.. (grid y = ns - 1).  Groups are
 // dealt to the XCDs in contiguous runs (the XCD share rounded to whole
-// groups).
+// groups); each wavefront loads the list bounds of its next group while it
+// works on the current one.
 template <int kMode>
 __global__ __launch_bounds__(kT) void k_cg_spmm_u(const CgArgs* __restrict__ AA) {
   const CgArgs& A = AA[blockIdx.z];
