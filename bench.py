@@ -168,8 +168,9 @@ def population(args, sd, wl, torch):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
-              "(see the sharding paragraph of the design notes)" % args.gpus, file=sys.stderr)
+        print("bench.py: the benchmark runs on one GPU only; --gpus %d is not supported (a multi-GPU "
+              "path would shard rows with halo exchanges of P and is not implemented)" % args.gpus,
+              file=sys.stderr)
         sys.exit(2)
     import torch
 
