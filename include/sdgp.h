@@ -154,7 +154,8 @@ sdgp_status sdgp_set_timing(sdgp_ctx* ctx, int enable);
  * past cg_max_iter do nothing; "staged_spmm" (0/1, default 0): with at most
  * 33 right-hand sides the CG SpMM stages each 64-row block's neighbour rows
  * in LDS (lists built once per solve); "union_spmm" (-1 default: on from
- * 65536 points, 0 off, 1 on): the
+ * 65536 points when the lists fit in half of the free device memory, 0 off,
+ * 1 on): the
  * CG SpMM reads, for every 4 consecutive rows of its row order, one sorted
  * list of the 4 rows' distinct columns with 4 values per entry (0 where a
  * row lacks the column), so each neighbour row of P is gathered once for

@@ -1913,24 +1913,25 @@ std::vector<CgResult> block_cg_multi(Ctx* c, const std::vector<CgMember>& mem, c
   // exclusive scan on the host (once per solve), columns and values
   // (automatic from kUnionMinRows rows: below that, building the lists costs
   // more than the solve saves)
-  const bool uni = !staged && ns > 0 && (c->union_spmm > 0 || (c->union_spmm < 0 && n >= kUnionMinRows));
+  bool uni = !staged && ns > 0 && (c->union_spmm > 0 || (c->union_spmm < 0 && n >= kUnionMinRows));
   const int64_t ng = (n + 3) / 4;
   int64_t* urp = nullptr;
   int32_t* ucol = nullptr;
   double* uval = nullptr;
   std::vector<int64_t> uoff(B + 1, 0);
+  std::vector<int64_t> hp;
+  const unsigned ugb = (unsigned)((ng + 255) / 256);
   if (uni) {
     int32_t* ucnt = c->get<int32_t>(S_CG_UCNT, (size_t)ng * B);
-    const unsigned gb = (unsigned)((ng + 255) / 256);
     for (int m = 0; m < B; ++m) {
-      k_union_count<<<gb, 256, 0, c->stream>>>(n, ng, mem[m].A.row_ptr, mem[m].A.col, s.sched,
-                                               ucnt + (size_t)m * ng);
+      k_union_count<<<ugb, 256, 0, c->stream>>>(n, ng, mem[m].A.row_ptr, mem[m].A.col, s.sched,
+                                                ucnt + (size_t)m * ng);
       SDGP_CHECK_LAUNCH();
     }
     std::vector<int32_t> hc((size_t)ng * B);
     SDGP_HIP(hipMemcpyAsync(hc.data(), ucnt, hc.size() * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
     SDGP_HIP(hipStreamSynchronize(c->stream));
-    std::vector<int64_t> hp((size_t)(ng + 1) * B);
+    hp.resize((size_t)(ng + 1) * B);
     for (int m = 0; m < B; ++m) {
       int64_t acc = 0;
       for (int64_t q = 0; q < ng; ++q) {
@@ -1941,13 +1942,22 @@ std::vector<CgResult> block_cg_multi(Ctx* c, const std::vector<CgMember>& mem, c
       require(acc <= mem[m].A.nnz || mem[m].A.nnz < 0, "union lists longer than the matrix");
       uoff[m + 1] = uoff[m] + acc;
     }
+    // the lists take 36 B per entry on top of the CSR; in automatic mode the
+    // CSR SpMM is used instead when they would take more than half of the
+    // free device memory (large populations)
+    size_t free_b = 0, total_b = 0;
+    const bool fits = hipMemGetInfo(&free_b, &total_b) != hipSuccess ||
+                      (double)uoff[B] * 36.0 + (double)hp.size() * 8.0 <= 0.5 * (double)free_b;
+    if (!fits && c->union_spmm < 0) uni = false;
+  }
+  if (uni) {
     urp = c->get<int64_t>(S_CG_UPTR, hp.size());
     SDGP_HIP(hipMemcpyAsync(urp, hp.data(), hp.size() * sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
     ucol = c->get<int32_t>(S_CG_UCOL, (size_t)std::max<int64_t>(uoff[B], 1));
     uval = c->get<double>(S_CG_UVAL, (size_t)std::max<int64_t>(uoff[B], 1) * 4);
     for (int m = 0; m < B; ++m) {
-      k_union_fill<<<gb, 256, 0, c->stream>>>(n, ng, mem[m].A.row_ptr, mem[m].A.col, mem[m].A.val, s.sched,
-                                              urp + (size_t)m * (ng + 1), ucol + uoff[m], uval + 4 * uoff[m]);
+      k_union_fill<<<ugb, 256, 0, c->stream>>>(n, ng, mem[m].A.row_ptr, mem[m].A.col, mem[m].A.val, s.sched,
+                                               urp + (size_t)m * (ng + 1), ucol + uoff[m], uval + 4 * uoff[m]);
       SDGP_CHECK_LAUNCH();
     }
     SDGP_HIP(hipStreamSynchronize(c->stream));   // hp is read by the copy above
