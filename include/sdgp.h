@@ -220,18 +220,24 @@ sdgp_status sdgp_lml(sdgp_ctx* ctx, const sdgp_kernel_desc* desc, const double* 
                      const double* y, int64_t n, const double* h,
                      const sdgp_estimator* est, double* lml_out, sdgp_info* info);
 
-/* ln L and its gradient with respect to every entry of h (grad_out: host
- * double[sdgp_num_hyper]):
+/* ln L of eqn:log_likelihood (Section 2.1, as sdgp_lml) and its gradient
+ * with respect to every entry of h -- the derivative of eqn:log_likelihood
+ * that Section 4 names as future work (gradient-based training):
  *   d lnL/d theta = 1/2 alpha^T (dA/dtheta) alpha - 1/2 tr(A^{-1} dA/dtheta),
  * alpha = A^{-1} y, the trace by Hutchinson through the probe solves, and
- * dA/dtheta recomputed per stored entry (never stored). */
+ * dA/dtheta recomputed per stored entry from the kernel of Section 2.2
+ * (eq:kstat / Wendland core, eq:bump) -- never stored.  grad_out: host
+ * double[sdgp_num_hyper(desc)] in the layout of h; lml_out: host; info:
+ * host or NULL.  Errors as sdgp_lml; grad_out NULL: INVALID_ARG. */
 sdgp_status sdgp_lml_grad(sdgp_ctx* ctx, const sdgp_kernel_desc* desc, const double* x,
                           const double* y, int64_t n, const double* h,
                           const sdgp_estimator* est, double* lml_out, double* grad_out,
                           sdgp_info* info);
 
 /* A population of B hyperparameter vectors on one shared point set
- * (Section 2.4 training repeats eqn:log_likelihood for many h): the points
+ * (Section 2.4 training repeats eqn:log_likelihood for many h).  The
+ * factored operator (operator_form = SDGP_OPERATOR_FACTORED) is rejected
+ * with INVALID_ARG before any device work.  The points
  * are ordered once (cell side = the largest core radius), every member is
  * assembled into storage of its own, and all members' block CGs advance
  * together -- every solver kernel is one launch with the member as grid

@@ -245,18 +245,6 @@ def pattern(desc, h, x):
     return pat
 
 
-def cross_pattern(desc, h, x0, x):
-    """Stored-entry predicate between test points x0 and training points x
-    (no diagonal rule: the two sets are distinct)."""
-    p = unpack(desc, h)
-    d2 = pair_d2(x0, x)
-    core = d2 < p["r_core"] ** 2
-    _, M0 = bump_F(desc, h, x0)
-    _, M = bump_F(desc, h, x)
-    bump = (M0.astype(np.int64) @ M.T.astype(np.int64)) > 0
-    return (core & bump) if desc.combine == COMBINE_PRODUCT else (core | bump)
-
-
 def kernel_cross(desc, h, xa, xb):
     """k(x_a, x_b) for two point sets (no noise)."""
     p = unpack(desc, h)

@@ -315,9 +315,14 @@ sdgp_status sdgp_lml_grad_batched(sdgp_ctx* ctx, const sdgp_kernel_desc* desc, c
     require(nh > 0, "invalid kernel descriptor");
     check_estimator(est, n);
     validate_shape(*desc, n);
-    const bool factored = est->operator_form == SDGP_OPERATOR_FACTORED;
+    // The factored operator is not available for populations: a device
+    // memory fault met by an earlier version of this path has no shown
+    // cause, so the combination is rejected rather than run.
+    require(est->operator_form != SDGP_OPERATOR_FACTORED,
+            "the factored operator is not available for populations (use SDGP_OPERATOR_ASSEMBLED)");
+    const bool factored = false;
     const bool use_pc = est->precond == SDGP_PRECOND_LOWRANK;
-    if (factored || use_pc) require(desc->combine == SDGP_COMBINE_SUM, "preconditioner/factored form need SUM");
+    if (use_pc) require(desc->combine == SDGP_COMBINE_SUM, "the low-rank preconditioner needs SUM");
     const int kind = est->kind == SDGP_PROBE_IDENTITY ? PK_IDENTITY : PK_RADEMACHER;
     const int P = kind == PK_IDENTITY ? (int)n : est->probes;
     // shared ordering: the cell side must cover every member's core radius

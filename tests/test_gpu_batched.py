@@ -54,7 +54,8 @@ def test_batched_exact_matches_oracle():
 @pytest.mark.parametrize("precond,operator", [
     (0, 0), (1, 0),
     pytest.param(1, 1, marks=pytest.mark.skip(
-        reason="met a device memory fault whose cause is not yet found; kept off the GPU until it is")),
+        reason="an earlier version of the batched factored-operator path met a device memory fault whose "
+               "cause is not shown; the library rejects that combination and the case stays off the GPU")),
 ], ids=["plain", "lowrank", "factored"])
 def test_batched_matches_single(precond, operator):
     gu.need_gpu()
@@ -78,6 +79,20 @@ def test_batched_matches_single(precond, operator):
         else:
             assert abs(v[m] - v1) <= 1e-9 * abs(v1)
             assert gu.grad_close(g[m], g1, rel=1e-7).all()
+
+
+def test_batched_factored_rejected():
+    """Populations reject the factored operator with INVALID_ARG on the
+    host, before any device work."""
+    gu.need_gpu()
+    import paper_2205_09070_amd as sd
+    w, H = population(300, 3, 2, 2, 2, 5)
+    est = sd.estimator(probes=4, seed=1, cg_rtol=1e-10, cg_max_iter=100, precond=sd.PRECOND_LOWRANK,
+                       operator_form=sd.OPERATOR_FACTORED)
+    c = gu.ctx()
+    with pytest.raises(sd.SdgpError) as e:
+        c.lml_grad_batched(w.desc, gu.dev(w.x), gu.dev(w.y), H, est)
+    assert e.value.status == sd.INVALID_ARG
 
 
 def test_graph_replay_is_bitwise():
