@@ -168,6 +168,10 @@ sdgp_status sdgp_set_timing(sdgp_ctx* ctx, int enable);
  * the grid size of the CG update kernels (at most one block per 16 rows);
  * "spmm_blocks" (0 default = 32768, or a multiple of 8 up to 65535): the
  * grid size of the CG SpMM (blocks are dealt to the 8 XCDs in turn).
+ * "workspace_cap" (bytes, 0 default = no cap): the most device workspace
+ * the context may hold; a call that would grow it further fails with
+ * SDGP_ERR_OOM before allocating (its outputs are then unspecified, the
+ * context stays usable).
  * "timing" and "graph" leave the results bitwise unchanged; "staged_spmm",
  * "union_spmm", "fw_mfma", "update_blocks" and "spmm_blocks" change only the
  * order of floating-point sums

@@ -20,6 +20,7 @@ void Ctx::release_all() {
   for (auto& b : member_bufs)
     if (b.p) { (void)hipFree(b.p); b.p = nullptr; b.bytes = 0; }
   member_bufs.clear();
+  held_bytes = 0;
   ev_used = 0;
 }
 
@@ -370,11 +371,15 @@ sdgp_status sdgp_lml_grad_batched(sdgp_ctx* ctx, const sdgp_kernel_desc* desc, c
         for (int q = 0; q < 7; ++q) off[q + 1] = off[q] + (szs[q] + 255) / 256 * 256;
         DevBuf& db = ctx->member_bufs[m];
         if (db.bytes < off[7]) {
+          if (ctx->cap_bytes > 0 && ctx->held_bytes - db.bytes + off[7] > ctx->cap_bytes)
+            throw Error(SDGP_ERR_OOM, "device workspace would exceed the context's workspace_cap");
           if (db.p) SDGP_HIP(hipFree(db.p));
+          ctx->held_bytes -= db.bytes;
           db.p = nullptr;
           db.bytes = 0;
           SDGP_HIP(hipMalloc(&db.p, off[7]));
           db.bytes = off[7];
+          ctx->held_bytes += off[7];
         }
         char* base = static_cast<char*>(db.p);
         const void* src[7] = {as.A.row_ptr, as.A.col, as.A.val, as.b.F, as.b.M, as.b.bp,
@@ -472,6 +477,11 @@ sdgp_status sdgp_set_option(sdgp_ctx* ctx, const char* name, int64_t value) {
       return SDGP_ERR_INVALID_ARG;
     }
     ctx->spmm_blocks = (int)value;
+    return SDGP_OK;
+  }
+  if (k == "workspace_cap") {
+    if (value < 0) { ctx->err = "workspace_cap must be >= 0 (0: no cap)"; return SDGP_ERR_INVALID_ARG; }
+    ctx->cap_bytes = (size_t)value;
     return SDGP_OK;
   }
   if (k == "update_blocks") {

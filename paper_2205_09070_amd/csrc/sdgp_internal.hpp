@@ -95,6 +95,10 @@ struct Ctx {
   int update_blocks = 0;         // blocks of the CG update kernels (0: default cap)
   int spmm_blocks = 0;           // blocks of the CG SpMM (0: default cap; multiple of 8)
   std::vector<DevBuf> member_bufs;  // per-member storage of the population path
+  // Workspace limit: cap_bytes > 0 makes get() refuse (SDGP_ERR_OOM) to
+  // grow the context's device workspace beyond that many bytes.
+  size_t cap_bytes = 0;
+  size_t held_bytes = 0;
   hipStream_t gstream = nullptr; // private default-priority stream for graph capture
   hipStream_t graph_stream() {
     if (!gstream) SDGP_HIP(hipStreamCreateWithFlags(&gstream, hipStreamNonBlocking));
@@ -107,12 +111,17 @@ struct Ctx {
     if (need == 0) need = sizeof(T);
     DevBuf& b = buf[s];
     if (b.bytes < need) {
+      const size_t cap = need + need / 8 + 256;
+      if (cap_bytes > 0 && held_bytes - b.bytes + cap > cap_bytes)
+        throw Error(SDGP_ERR_OOM, "device workspace would exceed the context's workspace_cap of " +
+                                      std::to_string(cap_bytes) + " bytes");
       if (b.p) SDGP_HIP(hipFree(b.p));
+      held_bytes -= b.bytes;
       b.p = nullptr;
       b.bytes = 0;
-      size_t cap = need + need / 8 + 256;
       SDGP_HIP(hipMalloc(&b.p, cap));
       b.bytes = cap;
+      held_bytes += cap;
     }
     return static_cast<T*>(b.p);
   }

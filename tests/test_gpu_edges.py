@@ -94,3 +94,28 @@ def test_tiny_preconditioned_matches_oracle_estimator(n, operator):
     c.set_option("union_spmm", -1)
     assert abs(vu - v0) <= 1e-7 * abs(v0) + 1e-10
     assert gu.grad_close(gu_, g0, rel=1e-6).all()
+
+
+def test_workspace_cap_gives_oom():
+    """A context whose workspace_cap is below what the call needs fails with
+    OOM before allocating past the cap, and works again once the cap is
+    lifted (same result as a fresh context)."""
+    gu.need_gpu()
+    import paper_2205_09070_amd as sd
+    w = wl.random_small(3000, 3, 4, 2, 5, combine=1, per_row=20.0, noise_var=1e-2)
+    est = sd.estimator(probes=8, seed=3, cg_rtol=1e-10, cg_max_iter=2000, precond=sd.PRECOND_LOWRANK)
+    gu.log("workspace cap -> OOM")
+    x, y = gu.dev(w.x), gu.dev(w.y)
+    ref = gu.ctx()
+    v0, g0, _ = ref.lml_grad(w.desc, x, y, w.h, est)
+    c = gu.ctx()
+    c.set_option("workspace_cap", 1 << 20)
+    with pytest.raises(sd.SdgpError) as e:
+        c.lml_grad(w.desc, x, y, w.h, est)
+    assert e.value.status == sd.OOM
+    assert "workspace_cap" in str(e.value)
+    c.set_option("workspace_cap", 0)
+    v1, g1, _ = c.lml_grad(w.desc, x, y, w.h, est)
+    assert v1 == v0 and np.array_equal(g1, g0)
+    with pytest.raises(sd.SdgpError):
+        c.set_option("workspace_cap", -1)
