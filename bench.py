@@ -51,6 +51,8 @@ def parse():
                    help="grid size of the CG SpMM (multiple of 8; 0: library default)")
     p.add_argument("--update-blocks", type=int, default=0,
                    help="grid size of the CG update kernels (0: library default)")
+    p.add_argument("--autotune", type=int, default=1, choices=[0, 1, 2],
+                   help="CG launch-shape autotuner (1: library default; the first warm-up step tunes)")
     p.add_argument("--fw-mfma", type=int, default=-1, choices=[-1, 0, 1],
                    help="F w products of the CG updates on the matrix cores (-1: automatic)")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -140,6 +142,9 @@ def population(args, sd, wl, torch):
     ctx.lml_grad(w.desc, x, y, H[0], est)
     ctx.set_option("graph", 1)
     ctx.lml_grad_batched(w.desc, x, y, H[:1], est)
+    # a small population first: the launch-shape tuner of the population
+    # class runs here, outside the timed call
+    ctx.lml_grad_batched(w.desc, x, y, H[:4], est)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     vb, gb, st, infos = ctx.lml_grad_batched(w.desc, x, y, H, est)
@@ -223,6 +228,7 @@ def main():
     ctx.set_option("fw_mfma", args.fw_mfma)
     ctx.set_option("update_blocks", args.update_blocks)
     ctx.set_option("spmm_blocks", args.spmm_blocks)
+    ctx.set_option("autotune", args.autotune)
     print("bench: N=%d dim=%d n1=%d n2=%d probes=%d" % (n, w.desc.dim, w.desc.n1, w.desc.n2, args.probes),
           file=sys.stderr, flush=True)
     for i in range(args.warmup):
@@ -241,6 +247,17 @@ def main():
     K = args.steps
     value = K / dt
     ms_step = 1000.0 * dt / K
+    # the same evaluation through the torch.autograd.Function path (forward
+    # + backward), timed beside the plain call
+    from paper_2205_09070_amd import autograd as sd_ag
+    h_t = torch.tensor(w.h, dtype=torch.float64, requires_grad=True)
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    out_ag = sd_ag.lml(h_t, ctx, w.desc, x, y, est)
+    out_ag.backward()
+    torch.cuda.synchronize()
+    autograd_s = time.perf_counter() - ta
+    autograd_same = bool(float(out_ag.detach()) == val and np.array_equal(h_t.grad.numpy(), g))
     # phases (mean over timed steps)
     ms = np.mean(np.array([d["ms"] for d in infos]), axis=0)
     nnz = infos[-1]["nnz"]
@@ -311,8 +328,9 @@ def main():
         "solver_matrix_assembly_ms": asm_ms,
         "spmv": {"ms": spmv_ms, "GBps": spmv_gbps, "frac_hbm": spmv_gbps / HBM_PEAK_GBPS, "bytes": spmv_bytes,
                  "matrix": "full assembled K + noise (%d nnz)" % spmv_nnz},
-        "roofline": {"kernel": "k_cg_spmm_u (CG SpMM over 4-row union lists, %d right-hand sides; "
-                               "algorithmic bytes of the CSR form)" % R, "bound": "hbm",
+        "roofline": {"kernel": ("k_cg_spmm_u (CG SpMM over 4-row union lists" if ctx.get_option("last_union_spmm")
+                               else "k_cg_spmm (CG SpMM over CSR rows") +
+                              ", %d right-hand sides; algorithmic bytes of the CSR form)" % R, "bound": "hbm",
                      "achieved": spmm_gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": spmm_gbps / HBM_PEAK_GBPS,
                      "traffic": ((spmm_traffic(args.operator) or {}).get("GB_per_launch")
@@ -321,6 +339,11 @@ def main():
                      "avg_launch_ms": spmm_avg_ms, "launches": spmm_launches,
                      "algorithmic_bytes_per_launch": spmm_bytes},
         "lml": val,
+        "autograd_path": {"s": autograd_s, "plain_s": dt / K, "bitwise_equal_to_plain": autograd_same,
+                          "note": "one evaluation through torch.autograd.Function (forward + backward) after "
+                                  "the timed steps"},
+        "cg_launch_shape": {k: ctx.get_option("last_" + k) for k in
+                            ("spmm_blocks", "update_blocks", "union_spmm", "fw_mfma", "tuned")},
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w)

@@ -168,6 +168,16 @@ sdgp_status sdgp_set_timing(sdgp_ctx* ctx, int enable);
  * the grid size of the CG update kernels (at most one block per 16 rows);
  * "spmm_blocks" (0 default = 32768, or a multiple of 8 up to 65535): the
  * grid size of the CG SpMM (blocks are dealt to the 8 XCDs in turn).
+ * "autotune" (0 off, 1 default, 2): the CG launch-shape autotuner.  The
+ * first solve of a problem class (device architecture, bump-function count
+ * class, right-hand-side slabs, single or population, log2 of the rows,
+ * entries per row in half-octaves, operator form, preconditioner) times
+ * candidate shapes -- SpMM over union lists or CSR rows, SpMM grid, update
+ * grid, F w product form -- in short trial solves of 24 CG iterations on
+ * the call's own matrix, keeps the fastest, and stores it (see
+ * sdgp_tune_cache_get); later solves of the class read it back.  1: classes
+ * from 65536 rows; 2: every solve.  Explicitly set "union_spmm", "fw_mfma",
+ * "spmm_blocks" or "update_blocks" switch the tuner off for the context.
  * "workspace_cap" (bytes, 0 default = no cap): the most device workspace
  * the context may hold; a call that would grow it further fails with
  * SDGP_ERR_OOM before allocating (its outputs are then unspecified, the
@@ -178,6 +188,25 @@ sdgp_status sdgp_set_timing(sdgp_ctx* ctx, int enable);
  * (agreement to rounding).  Unknown names or
  * values: INVALID_ARG. */
 sdgp_status sdgp_set_option(sdgp_ctx* ctx, const char* name, int64_t value);
+
+/* Reads a context option (the names of sdgp_set_option) or the launch
+ * shape of the context's last CG solve: "last_spmm_blocks",
+ * "last_update_blocks", "last_union_spmm" (0/1), "last_fw_mfma" (0/1) and
+ * "last_tuned" (0: options or defaults, 1: tuned shape read from the store,
+ * 2: tuned during that call).  value: host.  Unknown name: INVALID_ARG. */
+sdgp_status sdgp_get_option(const sdgp_ctx* ctx, const char* name, int64_t* value);
+
+/* Persistent store of the autotuner: a JSON object in the file `path`
+ * (NULL: $SDGP_TUNE_CACHE, else $HOME/.cache/sdgp/autotune.json), one entry
+ * per problem-class key, values[4] = {spmm_blocks (multiple of 8, 8..65535),
+ * update_blocks (1..65535), union_spmm (-1..1), fw_mfma (-1..1)}.  get:
+ * INVALID_ARG when the key (or the file) is missing or the entry is
+ * malformed; put: INVALID_ARG for out-of-range values, a key holding '"'
+ * or a newline, or a file that cannot be written (the entry then still
+ * serves this process).  Unparsable lines of the file are ignored; the file
+ * is replaced atomically.  Host only. */
+sdgp_status sdgp_tune_cache_get(const char* path, const char* key, int64_t* values);
+sdgp_status sdgp_tune_cache_put(const char* path, const char* key, const int64_t* values);
 
 /* 2 + n1*n2*(3+dim) + 1, or -1 for an invalid descriptor. */
 int64_t sdgp_num_hyper(const sdgp_kernel_desc* desc);

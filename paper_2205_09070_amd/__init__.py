@@ -14,7 +14,7 @@ from ._lib import (Context, SdgpError, estimator, exact_estimator, load,  # noqa
                    PROBE_IDENTITY, PROBE_RADEMACHER, PRECOND_LOWRANK, PRECOND_NONE,
                    OPERATOR_ASSEMBLED, OPERATOR_FACTORED, OK, INVALID_ARG, OOM, NOT_SPD,
                    NOT_CONVERGED, HIP, CAPACITY, DE_LML, DE_AUGMENTED, DE_CONSTRAINED, de_trials,
-                   de_select)
+                   de_select, tune_cache_get, tune_cache_put)
 
 
 def __getattr__(name):

@@ -73,6 +73,9 @@ _SIGS = {
     "sdgp_last_error": (C.c_char_p, [VP]),
     "sdgp_set_timing": (I32, [VP, C.c_int]),
     "sdgp_set_option": (I32, [VP, C.c_char_p, I64]),
+    "sdgp_get_option": (I32, [VP, C.c_char_p, C.POINTER(I64)]),
+    "sdgp_tune_cache_get": (I32, [C.c_char_p, C.c_char_p, VP]),
+    "sdgp_tune_cache_put": (I32, [C.c_char_p, C.c_char_p, VP]),
     "sdgp_num_hyper": (I64, [C.POINTER(KernelDesc)]),
     "sdgp_kernel_nnz": (I32, [VP, C.POINTER(KernelDesc), VP, I64, VP, C.POINTER(I64)]),
     "sdgp_kernel_assemble": (I32, [VP, C.POINTER(KernelDesc), VP, I64, VP, C.c_int, VP, VP, VP, I64,
@@ -120,6 +123,27 @@ def sparsity_objective(lml, s, requirement):
     if st != OK:
         raise SdgpError(st, "sdgp_sparsity_objective failed")
     return float(a.value), bool(f.value)
+
+
+def tune_cache_get(path, key):
+    """Autotuner store entry for ``key`` (host-only library call):
+    (spmm_blocks, update_blocks, union_spmm, fw_mfma), or None when absent."""
+    lib = load()
+    v = np.zeros(4, dtype=np.int64)
+    st = lib.sdgp_tune_cache_get(None if path is None else str(path).encode(), key.encode(), v.ctypes.data)
+    return None if st != OK else tuple(int(t) for t in v)
+
+
+def tune_cache_put(path, key, values):
+    """Stores an autotuner entry (host-only library call); raises on invalid
+    values or keys."""
+    lib = load()
+    v = np.ascontiguousarray(np.asarray(values, dtype=np.int64))
+    if v.shape != (4,):
+        raise ValueError("values: (spmm_blocks, update_blocks, union_spmm, fw_mfma)")
+    st = lib.sdgp_tune_cache_put(None if path is None else str(path).encode(), key.encode(), v.ctypes.data)
+    if st != OK:
+        raise SdgpError(st, "sdgp_tune_cache_put failed")
 
 
 def _f64(a):
@@ -241,6 +265,11 @@ class Context:
 
     def set_option(self, name: str, value: int):
         self._check(self.lib.sdgp_set_option(self.h, name.encode(), int(value)))
+
+    def get_option(self, name: str) -> int:
+        out = I64(0)
+        self._check(self.lib.sdgp_get_option(self.h, name.encode(), C.byref(out)))
+        return int(out.value)
 
     def num_hyper(self, desc) -> int:
         d = desc_of(desc)

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsdgp.so")
-SOURCES = ["assemble.hip", "solve.hip", "cg.hip", "adjoint.hip", "abi.hip", "train.cpp"]
+SOURCES = ["assemble.hip", "solve.hip", "cg.hip", "adjoint.hip", "abi.hip", "train.cpp", "tune.cpp"]
 ARCH = os.environ.get("SDGP_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=" + ARCH, "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

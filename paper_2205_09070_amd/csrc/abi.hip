@@ -17,9 +17,6 @@ void Ctx::release_all() {
   for (auto e : ev_pool) (void)hipEventDestroy(e);
   ev_pool.clear();
   if (gstream) { (void)hipStreamDestroy(gstream); gstream = nullptr; }
-  for (auto& b : member_bufs)
-    if (b.p) { (void)hipFree(b.p); b.p = nullptr; b.bytes = 0; }
-  member_bufs.clear();
   held_bytes = 0;
   ev_used = 0;
 }
@@ -175,7 +172,12 @@ sdgp_status sdgp_create(sdgp_ctx** out, int device, void* hip_stream) {
     c->device = device;
     c->stream = static_cast<hipStream_t>(hip_stream);
     hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->cu_count = prop.multiProcessorCount;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+      c->cu_count = prop.multiProcessorCount;
+      std::string a(prop.gcnArchName);
+      c->arch = a.substr(0, a.find(':'));
+    }
+    if (c->arch.empty()) c->arch = "unknown";
     *out = c;
     return SDGP_OK;
   } catch (const Error& e) {
@@ -337,7 +339,33 @@ sdgp_status sdgp_lml_grad_batched(sdgp_ctx* ctx, const sdgp_kernel_desc* desc, c
     Sorted s = order_points(ctx, x, n, desc->dim, rmax);
     double* ys = ctx->get<double>(S_YS, n);
     gather_vector(ctx, s, y, ys);
-    // assemble every valid member into storage of its own
+    // validate every member; the valid ones are assembled together, every
+    // assembly phase one launch with the member as grid z
+    std::vector<int> idx;
+    std::vector<const double*> hv;
+    for (int m = 0; m < B; ++m) {
+      const double* hm = H + (int64_t)m * nh;
+      if (info) std::memset(info + m, 0, sizeof(sdgp_info));
+      lml_out[m] = NAN;
+      for (int64_t k = 0; k < nh; ++k) grad_out[(int64_t)m * nh + k] = NAN;
+      try {
+        validate(*desc, hm, n);
+        idx.push_back(m);
+        hv.push_back(hm);
+        member_status[m] = SDGP_OK;
+      } catch (const Error& e) {
+        member_status[m] = e.code;
+      }
+    }
+    if (idx.empty()) return;
+    std::vector<PopAssembled> pop = assemble_population(ctx, s, *desc, hv, true);
+    std::vector<Precond> pcs;
+    std::vector<std::string> pc_failed(pop.size());
+    if (use_pc) {
+      std::vector<KParams> kps;
+      for (const auto& p : pop) kps.push_back(p.kp);
+      pcs = lowrank_precond_pop(ctx, s, kps, pop[0].b.F, &pc_failed);
+    }
     struct Member {
       int idx;
       KParams kp;
@@ -347,66 +375,19 @@ sdgp_status sdgp_lml_grad_batched(sdgp_ctx* ctx, const sdgp_kernel_desc* desc, c
       int64_t candidates;
     };
     std::vector<Member> mem;
-    ctx->member_bufs.resize(B);
-    const int n1 = desc->n1;
-    const int64_t np = (int64_t)n1 * desc->n2 * (3 + desc->dim);
-    for (int m = 0; m < B; ++m) {
-      const double* hm = H + (int64_t)m * nh;
-      if (info) std::memset(info + m, 0, sizeof(sdgp_info));
-      lml_out[m] = NAN;
-      for (int64_t k = 0; k < nh; ++k) grad_out[(int64_t)m * nh + k] = NAN;
-      try {
-        validate(*desc, hm, n);
-        Assembled as = assemble_all(ctx, s, *desc, hm, true, nullptr, factored);
-        Precond pc;
-        if (use_pc) {
-          pc = lowrank_precond(ctx, s, as.kp, as.b);
-          pc.lowrank_op = factored ? 1 : 0;
-        }
-        // member-owned copies (the context slots are reused by the next member)
-        const size_t szs[7] = {(size_t)(n + 1) * 8, (size_t)as.A.nnz * 4, (size_t)as.A.nnz * 8,
-                               (size_t)n * (n1 > 0 ? n1 : 1) * 8, (size_t)n * 8, (size_t)(np > 0 ? np : 1) * 8,
-                               (size_t)(n1 > 0 ? n1 * n1 : 1) * 8};
-        size_t off[8] = {0};
-        for (int q = 0; q < 7; ++q) off[q + 1] = off[q] + (szs[q] + 255) / 256 * 256;
-        DevBuf& db = ctx->member_bufs[m];
-        if (db.bytes < off[7]) {
-          if (ctx->cap_bytes > 0 && ctx->held_bytes - db.bytes + off[7] > ctx->cap_bytes)
-            throw Error(SDGP_ERR_OOM, "device workspace would exceed the context's workspace_cap");
-          if (db.p) SDGP_HIP(hipFree(db.p));
-          ctx->held_bytes -= db.bytes;
-          db.p = nullptr;
-          db.bytes = 0;
-          SDGP_HIP(hipMalloc(&db.p, off[7]));
-          db.bytes = off[7];
-          ctx->held_bytes += off[7];
-        }
-        char* base = static_cast<char*>(db.p);
-        const void* src[7] = {as.A.row_ptr, as.A.col, as.A.val, as.b.F, as.b.M, as.b.bp,
-                              pc.Sinv ? (const void*)pc.Sinv : nullptr};
-        for (int q = 0; q < 7; ++q)
-          if (src[q] && szs[q] > 0)
-            SDGP_HIP(hipMemcpyAsync(base + off[q], src[q], szs[q], hipMemcpyDeviceToDevice, ctx->stream));
-        Member mb;
-        mb.idx = m;
-        mb.kp = as.kp;
-        mb.A = as.A;
-        mb.A.row_ptr = reinterpret_cast<int64_t*>(base + off[0]);
-        mb.A.col = reinterpret_cast<int32_t*>(base + off[1]);
-        mb.A.val = reinterpret_cast<double*>(base + off[2]);
-        mb.b.F = reinterpret_cast<double*>(base + off[3]);
-        mb.b.M = reinterpret_cast<uint64_t*>(base + off[4]);
-        mb.b.bp = reinterpret_cast<double*>(base + off[5]);
-        mb.pc = pc;
-        mb.pc.F = mb.b.F;
-        if (pc.Sinv) mb.pc.Sinv = reinterpret_cast<double*>(base + off[6]);
-        mb.candidates = as.candidates;
-        mem.push_back(mb);
-        member_status[m] = SDGP_OK;
-      } catch (const Error& e) {
-        member_status[m] = e.code;
-        if (e.code == SDGP_ERR_HIP || e.code == SDGP_ERR_OOM) throw;
+    for (size_t q = 0; q < pop.size(); ++q) {
+      if (!pc_failed[q].empty()) {
+        member_status[idx[q]] = SDGP_ERR_INVALID_ARG;
+        continue;
       }
+      Member mb;
+      mb.idx = idx[q];
+      mb.kp = pop[q].kp;
+      mb.b = pop[q].b;
+      mb.A = pop[q].A;
+      if (use_pc) mb.pc = pcs[q];
+      mb.candidates = pop[q].candidates;
+      mem.push_back(mb);
     }
     if (mem.empty()) return;
     // one batched (preconditioned) CG for every valid member
@@ -479,6 +460,11 @@ sdgp_status sdgp_set_option(sdgp_ctx* ctx, const char* name, int64_t value) {
     ctx->spmm_blocks = (int)value;
     return SDGP_OK;
   }
+  if (k == "autotune") {
+    if (value < 0 || value > 2) { ctx->err = "autotune must be 0, 1 or 2"; return SDGP_ERR_INVALID_ARG; }
+    ctx->autotune = (int)value;
+    return SDGP_OK;
+  }
   if (k == "workspace_cap") {
     if (value < 0) { ctx->err = "workspace_cap must be >= 0 (0: no cap)"; return SDGP_ERR_INVALID_ARG; }
     ctx->cap_bytes = (size_t)value;
@@ -491,6 +477,27 @@ sdgp_status sdgp_set_option(sdgp_ctx* ctx, const char* name, int64_t value) {
   }
   ctx->err = "unknown option '" + k + "'";
   return SDGP_ERR_INVALID_ARG;
+}
+
+sdgp_status sdgp_get_option(const sdgp_ctx* ctx, const char* name, int64_t* value) {
+  if (!ctx || !name || !value) return SDGP_ERR_INVALID_ARG;
+  const std::string k(name);
+  if (k == "timing") *value = ctx->timing ? 1 : 0;
+  else if (k == "graph") *value = ctx->use_graph ? 1 : 0;
+  else if (k == "staged_spmm") *value = ctx->staged_spmm ? 1 : 0;
+  else if (k == "union_spmm") *value = ctx->union_spmm;
+  else if (k == "fw_mfma") *value = ctx->fw_mfma;
+  else if (k == "spmm_blocks") *value = ctx->spmm_blocks;
+  else if (k == "update_blocks") *value = ctx->update_blocks;
+  else if (k == "autotune") *value = ctx->autotune;
+  else if (k == "workspace_cap") *value = (int64_t)ctx->cap_bytes;
+  else if (k == "last_spmm_blocks") *value = ctx->last_shape.spmm_blocks;
+  else if (k == "last_update_blocks") *value = ctx->last_shape.update_blocks;
+  else if (k == "last_union_spmm") *value = ctx->last_shape.union_spmm;
+  else if (k == "last_fw_mfma") *value = ctx->last_shape.fw_mfma;
+  else if (k == "last_tuned") *value = ctx->last_tuned;
+  else return SDGP_ERR_INVALID_ARG;
+  return SDGP_OK;
 }
 
 sdgp_status sdgp_posterior_mean_var(sdgp_ctx* ctx, const sdgp_kernel_desc* desc, const double* x,

@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <deque>
 
 #include "kernel_math.hpp"
 #include "sdgp_internal.hpp"
@@ -144,11 +145,9 @@ __global__ void k_point_morton(const double4* __restrict__ xs, int64_t n, Morton
 // F[s, i] = sum_j a_ij exp(beta_ij - beta_ij / (1 - q_ij(x_s))) over the
 // balls that strictly contain x_s (q < 1, decided as |x-c|^2 < r^2), and the
 // membership mask M[s] (bit i: x_s inside some ball of bump function i).
-__global__ void k_bumps(const double4* __restrict__ xs, int64_t n, int dim, int n1, int n2,
-                        const double* __restrict__ bp, double* __restrict__ F,
-                        uint64_t* __restrict__ M) {
-  int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (s >= n) return;
+__device__ __forceinline__ void bumps_at(const double4* __restrict__ xs, int64_t s, int dim, int n1, int n2,
+                                         const double* __restrict__ bp, double* __restrict__ F,
+                                         uint64_t* __restrict__ M) {
   const double4 p = xs[s];
   const int stride = 3 + dim;
   uint64_t m = 0;
@@ -173,6 +172,40 @@ __global__ void k_bumps(const double4* __restrict__ xs, int64_t n, int dim, int 
   M[s] = m;
 }
 
+__global__ void k_bumps(const double4* __restrict__ xs, int64_t n, int dim, int n1, int n2,
+                        const double* __restrict__ bp, double* __restrict__ F,
+                        uint64_t* __restrict__ M) {
+  const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (s < n) bumps_at(xs, s, dim, n1, n2, bp, F, M);
+}
+
+// Per-member storage of the population assembly: every population kernel
+// runs member blockIdx.z on its own bump parameters and outputs.
+struct PopMember {
+  const double* bp;          // bump parameters
+  double* F;                 // [n, n1]
+  uint64_t* M;               // [n]
+  uint64_t* cm;              // [n_cells] cell masks
+  int32_t* run_cnt;          // [n1]
+  int32_t* run_ptr;          // [n1 + 1]
+  int2* runs;                // bump-function cell runs
+  int32_t* iv_cnt;           // [n_cells + 1]
+  const int32_t* iv_ptr;     // [n_cells + 1]
+  int2* iv;                  // candidate intervals
+  int64_t* row_nnz;          // [n + 1]
+  const int64_t* row_ptr;    // [n + 1]
+  int32_t* col;
+  double* val;
+  unsigned long long* cand;  // candidate-pair counter
+};
+
+__global__ void k_bumps_pop(const double4* __restrict__ xs, int64_t n, int dim, int n1, int n2,
+                            const PopMember* __restrict__ pm) {
+  const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const PopMember& P = pm[blockIdx.z];
+  if (s < n) bumps_at(xs, s, dim, n1, n2, P.bp, P.F, P.M);
+}
+
 // ---------------------------------------------------------------- pruning
 __global__ void k_cellmask(const int32_t* __restrict__ cell_start, int64_t n_cells,
                            const uint64_t* __restrict__ M, uint64_t* __restrict__ cm) {
@@ -183,12 +216,22 @@ __global__ void k_cellmask(const int32_t* __restrict__ cell_start, int64_t n_cel
   cm[c] = m;
 }
 
+__global__ void k_cellmask_pop(const int32_t* __restrict__ cell_start, int64_t n_cells,
+                               const PopMember* __restrict__ pm) {
+  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= n_cells) return;
+  const PopMember& P = pm[blockIdx.z];
+  uint64_t m = 0;
+  for (int32_t s = cell_start[c]; s < cell_start[c + 1]; ++s) m |= P.M[s];
+  P.cm[c] = m;
+}
+
 // Runs of consecutive cells whose mask has bit i: one block per bump
 // function scans all cells in order (count pass, then fill pass).
 template <bool kFill>
-__global__ void k_bump_runs(const uint64_t* __restrict__ cm, int64_t n_cells,
-                            int32_t* __restrict__ run_cnt, const int32_t* __restrict__ run_ptr,
-                            int2* __restrict__ runs) {
+__device__ __forceinline__ void bump_runs_body(const uint64_t* __restrict__ cm, int64_t n_cells,
+                                               int32_t* __restrict__ run_cnt, const int32_t* __restrict__ run_ptr,
+                                               int2* __restrict__ runs) {
   const int i = blockIdx.x;
   typedef hipcub::BlockScan<int, kBlock> Scan;
   __shared__ typename Scan::TempStorage tmp;
@@ -217,6 +260,19 @@ __global__ void k_bump_runs(const uint64_t* __restrict__ cm, int64_t n_cells,
     __syncthreads();
   }
   if (!kFill && threadIdx.x == 0) run_cnt[i] = base_s;
+}
+
+template <bool kFill>
+__global__ void k_bump_runs(const uint64_t* __restrict__ cm, int64_t n_cells,
+                            int32_t* __restrict__ run_cnt, const int32_t* __restrict__ run_ptr,
+                            int2* __restrict__ runs) {
+  bump_runs_body<kFill>(cm, n_cells, run_cnt, run_ptr, runs);
+}
+
+template <bool kFill>
+__global__ void k_bump_runs_pop(int64_t n_cells, const PopMember* __restrict__ pm) {
+  const PopMember& P = pm[blockIdx.z];
+  bump_runs_body<kFill>(P.cm, n_cells, P.run_cnt, P.run_ptr, P.runs);
 }
 
 struct IvArgs {
@@ -342,6 +398,28 @@ __global__ void k_cell_intervals(IvArgs A, int32_t* __restrict__ iv_cnt,
   if (!kFill) iv_cnt[c] = cnt;
 }
 
+// Population form: member z's intervals with its own masks and runs (the
+// cell grid is shared).
+template <bool kFill>
+__global__ void k_cell_intervals_pop(IvArgs A, const PopMember* __restrict__ pm) {
+  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= A.g.n_cells) return;
+  const PopMember& P = pm[blockIdx.z];
+  A.cm = P.cm;
+  if (A.use_bumps) {
+    A.run_ptr = P.run_ptr;
+    A.runs = P.runs;
+  }
+  int cc[kMaxDim];
+  {
+    int64_t r = c;
+    for (int k = 0; k < A.g.dim; ++k) { cc[k] = (int)(r % A.g.G[k]); r /= A.g.G[k]; }
+  }
+  const uint64_t mask = A.use_bumps ? A.cm[c] : 0ull;
+  const int cnt = merge_intervals<kFill>(A, cc, mask, kFill ? P.iv + P.iv_ptr[c] : nullptr);
+  if (!kFill) P.iv_cnt[c] = cnt;
+}
+
 // Candidate intervals of test points: the clamped cell of each point (a
 // training point within the core radius lies at most one cell away per axis
 // also after clamping) and the bump functions whose support holds the point.
@@ -387,10 +465,10 @@ constexpr int kCRows = 1024;  // rows per row group
 constexpr int kCSeg = 64;     // interval pieces per chunk
 
 template <bool kFill>
-__global__ __launch_bounds__(kBlock) void k_cell_rows(RowArgs A, int64_t* __restrict__ row_nnz,
-                                                      unsigned long long* __restrict__ cand_total,
-                                                      const int64_t* __restrict__ row_ptr,
-                                                      int32_t* __restrict__ col, double* __restrict__ val) {
+__device__ __forceinline__ void cell_rows_body(const RowArgs& A, int64_t* __restrict__ row_nnz,
+                                               unsigned long long* __restrict__ cand_total,
+                                               const int64_t* __restrict__ row_ptr,
+                                               int32_t* __restrict__ col, double* __restrict__ val) {
   __shared__ double4 sx[kCC];
   __shared__ uint64_t sm[kCC];
   __shared__ int32_t sb[kCC];
@@ -497,6 +575,33 @@ __global__ __launch_bounds__(kBlock) void k_cell_rows(RowArgs A, int64_t* __rest
     for (int32_t q = i0; q < i1; ++q) cnt += (unsigned long long)(A.iv[q].y - A.iv[q].x);
     atomicAdd(cand_total, cnt * (unsigned long long)(r1 - r0));
   }
+}
+
+template <bool kFill>
+__global__ __launch_bounds__(kBlock) void k_cell_rows(RowArgs A, int64_t* __restrict__ row_nnz,
+                                                      unsigned long long* __restrict__ cand_total,
+                                                      const int64_t* __restrict__ row_ptr,
+                                                      int32_t* __restrict__ col, double* __restrict__ val) {
+  cell_rows_body<kFill>(A, row_nnz, cand_total, row_ptr, col, val);
+}
+
+// Population form: member z's rows (RowArgs[z] holds its kernel
+// parameters and inputs, PopMember[z] its outputs).
+template <bool kFill>
+__global__ __launch_bounds__(kBlock) void k_cell_rows_pop(const RowArgs* __restrict__ ra,
+                                                          const PopMember* __restrict__ pm) {
+  const PopMember& P = pm[blockIdx.z];
+  cell_rows_body<kFill>(ra[blockIdx.z], P.row_nnz, P.cand, P.row_ptr, P.col, P.val);
+}
+
+// row_ptr of every member from one scan over the members' concatenated
+// count arrays (each [n + 1] with a zero last entry): subtract the
+// member's base.
+__global__ void k_rebase_pop(const int64_t* __restrict__ scan, int64_t n, int64_t* __restrict__ out) {
+  const int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (a > n) return;
+  const int64_t o = (int64_t)blockIdx.z * (n + 1);
+  out[o + a] = scan[o + a] - scan[o];
 }
 
 
@@ -875,6 +980,188 @@ Csr assemble_sorted(Ctx* c, const Sorted& s, const KParams& kp, const Bumps& b, 
   Csr k;
   k.n = n; k.nnz = nnz; k.row_ptr = row_ptr; k.col = col; k.val = val;
   return k;
+}
+
+std::vector<PopAssembled> assemble_population(Ctx* c, const Sorted& s, const sdgp_kernel_desc& d,
+                                              const std::vector<const double*>& h, bool add_noise) {
+  const int B = (int)h.size();
+  require(B >= 1 && B <= 65535, "1..65535 members");
+  const int64_t n = s.n;
+  const int64_t nc = s.grid.n_cells;
+  require(nc < 0x7fffffff, "too many cells");
+  const int n1 = d.n1;
+  const int n1s = n1 > 0 ? n1 : 1;
+  const int64_t np = (int64_t)n1 * d.n2 * (3 + d.dim);
+  const int64_t nps = np > 0 ? np : 1;
+  std::vector<PopAssembled> out(B);
+  std::vector<double> hbp((size_t)B * nps, 0.0);
+  for (int m = 0; m < B; ++m) {
+    out[m].kp = make_params(d, h[m]);
+    for (int64_t k = 0; k < np; ++k) hbp[(size_t)m * nps + k] = h[m][2 + k];
+  }
+  double* bp = c->get<double>(S_POP_BP, hbp.size());
+  SDGP_HIP(hipMemcpyAsync(bp, hbp.data(), hbp.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  double* F = c->get<double>(S_POP_F, (size_t)B * n * n1s);
+  uint64_t* M = c->get<uint64_t>(S_POP_M, (size_t)B * n);
+  uint64_t* cm = c->get<uint64_t>(S_POP_CM, (size_t)B * nc);
+  std::vector<PopMember> pm(B);
+  for (int m = 0; m < B; ++m) {
+    PopMember& P = pm[m];
+    std::memset(&P, 0, sizeof(P));
+    P.bp = bp + (size_t)m * nps;
+    P.F = F + (size_t)m * n * n1s;
+    P.M = M + (size_t)m * n;
+    P.cm = cm + (size_t)m * nc;
+    out[m].b.bp = const_cast<double*>(P.bp);
+    out[m].b.F = P.F;
+    out[m].b.M = P.M;
+  }
+  PopMember* dpm = c->get<PopMember>(S_POP_ARGS, B);
+  // each upload copies from a snapshot that lives until the function's
+  // last synchronisation, so pm may change while a copy is pending
+  std::deque<std::vector<PopMember>> snaps;
+  auto upload = [&]() {
+    snaps.push_back(pm);
+    SDGP_HIP(hipMemcpyAsync(dpm, snaps.back().data(), B * sizeof(PopMember), hipMemcpyHostToDevice, c->stream));
+  };
+  upload();
+  const unsigned gn = (unsigned)grid_for(n, kBlock), gc = (unsigned)grid_for(nc, kBlock);
+  // bump values and masks, cell masks
+  k_bumps_pop<<<dim3(gn, 1, B), kBlock, 0, c->stream>>>(s.xs, n, d.dim, n1, d.n2, dpm);
+  SDGP_CHECK_LAUNCH();
+  k_cellmask_pop<<<dim3(gc, 1, B), kBlock, 0, c->stream>>>(s.cell_start, nc, dpm);
+  SDGP_CHECK_LAUNCH();
+  // bump-function cell runs (SUM)
+  IvArgs A;
+  A.g = s.grid;
+  A.cell_start = s.cell_start;
+  A.cm = nullptr;
+  A.run_ptr = nullptr;
+  A.runs = nullptr;
+  A.use_bumps = (d.combine == SDGP_COMBINE_SUM && n1 > 0) ? 1 : 0;
+  if (A.use_bumps) {
+    int32_t* run_cnt = c->get<int32_t>(S_POP_RUNCNT, (size_t)B * n1);
+    for (int m = 0; m < B; ++m) pm[m].run_cnt = run_cnt + (size_t)m * n1;
+    upload();
+    k_bump_runs_pop<false><<<dim3(n1, 1, B), kBlock, 0, c->stream>>>(nc, dpm);
+    SDGP_CHECK_LAUNCH();
+    std::vector<int32_t> cnt((size_t)B * n1);
+    SDGP_HIP(hipMemcpyAsync(cnt.data(), run_cnt, cnt.size() * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    SDGP_HIP(hipStreamSynchronize(c->stream));
+    std::vector<int32_t> ptr((size_t)B * (n1 + 1), 0);
+    int64_t total = 0;
+    for (int m = 0; m < B; ++m) {
+      int32_t acc = 0;
+      for (int i = 0; i < n1; ++i) {
+        ptr[(size_t)m * (n1 + 1) + i] = acc;
+        acc += cnt[(size_t)m * n1 + i];
+      }
+      ptr[(size_t)m * (n1 + 1) + n1] = acc;
+      total += acc;
+    }
+    int32_t* run_ptr = c->get<int32_t>(S_POP_RUNPTR, ptr.size());
+    SDGP_HIP(hipMemcpyAsync(run_ptr, ptr.data(), ptr.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
+    int2* runs = c->get<int2>(S_POP_RUNS, (size_t)std::max<int64_t>(total, 1));
+    int64_t off = 0;
+    for (int m = 0; m < B; ++m) {
+      pm[m].run_ptr = run_ptr + (size_t)m * (n1 + 1);
+      pm[m].runs = runs + off;
+      off += ptr[(size_t)m * (n1 + 1) + n1];
+    }
+    upload();
+    k_bump_runs_pop<true><<<dim3(n1, 1, B), kBlock, 0, c->stream>>>(nc, dpm);
+    SDGP_CHECK_LAUNCH();
+  }
+  // candidate intervals per cell: counts, one scan over all members'
+  // concatenated counts (global offsets into one interval array), fill
+  int32_t* iv_cnt = c->get<int32_t>(S_POP_IVCNT, (size_t)B * (nc + 1));
+  SDGP_HIP(hipMemsetAsync(iv_cnt, 0, (size_t)B * (nc + 1) * sizeof(int32_t), c->stream));
+  int32_t* iv_ptr = c->get<int32_t>(S_POP_IVPTR, (size_t)B * (nc + 1));
+  for (int m = 0; m < B; ++m) {
+    pm[m].iv_cnt = iv_cnt + (size_t)m * (nc + 1);
+    pm[m].iv_ptr = iv_ptr + (size_t)m * (nc + 1);
+  }
+  upload();
+  k_cell_intervals_pop<false><<<dim3(gc, 1, B), kBlock, 0, c->stream>>>(A, dpm);
+  SDGP_CHECK_LAUNCH();
+  require((int64_t)B * (nc + 1) < 0x7fffffffLL, "population too large for one interval scan");
+  {
+    size_t tb = 0;
+    SDGP_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, iv_cnt, iv_ptr, (int)(B * (nc + 1)), c->stream));
+    void* tmp = c->get<char>(S_SORT_TMP, tb);
+    SDGP_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, tb, iv_cnt, iv_ptr, (int)(B * (nc + 1)), c->stream));
+  }
+  int32_t iv_total = 0;
+  SDGP_HIP(hipMemcpyAsync(&iv_total, iv_ptr + (size_t)B * (nc + 1) - 1, sizeof(int32_t), hipMemcpyDeviceToHost,
+                          c->stream));
+  SDGP_HIP(hipStreamSynchronize(c->stream));
+  require(iv_total >= 0, "too many candidate intervals");
+  int2* iv = c->get<int2>(S_POP_IV, (size_t)std::max<int32_t>(iv_total, 1));
+  for (int m = 0; m < B; ++m) pm[m].iv = iv;
+  upload();
+  k_cell_intervals_pop<true><<<dim3(gc, 1, B), kBlock, 0, c->stream>>>(A, dpm);
+  SDGP_CHECK_LAUNCH();
+  // count: row lengths of every member; one scan; row pointers rebased per
+  // member so that each member's CSR starts at 0
+  int64_t* row_nnz = c->get<int64_t>(S_POP_ROWNNZ, (size_t)B * (n + 1));
+  SDGP_HIP(hipMemsetAsync(row_nnz, 0, (size_t)B * (n + 1) * sizeof(int64_t), c->stream));
+  unsigned long long* cand = c->get<unsigned long long>(S_POP_CAND, B);
+  SDGP_HIP(hipMemsetAsync(cand, 0, B * sizeof(unsigned long long), c->stream));
+  std::vector<RowArgs> ra(B);
+  for (int m = 0; m < B; ++m) {
+    Bumps bm;
+    bm.F = pm[m].F;
+    bm.M = pm[m].M;
+    bm.bp = const_cast<double*>(pm[m].bp);
+    ra[m] = row_args(s, out[m].kp, bm, pm[m].iv_ptr, iv, add_noise, false);
+    pm[m].row_nnz = row_nnz + (size_t)m * (n + 1);
+    pm[m].cand = cand + m;
+  }
+  RowArgs* dra = c->get<RowArgs>(S_POP_RARGS, B);
+  SDGP_HIP(hipMemcpyAsync(dra, ra.data(), B * sizeof(RowArgs), hipMemcpyHostToDevice, c->stream));
+  upload();
+  k_cell_rows_pop<false><<<dim3((unsigned)nc, 1, B), kBlock, 0, c->stream>>>(dra, dpm);
+  SDGP_CHECK_LAUNCH();
+  int64_t* scan = c->get<int64_t>(S_POP_SCAN, (size_t)B * (n + 1));
+  require((int64_t)B * (n + 1) < 0x7fffffffLL, "population too large for one row scan");
+  {
+    size_t tb = 0;
+    SDGP_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, row_nnz, scan, (int)(B * (n + 1)), c->stream));
+    void* tmp = c->get<char>(S_SORT_TMP, tb);
+    SDGP_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, tb, row_nnz, scan, (int)(B * (n + 1)), c->stream));
+  }
+  int64_t* row_ptr = c->get<int64_t>(S_POP_ROWPTR, (size_t)B * (n + 1));
+  k_rebase_pop<<<dim3((unsigned)grid_for(n + 1, kBlock), 1, B), kBlock, 0, c->stream>>>(scan, n, row_ptr);
+  SDGP_CHECK_LAUNCH();
+  std::vector<int64_t> base((size_t)B + 1);
+  for (int m = 0; m < B; ++m)
+    SDGP_HIP(hipMemcpyAsync(&base[m], scan + (size_t)m * (n + 1), sizeof(int64_t), hipMemcpyDeviceToHost,
+                            c->stream));
+  SDGP_HIP(hipMemcpyAsync(&base[B], scan + (size_t)B * (n + 1) - 1, sizeof(int64_t), hipMemcpyDeviceToHost,
+                          c->stream));
+  std::vector<unsigned long long> hcand(B);
+  SDGP_HIP(hipMemcpyAsync(hcand.data(), cand, B * sizeof(unsigned long long), hipMemcpyDeviceToHost, c->stream));
+  SDGP_HIP(hipStreamSynchronize(c->stream));
+  const int64_t total = base[B];
+  int32_t* col = c->get<int32_t>(S_POP_COL, (size_t)std::max<int64_t>(total, 1));
+  double* val = c->get<double>(S_POP_VAL, (size_t)std::max<int64_t>(total, 1));
+  for (int m = 0; m < B; ++m) {
+    pm[m].row_ptr = row_ptr + (size_t)m * (n + 1);
+    pm[m].col = col + base[m];
+    pm[m].val = val + base[m];
+    Csr& K = out[m].A;
+    K.n = n;
+    K.nnz = base[m + 1] - base[m];
+    K.row_ptr = row_ptr + (size_t)m * (n + 1);
+    K.col = pm[m].col;
+    K.val = pm[m].val;
+    out[m].candidates = (int64_t)hcand[m];
+  }
+  upload();
+  SDGP_HIP(hipStreamSynchronize(c->stream));   // the host copies (snapshots, bp, row arguments) are done
+  k_cell_rows_pop<true><<<dim3((unsigned)nc, 1, B), kBlock, 0, c->stream>>>(dra, dpm);
+  SDGP_CHECK_LAUNCH();
+  return out;
 }
 
 Csr assemble_cross(Ctx* c, const Sorted& s, const KParams& kp, const Bumps& b, const double* x0, int64_t n0,

@@ -1828,7 +1828,112 @@ int update_blocks_per_cu(int NI, bool fw) {
   }
 }
 
+// ------------------------------------------------------------ autotuner
+// The first solve of a problem class (architecture, bump-function class,
+// right-hand-side slabs, population or single, log2 of the rows, entries
+// per row in half-octaves, operator form, preconditioner) times candidate
+// launch shapes on the caller's own problem: short trial solves of
+// kTrialIters CG iterations each, timed with HIP events over the
+// iterations after the first kTrialSkip.  Stage 1 sweeps the SpMM form
+// (union lists or CSR rows) and its grid; stage 2 sweeps the update
+// kernels' grid (one, two or three resident rounds) and the F w product
+// form.  A candidate replaces the incumbent only when it is at least 1%
+// faster.  The winner goes to the persistent store and is used from then
+// on; the shapes change only the order of floating-point sums.
+constexpr int kTrialIters = 24;
+constexpr int kTrialSkip = 8;
+constexpr int64_t kTuneMinRows = 65536;
+
+struct ShapeGuard {   // leaves trial mode on every exit path
+  Ctx* c;
+  ~ShapeGuard() { c->in_trial = false; }
+};
+
+std::string tune_key(const Ctx* c, int NI, int ns, int B, int64_t n, int64_t nnz, bool lr, bool pc) {
+  const double per_row = std::max(1.0, (double)nnz / (double)std::max<int64_t>(n, 1));
+  int lgn = 0;
+  while (((int64_t)2 << lgn) <= n) ++lgn;
+  char buf[160];
+  std::snprintf(buf, sizeof(buf), "%s|ni%d|ns%d|b%d|n%d|r%d|lr%d|pc%d", c->arch.c_str(), NI, ns, B > 1 ? 2 : 1,
+                lgn, (int)std::lround(2.0 * std::log2(per_row)), lr ? 1 : 0, pc ? 1 : 0);
+  return buf;
+}
+
 }  // namespace
+
+// Trial solves of the tuner (see above); returns the fastest shape, with
+// ms_per_iter < 0 when the solve is too short to time.
+static TuneChoice run_tuner(Ctx* c, const std::vector<CgMember>& mem, const Sorted& s, const double* ys, int kind,
+                            int P, uint64_t seed, double rtol, const double* dense_rhs, int dense_R, int NI,
+                            int ns, int64_t n, int n1) {
+  ShapeGuard guard{c};
+  const int64_t tiles = (n + kTile - 1) / kTile;
+  auto trial = [&](const TuneChoice& t) -> double {
+    c->in_trial = true;
+    c->trial = t;
+    c->trial_ms = -1.0;
+    block_cg_multi(c, mem, s, ys, kind, P, seed, rtol, kTrialIters, dense_rhs, dense_R, false, false);
+    c->in_trial = false;
+    return c->trial_ms;
+  };
+  TuneChoice best;   // the defaults, made explicit
+  best.spmm_blocks = (int)std::min<int64_t>(kMaxNbs, round8(tiles));
+  best.union_spmm = (ns > 0 && n >= kUnionMinRows) ? 1 : 0;
+  best.fw_mfma = (ns > 0 && n1 > 0) ? 1 : 0;
+  const int round1 = update_blocks_per_cu(NI, best.fw_mfma != 0) * c->cu_count;
+  best.update_blocks = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)kMaxNbu, (int64_t)round1, round8(tiles)}));
+  double t_best = trial(best);
+  best.default_ms_per_iter = t_best;
+  best.ms_per_iter = t_best;
+  if (t_best <= 0.0) return best;
+  auto consider = [&](const TuneChoice& cand) {
+    const double t = trial(cand);
+    if (t > 0.0 && t < 0.99 * t_best) {
+      const double d = best.default_ms_per_iter;
+      best = cand;
+      best.default_ms_per_iter = d;
+      best.ms_per_iter = t;
+      t_best = t;
+    }
+  };
+  // stage 1: SpMM form and grid
+  {
+    const TuneChoice base = best;
+    std::vector<int> grids;
+    for (int g : {8192, 16384, 32768, 65528}) {
+      const int v = (int)std::min<int64_t>(g, round8(tiles));
+      if (std::find(grids.begin(), grids.end(), v) == grids.end()) grids.push_back(v);
+    }
+    std::vector<int> forms = {base.union_spmm};
+    if (ns > 0) forms.push_back(1 - base.union_spmm);
+    for (int u : forms)
+      for (int g : grids) {
+        if (u == base.union_spmm && g == base.spmm_blocks) continue;
+        TuneChoice cand = base;
+        cand.union_spmm = u;
+        cand.spmm_blocks = g;
+        consider(cand);
+      }
+  }
+  // stage 2: update grid and F w product form
+  {
+    const TuneChoice base = best;
+    std::vector<int> fws = {base.fw_mfma};
+    if (ns > 0 && n1 > 0) fws.push_back(1 - base.fw_mfma);
+    for (int f : fws) {
+      const int r1 = update_blocks_per_cu(NI, f != 0) * c->cu_count;
+      for (int k = 1; k <= 3; ++k) {
+        const int ub = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)k * r1, (int64_t)65535, round8(tiles)}));
+        if (f == base.fw_mfma && ub == base.update_blocks) continue;
+        TuneChoice cand = base;
+        cand.fw_mfma = f;
+        cand.update_blocks = ub;
+        consider(cand);
+      }
+    }
+  }
+  return best;
+}
 
 std::vector<CgResult> block_cg_multi(Ctx* c, const std::vector<CgMember>& mem, const Sorted& s, const double* ys,
                                      int kind, int P, uint64_t seed, double rtol, int max_iter,
@@ -1868,14 +1973,44 @@ std::vector<CgResult> block_cg_multi(Ctx* c, const std::vector<CgMember>& mem, c
   const int64_t tiles = (n + kTile - 1) / kTile;
   const bool staged = c->staged_spmm && ns == 1;
   const int64_t nlb = (n + kLRows - 1) / kLRows;
-  const int64_t nbs_cap = c->spmm_blocks > 0 ? c->spmm_blocks : kMaxNbs;
+  // Launch shape: a tuner trial's candidate; else the context options when
+  // any is set; else the tuned shape of this problem class (tuned now when
+  // the store has none); else the defaults.
+  TuneChoice sh;
+  int tuned = 0;
+  const bool user_shape = c->spmm_blocks > 0 || c->update_blocks > 0 || c->union_spmm >= 0 || c->fw_mfma >= 0;
+  if (c->in_trial) {
+    sh = c->trial;
+  } else if (user_shape) {
+    sh.spmm_blocks = c->spmm_blocks;
+    sh.update_blocks = c->update_blocks;
+    sh.union_spmm = c->union_spmm;
+    sh.fw_mfma = c->fw_mfma;
+  } else if (!staged && (c->autotune == 2 || (c->autotune == 1 && n >= kTuneMinRows))) {
+    int64_t nnz = 0;
+    for (const auto& mm : mem) nnz = std::max<int64_t>(nnz, mm.A.nnz);
+    const std::string key = tune_key(c, NI, ns, B, n, nnz, use_lr, use_pc);
+    const std::string path = tune_cache_path();
+    TuneChoice t;
+    if (tune_cache_get(path, key, &t)) {
+      sh = t;
+      tuned = 1;
+    } else {
+      t = run_tuner(c, mem, s, ys, kind, P, seed, rtol, dense_rhs, dense_R, NI, ns, n, n1);
+      if (t.ms_per_iter > 0.0) {
+        tune_cache_put(path, key, t);
+        sh = t;
+        tuned = 2;
+      }
+    }
+  }
+  const int64_t nbs_cap = sh.spmm_blocks > 0 ? sh.spmm_blocks : kMaxNbs;
   const int nbs = staged ? (int)round8(nlb) : (int)std::min<int64_t>(nbs_cap, round8(tiles));
   // F w products of the update kernels on the matrix cores (measured faster at
-  // 16 and at 32 bump functions); context option "fw_mfma": -1 automatic,
-  // 0 broadcasts, 1 cores
-  const bool fw = ns > 0 && n1 > 0 && (c->fw_mfma < 0 || c->fw_mfma > 0);
-  const int64_t nbu_cap = c->update_blocks > 0
-                              ? c->update_blocks
+  // 16 and at 32 bump functions); 0 per-row broadcasts
+  const bool fw = ns > 0 && n1 > 0 && sh.fw_mfma != 0;
+  const int64_t nbu_cap = sh.update_blocks > 0
+                              ? sh.update_blocks
                               : std::min<int64_t>(kMaxNbu, (int64_t)update_blocks_per_cu(NI, fw) * c->cu_count);
   const int nbu = (int)std::max<int64_t>(1, std::min<int64_t>(nbu_cap, round8(tiles)));
   require(!staged || nbs < 0x7fffffff, "too many row blocks");
@@ -1913,7 +2048,7 @@ std::vector<CgResult> block_cg_multi(Ctx* c, const std::vector<CgMember>& mem, c
   // exclusive scan on the host (once per solve), columns and values
   // (automatic from kUnionMinRows rows: below that, building the lists costs
   // more than the solve saves)
-  bool uni = !staged && ns > 0 && (c->union_spmm > 0 || (c->union_spmm < 0 && n >= kUnionMinRows));
+  bool uni = !staged && ns > 0 && (sh.union_spmm > 0 || (sh.union_spmm < 0 && n >= kUnionMinRows));
   const int64_t ng = (n + 3) / 4;
   int64_t* urp = nullptr;
   int32_t* ucol = nullptr;
@@ -1948,7 +2083,7 @@ std::vector<CgResult> block_cg_multi(Ctx* c, const std::vector<CgMember>& mem, c
     size_t free_b = 0, total_b = 0;
     const bool fits = hipMemGetInfo(&free_b, &total_b) != hipSuccess ||
                       (double)uoff[B] * 36.0 + (double)hp.size() * 8.0 <= 0.5 * (double)free_b;
-    if (!fits && c->union_spmm < 0) uni = false;
+    if (!fits && c->union_spmm <= 0) uni = false;   // unless the caller asked for the lists
   }
   if (uni) {
     urp = c->get<int64_t>(S_CG_UPTR, hp.size());
@@ -2030,6 +2165,15 @@ std::vector<CgResult> block_cg_multi(Ctx* c, const std::vector<CgMember>& mem, c
   CgArgs* dA = c->get<CgArgs>(S_CG_ARGS, B);
   SDGP_HIP(hipMemcpyAsync(dA, hA.data(), B * sizeof(CgArgs), hipMemcpyHostToDevice, c->stream));
   Launch L{nbs, nbu, ns, R, n1, use_pc, use_lr, B, staged, uni, fw};
+  if (!c->in_trial) {
+    c->last_shape.spmm_blocks = nbs;
+    c->last_shape.update_blocks = nbu;
+    c->last_shape.union_spmm = uni ? 1 : 0;
+    c->last_shape.fw_mfma = fw ? 1 : 0;
+    c->last_shape.ms_per_iter = sh.ms_per_iter;
+    c->last_shape.default_ms_per_iter = sh.default_ms_per_iter;
+    c->last_tuned = tuned;
+  }
   {
     const int64_t gx = ((int64_t)NV + 255) / 256;
     require(gx < 0x7fffffff, "n*R too large");
@@ -2107,11 +2251,29 @@ std::vector<CgResult> block_cg_multi(Ctx* c, const std::vector<CgMember>& mem, c
     SDGP_HIP(hipStreamWaitEvent(c->stream, back, 0));
   } else {
     int check = 8;
+    hipEvent_t t0 = nullptr;
     while (!active.empty() && launched < max_iter) {
       const int upto = std::min(max_iter, launched + check);
       for (; launched < upto; ++launched) cg_iteration(NI, c->stream, dA, L, c);
+      if (c->in_trial && launched == kTrialSkip) {
+        t0 = c->event();
+        SDGP_HIP(hipEventRecord(t0, c->stream));
+      }
       poll(c->stream);
       check = std::min(check * 2, 64);
+    }
+    // trial: timed only when no member converged before the end (the
+    // iterations after convergence would be empty launches)
+    bool full = true;
+    for (int m = 0; m < B; ++m)
+      if (flags[3 * m] != 0) full = false;
+    if (c->in_trial && t0 && full && launched > kTrialSkip) {
+      hipEvent_t t1 = c->event();
+      SDGP_HIP(hipEventRecord(t1, c->stream));
+      SDGP_HIP(hipEventSynchronize(t1));
+      float ms = 0.0f;
+      SDGP_HIP(hipEventElapsedTime(&ms, t0, t1));
+      c->trial_ms = (double)ms / (double)(launched - kTrialSkip);
     }
   }
   // every member's arguments again, for the unpack

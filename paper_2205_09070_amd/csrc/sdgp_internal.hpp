@@ -64,6 +64,27 @@ struct Grid {
 
 struct Ctx;
 
+// Launch shape of the block CG (the autotuner's search space).  0 / -1 mean
+// "the library default": spmm_blocks 0 = 32768 blocks, update_blocks 0 = one
+// resident round of the update kernels, union_spmm -1 = union lists from
+// 65536 rows, fw_mfma -1 = matrix-core F w products.
+struct TuneChoice {
+  int spmm_blocks = 0;
+  int update_blocks = 0;
+  int union_spmm = -1;
+  int fw_mfma = -1;
+  double ms_per_iter = 0.0;          // measured with this shape (tuner)
+  double default_ms_per_iter = 0.0;  // measured with the defaults (tuner)
+};
+
+// Persistent store of tuned shapes (tune.cpp): a JSON object keyed by the
+// problem class; path from SDGP_TUNE_CACHE, else ~/.cache/sdgp/autotune.json.
+bool parse_entry(const std::string& line, TuneChoice* t);
+std::string format_entry(const std::string& key, const TuneChoice& t);
+std::string tune_cache_path();
+bool tune_cache_get(const std::string& path, const std::string& key, TuneChoice* out);
+bool tune_cache_put(const std::string& path, const std::string& key, const TuneChoice& t);
+
 // Workspace slots.
 enum Slot {
   S_KEYS, S_KEYS_ALT, S_IDX, S_PERM, S_XS, S_YS, S_CELL_START, S_BBOX,
@@ -75,6 +96,10 @@ enum Slot {
   S_CG_V, S_CG_PART2, S_CG_ARGS, S_CG_PARTG, S_CG_G, S_CG_GP, S_PC_PART, S_PC_SINV, S_LR_PART, S_LR_FX, S_LR_FV,
   S_MORTON_KEYS, S_MORTON_KEYS2, S_MORTON_IDS, S_MORTON_ORDER, S_MORTON_SZ, S_MORTON_OFF, S_SCHED,
   S_CG_SRED, S_CG_WRED, S_CG_LNB, S_CG_LCNT, S_CG_LSLOT, S_CG_UCNT, S_CG_UPTR, S_CG_UCOL, S_CG_UVAL, S_QF, S_QM, S_KXX, S_QIV_CNT, S_QIV_PTR, S_QIV, S_QROW_NNZ, S_QROW_PTR, S_QCOL, S_QVAL,
+  // population assembly (all members at once)
+  S_POP_ARGS, S_POP_RARGS, S_POP_BP, S_POP_F, S_POP_M, S_POP_CM, S_POP_RUNCNT, S_POP_RUNPTR, S_POP_RUNS,
+  S_POP_IVCNT, S_POP_IVPTR, S_POP_IV, S_POP_ROWNNZ, S_POP_SCAN, S_POP_ROWPTR, S_POP_COL, S_POP_VAL, S_POP_CAND,
+  S_POP_GRAM, S_POP_SINV,
   S_NUM
 };
 
@@ -94,7 +119,13 @@ struct Ctx {
   int fw_mfma = -1;              // F w products on the matrix cores: -1 auto, 0 off, 1 on
   int update_blocks = 0;         // blocks of the CG update kernels (0: default cap)
   int spmm_blocks = 0;           // blocks of the CG SpMM (0: default cap; multiple of 8)
-  std::vector<DevBuf> member_bufs;  // per-member storage of the population path
+  int autotune = 1;              // CG launch-shape tuner: 0 off, 1 from 65536 rows, 2 every solve
+  std::string arch;              // device architecture (tuner key)
+  bool in_trial = false;         // a tuner trial solve is running (shape = trial)
+  TuneChoice trial;
+  double trial_ms = -1.0;        // ms per timed iteration of the last trial (< 0: not measurable)
+  TuneChoice last_shape;         // shape used by the last CG solve
+  int last_tuned = 0;            // 0 defaults / options, 1 tuned shape from the store, 2 tuned in that call
   // Workspace limit: cap_bytes > 0 makes get() refuse (SDGP_ERR_OOM) to
   // grow the context's device workspace beyond that many bytes.
   size_t cap_bytes = 0;
@@ -193,6 +224,20 @@ void prune(Ctx* c, const Sorted& s, const KParams& kp, const Bumps& b,
 Csr assemble_sorted(Ctx* c, const Sorted& s, const KParams& kp, const Bumps& b,
                     const int32_t* iv_ptr, const int2* iv, bool add_noise,
                     int64_t* candidates, PhaseTimer* t, bool core_only = false);
+// Population assembly: members m = 0..B-1 with hyperparameters h[m] on the
+// shared ordering s, every phase (bump values, cell masks, bump runs,
+// candidate intervals, count, scan, fill) one launch with the member as
+// grid z.  Each member's outputs (F, M, bump parameters, CSR) live in
+// context storage of the population and stay valid until the next
+// population call; a member's CSR is the one assemble_sorted would build.
+struct PopAssembled {
+  KParams kp;
+  Bumps b;
+  Csr A;
+  int64_t candidates = 0;
+};
+std::vector<PopAssembled> assemble_population(Ctx* c, const Sorted& s, const sdgp_kernel_desc& d,
+                                              const std::vector<const double*>& h, bool add_noise);
 // Canonical (caller order, ascending columns) copy of a sorted-order CSR.
 void canonicalize(Ctx* c, const Sorted& s, const Csr& k, int64_t* row_ptr,
                   int32_t* col, double* val);
@@ -253,6 +298,12 @@ std::vector<CgResult> block_cg_multi(Ctx* c, const std::vector<CgMember>& mem, c
                                      int max_iter, const double* dense_rhs, int dense_R, bool keep_v,
                                      bool use_graph);
 Precond lowrank_precond(Ctx* c, const Sorted& s, const KParams& kp, const Bumps& b);
+// The same for every member of a population (one Gram launch, grid z =
+// member); the members' bump values are contiguous from F0 with stride
+// n * max(n1, 1).  failed[m] is set to the reason when member m has no
+// valid preconditioner (its Precond is then unusable).
+std::vector<Precond> lowrank_precond_pop(Ctx* c, const Sorted& s, const std::vector<KParams>& kp,
+                                         const double* F0, std::vector<std::string>* failed);
 void spmm(Ctx* c, const Csr& A, const double* X, int R, double* Y);
 // Y = A X for row-major [n][R] blocks with even R (16-byte aligned).
 void spmm_slab(Ctx* c, const Csr& A, const double* X, int R, double* Y);

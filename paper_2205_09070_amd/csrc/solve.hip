@@ -341,6 +341,9 @@ namespace {
 // 64 at a time in LDS; thread t owns the pairs idx = t, t+256, ...
 __global__ __launch_bounds__(256) void k_gram(const double* __restrict__ F, int64_t n, int n1, int64_t slab,
                                               double* __restrict__ part) {
+  // population form: member blockIdx.z's F (stride n * n1) and partials
+  F += (int64_t)blockIdx.z * n * n1;
+  part += (int64_t)blockIdx.z * gridDim.x * n1 * n1;
   __shared__ double rows[64 * kMaxN1];
   const int np = n1 * n1;
   double acc[16];
@@ -372,30 +375,27 @@ __global__ __launch_bounds__(256) void k_gram(const double* __restrict__ F, int6
 
 }  // namespace
 
-Precond lowrank_precond(Ctx* c, const Sorted& s, const KParams& kp, const Bumps& b) {
+namespace {
+
+// c and ln det M of the low-rank preconditioner, without the bump part.
+Precond lowrank_base(const KParams& kp, int64_t n, const double* F) {
   Precond pc;
-  const int n1 = kp.n1;
-  const int64_t n = s.n;
   const double psi0 = kp.core == SDGP_CORE_KSTAT ? 0.26596152026762178529 : 1.0;
   pc.c = kp.sigma2 * psi0 + kp.noise;
   require(pc.c > 0.0, "the low-rank preconditioner needs sigma2 psi(0) + noise_var > 0");
-  pc.n1 = n1;
-  pc.F = b.F;
-  if (n1 == 0) {
-    pc.logdetM = (double)n * std::log(pc.c);
-    return pc;
-  }
-  const int64_t nbk = std::min<int64_t>(256, (n + 4095) / 4096);
-  const int64_t slab = (n + nbk - 1) / nbk;
+  pc.n1 = kp.n1;
+  pc.F = F;
+  if (kp.n1 == 0) pc.logdetM = (double)n * std::log(pc.c);
+  return pc;
+}
+
+// From the Gram partials hp[nbk][n1*n1]: S = c I + F^T F, its Cholesky
+// factor, ln det M and S^{-1} (into Si, host).
+void lowrank_finish(Precond& pc, int64_t n, int64_t nbk, const double* hp, std::vector<double>& Si) {
+  const int n1 = pc.n1;
   const int np = n1 * n1;
-  double* part = c->get<double>(S_PC_PART, (size_t)nbk * np);
-  k_gram<<<(unsigned)nbk, 256, 0, c->stream>>>(b.F, n, n1, slab, part);
-  SDGP_CHECK_LAUNCH();
-  std::vector<double> hp((size_t)nbk * np);
-  SDGP_HIP(hipMemcpyAsync(hp.data(), part, hp.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-  SDGP_HIP(hipStreamSynchronize(c->stream));
-  // S = c I + F^T F; Cholesky S = L L^T; ln det S; S^{-1}
-  std::vector<double> S((size_t)np, 0.0), L((size_t)np, 0.0), Si((size_t)np, 0.0);
+  std::vector<double> S((size_t)np, 0.0), L((size_t)np, 0.0);
+  Si.assign((size_t)np, 0.0);
   for (int64_t bb = 0; bb < nbk; ++bb)
     for (int q = 0; q < np; ++q) S[q] += hp[bb * np + q];
   for (int i = 0; i < n1; ++i) S[i * n1 + i] += pc.c;
@@ -426,12 +426,74 @@ Precond lowrank_precond(Ctx* c, const Sorted& s, const KParams& kp, const Bumps&
       Si[i * n1 + col] = v / L[i * n1 + i];
     }
   }
+  pc.logdetM = (double)(n - n1) * std::log(pc.c) + logdetS;
+}
+
+}  // namespace
+
+Precond lowrank_precond(Ctx* c, const Sorted& s, const KParams& kp, const Bumps& b) {
+  const int64_t n = s.n;
+  Precond pc = lowrank_base(kp, n, b.F);
+  const int n1 = kp.n1;
+  if (n1 == 0) return pc;
+  const int64_t nbk = std::min<int64_t>(256, (n + 4095) / 4096);
+  const int64_t slab = (n + nbk - 1) / nbk;
+  const int np = n1 * n1;
+  double* part = c->get<double>(S_PC_PART, (size_t)nbk * np);
+  k_gram<<<(unsigned)nbk, 256, 0, c->stream>>>(b.F, n, n1, slab, part);
+  SDGP_CHECK_LAUNCH();
+  std::vector<double> hp((size_t)nbk * np);
+  SDGP_HIP(hipMemcpyAsync(hp.data(), part, hp.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  SDGP_HIP(hipStreamSynchronize(c->stream));
+  std::vector<double> Si;
+  lowrank_finish(pc, n, nbk, hp.data(), Si);
   double* dSi = c->get<double>(S_PC_SINV, np);
   SDGP_HIP(hipMemcpyAsync(dSi, Si.data(), np * sizeof(double), hipMemcpyHostToDevice, c->stream));
   SDGP_HIP(hipStreamSynchronize(c->stream));
   pc.Sinv = dSi;
-  pc.logdetM = (double)(n - n1) * std::log(pc.c) + logdetS;
   return pc;
+}
+
+std::vector<Precond> lowrank_precond_pop(Ctx* c, const Sorted& s, const std::vector<KParams>& kp,
+                                         const double* F0, std::vector<std::string>* failed) {
+  const int B = (int)kp.size();
+  const int64_t n = s.n;
+  const int n1 = B > 0 ? kp[0].n1 : 0;
+  const int n1s = n1 > 0 ? n1 : 1;
+  std::vector<Precond> pcs(B);
+  failed->assign(B, std::string());
+  for (int m = 0; m < B; ++m) {
+    try {
+      pcs[m] = lowrank_base(kp[m], n, F0 + (size_t)m * n * n1s);
+    } catch (const Error& e) {
+      (*failed)[m] = e.what();
+    }
+  }
+  if (n1 == 0 || B == 0) return pcs;
+  const int64_t nbk = std::min<int64_t>(256, (n + 4095) / 4096);
+  const int64_t slab = (n + nbk - 1) / nbk;
+  const int np = n1 * n1;
+  double* part = c->get<double>(S_POP_GRAM, (size_t)B * nbk * np);
+  k_gram<<<dim3((unsigned)nbk, 1, B), 256, 0, c->stream>>>(F0, n, n1, slab, part);
+  SDGP_CHECK_LAUNCH();
+  std::vector<double> hp((size_t)B * nbk * np);
+  SDGP_HIP(hipMemcpyAsync(hp.data(), part, hp.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  SDGP_HIP(hipStreamSynchronize(c->stream));
+  std::vector<double> all((size_t)B * np), Si;
+  for (int m = 0; m < B; ++m) {
+    if (!(*failed)[m].empty()) continue;
+    try {
+      lowrank_finish(pcs[m], n, nbk, hp.data() + (size_t)m * nbk * np, Si);
+      std::copy(Si.begin(), Si.end(), all.begin() + (size_t)m * np);
+    } catch (const Error& e) {
+      (*failed)[m] = e.what();
+    }
+  }
+  double* dSi = c->get<double>(S_POP_SINV, all.size());
+  SDGP_HIP(hipMemcpyAsync(dSi, all.data(), all.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  SDGP_HIP(hipStreamSynchronize(c->stream));
+  for (int m = 0; m < B; ++m) pcs[m].Sinv = dSi + (size_t)m * np;
+  return pcs;
 }
 
 

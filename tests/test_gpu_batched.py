@@ -36,11 +36,14 @@ def population(n, dim, n1, n2, members, seed, combine=1, per_row=12.0):
     return w, H
 
 
-def test_batched_exact_matches_oracle():
+@pytest.mark.parametrize("combine", [1, 0], ids=["sum", "product"])
+def test_batched_exact_matches_oracle(combine):
+    """Every member of a population (assembled together, every assembly
+    phase one launch over all members) against the dense oracle."""
     gu.need_gpu()
     import paper_2205_09070_amd as sd
-    w, H = population(1200, 3, 2, 2, 3, 21)
-    gu.log("batched exact B=%d n=%d" % (H.shape[0], w.x.shape[0]))
+    w, H = population(1200, 3, 2, 2, 3, 21, combine=combine)
+    gu.log("batched exact B=%d n=%d combine=%d" % (H.shape[0], w.x.shape[0], combine))
     c = gu.ctx()
     v, g, st, infos = c.lml_grad_batched(w.desc, gu.dev(w.x), gu.dev(w.y), H, sd.exact_estimator())
     assert (st == sd.OK).all(), st
