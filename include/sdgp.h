@@ -267,6 +267,28 @@ sdgp_status sdgp_lml_grad(sdgp_ctx* ctx, const sdgp_kernel_desc* desc, const dou
                           const sdgp_estimator* est, double* lml_out, double* grad_out,
                           sdgp_info* info);
 
+/* For callers that cannot allocate device memory (code under stream or
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * sdgp_lml_grad with no device allocation.  Same arguments, results and
+ * errors as sdgp_lml_grad, with these differences:
+ *  - every piece of device workspace is carved from a static array of
+ *    256 MiB that the library holds on each device it runs on until the
+ *    process ends; the call makes no hipMalloc / hipFree and calls no
+ *    allocating library routine;
+ *  - n > 65535: INVALID_ARG before any device work; an input whose
+ *    workspace exceeds 256 MiB (many points with many probes, identity
+ *    probes beyond a few thousand points) fails with SDGP_ERR_OOM;
+ *  - the context's "timing" and "graph" options are ignored for the call;
+ *  - all calls on one device share the array: the library serialises them
+ *    (a mutex per device, held until the call's device work has finished),
+ *    and each call clears what it needs; work that the caller overlaps with
+ *    the call outside the library never touches the array.
+ * The context's own workspace (of the other entry points) is untouched. */
+sdgp_status sdgp_lml_grad_noalloc(sdgp_ctx* ctx, const sdgp_kernel_desc* desc, const double* x,
+                                  const double* y, int64_t n, const double* h,
+                                  const sdgp_estimator* est, double* lml_out, double* grad_out,
+                                  sdgp_info* info);
+
 /* A population of B hyperparameter vectors on one shared point set
  * (Section 2.4 training repeats eqn:log_likelihood for many h).  The
  * factored operator (operator_form = SDGP_OPERATOR_FACTORED) is rejected

@@ -87,6 +87,8 @@ _SIGS = {
                        C.POINTER(Info)]),
     "sdgp_lml_grad": (I32, [VP, C.POINTER(KernelDesc), VP, VP, I64, VP, C.POINTER(Estimator), VP, VP,
                             C.POINTER(Info)]),
+    "sdgp_lml_grad_noalloc": (I32, [VP, C.POINTER(KernelDesc), VP, VP, I64, VP, C.POINTER(Estimator), VP, VP,
+                                    C.POINTER(Info)]),
     "sdgp_lml_grad_batched": (I32, [VP, C.POINTER(KernelDesc), VP, VP, I64, VP, I32,
                                     C.POINTER(Estimator), VP, VP, VP, VP]),
     "sdgp_posterior_mean_var": (I32, [VP, C.POINTER(KernelDesc), VP, VP, I64, VP, VP, I64,
@@ -348,6 +350,21 @@ class Context:
         g = np.zeros(hh.shape[0])
         st = self.lib.sdgp_lml_grad(self.h, C.byref(d), _ptr(x), _ptr(y), x.shape[0], _hptr(hh), C.byref(e),
                                     _hptr(v), _hptr(g), C.byref(info))
+        self._check(st, (NOT_CONVERGED,) if allow_not_converged else ())
+        return float(v[0]), g, info
+
+    def lml_grad_noalloc(self, desc, x, y, h, est=None, allow_not_converged=False):
+        """sdgp_lml_grad_noalloc: lml_grad with the device workspace taken
+        from the library's static per-device array (no device allocation)."""
+        x, y = _dev_f64(x), _dev_f64(y)
+        hh = self._h(h)
+        d = desc_of(desc)
+        e = est or estimator()
+        info = Info()
+        v = np.zeros(1)
+        g = np.zeros(hh.shape[0])
+        st = self.lib.sdgp_lml_grad_noalloc(self.h, C.byref(d), _ptr(x), _ptr(y), x.shape[0], _hptr(hh),
+                                            C.byref(e), _hptr(v), _hptr(g), C.byref(info))
         self._check(st, (NOT_CONVERGED,) if allow_not_converged else ())
         return float(v[0]), g, info
 

@@ -1,6 +1,7 @@
 // extern "C" entry points of libsdgp.so (declared in include/sdgp.h).
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -8,6 +9,38 @@
 #include "sdgp_internal.hpp"
 
 struct sdgp_ctx : sdgp::Ctx {};
+
+// Static device workspace of sdgp_lml_grad_noalloc: every device the library
+// runs on holds one copy until the process ends.  In host code `scratch` is
+// only the host-side stand-in of the symbol; its device address comes from
+// hipGetSymbolAddress (kept per device in g_scratch) and only that address
+// is ever passed to kernels or copies.
+constexpr size_t kScratchBytes = size_t(256) << 20;
+constexpr int64_t kNoAllocMaxN = 65535;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;                     // guards g_scratch
+char* g_scratch[kMaxDevices] = {};           // device address of `scratch` per device
+std::mutex g_scratch_call_mu[kMaxDevices];   // serialises static-workspace calls per device
+
+// Resolves the device address of the static workspace on the current
+// device (once per device).
+sdgp_status resolve_scratch(int device, std::string* err) {
+  if (device < 0 || device >= kMaxDevices) return SDGP_OK;   // the static-workspace call then refuses
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (g_scratch[device]) return SDGP_OK;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || p == nullptr) {
+    *err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+    return SDGP_ERR_HIP;
+  }
+  g_scratch[device] = static_cast<char*>(p);
+  return SDGP_OK;
+}
+}  // namespace
 
 namespace sdgp {
 
@@ -168,6 +201,8 @@ sdgp_status sdgp_create(sdgp_ctx** out, int device, void* hip_stream) {
     SDGP_HIP(hipGetDeviceCount(&count));
     require(device >= 0 && device < count, "no such HIP device");
     SDGP_HIP(hipSetDevice(device));
+    std::string serr;
+    if (resolve_scratch(device, &serr) != SDGP_OK) throw Error(SDGP_ERR_HIP, serr);
     sdgp_ctx* c = new sdgp_ctx();
     c->device = device;
     c->stream = static_cast<hipStream_t>(hip_stream);
@@ -306,6 +341,48 @@ sdgp_status sdgp_lml_grad(sdgp_ctx* ctx, const sdgp_kernel_desc* desc, const dou
                           double* grad_out, sdgp_info* info) {
   if (!grad_out) return SDGP_ERR_INVALID_ARG;
   return lml_common(ctx, desc, x, y, n, h, est, lml_out, grad_out, info);
+}
+
+sdgp_status sdgp_lml_grad_noalloc(sdgp_ctx* ctx, const sdgp_kernel_desc* desc, const double* x, const double* y,
+                                  int64_t n, const double* h, const sdgp_estimator* est, double* lml_out,
+                                  double* grad_out, sdgp_info* info) {
+  if (!ctx) return SDGP_ERR_INVALID_ARG;
+  if (!grad_out) {
+    ctx->err = "grad_out is NULL";
+    return SDGP_ERR_INVALID_ARG;
+  }
+  if (n > kNoAllocMaxN) {
+    ctx->err = "sdgp_lml_grad_noalloc takes at most " + std::to_string(kNoAllocMaxN) + " points";
+    return SDGP_ERR_INVALID_ARG;
+  }
+  const int dev = ctx->device;
+  char* base = (dev >= 0 && dev < kMaxDevices) ? g_scratch[dev] : nullptr;
+  if (!base) {
+    ctx->err = "no static workspace on this device";
+    return SDGP_ERR_HIP;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_call_mu[dev]);
+  const bool timing = ctx->timing, graph = ctx->use_graph;
+  ctx->timing = false;     // events and graphs would allocate
+  ctx->use_graph = false;
+  ctx->arena = base;
+  ctx->arena_cap = kScratchBytes;
+  ctx->arena_used = 0;
+  for (auto& a : ctx->abuf) a = DevBuf{};
+  sdgp_status st = lml_common(ctx, desc, x, y, n, h, est, lml_out, grad_out, info);
+  // the next call may reuse the workspace only after this call's device work
+  const hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess && st == SDGP_OK) {
+    ctx->err = std::string("hipStreamSynchronize: ") + hipGetErrorString(e);
+    st = SDGP_ERR_HIP;
+  }
+  ctx->arena = nullptr;
+  ctx->arena_cap = 0;
+  ctx->arena_used = 0;
+  for (auto& a : ctx->abuf) a = DevBuf{};
+  ctx->timing = timing;
+  ctx->use_graph = graph;
+  return st;
 }
 
 sdgp_status sdgp_lml_grad_batched(sdgp_ctx* ctx, const sdgp_kernel_desc* desc, const double* x, const double* y,

@@ -1995,7 +1995,7 @@ std::vector<CgResult> block_cg_multi(Ctx* c, const std::vector<CgMember>& mem, c
     if (tune_cache_get(path, key, &t)) {
       sh = t;
       tuned = 1;
-    } else {
+    } else if (!c->arena) {   // trials need events; the static-workspace call only reads the store
       t = run_tuner(c, mem, s, ys, kind, P, seed, rtol, dense_rhs, dense_R, NI, ns, n, n1);
       if (t.ms_per_iter > 0.0) {
         tune_cache_put(path, key, t);

@@ -126,10 +126,16 @@ struct Ctx {
   double trial_ms = -1.0;        // ms per timed iteration of the last trial (< 0: not measurable)
   TuneChoice last_shape;         // shape used by the last CG solve
   int last_tuned = 0;            // 0 defaults / options, 1 tuned shape from the store, 2 tuned in that call
-  // Workspace limit: cap_bytes > 0 makes get() refuse (SDGP_ERR_OOM) to
-  // grow the context's device workspace beyond that many bytes.
+  // Workspace limits.  cap_bytes > 0: get() refuses (SDGP_ERR_OOM) to grow
+  // the context's workspace beyond that many bytes.  arena != nullptr
+  // (static-workspace calls): get() hands out 256-byte aligned slices of the
+  // arena instead of calling hipMalloc; abuf holds those slices per slot.
   size_t cap_bytes = 0;
   size_t held_bytes = 0;
+  char* arena = nullptr;
+  size_t arena_cap = 0;
+  size_t arena_used = 0;
+  DevBuf abuf[S_NUM];
   hipStream_t gstream = nullptr; // private default-priority stream for graph capture
   hipStream_t graph_stream() {
     if (!gstream) SDGP_HIP(hipStreamCreateWithFlags(&gstream, hipStreamNonBlocking));
@@ -140,6 +146,19 @@ struct Ctx {
   T* get(Slot s, size_t count) {
     size_t need = count * sizeof(T);
     if (need == 0) need = sizeof(T);
+    if (arena) {
+      DevBuf& a = abuf[s];
+      if (a.bytes < need) {
+        const size_t cap = (need + need / 8 + 256 + 255) / 256 * 256;   // same slack as hipMalloc'd slots
+        if (cap > arena_cap - arena_used)
+          throw Error(SDGP_ERR_OOM, "this input needs more device workspace than the static workspace of " +
+                                        std::to_string(arena_cap >> 20) + " MiB");
+        a.p = arena + arena_used;
+        a.bytes = cap;
+        arena_used += cap;
+      }
+      return static_cast<T*>(a.p);
+    }
     DevBuf& b = buf[s];
     if (b.bytes < need) {
       const size_t cap = need + need / 8 + 256;
