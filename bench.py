@@ -65,6 +65,9 @@ def parse():
                    help="instead of the N=1M line, time a population of B hyperparameter vectors on a shared "
                         "N=200,000 point set: one batched call against B sequential calls")
     p.add_argument("--pop-n", type=int, default=200_000)
+    p.add_argument("--assembly-only", type=int, default=0, metavar="K",
+                   help="instead of the LML line, time K full-K assemblies (sorted order, noise on the diagonal) "
+                        "of the workload and print their rate (the assembly part of the metric)")
     p.add_argument("--copy-ref-mib", type=int, default=0,
                    help="before the benchmark, copy a buffer of this many MiB three times (a plain device copy "
                         "of known size, the reference that scales profiler byte counters)")
@@ -180,6 +183,26 @@ def population(args, sd, wl, torch):
     print(json.dumps(out))
 
 
+def assembly_only(args, sd, w, wdesc, x, torch):
+    """K timed full-K assemblies (sdgp_kernel_assemble_sorted: order, bump
+    values, pruning, count, scan, fill) after one untimed one."""
+    ctx = sd.Context(0)
+    s = ctx.stream
+    nnz = ctx.kernel_nnz(w.desc, x, w.h)
+    ctx.kernel_assemble(w.desc, x, w.h, add_noise=True, sorted_order=True, nnz=nnz)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(args.assembly_only):
+        ctx.kernel_assemble(w.desc, x, w.h, add_noise=True, sorted_order=True, nnz=nnz)
+    e1.record(s)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / args.assembly_only
+    print(json.dumps({"metric": "assembly nnz/s (full K, FP64)", "value": nnz / (ms * 1e-3), "unit": "nnz/s",
+                      "ms_per_assembly": ms, "nnz": int(nnz), "assemblies": args.assembly_only,
+                      "config": {"workload": wdesc}}))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -219,6 +242,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.assembly_only > 0:
+        assembly_only(args, sd, w, wdesc, x, torch)
+        return
     pc = sd.PRECOND_LOWRANK if args.precond == "lowrank" else sd.PRECOND_NONE
     op = sd.OPERATOR_FACTORED if args.operator == "factored" else sd.OPERATOR_ASSEMBLED
     est = sd.estimator(probes=args.probes, seed=1, cg_rtol=args.rtol, cg_max_iter=20000, precond=pc,

@@ -186,9 +186,8 @@ struct PopMember {
   double* F;                 // [n, n1]
   uint64_t* M;               // [n]
   uint64_t* cm;              // [n_cells] cell masks
-  int32_t* run_cnt;          // [n1]
-  int32_t* run_ptr;          // [n1 + 1]
-  int2* runs;                // bump-function cell runs
+  const int32_t* run_ptr;    // [n1 + 1], offsets into runs
+  const int2* runs;          // bump-function cell runs of all members
   int32_t* iv_cnt;           // [n_cells + 1]
   const int32_t* iv_ptr;     // [n_cells + 1]
   int2* iv;                  // candidate intervals
@@ -226,53 +225,50 @@ __global__ void k_cellmask_pop(const int32_t* __restrict__ cell_start, int64_t n
   P.cm[c] = m;
 }
 
-// Runs of consecutive cells whose mask has bit i: one block per bump
-// function scans all cells in order (count pass, then fill pass).
-template <bool kFill>
-__device__ __forceinline__ void bump_runs_body(const uint64_t* __restrict__ cm, int64_t n_cells,
-                                               int32_t* __restrict__ run_cnt, const int32_t* __restrict__ run_ptr,
-                                               int2* __restrict__ runs) {
-  const int i = blockIdx.x;
-  typedef hipcub::BlockScan<int, kBlock> Scan;
-  __shared__ typename Scan::TempStorage tmp;
-  __shared__ int base_s, base_e;
-  if (threadIdx.x == 0) { base_s = 0; base_e = 0; }
-  __syncthreads();
-  for (int64_t c0 = 0; c0 < n_cells; c0 += kBlock) {
-    const int64_t c = c0 + threadIdx.x;
-    const bool in = c < n_cells;
-    const bool f = in && ((cm[c] >> i) & 1ull);
-    const bool fp = in && c > 0 && ((cm[c - 1] >> i) & 1ull);
-    const bool fn = in && c + 1 < n_cells && ((cm[c + 1] >> i) & 1ull);
-    const int st = (f && !fp) ? 1 : 0;
-    const int en = (f && !fn) ? 1 : 0;
-    int ps, pe, ts, te;
-    Scan(tmp).ExclusiveSum(st, ps, ts);
-    __syncthreads();
-    Scan(tmp).ExclusiveSum(en, pe, te);
-    if (kFill) {
-      const int64_t o = run_ptr[i];
-      if (st) runs[o + base_s + ps].x = (int)c;
-      if (en) runs[o + base_e + pe].y = (int)c;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) { base_s += ts; base_e += te; }
-    __syncthreads();
-  }
-  if (!kFill && threadIdx.x == 0) run_cnt[i] = base_s;
+// Runs of consecutive cells whose mask has bit i, for every bump function
+// (grid y) of every member (grid z), all in parallel: k_run_flags marks the
+// cells that start a run, one exclusive scan over the flags of all
+// (member, function, cell) triples gives every run its slot, and
+// k_run_write puts a run's first cell at its slot and its last cell at the
+// slot of the run it closes (the number of run starts up to and including
+// that cell, minus one).  The runs of function i of member z are
+// runs[pos[(z n1 + i) nc] .. pos[(z n1 + i + 1) nc]).
+__device__ __forceinline__ bool cell_bit(const uint64_t* __restrict__ cm, int64_t c, int i) {
+  return (cm[c] >> i) & 1ull;
 }
 
-template <bool kFill>
-__global__ void k_bump_runs(const uint64_t* __restrict__ cm, int64_t n_cells,
-                            int32_t* __restrict__ run_cnt, const int32_t* __restrict__ run_ptr,
+__global__ void k_run_flags(const uint64_t* __restrict__ cm, int64_t nc, int n1, int32_t* __restrict__ flag) {
+  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  const int i = blockIdx.y;
+  const uint64_t* m = cm + (int64_t)blockIdx.z * nc;
+  const bool f = cell_bit(m, c, i);
+  const bool fp = c > 0 && cell_bit(m, c - 1, i);
+  flag[((int64_t)blockIdx.z * n1 + i) * nc + c] = (f && !fp) ? 1 : 0;
+}
+
+__global__ void k_run_write(const uint64_t* __restrict__ cm, int64_t nc, int n1, const int32_t* __restrict__ pos,
                             int2* __restrict__ runs) {
-  bump_runs_body<kFill>(cm, n_cells, run_cnt, run_ptr, runs);
+  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  const int i = blockIdx.y;
+  const uint64_t* m = cm + (int64_t)blockIdx.z * nc;
+  if (!cell_bit(m, c, i)) return;
+  const bool fp = c > 0 && cell_bit(m, c - 1, i);
+  const bool fn = c + 1 < nc && cell_bit(m, c + 1, i);
+  const int32_t p = pos[((int64_t)blockIdx.z * n1 + i) * nc + c];
+  if (!fp) runs[p].x = (int)c;
+  if (!fn) runs[fp ? p - 1 : p].y = (int)c;
 }
 
-template <bool kFill>
-__global__ void k_bump_runs_pop(int64_t n_cells, const PopMember* __restrict__ pm) {
-  const PopMember& P = pm[blockIdx.z];
-  bump_runs_body<kFill>(P.cm, n_cells, P.run_cnt, P.run_ptr, P.runs);
+// run_ptr[z (n1 + 1) + i] = pos[(z n1 + i) nc] for i <= n1 (offsets into
+// the one run array of all members).
+__global__ void k_run_ptr(const int32_t* __restrict__ pos, int64_t nc, int n1, int B,
+                          int32_t* __restrict__ run_ptr) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= (int64_t)B * (n1 + 1)) return;
+  const int64_t z = e / (n1 + 1), i = e % (n1 + 1);
+  run_ptr[e] = pos[(z * n1 + i) * nc];
 }
 
 struct IvArgs {
@@ -457,124 +453,122 @@ struct RowArgs {
 // and bump masks are staged in LDS once per chunk of 512 candidates and every
 // row of the cell (one wavefront per row, rows dealt to the four wavefronts)
 // tests them from there: a candidate point is read from memory once per cell
-// instead of once per row.  Columns stay ascending (chunks follow the sorted
-// disjoint intervals); each row's output position persists in LDS across
-// chunks.  Cells with more than 1024 rows are processed in row groups.
+// instead of once per row.  The cell's intervals are read in windows of 256
+// (one per thread) with their exclusive length prefix from a block scan, so
+// every thread finds its candidate of a chunk by a binary search in LDS.
+// Columns stay ascending (chunks follow the sorted disjoint intervals); each
+// row's output position persists in LDS across chunks.  Cells with more
+// than 1024 rows are processed in row groups.
 constexpr int kCC = 512;      // staged candidates per chunk
 constexpr int kCRows = 1024;  // rows per row group
-constexpr int kCSeg = 64;     // interval pieces per chunk
+constexpr int kIvWin = kBlock;  // intervals per window
 
 template <bool kFill>
 __device__ __forceinline__ void cell_rows_body(const RowArgs& A, int64_t* __restrict__ row_nnz,
                                                unsigned long long* __restrict__ cand_total,
                                                const int64_t* __restrict__ row_ptr,
                                                int32_t* __restrict__ col, double* __restrict__ val) {
+  typedef hipcub::BlockScan<int, kBlock> Scan;
+  __shared__ typename Scan::TempStorage scan_tmp;
   __shared__ double4 sx[kCC];
   __shared__ uint64_t sm[kCC];
   __shared__ int32_t sb[kCC];
   __shared__ int64_t spos[kCRows];
-  __shared__ int32_t seg_b[kCSeg];
-  __shared__ int32_t seg_off[kCSeg + 1];
-  __shared__ int32_t st_q, st_o, st_n, st_fill;
+  __shared__ int32_t wb[kIvWin];        // window: first point of each interval
+  __shared__ int32_t wpre[kIvWin + 1];  // window: exclusive prefix of the lengths
   const int64_t c = blockIdx.x;
   const int32_t r0 = A.cell_start[c], r1 = A.cell_start[c + 1];
   if (r1 <= r0) return;                       // uniform: empty cell
   const int32_t i0 = A.iv_ptr[c], i1 = A.iv_ptr[c + 1];
   const int t = threadIdx.x, lane = lane_id(), w = t >> 6;
   constexpr int kWaves = kBlock / kWave;
+  unsigned long long ncand = 0;               // candidates per row (thread 0)
   for (int32_t g0 = r0; g0 < r1; g0 += kCRows) {
     const int nr = min(r1 - g0, kCRows);
     for (int r = t; r < nr; r += kBlock) spos[r] = kFill ? row_ptr[g0 + r] : 0;
-    if (t == 0) { st_q = i0; st_o = 0; }
-    __syncthreads();
-    for (;;) {
-      if (t == 0) {  // next chunk: pieces of the remaining intervals, up to kCC candidates
-        int q = st_q, o = st_o, filled = 0, ns = 0;
-        while (q < i1 && filled < kCC && ns < kCSeg) {
-          const int2 iv = A.iv[q];
-          const int len = iv.y - iv.x - o;
-          const int take = min(len, kCC - filled);
-          seg_b[ns] = iv.x + o;
-          seg_off[ns] = filled;
-          ++ns;
-          filled += take;
-          if (take == len) { ++q; o = 0; } else { o += take; }
-        }
-        seg_off[ns] = filled;
-        st_n = ns;
-        st_fill = filled;
-        st_q = q;
-        st_o = o;
+    for (int32_t q0 = i0; q0 < i1; q0 += kIvWin) {
+      const int nw = min(i1 - q0, kIvWin);
+      int len = 0;
+      if (t < nw) {
+        const int2 iv = A.iv[q0 + t];
+        wb[t] = iv.x;
+        len = iv.y - iv.x;
+      }
+      int pre = 0, tot = 0;
+      Scan(scan_tmp).ExclusiveSum(len, pre, tot);
+      if (t < nw) wpre[t] = pre;
+      if (t == 0) {
+        wpre[nw] = tot;
+        if (g0 == r0) ncand += (unsigned long long)tot;
       }
       __syncthreads();
-      const int filled = st_fill, ns = st_n;
-      if (filled == 0) break;                 // uniform
-      for (int k = t; k < filled; k += kBlock) {
-        int lo = 0, hi = ns;                  // seg_off[lo] <= k < seg_off[hi]
-        while (hi - lo > 1) {
-          const int mid = (lo + hi) >> 1;
-          if (seg_off[mid] <= k) lo = mid; else hi = mid;
-        }
-        const int32_t b = seg_b[lo] + (k - seg_off[lo]);
-        sx[k] = A.xs[b];
-        sm[k] = A.M[b];
-        sb[k] = b;
-      }
-      __syncthreads();
-      for (int r = w; r < nr; r += kWaves) {
-        const int64_t a = (int64_t)g0 + r;
-        const double4 xa = A.xs[a];
-        const uint64_t Ma = A.M[a];
-        const double* Fa = A.F + a * (int64_t)A.n1;
-        int64_t pos = spos[r];
-        for (int k0 = 0; k0 < filled; k0 += kWave) {
-          const int k = k0 + lane;
-          bool keep = false, core = false;
-          double d2 = 0.0;
-          uint64_t mm = 0;
-          int32_t b = 0;
-          if (k < filled) {
-            b = sb[k];
-            d2 = dist2(xa, sx[k], A.dim);
-            core = d2 < A.rc2;
-            mm = Ma & sm[k];
-            const bool bump = mm != 0;
-            keep = (b == a) || (A.core_only ? core : (A.combine == 0 ? (core && bump) : (core || bump)));
-            if (A.core_only) mm = 0;
+      for (int k0 = 0; k0 < tot; k0 += kCC) {
+        const int filled = min(kCC, tot - k0);
+        for (int k = t; k < filled; k += kBlock) {
+          const int kk = k0 + k;
+          int lo = 0, hi = nw;                // wpre[lo] <= kk < wpre[hi]
+          while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (wpre[mid] <= kk) lo = mid; else hi = mid;
           }
-          const uint64_t bal = ballot64(keep);
-          if (kFill && keep) {
-            double psi = 0.0;
-            if (core) psi = core_psi(sqrt(d2) / A.r_core, A.core, A.ell);
-            double B = 0.0;
-            const double* Fb = A.F + (int64_t)b * A.n1;
-            uint64_t tm = mm;
-            while (tm) {
-              const int i = __builtin_ctzll(tm);
-              tm &= tm - 1;
-              B += Fa[i] * Fb[i];
+          const int32_t b = wb[lo] + (kk - wpre[lo]);
+          sx[k] = A.xs[b];
+          sm[k] = A.M[b];
+          sb[k] = b;
+        }
+        __syncthreads();
+        for (int r = w; r < nr; r += kWaves) {
+          const int64_t a = (int64_t)g0 + r;
+          const double4 xa = A.xs[a];
+          const uint64_t Ma = A.M[a];
+          const double* Fa = A.F + a * (int64_t)A.n1;
+          int64_t pos = spos[r];
+          for (int j0 = 0; j0 < filled; j0 += kWave) {
+            const int k = j0 + lane;
+            bool keep = false, core = false;
+            double d2 = 0.0;
+            uint64_t mm = 0;
+            int32_t b = 0;
+            if (k < filled) {
+              b = sb[k];
+              d2 = dist2(xa, sx[k], A.dim);
+              core = d2 < A.rc2;
+              mm = Ma & sm[k];
+              const bool bump = mm != 0;
+              keep = (b == a) || (A.core_only ? core : (A.combine == 0 ? (core && bump) : (core || bump)));
+              if (A.core_only) mm = 0;
             }
-            double kv = A.combine == 0 ? A.sigma2 * psi * B : A.sigma2 * psi + B;
-            if (b == a && A.add_noise) kv += A.noise;
-            const int64_t o = pos + lanes_below(bal);
-            col[o] = b;
-            val[o] = kv;
+            const uint64_t bal = ballot64(keep);
+            if (kFill && keep) {
+              double psi = 0.0;
+              if (core) psi = core_psi(sqrt(d2) / A.r_core, A.core, A.ell);
+              double B = 0.0;
+              const double* Fb = A.F + (int64_t)b * A.n1;
+              uint64_t tm = mm;
+              while (tm) {
+                const int i = __builtin_ctzll(tm);
+                tm &= tm - 1;
+                B += Fa[i] * Fb[i];
+              }
+              double kv = A.combine == 0 ? A.sigma2 * psi * B : A.sigma2 * psi + B;
+              if (b == a && A.add_noise) kv += A.noise;
+              const int64_t o = pos + lanes_below(bal);
+              col[o] = b;
+              val[o] = kv;
+            }
+            pos += __popcll(bal);
           }
-          pos += __popcll(bal);
+          if (lane == 0) spos[r] = pos;
         }
-        if (lane == 0) spos[r] = pos;
+        __syncthreads();
       }
-      __syncthreads();
+      __syncthreads();                        // window storage and scan storage free again
     }
     if (!kFill)
       for (int r = t; r < nr; r += kBlock) row_nnz[g0 + r] = spos[r];
     __syncthreads();
   }
-  if (!kFill && t == 0) {
-    unsigned long long cnt = 0;
-    for (int32_t q = i0; q < i1; ++q) cnt += (unsigned long long)(A.iv[q].y - A.iv[q].x);
-    atomicAdd(cand_total, cnt * (unsigned long long)(r1 - r0));
-  }
+  if (!kFill && t == 0) atomicAdd(cand_total, ncand * (unsigned long long)(r1 - r0));
 }
 
 template <bool kFill>
@@ -888,6 +882,33 @@ Bumps bump_precompute(Ctx* c, const Sorted& s, const KParams& kp, const double* 
   return b;
 }
 
+// Bump-function cell runs of B members (masks cm[z nc + c]) with no host
+// round trip: flags, one scan, run pointers and runs (storage sized for the
+// most runs a function can have, ceil(nc / 2)).
+static void bump_runs(Ctx* c, const uint64_t* cm, int64_t nc, int n1, int B, Slot s_flag, Slot s_pos, Slot s_ptr,
+                      Slot s_runs, int32_t** run_ptr_out, int2** runs_out) {
+  const int64_t nflag = (int64_t)B * n1 * nc + 1;
+  require(nflag < 0x7fffffffLL, "too many (member, bump function, cell) triples");
+  int32_t* flag = c->get<int32_t>(s_flag, nflag);
+  int32_t* pos = c->get<int32_t>(s_pos, nflag);
+  SDGP_HIP(hipMemsetAsync(flag + nflag - 1, 0, sizeof(int32_t), c->stream));
+  const unsigned gc = (unsigned)grid_for(nc, kBlock);
+  k_run_flags<<<dim3(gc, n1, B), kBlock, 0, c->stream>>>(cm, nc, n1, flag);
+  SDGP_CHECK_LAUNCH();
+  size_t tb = 0;
+  SDGP_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, flag, pos, (int)nflag, c->stream));
+  void* tmp = c->get<char>(S_SORT_TMP, tb);
+  SDGP_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, tb, flag, pos, (int)nflag, c->stream));
+  int32_t* run_ptr = c->get<int32_t>(s_ptr, (size_t)B * (n1 + 1));
+  k_run_ptr<<<(unsigned)grid_for((int64_t)B * (n1 + 1), kBlock), kBlock, 0, c->stream>>>(pos, nc, n1, B, run_ptr);
+  SDGP_CHECK_LAUNCH();
+  int2* runs = c->get<int2>(s_runs, (size_t)B * n1 * ((nc + 1) / 2) + 1);
+  k_run_write<<<dim3(gc, n1, B), kBlock, 0, c->stream>>>(cm, nc, n1, pos, runs);
+  SDGP_CHECK_LAUNCH();
+  *run_ptr_out = run_ptr;
+  *runs_out = runs;
+}
+
 void prune(Ctx* c, const Sorted& s, const KParams& kp, const Bumps& b, int32_t** iv_ptr_out,
            int2** iv_out, bool core_only) {
   const int64_t nc = s.grid.n_cells;
@@ -902,19 +923,9 @@ void prune(Ctx* c, const Sorted& s, const KParams& kp, const Bumps& b, int32_t**
   A.runs = nullptr;
   A.use_bumps = (kp.combine == SDGP_COMBINE_SUM && kp.n1 > 0 && !core_only) ? 1 : 0;
   if (A.use_bumps) {
-    int32_t* run_cnt = c->get<int32_t>(S_RUN_CNT, kp.n1);
-    k_bump_runs<false><<<kp.n1, kBlock, 0, c->stream>>>(cm, nc, run_cnt, nullptr, nullptr);
-    SDGP_CHECK_LAUNCH();
-    std::vector<int32_t> cnt(kp.n1);
-    SDGP_HIP(hipMemcpyAsync(cnt.data(), run_cnt, kp.n1 * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
-    SDGP_HIP(hipStreamSynchronize(c->stream));
-    std::vector<int32_t> ptr(kp.n1 + 1, 0);
-    for (int i = 0; i < kp.n1; ++i) ptr[i + 1] = ptr[i] + cnt[i];
-    int32_t* run_ptr = c->get<int32_t>(S_RUN_PTR, kp.n1 + 1);
-    SDGP_HIP(hipMemcpyAsync(run_ptr, ptr.data(), ptr.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
-    int2* runs = c->get<int2>(S_RUNS, ptr[kp.n1] > 0 ? ptr[kp.n1] : 1);
-    k_bump_runs<true><<<kp.n1, kBlock, 0, c->stream>>>(cm, nc, nullptr, run_ptr, runs);
-    SDGP_CHECK_LAUNCH();
+    int32_t* run_ptr = nullptr;
+    int2* runs = nullptr;
+    bump_runs(c, cm, nc, kp.n1, 1, S_RUN_CNT, S_RUN_POS, S_RUN_PTR, S_RUNS, &run_ptr, &runs);
     A.run_ptr = run_ptr;
     A.runs = runs;
   }
@@ -1040,37 +1051,13 @@ std::vector<PopAssembled> assemble_population(Ctx* c, const Sorted& s, const sdg
   A.runs = nullptr;
   A.use_bumps = (d.combine == SDGP_COMBINE_SUM && n1 > 0) ? 1 : 0;
   if (A.use_bumps) {
-    int32_t* run_cnt = c->get<int32_t>(S_POP_RUNCNT, (size_t)B * n1);
-    for (int m = 0; m < B; ++m) pm[m].run_cnt = run_cnt + (size_t)m * n1;
-    upload();
-    k_bump_runs_pop<false><<<dim3(n1, 1, B), kBlock, 0, c->stream>>>(nc, dpm);
-    SDGP_CHECK_LAUNCH();
-    std::vector<int32_t> cnt((size_t)B * n1);
-    SDGP_HIP(hipMemcpyAsync(cnt.data(), run_cnt, cnt.size() * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
-    SDGP_HIP(hipStreamSynchronize(c->stream));
-    std::vector<int32_t> ptr((size_t)B * (n1 + 1), 0);
-    int64_t total = 0;
-    for (int m = 0; m < B; ++m) {
-      int32_t acc = 0;
-      for (int i = 0; i < n1; ++i) {
-        ptr[(size_t)m * (n1 + 1) + i] = acc;
-        acc += cnt[(size_t)m * n1 + i];
-      }
-      ptr[(size_t)m * (n1 + 1) + n1] = acc;
-      total += acc;
-    }
-    int32_t* run_ptr = c->get<int32_t>(S_POP_RUNPTR, ptr.size());
-    SDGP_HIP(hipMemcpyAsync(run_ptr, ptr.data(), ptr.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
-    int2* runs = c->get<int2>(S_POP_RUNS, (size_t)std::max<int64_t>(total, 1));
-    int64_t off = 0;
+    int32_t* run_ptr = nullptr;
+    int2* runs = nullptr;
+    bump_runs(c, cm, nc, n1, B, S_POP_RUNCNT, S_POP_RUNPOS, S_POP_RUNPTR, S_POP_RUNS, &run_ptr, &runs);
     for (int m = 0; m < B; ++m) {
       pm[m].run_ptr = run_ptr + (size_t)m * (n1 + 1);
-      pm[m].runs = runs + off;
-      off += ptr[(size_t)m * (n1 + 1) + n1];
+      pm[m].runs = runs;                     // run pointers index the one array of all members
     }
-    upload();
-    k_bump_runs_pop<true><<<dim3(n1, 1, B), kBlock, 0, c->stream>>>(nc, dpm);
-    SDGP_CHECK_LAUNCH();
   }
   // candidate intervals per cell: counts, one scan over all members'
   // concatenated counts (global offsets into one interval array), fill

@@ -88,7 +88,7 @@ bool tune_cache_put(const std::string& path, const std::string& key, const TuneC
 // Workspace slots.
 enum Slot {
   S_KEYS, S_KEYS_ALT, S_IDX, S_PERM, S_XS, S_YS, S_CELL_START, S_BBOX,
-  S_F, S_M, S_BP, S_CELLMASK, S_RUN_CNT, S_RUN_PTR, S_RUNS, S_IV_CNT, S_IV_PTR, S_IV,
+  S_F, S_M, S_BP, S_CELLMASK, S_RUN_CNT, S_RUN_POS, S_RUN_PTR, S_RUNS, S_IV_CNT, S_IV_PTR, S_IV,
   S_ROW_NNZ, S_ROW_PTR, S_COL, S_VAL, S_SORT_TMP, S_COL2, S_VAL2, S_ROWLEN2,
   S_CG_X, S_CG_R, S_CG_P, S_CG_Q, S_CG_SCAL, S_CG_PART, S_CG_HIST_A, S_CG_HIST_B,
   S_CG_STATE, S_ZBITS, S_SLQ_WORK, S_SLQ_OUT, S_ADJ_ROW, S_ADJ_G, S_ADJ_PART,
@@ -97,7 +97,7 @@ enum Slot {
   S_MORTON_KEYS, S_MORTON_KEYS2, S_MORTON_IDS, S_MORTON_ORDER, S_MORTON_SZ, S_MORTON_OFF, S_SCHED,
   S_CG_SRED, S_CG_WRED, S_CG_LNB, S_CG_LCNT, S_CG_LSLOT, S_CG_UCNT, S_CG_UPTR, S_CG_UCOL, S_CG_UVAL, S_QF, S_QM, S_KXX, S_QIV_CNT, S_QIV_PTR, S_QIV, S_QROW_NNZ, S_QROW_PTR, S_QCOL, S_QVAL,
   // population assembly (all members at once)
-  S_POP_ARGS, S_POP_RARGS, S_POP_BP, S_POP_F, S_POP_M, S_POP_CM, S_POP_RUNCNT, S_POP_RUNPTR, S_POP_RUNS,
+  S_POP_ARGS, S_POP_RARGS, S_POP_BP, S_POP_F, S_POP_M, S_POP_CM, S_POP_RUNCNT, S_POP_RUNPOS, S_POP_RUNPTR, S_POP_RUNS,
   S_POP_IVCNT, S_POP_IVPTR, S_POP_IV, S_POP_ROWNNZ, S_POP_SCAN, S_POP_ROWPTR, S_POP_COL, S_POP_VAL, S_POP_CAND,
   S_POP_GRAM, S_POP_SINV,
   S_NUM
