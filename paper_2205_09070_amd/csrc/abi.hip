@@ -253,7 +253,7 @@ sdgp_status sdgp_kernel_nnz(sdgp_ctx* ctx, const sdgp_kernel_desc* desc, const d
   return guarded(ctx, [&] {
     require(desc && x && nnz_out, "NULL argument");
     validate(*desc, h, n);
-    Sorted s = order_points(ctx, x, n, desc->dim, h[1]);
+    Sorted s = order_points(ctx, x, n, desc->dim, h[1], false);
     Assembled as = assemble_all(ctx, s, *desc, h, true, nullptr);
     *nnz_out = as.A.nnz;
   });
@@ -265,7 +265,7 @@ sdgp_status sdgp_kernel_assemble(sdgp_ctx* ctx, const sdgp_kernel_desc* desc, co
   sdgp_status st = guarded(ctx, [&] {
     require(desc && x && nnz_out && row_ptr, "NULL argument");
     validate(*desc, h, n);
-    Sorted s = order_points(ctx, x, n, desc->dim, h[1]);
+    Sorted s = order_points(ctx, x, n, desc->dim, h[1], false);
     Assembled as = assemble_all(ctx, s, *desc, h, add_noise != 0, nullptr);
     *nnz_out = as.A.nnz;
     if (as.A.nnz > capacity) throw Error(SDGP_ERR_CAPACITY, "capacity smaller than nnz");
@@ -282,7 +282,7 @@ sdgp_status sdgp_kernel_assemble_sorted(sdgp_ctx* ctx, const sdgp_kernel_desc* d
   return guarded(ctx, [&] {
     require(desc && x && nnz_out && row_ptr && perm, "NULL argument");
     validate(*desc, h, n);
-    Sorted s = order_points(ctx, x, n, desc->dim, h[1]);
+    Sorted s = order_points(ctx, x, n, desc->dim, h[1], false);
     Assembled as = assemble_all(ctx, s, *desc, h, add_noise != 0, nullptr);
     *nnz_out = as.A.nnz;
     if (as.A.nnz > capacity) throw Error(SDGP_ERR_CAPACITY, "capacity smaller than nnz");

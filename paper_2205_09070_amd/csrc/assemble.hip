@@ -758,9 +758,10 @@ void validate(const sdgp_kernel_desc& d, const double* h, int64_t n) {
     }
 }
 
-Sorted order_points(Ctx* c, const double* x, int64_t n, int dim, double r_cell) {
+Sorted order_points(Ctx* c, const double* x, int64_t n, int dim, double r_cell, bool with_schedule) {
   Sorted s;
   s.n = n;
+  s.sched = nullptr;
   // bounding box
   const int nb = std::min<int64_t>(1024, (n + kBlock - 1) / kBlock);
   double* part = c->get<double>(S_BBOX, (size_t)nb * 2 * kMaxDim);
@@ -832,8 +833,9 @@ Sorted order_points(Ctx* c, const double* x, int64_t n, int dim, double r_cell) 
   // Row schedule: the sorted points in Morton (Z-curve) order of their
   // coordinates quantised to 2^mb steps per axis; consecutive schedule
   // positions are spatial neighbours at every scale, so a window of rows in
-  // flight gathers from a compact neighbourhood.
-  {
+  // flight gathers from a compact neighbourhood.  Only the solver and the
+  // adjoint walk it; assembly alone does not need it.
+  if (with_schedule) {
     MortonQ mq;
     mq.dim = dim;
     mq.bits = std::min(16, 62 / dim);

@@ -231,7 +231,9 @@ void validate_shape(const sdgp_kernel_desc& d, int64_t n);
 void validate(const sdgp_kernel_desc& d, const double* h, int64_t n);
 
 // Sort points into grid cells whose side is at least r_cell.
-Sorted order_points(Ctx* c, const double* x, int64_t n, int dim, double r_cell);
+// with_schedule: also the Morton row schedule (sched; null otherwise), which
+// the solver and the adjoint walk.
+Sorted order_points(Ctx* c, const double* x, int64_t n, int dim, double r_cell, bool with_schedule = true);
 void gather_vector(Ctx* c, const Sorted& s, const double* src, double* dst);
 Bumps bump_precompute(Ctx* c, const Sorted& s, const KParams& kp, const double* h);
 // Candidate column intervals per cell (pruning); returns interval count.
