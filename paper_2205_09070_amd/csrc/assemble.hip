@@ -145,38 +145,59 @@ __global__ void k_point_morton(const double4* __restrict__ xs, int64_t n, Morton
 // F[s, i] = sum_j a_ij exp(beta_ij - beta_ij / (1 - q_ij(x_s))) over the
 // balls that strictly contain x_s (q < 1, decided as |x-c|^2 < r^2), and the
 // membership mask M[s] (bit i: x_s inside some ball of bump function i).
-__device__ __forceinline__ void bumps_at(const double4* __restrict__ xs, int64_t s, int dim, int n1, int n2,
-                                         const double* __restrict__ bp, double* __restrict__ F,
-                                         uint64_t* __restrict__ M) {
-  const double4 p = xs[s];
+// One block of kBlock points: each thread evaluates its point's F values
+// 16 bump functions at a time into an LDS tile, and the block writes the
+// tile out row-contiguously (16 consecutive lanes per 128-byte row piece),
+// so F is written in whole cache lines instead of one 8-byte word per lane
+// at a stride of n1 doubles.
+constexpr int kFT = 16;   // bump functions per tile
+
+__device__ __forceinline__ void bumps_block(const double4* __restrict__ xs, int64_t n, int dim, int n1, int n2,
+                                            const double* __restrict__ bp, double* __restrict__ F,
+                                            uint64_t* __restrict__ M) {
+  __shared__ double tile[kBlock][kFT + 1];
+  const int t = threadIdx.x;
+  const int64_t s0 = (int64_t)blockIdx.x * kBlock;
+  const int64_t s = s0 + t;
+  const bool live = s < n;
+  const double4 p = live ? xs[s] : make_double4(0.0, 0.0, 0.0, 0.0);
   const int stride = 3 + dim;
   uint64_t m = 0;
-  for (int i = 0; i < n1; ++i) {
-    double f = 0.0;
-    for (int j = 0; j < n2; ++j) {
-      const double* q = bp + (i * n2 + j) * stride;
-      double d2 = 0.0;
-      for (int k = 0; k < dim; ++k) {
-        double d = comp(p, k) - q[3 + k];
-        d2 += d * d;
+  for (int i0 = 0; i0 < n1; i0 += kFT) {
+    const int wt = min(kFT, n1 - i0);
+    for (int ii = 0; ii < wt; ++ii) {
+      const int i = i0 + ii;
+      double f = 0.0;
+      for (int j = 0; j < n2; ++j) {
+        const double* q = bp + (i * n2 + j) * stride;
+        double d2 = 0.0;
+        for (int k = 0; k < dim; ++k) {
+          double d = comp(p, k) - q[3 + k];
+          d2 += d * d;
+        }
+        const double r2 = q[2] * q[2];
+        if (d2 < r2) {
+          const double qq = d2 / r2;
+          f += q[0] * exp(q[1] - q[1] / (1.0 - qq));
+          m |= (1ull << i);
+        }
       }
-      const double r2 = q[2] * q[2];
-      if (d2 < r2) {
-        const double qq = d2 / r2;
-        f += q[0] * exp(q[1] - q[1] / (1.0 - qq));
-        m |= (1ull << i);
-      }
+      tile[t][ii] = f;
     }
-    F[s * n1 + i] = f;
+    __syncthreads();
+    for (int e = t; e < kBlock * wt; e += kBlock) {
+      const int r = e / wt, cc = e - r * wt;
+      if (s0 + r < n) F[(s0 + r) * n1 + i0 + cc] = tile[r][cc];
+    }
+    __syncthreads();
   }
-  M[s] = m;
+  if (live) M[s] = m;
 }
 
-__global__ void k_bumps(const double4* __restrict__ xs, int64_t n, int dim, int n1, int n2,
-                        const double* __restrict__ bp, double* __restrict__ F,
-                        uint64_t* __restrict__ M) {
-  const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (s < n) bumps_at(xs, s, dim, n1, n2, bp, F, M);
+__global__ __launch_bounds__(kBlock) void k_bumps(const double4* __restrict__ xs, int64_t n, int dim, int n1,
+                                                  int n2, const double* __restrict__ bp, double* __restrict__ F,
+                                                  uint64_t* __restrict__ M) {
+  bumps_block(xs, n, dim, n1, n2, bp, F, M);
 }
 
 // Per-member storage of the population assembly: every population kernel
@@ -198,11 +219,10 @@ struct PopMember {
   unsigned long long* cand;  // candidate-pair counter
 };
 
-__global__ void k_bumps_pop(const double4* __restrict__ xs, int64_t n, int dim, int n1, int n2,
-                            const PopMember* __restrict__ pm) {
-  const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kBlock) void k_bumps_pop(const double4* __restrict__ xs, int64_t n, int dim, int n1,
+                                                      int n2, const PopMember* __restrict__ pm) {
   const PopMember& P = pm[blockIdx.z];
-  if (s < n) bumps_at(xs, s, dim, n1, n2, P.bp, P.F, P.M);
+  bumps_block(xs, n, dim, n1, n2, P.bp, P.F, P.M);
 }
 
 // ---------------------------------------------------------------- pruning
@@ -460,8 +480,26 @@ struct RowArgs {
 // row's output position persists in LDS across chunks.  Cells with more
 // than 1024 rows are processed in row groups.
 constexpr int kCC = 512;      // staged candidates per chunk
-constexpr int kCRows = 1024;  // rows per row group
+constexpr int kCRows = 256;   // rows per row group
 constexpr int kIvWin = kBlock;  // intervals per window
+
+// Value of a stored entry (row a with bump values Fa, column b): the kernel
+// of the stored-pattern predicate's pair, plus the noise on the diagonal.
+__device__ __forceinline__ double entry_value(const RowArgs& A, int64_t a, const double* Fa, int32_t b, double d2,
+                                              uint64_t mm) {
+  double psi = 0.0;
+  if (d2 < A.rc2) psi = core_psi(sqrt(d2) / A.r_core, A.core, A.ell);
+  double B = 0.0;
+  const double* Fb = A.F + (int64_t)b * A.n1;
+  while (mm) {
+    const int i = __builtin_ctzll(mm);
+    mm &= mm - 1;
+    B += Fa[i] * Fb[i];
+  }
+  double kv = A.combine == 0 ? A.sigma2 * psi * B : A.sigma2 * psi + B;
+  if (b == a && A.add_noise) kv += A.noise;
+  return kv;
+}
 
 template <bool kFill>
 __device__ __forceinline__ void cell_rows_body(const RowArgs& A, int64_t* __restrict__ row_nnz,
@@ -476,6 +514,13 @@ __device__ __forceinline__ void cell_rows_body(const RowArgs& A, int64_t* __rest
   __shared__ int64_t spos[kCRows];
   __shared__ int32_t wb[kIvWin];        // window: first point of each interval
   __shared__ int32_t wpre[kIvWin + 1];  // window: exclusive prefix of the lengths
+  // fill: per wavefront, the kept entries of the current row compacted in
+  // order (column, squared distance, common bump mask), so that values are
+  // computed and stored 64 at a time with every lane busy
+  constexpr int kCB = kFill ? 2 * kWave : 1;
+  __shared__ int32_t kb_col[kBlock / kWave][kCB];
+  __shared__ double kb_d2[kBlock / kWave][kCB];
+  __shared__ uint64_t kb_mm[kBlock / kWave][kCB];
   const int64_t c = blockIdx.x;
   const int32_t r0 = A.cell_start[c], r1 = A.cell_start[c + 1];
   if (r1 <= r0) return;                       // uniform: empty cell
@@ -523,6 +568,7 @@ __device__ __forceinline__ void cell_rows_body(const RowArgs& A, int64_t* __rest
           const uint64_t Ma = A.M[a];
           const double* Fa = A.F + a * (int64_t)A.n1;
           int64_t pos = spos[r];
+          int nk = 0;                         // compacted kept entries (fill; uniform)
           for (int j0 = 0; j0 < filled; j0 += kWave) {
             const int k = j0 + lane;
             bool keep = false, core = false;
@@ -539,24 +585,49 @@ __device__ __forceinline__ void cell_rows_body(const RowArgs& A, int64_t* __rest
               if (A.core_only) mm = 0;
             }
             const uint64_t bal = ballot64(keep);
-            if (kFill && keep) {
-              double psi = 0.0;
-              if (core) psi = core_psi(sqrt(d2) / A.r_core, A.core, A.ell);
-              double B = 0.0;
-              const double* Fb = A.F + (int64_t)b * A.n1;
-              uint64_t tm = mm;
-              while (tm) {
-                const int i = __builtin_ctzll(tm);
-                tm &= tm - 1;
-                B += Fa[i] * Fb[i];
-              }
-              double kv = A.combine == 0 ? A.sigma2 * psi * B : A.sigma2 * psi + B;
-              if (b == a && A.add_noise) kv += A.noise;
-              const int64_t o = pos + lanes_below(bal);
-              col[o] = b;
-              val[o] = kv;
+            if (!kFill) {
+              pos += __popcll(bal);
+              continue;
             }
-            pos += __popcll(bal);
+            if (keep) {
+              const int q = nk + lanes_below(bal);
+              kb_col[w][q] = b;
+              kb_d2[w][q] = d2;
+              kb_mm[w][q] = mm;
+            }
+            nk += __popcll(bal);
+            if (nk >= kWave) {                // 64 buffered: values and stores with every lane
+              __builtin_amdgcn_wave_barrier();
+              const int32_t bb = kb_col[w][lane];
+              col[pos + lane] = bb;
+              val[pos + lane] = entry_value(A, a, Fa, bb, kb_d2[w][lane], kb_mm[w][lane]);
+              pos += kWave;
+              nk -= kWave;
+              __builtin_amdgcn_wave_barrier();
+              int32_t mc = 0;
+              double md = 0.0;
+              uint64_t mb = 0;
+              if (lane < nk) {
+                mc = kb_col[w][kWave + lane];
+                md = kb_d2[w][kWave + lane];
+                mb = kb_mm[w][kWave + lane];
+              }
+              __builtin_amdgcn_wave_barrier();
+              if (lane < nk) {
+                kb_col[w][lane] = mc;
+                kb_d2[w][lane] = md;
+                kb_mm[w][lane] = mb;
+              }
+            }
+          }
+          if (kFill && nk > 0) {              // the rest of the row's kept entries of this chunk
+            __builtin_amdgcn_wave_barrier();
+            if (lane < nk) {
+              const int32_t bb = kb_col[w][lane];
+              col[pos + lane] = bb;
+              val[pos + lane] = entry_value(A, a, Fa, bb, kb_d2[w][lane], kb_mm[w][lane]);
+            }
+            pos += nk;
           }
           if (lane == 0) spos[r] = pos;
         }
