@@ -476,11 +476,12 @@ struct RowArgs {
 // instead of once per row.  The cell's intervals are read in windows of 256
 // (one per thread) with their exclusive length prefix from a block scan, so
 // every thread finds its candidate of a chunk by a binary search in LDS.
+// The row group's own points and masks are staged in LDS as well.
 // Columns stay ascending (chunks follow the sorted disjoint intervals); each
 // row's output position persists in LDS across chunks.  Cells with more
-// than 1024 rows are processed in row groups.
+// than 64 rows are processed in row groups.
 constexpr int kCC = 512;      // staged candidates per chunk
-constexpr int kCRows = 256;   // rows per row group
+constexpr int kCRows = 64;    // rows per row group
 constexpr int kIvWin = kBlock;  // intervals per window
 
 // Value of a stored entry (row a with bump values Fa, column b): the kernel
@@ -512,6 +513,8 @@ __device__ __forceinline__ void cell_rows_body(const RowArgs& A, int64_t* __rest
   __shared__ uint64_t sm[kCC];
   __shared__ int32_t sb[kCC];
   __shared__ int64_t spos[kCRows];
+  __shared__ double4 rx[kCRows];        // the row group's points and bump masks
+  __shared__ uint64_t rmk[kCRows];
   __shared__ int32_t wb[kIvWin];        // window: first point of each interval
   __shared__ int32_t wpre[kIvWin + 1];  // window: exclusive prefix of the lengths
   // fill: per wavefront, the kept entries of the current row compacted in
@@ -530,7 +533,11 @@ __device__ __forceinline__ void cell_rows_body(const RowArgs& A, int64_t* __rest
   unsigned long long ncand = 0;               // candidates per row (thread 0)
   for (int32_t g0 = r0; g0 < r1; g0 += kCRows) {
     const int nr = min(r1 - g0, kCRows);
-    for (int r = t; r < nr; r += kBlock) spos[r] = kFill ? row_ptr[g0 + r] : 0;
+    for (int r = t; r < nr; r += kBlock) {
+      spos[r] = kFill ? row_ptr[g0 + r] : 0;
+      rx[r] = A.xs[g0 + r];
+      rmk[r] = A.M[g0 + r];
+    }
     for (int32_t q0 = i0; q0 < i1; q0 += kIvWin) {
       const int nw = min(i1 - q0, kIvWin);
       int len = 0;
@@ -564,8 +571,8 @@ __device__ __forceinline__ void cell_rows_body(const RowArgs& A, int64_t* __rest
         __syncthreads();
         for (int r = w; r < nr; r += kWaves) {
           const int64_t a = (int64_t)g0 + r;
-          const double4 xa = A.xs[a];
-          const uint64_t Ma = A.M[a];
+          const double4 xa = rx[r];
+          const uint64_t Ma = rmk[r];
           const double* Fa = A.F + a * (int64_t)A.n1;
           int64_t pos = spos[r];
           int nk = 0;                         // compacted kept entries (fill; uniform)

@@ -129,6 +129,62 @@ __global__ __launch_bounds__(256) void k_spmv(int64_t n, const int64_t* __restri
   }
 }
 
+// SpMV with paired loads: 16 lanes per row, four rows per wavefront, 16 rows
+// per 256-thread block.  A row's entries are read in 16-byte-aligned pairs
+// (one 8-byte column pair and one 16-byte value pair per lane; pair halves
+// outside the row are masked), two pairs per lane in flight and their four
+// gathers issued together.  A pair is only loaded whole when its second
+// entry exists in the arrays (nnz = row_ptr[n]); the last entry of the
+// matrix is read alone.  Needs val 16-byte and col 8-byte aligned.
+constexpr int kSpw = 16;
+__global__ __launch_bounds__(256) void k_spmv_w(int64_t n, const int64_t* __restrict__ row_ptr,
+                                                const int32_t* __restrict__ col, const double* __restrict__ val,
+                                                const double* __restrict__ x, double* __restrict__ y) {
+  constexpr int G = 256 / kSpw;
+  const int64_t nnz = row_ptr[n];
+  const int sub = threadIdx.x & (kSpw - 1);
+  const int r = threadIdx.x / kSpw;
+  const int xcd = blockIdx.x & 7;
+  const int64_t bi = blockIdx.x >> 3, nbx = gridDim.x >> 3;
+  const int64_t nx = (n + 7) >> 3, lo = xcd * nx, hi = min(n, lo + nx);
+  for (int64_t base = lo + bi * G; base < hi; base += nbx * G) {
+    const int64_t a = base + r;
+    double acc = 0.0;
+    if (a < hi) {
+      const int64_t k0 = row_ptr[a], k1 = row_ptr[a + 1];
+      for (int64_t e = (k0 & ~(int64_t)1) + 2 * sub; e < k1; e += 4 * kSpw) {
+        int cj[4] = {0, 0, 0, 0};
+        double vj[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int64_t ep = e + 2 * kSpw * h;
+          if (ep < k1) {
+            if (ep + 1 < nnz) {
+              const int2 cc = *reinterpret_cast<const int2*>(col + ep);
+              const double2 vv = *reinterpret_cast<const double2*>(val + ep);
+              cj[2 * h] = cc.x;
+              cj[2 * h + 1] = cc.y;
+              vj[2 * h] = ep >= k0 ? vv.x : 0.0;
+              vj[2 * h + 1] = ep + 1 < k1 ? vv.y : 0.0;
+            } else {
+              cj[2 * h] = col[ep];
+              vj[2 * h] = ep >= k0 ? val[ep] : 0.0;
+            }
+          }
+        }
+        double xv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) xv[u] = x[cj[u]];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc += vj[u] * xv[u];
+      }
+    }
+#pragma unroll
+    for (int o = kSpw / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kSpw);
+    if (a < hi && sub == 0) y[a] = acc;
+  }
+}
+
 // ------------------------------------------------------------ utilities
 __global__ void k_dot_part(const double* __restrict__ a, int64_t sa, const double* __restrict__ b,
                            int64_t sb, int64_t n, double* __restrict__ part) {
@@ -298,6 +354,15 @@ void spmm(Ctx* c, const Csr& A, const double* X, int R, double* Y) {
   require(R >= 1 && R <= (1 << 20), "R must be in 1..2^20");
   const int64_t cu = std::max(8, c->cu_count);
   if (R == 1) {
+    const bool aligned = (reinterpret_cast<uintptr_t>(A.val) % 16) == 0 && (reinterpret_cast<uintptr_t>(A.col) % 8) == 0;
+    if (aligned) {
+      // 16 rows per block step, up to 32768 blocks
+      int64_t blocks = std::min<int64_t>((A.n + 15) / 16, 32768);
+      blocks = std::max<int64_t>(8, (blocks + 7) / 8 * 8);
+      k_spmv_w<<<(unsigned)blocks, 256, 0, c->stream>>>(A.n, A.row_ptr, A.col, A.val, X, Y);
+      SDGP_CHECK_LAUNCH();
+      return;
+    }
     // 8 rows per block step, up to 32768 blocks
     int64_t blocks = std::min<int64_t>((A.n + 7) / 8, 32768);
     blocks = std::max<int64_t>(8, (blocks + 7) / 8 * 8);
