@@ -140,6 +140,7 @@ def population(args, sd, wl, torch):
     est = sd.estimator(probes=args.probes, seed=1, cg_rtol=args.rtol, cg_max_iter=20000, precond=pc,
                        operator_form=op)
     ctx = sd.Context(0)
+    ctx.set_option("autotune", args.autotune)
     print("population: N=%d B=%d" % (w.x.shape[0], B), file=sys.stderr, flush=True)
     # warm-up: one member each way
     ctx.lml_grad(w.desc, x, y, H[0], est)
@@ -153,7 +154,9 @@ def population(args, sd, wl, torch):
     vb, gb, st, infos = ctx.lml_grad_batched(w.desc, x, y, H, est)
     torch.cuda.synchronize()
     tb = time.perf_counter() - t0
-    print("batched: %.2f s" % tb, file=sys.stderr, flush=True)
+    shape_b = {k: ctx.get_option("last_" + k) for k in ("spmm_blocks", "update_blocks", "union_spmm", "fw_mfma",
+                                                         "tuned")}
+    print("batched: %.2f s, CG launch shape %s" % (tb, shape_b), file=sys.stderr, flush=True)
     ctx.set_option("graph", 0)
     vs = np.zeros(B)
     its = []
@@ -177,6 +180,7 @@ def population(args, sd, wl, torch):
                                   "heights ~ U(0, 1), SUM combine, %d probes, CG rtol %g, preconditioner %s, "
                                   "operator %s" % (w.x.shape[0], B, args.probes, args.rtol, args.precond,
                                                    args.operator)},
+           "cg_launch_shape_batched": shape_b,
            "member_status": [int(v) for v in st], "cg_iters": its,
            "nnz_per_row": [v / w.x.shape[0] for v in nnz],
            "max_rel_diff_batched_vs_sequential": rel}

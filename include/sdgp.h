@@ -171,7 +171,8 @@ sdgp_status sdgp_set_timing(sdgp_ctx* ctx, int enable);
  * "autotune" (0 off, 1 default, 2): the CG launch-shape autotuner.  The
  * first solve of a problem class (device architecture, bump-function count
  * class, right-hand-side slabs, single or population, log2 of the rows,
- * entries per row in half-octaves, operator form, preconditioner) times
+ * entries per row in half-octaves for single solves, operator form,
+ * preconditioner) times
  * candidate shapes -- SpMM over union lists or CSR rows, SpMM grid, update
  * grid, F w product form -- in short trial solves of 24 CG iterations on
  * the call's own matrix, keeps the fastest, and stores it (see
@@ -230,7 +231,10 @@ sdgp_status sdgp_kernel_assemble(sdgp_ctx* ctx, const sdgp_kernel_desc* desc,
 
 /* Same matrix in the library's locality order (points sorted by grid cell):
  * row/column s of the output is caller point perm[s]; perm: device
- * int32[n].  This is the order the solver runs in. */
+ * int32[n].  This is the order the solver runs in.  The count's prefix sum
+ * and the fill write row_ptr / col / val directly (no staging copy); when
+ * nnz exceeds capacity the call returns SDGP_ERR_CAPACITY with row_ptr
+ * written and col / val / perm untouched. */
 sdgp_status sdgp_kernel_assemble_sorted(sdgp_ctx* ctx, const sdgp_kernel_desc* desc,
                                         const double* x, int64_t n, const double* h,
                                         int add_noise, int64_t* row_ptr, int32_t* col,

@@ -91,7 +91,7 @@ struct Assembled {
 };
 
 Assembled assemble_all(Ctx* c, const Sorted& s, const sdgp_kernel_desc& d, const double* h, bool add_noise,
-                       PhaseTimer* t, bool core_only = false) {
+                       PhaseTimer* t, bool core_only = false, const CsrOut* out = nullptr) {
   Assembled r;
   r.kp = make_params(d, h);
   r.b = bump_precompute(c, s, r.kp, h);
@@ -100,7 +100,7 @@ Assembled assemble_all(Ctx* c, const Sorted& s, const sdgp_kernel_desc& d, const
   int2* iv;
   prune(c, s, r.kp, r.b, &iv_ptr, &iv, core_only);
   if (t) t->mark(3);
-  r.A = assemble_sorted(c, s, r.kp, r.b, iv_ptr, iv, add_noise, &r.candidates, t, core_only);
+  r.A = assemble_sorted(c, s, r.kp, r.b, iv_ptr, iv, add_noise, &r.candidates, t, core_only, out);
   if (t) t->mark(5);
   return r;
 }
@@ -283,13 +283,12 @@ sdgp_status sdgp_kernel_assemble_sorted(sdgp_ctx* ctx, const sdgp_kernel_desc* d
     require(desc && x && nnz_out && row_ptr && perm, "NULL argument");
     validate(*desc, h, n);
     Sorted s = order_points(ctx, x, n, desc->dim, h[1], false);
-    Assembled as = assemble_all(ctx, s, *desc, h, add_noise != 0, nullptr);
+    // the count's scan and the fill write the caller's arrays directly
+    const CsrOut out{row_ptr, col, val, (col && val) ? capacity : -1};
+    Assembled as = assemble_all(ctx, s, *desc, h, add_noise != 0, nullptr, false, &out);
     *nnz_out = as.A.nnz;
     if (as.A.nnz > capacity) throw Error(SDGP_ERR_CAPACITY, "capacity smaller than nnz");
     require(col && val, "NULL col/val");
-    SDGP_HIP(hipMemcpyAsync(row_ptr, as.A.row_ptr, (n + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice, ctx->stream));
-    SDGP_HIP(hipMemcpyAsync(col, as.A.col, as.A.nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, ctx->stream));
-    SDGP_HIP(hipMemcpyAsync(val, as.A.val, as.A.nnz * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
     SDGP_HIP(hipMemcpyAsync(perm, s.perm, n * sizeof(int32_t), hipMemcpyDeviceToDevice, ctx->stream));
     SDGP_HIP(hipStreamSynchronize(ctx->stream));
   });

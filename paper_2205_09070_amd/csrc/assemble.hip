@@ -1041,7 +1041,8 @@ static RowArgs row_args(const Sorted& s, const KParams& kp, const Bumps& b, cons
 }
 
 Csr assemble_sorted(Ctx* c, const Sorted& s, const KParams& kp, const Bumps& b, const int32_t* iv_ptr,
-                    const int2* iv, bool add_noise, int64_t* candidates, PhaseTimer* t, bool core_only) {
+                    const int2* iv, bool add_noise, int64_t* candidates, PhaseTimer* t, bool core_only,
+                    const CsrOut* out) {
   const int64_t n = s.n;
   RowArgs A = row_args(s, kp, b, iv_ptr, iv, add_noise, core_only);
   int64_t* row_nnz = c->get<int64_t>(S_ROW_NNZ, n + 1);
@@ -1052,7 +1053,7 @@ Csr assemble_sorted(Ctx* c, const Sorted& s, const KParams& kp, const Bumps& b, 
   require(ncell < 0x7fffffff, "too many cells");
   k_cell_rows<false><<<(unsigned)ncell, kBlock, 0, c->stream>>>(A, row_nnz, cand, nullptr, nullptr, nullptr);
   SDGP_CHECK_LAUNCH();
-  int64_t* row_ptr = c->get<int64_t>(S_ROW_PTR, n + 1);
+  int64_t* row_ptr = out ? out->row_ptr : c->get<int64_t>(S_ROW_PTR, n + 1);
   size_t tb = 0;
   SDGP_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, row_nnz, row_ptr, (int)(n + 1), c->stream));
   void* tmp = c->get<char>(S_SORT_TMP, tb);
@@ -1064,11 +1065,15 @@ Csr assemble_sorted(Ctx* c, const Sorted& s, const KParams& kp, const Bumps& b, 
   SDGP_HIP(hipStreamSynchronize(c->stream));
   if (candidates) *candidates = (int64_t)ncand;
   if (t) t->mark(4);
-  int32_t* col = c->get<int32_t>(S_COL, nnz);
-  double* val = c->get<double>(S_VAL, nnz);
+  Csr k;
+  if (out && nnz > out->capacity) {   // the caller's arrays are too small: no fill
+    k.n = n; k.nnz = nnz; k.row_ptr = row_ptr; k.col = nullptr; k.val = nullptr;
+    return k;
+  }
+  int32_t* col = out ? out->col : c->get<int32_t>(S_COL, nnz);
+  double* val = out ? out->val : c->get<double>(S_VAL, nnz);
   k_cell_rows<true><<<(unsigned)ncell, kBlock, 0, c->stream>>>(A, nullptr, nullptr, row_ptr, col, val);
   SDGP_CHECK_LAUNCH();
-  Csr k;
   k.n = n; k.nnz = nnz; k.row_ptr = row_ptr; k.col = col; k.val = val;
   return k;
 }

@@ -1831,7 +1831,8 @@ int update_blocks_per_cu(int NI, bool fw) {
 // ------------------------------------------------------------ autotuner
 // The first solve of a problem class (architecture, bump-function class,
 // right-hand-side slabs, population or single, log2 of the rows, entries
-// per row in half-octaves, operator form, preconditioner) times candidate
+// per row in half-octaves for single solves, operator form, preconditioner)
+// times candidate
 // launch shapes on the caller's own problem: short trial solves of
 // kTrialIters CG iterations each, timed with HIP events over the
 // iterations after the first kTrialSkip.  Stage 1 sweeps the SpMM form
@@ -1849,13 +1850,16 @@ struct ShapeGuard {   // leaves trial mode on every exit path
   ~ShapeGuard() { c->in_trial = false; }
 };
 
+// A population's members differ in their entries per row, so its class
+// leaves that out (one tuned shape serves every population of the class).
 std::string tune_key(const Ctx* c, int NI, int ns, int B, int64_t n, int64_t nnz, bool lr, bool pc) {
   const double per_row = std::max(1.0, (double)nnz / (double)std::max<int64_t>(n, 1));
   int lgn = 0;
   while (((int64_t)2 << lgn) <= n) ++lgn;
+  const int rb = B > 1 ? -1 : (int)std::lround(2.0 * std::log2(per_row));
   char buf[160];
   std::snprintf(buf, sizeof(buf), "%s|ni%d|ns%d|b%d|n%d|r%d|lr%d|pc%d", c->arch.c_str(), NI, ns, B > 1 ? 2 : 1,
-                lgn, (int)std::lround(2.0 * std::log2(per_row)), lr ? 1 : 0, pc ? 1 : 0);
+                lgn, rb, lr ? 1 : 0, pc ? 1 : 0);
   return buf;
 }
 

@@ -240,11 +240,22 @@ Bumps bump_precompute(Ctx* c, const Sorted& s, const KParams& kp, const double* 
 // core_only: only the core supports (the factored SUM operator).
 void prune(Ctx* c, const Sorted& s, const KParams& kp, const Bumps& b,
            int32_t** iv_ptr, int2** iv, bool core_only = false);
-// Count + fill; the CSR lives in context buffers (S_ROW_PTR, S_COL, S_VAL).
+// Caller-owned CSR arrays: row_ptr (n + 1), col and val (capacity entries).
+struct CsrOut {
+  int64_t* row_ptr;
+  int32_t* col;
+  double* val;
+  int64_t capacity;
+};
+// Count + fill; the CSR lives in context buffers (S_ROW_PTR, S_COL, S_VAL),
+// or in the caller's arrays when out is given (then, when nnz exceeds
+// out->capacity, row_ptr is written and the fill is skipped: col / val of
+// the returned Csr are null).
 // core_only: store the core part only (K_core + noise on the diagonal).
 Csr assemble_sorted(Ctx* c, const Sorted& s, const KParams& kp, const Bumps& b,
                     const int32_t* iv_ptr, const int2* iv, bool add_noise,
-                    int64_t* candidates, PhaseTimer* t, bool core_only = false);
+                    int64_t* candidates, PhaseTimer* t, bool core_only = false,
+                    const CsrOut* out = nullptr);
 // Population assembly: members m = 0..B-1 with hyperparameters h[m] on the
 // shared ordering s, every phase (bump values, cell masks, bump runs,
 // candidate intervals, count, scan, fill) one launch with the member as

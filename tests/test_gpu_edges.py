@@ -119,3 +119,59 @@ def test_workspace_cap_gives_oom():
     assert v1 == v0 and np.array_equal(g1, g0)
     with pytest.raises(sd.SdgpError):
         c.set_option("workspace_cap", -1)
+
+
+def test_assemble_capacity_checked():
+    """sdgp_kernel_assemble_sorted writes the caller's arrays directly: with
+    too little capacity it returns CAPACITY, reports the count, and leaves
+    col / val / perm untouched; with enough it returns the oracle's matrix
+    (in the returned order) and row_ptr ends at the count."""
+    gu.need_gpu()
+    import ctypes as C
+    import torch
+    import paper_2205_09070_amd as sd
+    from paper_2205_09070_amd import _lib
+    from oracle import kernel as okn
+    w = wl.random_small(1500, 3, 4, 2, 8, combine=1, per_row=20.0, noise_var=1e-2)
+    c = gu.ctx()
+    x = gu.dev(w.x)
+    n = w.x.shape[0]
+    nnz = c.kernel_nnz(w.desc, x, w.h)
+    gu.log("assemble capacity: n=%d nnz=%d" % (n, nnz))
+    d = _lib.desc_of(w.desc)
+    hh = np.ascontiguousarray(w.h, dtype=np.float64)
+    dev = x.device
+    for cap in (nnz - 1, nnz):
+        row_ptr = torch.full((n + 1,), -7, dtype=torch.int64, device=dev)
+        col = torch.full((nnz,), -5, dtype=torch.int32, device=dev)
+        val = torch.full((nnz,), -3.0, dtype=torch.float64, device=dev)
+        perm = torch.full((n,), -9, dtype=torch.int32, device=dev)
+        out = C.c_int64(0)
+        st = c.lib.sdgp_kernel_assemble_sorted(
+            c.h, C.byref(d), C.c_void_p(x.data_ptr()), n, hh.ctypes.data_as(C.c_void_p), 1,
+            C.c_void_p(row_ptr.data_ptr()), C.c_void_p(col.data_ptr()), C.c_void_p(val.data_ptr()),
+            C.c_void_p(perm.data_ptr()), cap, C.byref(out))
+        torch.cuda.synchronize()
+        assert out.value == nnz
+        if cap < nnz:
+            assert st == sd.CAPACITY
+            assert (col == -5).all() and (val == -3.0).all() and (perm == -9).all()
+            continue
+        assert st == sd.OK
+        rp = row_ptr.cpu().numpy()
+        assert rp[0] == 0 and rp[-1] == nnz and (np.diff(rp) >= 1).all()
+        p = perm.cpu().numpy()
+        assert np.array_equal(np.sort(p), np.arange(n))
+        ix = np.ix_(p, p)
+        K = okn.kernel_matrix(w.desc, w.h, w.x)[ix]
+        pat = okn.pattern(w.desc, w.h, w.x)[ix]
+        bnd = okn.boundary_pairs(w.desc, w.h, w.x)[ix]
+        cc, vv = col.cpu().numpy(), val.cpu().numpy()
+        rows = np.repeat(np.arange(n), np.diff(rp))
+        gpat = np.zeros((n, n), dtype=bool)
+        gpat[rows, cc] = True
+        assert not ((gpat != pat) & ~bnd).any()
+        Kg = np.zeros((n, n))
+        Kg[rows, cc] = vv
+        both = gpat & pat
+        assert gu.check_k_entries(Kg[both], K[both], np.abs(np.diag(K)).max()).all()
