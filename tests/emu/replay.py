@@ -1,0 +1,168 @@
+"""Replays GPU test configurations on the CPU emulation build under
+AddressSanitizer (run in a child process started with emu_env()):
+
+    python tests/emu/replay.py LIB CASE
+
+Cases:
+  batched_factored  the population of test_batched_matches_single[factored]
+                    (4000 points in 3-D, 4 x 2 bumps, 5 members, 12 probes,
+                    low-rank preconditioner, factored operator): the batched
+                    call, then one single call per member, compared as that
+                    test compares them;
+  ci                small cases of every device path of the current tree
+                    against the oracle (the CPU test suite runs this one);
+  lowrank_small     one single evaluation (1200 points, 2-D), low-rank
+                    preconditioner, both operators, against the oracle's
+                    estimator on the same probes;
+  block_<id>        the block-preconditioner cases of the withdrawn device
+                    path (builds of a source tree that has it).
+Every device access the library makes is checked by the sanitizer; a report
+aborts the process.
+"""
+from __future__ import annotations
+
+import sys
+import time
+
+import numpy as np
+
+from oracle import estimators as es
+from paper_2205_09070_amd import _lib
+from paper_2205_09070_amd import workloads as wl
+from tests.emu.emu_ctx import EmuContext
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+def population(n, dim, n1, n2, members, seed, per_row=12.0):
+    """The population recipe of the GPU batched tests."""
+    w = wl.random_small(n, dim, n1, n2, seed, combine=1, per_row=per_row, noise_var=1e-3)
+    rng = np.random.default_rng(seed + 1000)
+    H = np.tile(w.h, (members, 1))
+    for m in range(members):
+        p = wl.unpack_hyper(w.desc, w.h)
+        s2 = 1.0 if m == 0 else rng.uniform(0.5, 1.5)
+        rc = p["r_core"] * (1.0 if m == 0 else rng.uniform(0.6, 0.95))
+        a = p["a"] * (1.0 if m == 0 else rng.uniform(0.3, 1.0, size=p["a"].shape))
+        H[m] = wl.pack_hyper(w.desc, s2, rc, a, p["beta"], p["r"], p["c"], p["noise_var"])
+    return w, H
+
+
+def case_batched_factored(lib):
+    w, H = population(4000, 3, 4, 2, 5, 7)
+    est = _lib.estimator(probes=12, seed=77, cg_rtol=1e-11, cg_max_iter=5000, precond=1, operator_form=1)
+    c = EmuContext(lib)
+    t = time.time()
+    v, g, st, infos = c.lml_grad_batched(w.desc, w.x, w.y, H, est)
+    log("batched: status %s, %.0f s" % (list(st), time.time() - t))
+    ok = True
+    for m in range(H.shape[0]):
+        v1, g1, i1 = c.lml_grad(w.desc, w.x, w.y, H[m], est)
+        d = abs(v[m] - v1) / abs(v1)
+        gd = np.abs(g[m] - g1).max() / np.abs(g1).max()
+        log("  member %d batched %.15g single %.15g (rel %.2e, grad %.2e) iters %d/%d"
+            % (m, v[m], v1, d, gd, infos[m].cg_iters, i1.cg_iters))
+        ok &= st[m] == 0 and d <= 1e-9 and gd <= 1e-6
+    return ok
+
+
+def case_lowrank_small(lib):
+    ok = True
+    w = wl.random_small(1200, 2, 3, 2, 24, combine=1, per_row=14.0, noise_var=1e-3)
+    v0, g0, ld0, _ = es.preconditioned_lml_grad(w.desc, w.h, w.x, w.y, 9090, 12, 400)
+    for op in (0, 1):
+        c = EmuContext(lib)
+        est = _lib.estimator(probes=12, seed=9090, cg_rtol=1e-12, cg_max_iter=5000, precond=1, operator_form=op)
+        v, g, info = c.lml_grad(w.desc, w.x, w.y, w.h, est)
+        d = abs(v - v0) / abs(v0)
+        gd = np.abs(g - g0).max() / np.abs(g0).max()
+        log("operator %d: lml %.15g oracle %.15g (rel %.2e, grad %.2e) iters %d" % (op, v, v0, d, gd,
+                                                                                  info.cg_iters))
+        ok &= d <= 1e-7 and gd <= 1e-5
+    return ok
+
+
+def case_ci(lib):
+    """Small cases of every device path of the current library, against the
+    oracle: assembly (sorted order), single evaluations with the low-rank
+    preconditioner (assembled operator, CSR SpMM, broadcast F w products;
+    factored operator, union-list SpMM, matrix-core F w products), and a
+    population with graph replay, all on the oracle's probes."""
+    from oracle import kernel as okn
+    ok = True
+    w = wl.random_small(200, 2, 3, 2, 11, combine=1, per_row=12.0, noise_var=1e-2)
+    c = EmuContext(lib)
+    nnz = c.kernel_nnz(w.desc, w.x, w.h)
+    rp, col, val, perm = c.kernel_assemble_sorted(w.desc, w.x, w.h, nnz)
+    K = okn.kernel_matrix(w.desc, w.h, w.x)[np.ix_(perm, perm)]
+    Kg = np.zeros_like(K)
+    Kg[np.repeat(np.arange(len(perm)), np.diff(rp)), col] = val
+    d = np.abs(Kg - K).max() / np.abs(K).max()
+    log("assembly: nnz %d, max difference %.2e of max |K|" % (nnz, d))
+    ok &= d <= 1e-13
+    v0, g0, _, _ = es.preconditioned_lml_grad(w.desc, w.h, w.x, w.y, 3, 4, 400)
+    for op, opts in ((0, {"union_spmm": 0, "fw_mfma": 0}), (1, {"union_spmm": 1, "fw_mfma": 1})):
+        c = EmuContext(lib)
+        for k, v in opts.items():
+            c.set_option(k, v)
+        est = _lib.estimator(probes=4, seed=3, cg_rtol=1e-11, cg_max_iter=3000, precond=1, operator_form=op)
+        v, g, info = c.lml_grad(w.desc, w.x, w.y, w.h, est)
+        d = abs(v - v0) / abs(v0)
+        gd = np.abs(g - g0).max() / np.abs(g0).max()
+        log("operator %d %s: lml rel %.2e, grad %.2e, iters %d" % (op, opts, d, gd, info.cg_iters))
+        ok &= d <= 1e-8 and gd <= 1e-6
+    wp, H = population(200, 2, 2, 2, 3, 5)
+    c = EmuContext(lib)
+    c.set_option("graph", 1)
+    est = _lib.estimator(probes=4, seed=8, cg_rtol=1e-11, cg_max_iter=3000, precond=1)
+    v, g, st, infos = c.lml_grad_batched(wp.desc, wp.x, wp.y, H, est)
+    for m in range(H.shape[0]):
+        vm, gm, _, _ = es.preconditioned_lml_grad(wp.desc, H[m], wp.x, wp.y, 8, 4, 400)
+        d = abs(v[m] - vm) / abs(vm)
+        gd = np.abs(g[m] - gm).max() / np.abs(gm).max()
+        log("population member %d (graph replay): lml rel %.2e, grad %.2e" % (m, d, gd))
+        ok &= st[m] == 0 and d <= 1e-8 and gd <= 1e-6
+    return ok
+
+
+BLOCK_CASES = {"2d-n1_3-factored": (2, 3, 1203, True), "3d-n1_5-factored": (3, 5, 1200, True),
+               "3d-n1_12-assembled": (3, 12, 1211, False), "3d-n1_0": (3, 0, 1000, True)}
+
+
+def case_block(lib, name):
+    from tests import sched_ref
+    dim, n1, n, factored = BLOCK_CASES[name]
+    w = wl.random_small(n, dim, n1, 2, 21 + n1, combine=1, per_row=14.0, noise_var=1e-3)
+    P, seed = 12, 9090
+    tiles = sched_ref.schedule_tiles(w.x, wl.unpack_hyper(w.desc, w.h)["r_core"])
+    c = EmuContext(lib)
+    est = _lib.estimator(probes=P, seed=seed, cg_rtol=1e-12, cg_max_iter=5000, precond=2,
+                         operator_form=1 if factored else 0)
+    t = time.time()
+    v, g, info = c.lml_grad(w.desc, w.x, w.y, w.h, est)
+    v0, g0, ld0, se0 = es.block_preconditioned_lml_grad(w.desc, w.h, w.x, w.y, seed, P, 400, tiles,
+                                                        factored=factored)
+    d = abs(v - v0) / abs(v0)
+    gd = np.abs(g - g0).max() / np.abs(g0).max()
+    log("block %s: lml %.15g oracle %.15g (rel %.2e, grad %.2e) logdet %.12g / %.12g iters %d, %.0f s"
+        % (name, v, v0, d, gd, info.logdet, ld0, info.cg_iters, time.time() - t))
+    return d <= 1e-7 and gd <= 1e-5
+
+
+if __name__ == "__main__":
+    lib, case = sys.argv[1], sys.argv[2]
+    log("replay %s on %s" % (case, lib))
+    if case == "batched_factored":
+        good = case_batched_factored(lib)
+    elif case == "ci":
+        good = case_ci(lib)
+    elif case == "lowrank_small":
+        good = case_lowrank_small(lib)
+    elif case.startswith("block_"):
+        good = case_block(lib, case[len("block_"):])
+    else:
+        raise SystemExit("unknown case " + case)
+    log("replay %s: %s" % (case, "results agree" if good else "RESULTS DIFFER"))
+    sys.exit(0 if good else 3)
