@@ -189,7 +189,7 @@ def population(args, sd, wl, torch):
 
 def assembly_only(args, sd, w, wdesc, x, torch):
     """K timed full-K assemblies (sdgp_kernel_assemble_sorted: order, bump
-    values, pruning, count, scan, fill) after one untimed one."""
+    values, pruning, count and fill) after one untimed one."""
     ctx = sd.Context(0)
     s = ctx.stream
     nnz = ctx.kernel_nnz(w.desc, x, w.h)

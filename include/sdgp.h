@@ -234,7 +234,7 @@ sdgp_status sdgp_kernel_assemble(sdgp_ctx* ctx, const sdgp_kernel_desc* desc,
  * int32[n].  This is the order the solver runs in.  The count's prefix sum
  * and the fill write row_ptr / col / val directly (no staging copy); when
  * nnz exceeds capacity the call returns SDGP_ERR_CAPACITY with row_ptr
- * written and col / val / perm untouched. */
+ * written (row_ptr[n] = nnz) and col / val / perm untouched. */
 sdgp_status sdgp_kernel_assemble_sorted(sdgp_ctx* ctx, const sdgp_kernel_desc* desc,
                                         const double* x, int64_t n, const double* h,
                                         int add_noise, int64_t* row_ptr, int32_t* col,

@@ -466,6 +466,11 @@ struct RowArgs {
   int dim, n1, core, ell, combine, add_noise;
   int core_only;   // keep only the core part (+ diagonal), values without B
   double sigma2, r_core, rc2, noise;
+  // keep masks of the count (one 64-bit word per row and 64-candidate step;
+  // cell c's words start at mask_ptr[c], step-major over the cell's rows),
+  // read by the masked fill; null: not recorded
+  const int64_t* mask_ptr = nullptr;
+  uint64_t* mask = nullptr;
 };
 
 // Count / fill with LDS-staged point tiles: one workgroup per cell.  All rows
@@ -502,37 +507,85 @@ __device__ __forceinline__ double entry_value(const RowArgs& A, int64_t a, const
   return kv;
 }
 
+// LDS of the row kernels.  The fill needs the compaction buffers (kCB = 2
+// wavefronts' worth of entries per wavefront); the count uses one entry.
 template <bool kFill>
-__device__ __forceinline__ void cell_rows_body(const RowArgs& A, int64_t* __restrict__ row_nnz,
-                                               unsigned long long* __restrict__ cand_total,
-                                               const int64_t* __restrict__ row_ptr,
-                                               int32_t* __restrict__ col, double* __restrict__ val) {
+struct CellLds {
   typedef hipcub::BlockScan<int, kBlock> Scan;
-  __shared__ typename Scan::TempStorage scan_tmp;
-  __shared__ double4 sx[kCC];
-  __shared__ uint64_t sm[kCC];
-  __shared__ int32_t sb[kCC];
-  __shared__ int64_t spos[kCRows];
-  __shared__ double4 rx[kCRows];        // the row group's points and bump masks
-  __shared__ uint64_t rmk[kCRows];
-  __shared__ int32_t wb[kIvWin];        // window: first point of each interval
-  __shared__ int32_t wpre[kIvWin + 1];  // window: exclusive prefix of the lengths
+  static constexpr int kCB = kFill ? 2 * kWave : 1;
+  typename Scan::TempStorage scan_tmp;
+  double4 sx[kCC];
+  uint64_t sm[kCC];
+  int32_t sb[kCC];
+  int64_t spos[kCRows];
+  double4 rx[kCRows];        // the row group's points and bump masks
+  uint64_t rmk[kCRows];
+  int32_t wb[kIvWin];        // window: first point of each interval
+  int32_t wpre[kIvWin + 1];  // window: exclusive prefix of the lengths
   // fill: per wavefront, the kept entries of the current row compacted in
   // order (column, squared distance, common bump mask), so that values are
   // computed and stored 64 at a time with every lane busy
-  constexpr int kCB = kFill ? 2 * kWave : 1;
-  __shared__ int32_t kb_col[kBlock / kWave][kCB];
-  __shared__ double kb_d2[kBlock / kWave][kCB];
-  __shared__ uint64_t kb_mm[kBlock / kWave][kCB];
-  const int64_t c = blockIdx.x;
+  int32_t kb_col[kBlock / kWave][kCB];
+  double kb_d2[kBlock / kWave][kCB];
+  uint64_t kb_mm[kBlock / kWave][kCB];
+};
+
+// Position of the r-th (from 0) set bit of m (r < popcount(m)).
+__device__ __forceinline__ int select_bit(uint64_t m, int r) {
+  int pos = 0;
+  int c = __popc((uint32_t)m);
+  if (r >= c) { r -= c; m >>= 32; pos += 32; }
+  c = __popc((uint32_t)m & 0xffffu);
+  if (r >= c) { r -= c; m >>= 16; pos += 16; }
+  c = __popc((uint32_t)m & 0xffu);
+  if (r >= c) { r -= c; m >>= 8; pos += 8; }
+  c = __popc((uint32_t)m & 0xfu);
+  if (r >= c) { r -= c; m >>= 4; pos += 4; }
+  c = __popc((uint32_t)m & 0x3u);
+  if (r >= c) { r -= c; m >>= 2; pos += 2; }
+  if (r >= (int)(m & 1u)) pos += 1;
+  return pos;
+}
+
+// Modes of the row body: the count (row_nnz[a] = stored entries of row a,
+// candidates added to cand_total, keep masks recorded when A.mask is set),
+// the fill that tests every candidate again (compacting each row's kept
+// entries in LDS), and the fill from the count's keep masks (every lane
+// takes one kept entry: no candidate is tested twice).
+constexpr int kRowCount = 0, kRowFillTest = 1, kRowFillMasked = 2;
+
+// Rows of cell c in mode kMode.  L: the block's LDS (a fill-sized one
+// serves every mode).
+template <int kMode, class Lds>
+__device__ __forceinline__ void cell_rows_body(const RowArgs& A, int64_t c, Lds& L, int64_t* __restrict__ row_nnz,
+                                               unsigned long long* __restrict__ cand_total,
+                                               const int64_t* __restrict__ row_ptr,
+                                               int32_t* __restrict__ col, double* __restrict__ val) {
+  constexpr bool kFill = kMode != kRowCount;
+  typedef typename Lds::Scan Scan;
+  auto& scan_tmp = L.scan_tmp;
+  auto& sx = L.sx;
+  auto& sm = L.sm;
+  auto& sb = L.sb;
+  auto& spos = L.spos;
+  auto& rx = L.rx;
+  auto& rmk = L.rmk;
+  auto& wb = L.wb;
+  auto& wpre = L.wpre;
+  auto& kb_col = L.kb_col;
+  auto& kb_d2 = L.kb_d2;
+  auto& kb_mm = L.kb_mm;
   const int32_t r0 = A.cell_start[c], r1 = A.cell_start[c + 1];
   if (r1 <= r0) return;                       // uniform: empty cell
   const int32_t i0 = A.iv_ptr[c], i1 = A.iv_ptr[c + 1];
   const int t = threadIdx.x, lane = lane_id(), w = t >> 6;
   constexpr int kWaves = kBlock / kWave;
   unsigned long long ncand = 0;               // candidates per row (thread 0)
+  const int64_t nrc = r1 - r0;                // rows of the cell (mask stride)
+  const int64_t mbase = A.mask ? A.mask_ptr[c] : 0;
   for (int32_t g0 = r0; g0 < r1; g0 += kCRows) {
     const int nr = min(r1 - g0, kCRows);
+    int st0 = 0;                              // 64-candidate steps before the chunk (uniform)
     for (int r = t; r < nr; r += kBlock) {
       spos[r] = kFill ? row_ptr[g0 + r] : 0;
       rx[r] = A.xs[g0 + r];
@@ -569,6 +622,46 @@ __device__ __forceinline__ void cell_rows_body(const RowArgs& A, int64_t* __rest
           sb[k] = b;
         }
         __syncthreads();
+        const int nsteps = (filled + kWave - 1) / kWave;   // <= kCC / 64
+        if constexpr (kMode == kRowFillMasked) {
+          for (int r = w; r < nr; r += kWaves) {
+            const int64_t a = (int64_t)g0 + r;
+            const double4 xa = rx[r];
+            const uint64_t Ma = A.core_only ? 0 : rmk[r];
+            const double* Fa = A.F + a * (int64_t)A.n1;
+            const int64_t pos = spos[r];      // read by every lane before lane 0 moves it on
+            const uint64_t mw = lane < nsteps ? A.mask[mbase + (int64_t)(st0 + lane) * nrc + (g0 - r0 + r)] : 0;
+            uint64_t m[kCC / kWave];
+            int pre[kCC / kWave + 1];
+            pre[0] = 0;
+#pragma unroll
+            for (int q = 0; q < kCC / kWave; ++q) {
+              const int lo = readlane_i32((int)(uint32_t)mw, q), hi = readlane_i32((int)(uint32_t)(mw >> 32), q);
+              m[q] = ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+              pre[q + 1] = pre[q] + __popcll(m[q]);
+            }
+            const int nkeep = pre[kCC / kWave];
+            for (int e = lane; e < nkeep; e += kWave) {
+              int q = 0;                      // step of kept entry e: pre[q] <= e < pre[q + 1]
+#pragma unroll
+              for (int z = 1; z < kCC / kWave; ++z) q += pre[z] <= e ? 1 : 0;
+              uint64_t mq = m[0];
+              int pq = 0;
+#pragma unroll
+              for (int z = 1; z < kCC / kWave; ++z)
+                if (q == z) { mq = m[z]; pq = pre[z]; }
+              const int k = q * kWave + select_bit(mq, e - pq);
+              const int32_t b = sb[k];
+              const double d2 = dist2(xa, sx[k], A.dim);
+              col[pos + e] = b;
+              val[pos + e] = entry_value(A, a, Fa, b, d2, Ma & sm[k]);
+            }
+            if (lane == 0) spos[r] = pos + nkeep;
+          }
+          st0 += nsteps;
+          __syncthreads();
+          continue;
+        }
         for (int r = w; r < nr; r += kWaves) {
           const int64_t a = (int64_t)g0 + r;
           const double4 xa = rx[r];
@@ -594,6 +687,7 @@ __device__ __forceinline__ void cell_rows_body(const RowArgs& A, int64_t* __rest
             const uint64_t bal = ballot64(keep);
             if (!kFill) {
               pos += __popcll(bal);
+              if (A.mask && lane == 0) A.mask[mbase + (int64_t)(st0 + j0 / kWave) * nrc + (g0 - r0 + r)] = bal;
               continue;
             }
             if (keep) {
@@ -638,6 +732,7 @@ __device__ __forceinline__ void cell_rows_body(const RowArgs& A, int64_t* __rest
           }
           if (lane == 0) spos[r] = pos;
         }
+        st0 += nsteps;
         __syncthreads();
       }
       __syncthreads();                        // window storage and scan storage free again
@@ -649,12 +744,13 @@ __device__ __forceinline__ void cell_rows_body(const RowArgs& A, int64_t* __rest
   if (!kFill && t == 0) atomicAdd(cand_total, ncand * (unsigned long long)(r1 - r0));
 }
 
-template <bool kFill>
+template <int kMode>
 __global__ __launch_bounds__(kBlock) void k_cell_rows(RowArgs A, int64_t* __restrict__ row_nnz,
                                                       unsigned long long* __restrict__ cand_total,
                                                       const int64_t* __restrict__ row_ptr,
                                                       int32_t* __restrict__ col, double* __restrict__ val) {
-  cell_rows_body<kFill>(A, row_nnz, cand_total, row_ptr, col, val);
+  __shared__ CellLds<kMode == kRowFillTest> L;
+  cell_rows_body<kMode>(A, blockIdx.x, L, row_nnz, cand_total, row_ptr, col, val);
 }
 
 // Population form: member z's rows (RowArgs[z] holds its kernel
@@ -663,7 +759,9 @@ template <bool kFill>
 __global__ __launch_bounds__(kBlock) void k_cell_rows_pop(const RowArgs* __restrict__ ra,
                                                           const PopMember* __restrict__ pm) {
   const PopMember& P = pm[blockIdx.z];
-  cell_rows_body<kFill>(ra[blockIdx.z], P.row_nnz, P.cand, P.row_ptr, P.col, P.val);
+  __shared__ CellLds<kFill> L;
+  cell_rows_body<kFill ? kRowFillTest : kRowCount>(ra[blockIdx.z], blockIdx.x, L, P.row_nnz, P.cand, P.row_ptr,
+                                                   P.col, P.val);
 }
 
 // row_ptr of every member from one scan over the members' concatenated
@@ -1040,18 +1138,54 @@ static RowArgs row_args(const Sorted& s, const KParams& kp, const Bumps& b, cons
   return A;
 }
 
-Csr assemble_sorted(Ctx* c, const Sorted& s, const KParams& kp, const Bumps& b, const int32_t* iv_ptr,
-                    const int2* iv, bool add_noise, int64_t* candidates, PhaseTimer* t, bool core_only,
-                    const CsrOut* out) {
+// Keep-mask words of each cell: its rows times its 64-candidate steps (the
+// row body walks the cell's intervals in windows of kIvWin and each
+// window's candidates in chunks of kCC, a multiple of 64, so a window of
+// `tot` candidates takes ceil(tot / 64) steps).  words[nc] = 0.
+__global__ void k_mask_words(const int32_t* __restrict__ cell_start, const int32_t* __restrict__ iv_ptr,
+                             const int2* __restrict__ iv, int64_t nc, int64_t* __restrict__ words) {
+  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c > nc) return;
+  if (c == nc) {
+    words[nc] = 0;
+    return;
+  }
+  const int32_t i0 = iv_ptr[c], i1 = iv_ptr[c + 1];
+  int64_t steps = 0;
+  for (int32_t q0 = i0; q0 < i1; q0 += kIvWin) {
+    const int32_t q1 = min(i1, q0 + kIvWin);
+    int64_t tot = 0;
+    for (int32_t q = q0; q < q1; ++q) tot += iv[q].y - iv[q].x;
+    steps += (tot + kWave - 1) / kWave;
+  }
+  words[c] = (int64_t)(cell_start[c + 1] - cell_start[c]) * steps;
+}
+
+// Count (recording keep masks), device-wide scan, host read of nnz, fill
+// from the masks.
+static Csr assemble_two_pass(Ctx* c, const Sorted& s, RowArgs A, int64_t* candidates, PhaseTimer* t,
+                             const CsrOut* out) {
   const int64_t n = s.n;
-  RowArgs A = row_args(s, kp, b, iv_ptr, iv, add_noise, core_only);
+  const int64_t ncell = s.grid.n_cells;
+  // keep masks of the count for the fill: offsets per cell, then storage
+  int64_t* mwords = c->get<int64_t>(S_MASK_CNT, ncell + 1);
+  k_mask_words<<<grid_for(ncell + 1, kBlock), kBlock, 0, c->stream>>>(s.cell_start, A.iv_ptr, A.iv, ncell, mwords);
+  SDGP_CHECK_LAUNCH();
+  int64_t* mptr = c->get<int64_t>(S_MASK_PTR, ncell + 1);
+  size_t tbm = 0;
+  SDGP_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tbm, mwords, mptr, (int)(ncell + 1), c->stream));
+  SDGP_HIP(hipcub::DeviceScan::ExclusiveSum(c->get<char>(S_SORT_TMP, tbm), tbm, mwords, mptr, (int)(ncell + 1),
+                                            c->stream));
+  int64_t nwords = 0;
+  SDGP_HIP(hipMemcpyAsync(&nwords, mptr + ncell, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+  SDGP_HIP(hipStreamSynchronize(c->stream));
+  A.mask_ptr = mptr;
+  A.mask = c->get<uint64_t>(S_MASK, nwords > 0 ? nwords : 1);
   int64_t* row_nnz = c->get<int64_t>(S_ROW_NNZ, n + 1);
   unsigned long long* cand = c->get<unsigned long long>(S_COUNTER, 4);
   SDGP_HIP(hipMemsetAsync(cand, 0, sizeof(unsigned long long), c->stream));
   SDGP_HIP(hipMemsetAsync(row_nnz + n, 0, sizeof(int64_t), c->stream));
-  const int64_t ncell = s.grid.n_cells;
-  require(ncell < 0x7fffffff, "too many cells");
-  k_cell_rows<false><<<(unsigned)ncell, kBlock, 0, c->stream>>>(A, row_nnz, cand, nullptr, nullptr, nullptr);
+  k_cell_rows<kRowCount><<<(unsigned)ncell, kBlock, 0, c->stream>>>(A, row_nnz, cand, nullptr, nullptr, nullptr);
   SDGP_CHECK_LAUNCH();
   int64_t* row_ptr = out ? out->row_ptr : c->get<int64_t>(S_ROW_PTR, n + 1);
   size_t tb = 0;
@@ -1072,10 +1206,18 @@ Csr assemble_sorted(Ctx* c, const Sorted& s, const KParams& kp, const Bumps& b, 
   }
   int32_t* col = out ? out->col : c->get<int32_t>(S_COL, nnz);
   double* val = out ? out->val : c->get<double>(S_VAL, nnz);
-  k_cell_rows<true><<<(unsigned)ncell, kBlock, 0, c->stream>>>(A, nullptr, nullptr, row_ptr, col, val);
+  k_cell_rows<kRowFillMasked><<<(unsigned)ncell, kBlock, 0, c->stream>>>(A, nullptr, nullptr, row_ptr, col, val);
   SDGP_CHECK_LAUNCH();
   k.n = n; k.nnz = nnz; k.row_ptr = row_ptr; k.col = col; k.val = val;
   return k;
+}
+
+Csr assemble_sorted(Ctx* c, const Sorted& s, const KParams& kp, const Bumps& b, const int32_t* iv_ptr,
+                    const int2* iv, bool add_noise, int64_t* candidates, PhaseTimer* t, bool core_only,
+                    const CsrOut* out) {
+  require(s.grid.n_cells < 0x7fffffff, "too many cells");
+  RowArgs A = row_args(s, kp, b, iv_ptr, iv, add_noise, core_only);
+  return assemble_two_pass(c, s, A, candidates, t, out);
 }
 
 std::vector<PopAssembled> assemble_population(Ctx* c, const Sorted& s, const sdgp_kernel_desc& d,

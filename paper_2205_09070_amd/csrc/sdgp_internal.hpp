@@ -92,7 +92,7 @@ enum Slot {
   S_ROW_NNZ, S_ROW_PTR, S_COL, S_VAL, S_SORT_TMP, S_COL2, S_VAL2, S_ROWLEN2,
   S_CG_X, S_CG_R, S_CG_P, S_CG_Q, S_CG_SCAL, S_CG_PART, S_CG_HIST_A, S_CG_HIST_B,
   S_CG_STATE, S_ZBITS, S_SLQ_WORK, S_SLQ_OUT, S_ADJ_ROW, S_ADJ_G, S_ADJ_PART,
-  S_RED_PART, S_RED_OUT, S_X0S, S_MISC, S_POST, S_COUNTER,
+  S_RED_PART, S_RED_OUT, S_X0S, S_MISC, S_POST, S_COUNTER, S_MASK_CNT, S_MASK_PTR, S_MASK,
   S_CG_V, S_CG_PART2, S_CG_ARGS, S_CG_PARTG, S_CG_G, S_CG_GP, S_PC_PART, S_PC_SINV, S_LR_PART, S_LR_FX, S_LR_FV,
   S_MORTON_KEYS, S_MORTON_KEYS2, S_MORTON_IDS, S_MORTON_ORDER, S_MORTON_SZ, S_MORTON_OFF, S_SCHED,
   S_CG_SRED, S_CG_WRED, S_CG_LNB, S_CG_LCNT, S_CG_LSLOT, S_CG_UCNT, S_CG_UPTR, S_CG_UCOL, S_CG_UVAL, S_QF, S_QM, S_KXX, S_QIV_CNT, S_QIV_PTR, S_QIV, S_QROW_NNZ, S_QROW_PTR, S_QCOL, S_QVAL,

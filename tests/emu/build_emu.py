@@ -88,7 +88,8 @@ def rewrite(text: str) -> str:
     return text
 
 
-def build(src_dir: str, out: str, jobs: int = 8, opt: str = "-O1", include: str = None, drops=()) -> str:
+def build(src_dir: str, out: str, jobs: int = 8, opt: str = "-O1", include: str = None, drops=(),
+          defines=()) -> str:
     gen = out + ".src"
     os.makedirs(gen, exist_ok=True)
     include = include or os.path.join(ROOT, "include")
@@ -109,7 +110,7 @@ def build(src_dir: str, out: str, jobs: int = 8, opt: str = "-O1", include: str 
     units.append(os.path.join(HERE, "hipemu.cpp"))
     flags = ["-std=c++17", opt, "-g", "-fPIC", "-fsanitize=address", "-shared-libsan", "-fno-omit-frame-pointer",
              "-Wno-unknown-attributes", "-Wno-unused-result", "-Wno-pass-failed",
-             "-I", os.path.join(HERE, "include"), "-I", HERE, "-I", include, "-I", gen]
+             "-I", os.path.join(HERE, "include"), "-I", HERE, "-I", include, "-I", gen] + ["-D" + d for d in defines]
 
     def cc(u):
         o = os.path.join(gen, os.path.basename(u) + ".o")
@@ -143,7 +144,8 @@ if __name__ == "__main__":
     ap.add_argument("--opt", default="-O1")
     ap.add_argument("--include", default=None, help="directory of sdgp.h (default: the repository's)")
     ap.add_argument("--drop", action="append", default=[], help="remove source lines containing this text")
+    ap.add_argument("--define", action="append", default=[], help="NAME=VALUE for the preprocessor")
     a = ap.parse_args()
     os.makedirs(os.path.dirname(a.out), exist_ok=True)
-    print(build(a.src, a.out, opt=a.opt, include=a.include, drops=a.drop))
+    print(build(a.src, a.out, opt=a.opt, include=a.include, drops=a.drop, defines=a.define))
     sys.exit(0)

@@ -63,6 +63,11 @@ class EmuContext:
     def set_option(self, name: str, value: int):
         self._check(self.lib.sdgp_set_option(self.h, name.encode(), int(value)))
 
+    def get_option(self, name: str) -> int:
+        v = _lib.I64(0)
+        self._check(self.lib.sdgp_get_option(self.h, name.encode(), C.byref(v)))
+        return int(v.value)
+
     def lml_grad(self, desc, x, y, h, est):
         x = np.ascontiguousarray(x, dtype=np.float64)
         y = np.ascontiguousarray(y, dtype=np.float64)
@@ -89,7 +94,7 @@ class EmuContext:
                                                    C.byref(est), _p(v), _p(g), _p(ms), C.cast(infos, _lib.VP)))
         return v, g, ms, list(infos)
 
-    def kernel_assemble_sorted(self, desc, x, h, nnz):
+    def kernel_assemble_sorted(self, desc, x, h, nnz, capacity=None):
         x = np.ascontiguousarray(x, dtype=np.float64)
         hh = np.ascontiguousarray(h, dtype=np.float64)
         n = x.shape[0]
@@ -99,8 +104,9 @@ class EmuContext:
         val = np.zeros(max(nnz, 1), dtype=np.float64)
         perm = np.zeros(n, dtype=np.int32)
         out = C.c_int64(0)
+        cap = col.shape[0] if capacity is None else capacity
         self._check(self.lib.sdgp_kernel_assemble_sorted(self.h, C.byref(d), _p(x), n, _p(hh), 1, _p(rp), _p(col),
-                                                         _p(val), _p(perm), col.shape[0], C.byref(out)))
+                                                         _p(val), _p(perm), cap, C.byref(out)))
         return rp, col[:out.value], val[:out.value], perm
 
     def kernel_nnz(self, desc, x, h):

@@ -93,26 +93,34 @@ def case_ci(lib):
     from oracle import kernel as okn
     ok = True
     w = wl.random_small(200, 2, 3, 2, 11, combine=1, per_row=12.0, noise_var=1e-2)
-    c = EmuContext(lib)
-    nnz = c.kernel_nnz(w.desc, w.x, w.h)
-    rp, col, val, perm = c.kernel_assemble_sorted(w.desc, w.x, w.h, nnz)
-    K = okn.kernel_matrix(w.desc, w.h, w.x)[np.ix_(perm, perm)]
-    Kg = np.zeros_like(K)
-    Kg[np.repeat(np.arange(len(perm)), np.diff(rp)), col] = val
-    d = np.abs(Kg - K).max() / np.abs(K).max()
-    log("assembly: nnz %d, max difference %.2e of max |K|" % (nnz, d))
-    ok &= d <= 1e-13
+    for rep in range(2):   # the second call reuses the context's storage
+        c = EmuContext(lib) if rep == 0 else c
+        nnz = c.kernel_nnz(w.desc, w.x, w.h)
+        try:
+            c.kernel_assemble_sorted(w.desc, w.x, w.h, nnz, capacity=nnz - 1)
+            ok = False
+            log("assembly with capacity nnz - 1 did not fail")
+        except _lib.SdgpError as e:
+            ok &= e.status == _lib.CAPACITY
+        rp, col, val, perm = c.kernel_assemble_sorted(w.desc, w.x, w.h, nnz)
+        K = okn.kernel_matrix(w.desc, w.h, w.x)[np.ix_(perm, perm)]
+        Kg = np.zeros_like(K)
+        Kg[np.repeat(np.arange(len(perm)), np.diff(rp)), col] = val
+        d = np.abs(Kg - K).max() / np.abs(K).max()
+        log("assembly (call %d): nnz %d, max difference %.2e of max |K|" % (rep, nnz, d))
+        ok &= d <= 1e-13 and rp[-1] == nnz
     v0, g0, _, _ = es.preconditioned_lml_grad(w.desc, w.h, w.x, w.y, 3, 4, 400)
     for op, opts in ((0, {"union_spmm": 0, "fw_mfma": 0}), (1, {"union_spmm": 1, "fw_mfma": 1})):
         c = EmuContext(lib)
         for k, v in opts.items():
             c.set_option(k, v)
         est = _lib.estimator(probes=4, seed=3, cg_rtol=1e-11, cg_max_iter=3000, precond=1, operator_form=op)
-        v, g, info = c.lml_grad(w.desc, w.x, w.y, w.h, est)
-        d = abs(v - v0) / abs(v0)
-        gd = np.abs(g - g0).max() / np.abs(g0).max()
-        log("operator %d %s: lml rel %.2e, grad %.2e, iters %d" % (op, opts, d, gd, info.cg_iters))
-        ok &= d <= 1e-8 and gd <= 1e-6
+        for rep in range(2):   # the second call assembles into the storage the first one left
+            v, g, info = c.lml_grad(w.desc, w.x, w.y, w.h, est)
+            d = abs(v - v0) / abs(v0)
+            gd = np.abs(g - g0).max() / np.abs(g0).max()
+            log("operator %d %s call %d: lml rel %.2e, grad %.2e, iters %d" % (op, opts, rep, d, gd, info.cg_iters))
+            ok &= d <= 1e-8 and gd <= 1e-6
     wp, H = population(200, 2, 2, 2, 3, 5)
     c = EmuContext(lib)
     c.set_option("graph", 1)

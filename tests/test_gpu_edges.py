@@ -123,9 +123,10 @@ def test_workspace_cap_gives_oom():
 
 def test_assemble_capacity_checked():
     """sdgp_kernel_assemble_sorted writes the caller's arrays directly: with
-    too little capacity it returns CAPACITY, reports the count, and leaves
-    col / val / perm untouched; with enough it returns the oracle's matrix
-    (in the returned order) and row_ptr ends at the count."""
+    too little capacity it returns CAPACITY, reports the count, writes
+    row_ptr and leaves col / val / perm untouched; with enough it returns
+    the oracle's matrix (in the returned order) and row_ptr ends at the
+    count."""
     gu.need_gpu()
     import ctypes as C
     import torch
@@ -156,6 +157,7 @@ def test_assemble_capacity_checked():
         if cap < nnz:
             assert st == sd.CAPACITY
             assert (col == -5).all() and (val == -3.0).all() and (perm == -9).all()
+            assert int(row_ptr[n]) == nnz
             continue
         assert st == sd.OK
         rp = row_ptr.cpu().numpy()
