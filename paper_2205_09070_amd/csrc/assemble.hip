@@ -509,10 +509,11 @@ __device__ __forceinline__ double entry_value(const RowArgs& A, int64_t a, const
 
 // LDS of the row kernels.  The fill needs the compaction buffers (kCB = 2
 // wavefronts' worth of entries per wavefront); the count uses one entry.
-template <bool kFill>
+template <bool kFill, bool kList = false>
 struct CellLds {
   typedef hipcub::BlockScan<int, kBlock> Scan;
   static constexpr int kCB = kFill ? 2 * kWave : 1;
+  static constexpr int kKL = kList ? kCC : 1;
   typename Scan::TempStorage scan_tmp;
   double4 sx[kCC];
   uint64_t sm[kCC];
@@ -528,30 +529,17 @@ struct CellLds {
   int32_t kb_col[kBlock / kWave][kCB];
   double kb_d2[kBlock / kWave][kCB];
   uint64_t kb_mm[kBlock / kWave][kCB];
+  // masked fill: per wavefront, the staged indices of the current row's
+  // kept candidates of the chunk, in order
+  int16_t kl[kBlock / kWave][kKL];
 };
-
-// Position of the r-th (from 0) set bit of m (r < popcount(m)).
-__device__ __forceinline__ int select_bit(uint64_t m, int r) {
-  int pos = 0;
-  int c = __popc((uint32_t)m);
-  if (r >= c) { r -= c; m >>= 32; pos += 32; }
-  c = __popc((uint32_t)m & 0xffffu);
-  if (r >= c) { r -= c; m >>= 16; pos += 16; }
-  c = __popc((uint32_t)m & 0xffu);
-  if (r >= c) { r -= c; m >>= 8; pos += 8; }
-  c = __popc((uint32_t)m & 0xfu);
-  if (r >= c) { r -= c; m >>= 4; pos += 4; }
-  c = __popc((uint32_t)m & 0x3u);
-  if (r >= c) { r -= c; m >>= 2; pos += 2; }
-  if (r >= (int)(m & 1u)) pos += 1;
-  return pos;
-}
 
 // Modes of the row body: the count (row_nnz[a] = stored entries of row a,
 // candidates added to cand_total, keep masks recorded when A.mask is set),
 // the fill that tests every candidate again (compacting each row's kept
-// entries in LDS), and the fill from the count's keep masks (every lane
-// takes one kept entry: no candidate is tested twice).
+// entries in LDS), and the fill from the count's keep masks (the masks'
+// set bits are listed per row in LDS and every lane takes one listed
+// entry: no candidate is tested twice).
 constexpr int kRowCount = 0, kRowFillTest = 1, kRowFillMasked = 2;
 
 // Rows of cell c in mode kMode.  L: the block's LDS (a fill-sized one
@@ -631,31 +619,22 @@ __device__ __forceinline__ void cell_rows_body(const RowArgs& A, int64_t c, Lds&
             const double* Fa = A.F + a * (int64_t)A.n1;
             const int64_t pos = spos[r];      // read by every lane before lane 0 moves it on
             const uint64_t mw = lane < nsteps ? A.mask[mbase + (int64_t)(st0 + lane) * nrc + (g0 - r0 + r)] : 0;
-            uint64_t m[kCC / kWave];
-            int pre[kCC / kWave + 1];
-            pre[0] = 0;
-#pragma unroll
-            for (int q = 0; q < kCC / kWave; ++q) {
-              const int lo = readlane_i32((int)(uint32_t)mw, q), hi = readlane_i32((int)(uint32_t)(mw >> 32), q);
-              m[q] = ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
-              pre[q + 1] = pre[q] + __popcll(m[q]);
+            int nkeep = 0;                    // uniform
+            for (int q = 0; q < nsteps; ++q) {
+              const uint64_t mq = ((uint64_t)(uint32_t)readlane_i32((int)(uint32_t)(mw >> 32), q) << 32) |
+                                  (uint32_t)readlane_i32((int)(uint32_t)mw, q);
+              if (mq >> lane & 1) L.kl[w][nkeep + lanes_below(mq)] = (int16_t)(q * kWave + lane);
+              nkeep += __popcll(mq);
             }
-            const int nkeep = pre[kCC / kWave];
+            __builtin_amdgcn_wave_barrier();
             for (int e = lane; e < nkeep; e += kWave) {
-              int q = 0;                      // step of kept entry e: pre[q] <= e < pre[q + 1]
-#pragma unroll
-              for (int z = 1; z < kCC / kWave; ++z) q += pre[z] <= e ? 1 : 0;
-              uint64_t mq = m[0];
-              int pq = 0;
-#pragma unroll
-              for (int z = 1; z < kCC / kWave; ++z)
-                if (q == z) { mq = m[z]; pq = pre[z]; }
-              const int k = q * kWave + select_bit(mq, e - pq);
+              const int k = L.kl[w][e];
               const int32_t b = sb[k];
               const double d2 = dist2(xa, sx[k], A.dim);
               col[pos + e] = b;
               val[pos + e] = entry_value(A, a, Fa, b, d2, Ma & sm[k]);
             }
+            __builtin_amdgcn_wave_barrier();  // the list is the next row's
             if (lane == 0) spos[r] = pos + nkeep;
           }
           st0 += nsteps;
@@ -749,7 +728,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_rows(RowArgs A, int64_t* __rest
                                                       unsigned long long* __restrict__ cand_total,
                                                       const int64_t* __restrict__ row_ptr,
                                                       int32_t* __restrict__ col, double* __restrict__ val) {
-  __shared__ CellLds<kMode == kRowFillTest> L;
+  __shared__ CellLds<kMode == kRowFillTest, kMode == kRowFillMasked> L;
   cell_rows_body<kMode>(A, blockIdx.x, L, row_nnz, cand_total, row_ptr, col, val);
 }
 
