@@ -129,14 +129,17 @@ __global__ __launch_bounds__(256) void k_spmv(int64_t n, const int64_t* __restri
   }
 }
 
-// SpMV with paired loads: 16 lanes per row, four rows per wavefront, 16 rows
-// per 256-thread block.  A row's entries are read in 16-byte-aligned pairs
+// SpMV with paired loads: 32 lanes per row, two rows per wavefront, 8 rows
+// per 256-thread block (measured at 1M points, ~90 entries per row: 32
+// lanes 0.341 ms, 16 lanes 0.366, 8 lanes 0.479, 64 lanes 0.383; two rows
+// per lane group or more pairs in flight no faster).  A row's entries are
+// read in 16-byte-aligned pairs
 // (one 8-byte column pair and one 16-byte value pair per lane; pair halves
 // outside the row are masked), two pairs per lane in flight and their four
 // gathers issued together.  A pair is only loaded whole when its second
 // entry exists in the arrays (nnz = row_ptr[n]); the last entry of the
 // matrix is read alone.  Needs val 16-byte and col 8-byte aligned.
-constexpr int kSpw = 16;
+constexpr int kSpw = 32;
 __global__ __launch_bounds__(256) void k_spmv_w(int64_t n, const int64_t* __restrict__ row_ptr,
                                                 const int32_t* __restrict__ col, const double* __restrict__ val,
                                                 const double* __restrict__ x, double* __restrict__ y) {
@@ -356,8 +359,8 @@ void spmm(Ctx* c, const Csr& A, const double* X, int R, double* Y) {
   if (R == 1) {
     const bool aligned = (reinterpret_cast<uintptr_t>(A.val) % 16) == 0 && (reinterpret_cast<uintptr_t>(A.col) % 8) == 0;
     if (aligned) {
-      // 16 rows per block step, up to 32768 blocks
-      int64_t blocks = std::min<int64_t>((A.n + 15) / 16, 32768);
+      // 8 rows per block step, up to 65528 blocks
+      int64_t blocks = std::min<int64_t>((A.n + 7) / 8, 65528);
       blocks = std::max<int64_t>(8, (blocks + 7) / 8 * 8);
       k_spmv_w<<<(unsigned)blocks, 256, 0, c->stream>>>(A.n, A.row_ptr, A.col, A.val, X, Y);
       SDGP_CHECK_LAUNCH();

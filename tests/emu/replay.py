@@ -109,6 +109,15 @@ def case_ci(lib):
         d = np.abs(Kg - K).max() / np.abs(K).max()
         log("assembly (call %d): nnz %d, max difference %.2e of max |K|" % (rep, nnz, d))
         ok &= d <= 1e-13 and rp[-1] == nnz
+        for R in (1, 3):   # the SpMV and the general SpMM on the returned CSR
+            X = np.ascontiguousarray(np.random.default_rng(R).standard_normal((len(perm), R)))
+            Y = np.zeros_like(X)
+            st = c.lib.sdgp_csr_spmm(c.h, len(perm), rp.ctypes.data, col.ctypes.data, val.ctypes.data,
+                                     X.ctypes.data, R, Y.ctypes.data)
+            ref = Kg @ X
+            d = np.abs(Y - ref).max() / np.abs(ref).max()
+            log("  csr_spmm R=%d: status %d, max difference %.2e" % (R, st, d))
+            ok &= st == 0 and d <= 1e-13
     v0, g0, _, _ = es.preconditioned_lml_grad(w.desc, w.h, w.x, w.y, 3, 4, 400)
     for op, opts in ((0, {"union_spmm": 0, "fw_mfma": 0}), (1, {"union_spmm": 1, "fw_mfma": 1})):
         c = EmuContext(lib)

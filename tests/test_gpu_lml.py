@@ -87,11 +87,14 @@ def test_stochastic_truncated_lanczos_matches_oracle_lanczos():
     assert abs(info.logdet - ld0) <= 1e-6 * abs(ld0)
 
 
-def test_spmm_matches_dense_product():
+@pytest.mark.parametrize("per_row", [20.0, 300.0])
+def test_spmm_matches_dense_product(per_row):
+    """R = 1 (the SpMV; at 300 neighbours per row the rows span several
+    128-entry steps of a 32-lane group) and wider right-hand sides."""
     gu.need_gpu()
     import torch
-    w = wl.random_small(900, 2, 2, 2, 1, per_row=20.0)
-    gu.log("spmm R in (1, 2, 5, 34, 64, 70)")
+    w = wl.random_small(900, 2, 2, 2, 1, per_row=per_row)
+    gu.log("spmm R in (1, 2, 5, 34, 64, 70), per_row %g" % per_row)
     c = gu.ctx()
     rp, col, val = c.kernel_assemble(w.desc, gu.dev(w.x), w.h)
     _, _, _, S = gu.csr_to_host(rp, col, val, w.x.shape[0])
