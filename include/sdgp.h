@@ -107,16 +107,27 @@ typedef struct {
  * solver's update pass, and the bump-parameter adjoint is formed from F^T X
  * and F^T V instead of a loop over the bump cliques.  Same results as the
  * assembled operator up to rounding; sdgp_info.nnz then counts the core
- * pattern.  SDGP_OPERATOR_ASSEMBLED (default) stores every entry of K. */
+ * pattern.  SDGP_OPERATOR_ASSEMBLED (default) stores every entry of K.
+ *
+ * probe_rtol (0 = cg_rtol): the tolerance of the probe columns' solves,
+ * whose only use is the stochastic log-det and trace estimates (Section
+ * 4: approximate log-determinants); y's solve keeps cg_rtol.  When every
+ * probe column has stopped while y still iterates, a single evaluation
+ * finishes y with the column-0 kernels only (a sparse matrix-vector
+ * product per iteration).  At the 1M-point workload probe_rtol 1e-6 moves
+ * the LML by 2e-13 and the gradient by 5e-10 (relative) against 1e-10,
+ * far inside the estimators' standard errors.  Batched evaluations apply
+ * the tolerance but keep every column in the launches. */
 typedef struct {
   int32_t probes;          /* P, 1..64 for Rademacher */
   int32_t lanczos_steps;   /* 0 = use every CG step */
   int32_t kind;            /* SDGP_PROBE_* */
   int32_t cg_max_iter;     /* > 0 */
   uint64_t seed;
-  double cg_rtol;          /* per column: |r| <= cg_rtol |b| */
+  double cg_rtol;          /* y (and identity / caller columns): |r| <= cg_rtol |b| */
   int32_t precond;         /* SDGP_PRECOND_* */
   int32_t operator_form;   /* SDGP_OPERATOR_* */
+  double probe_rtol;       /* >= 0; Rademacher probe columns (0 = cg_rtol) */
 } sdgp_estimator;
 
 /* Per-call diagnostics (all optional). ms[] phase times when timing is on:
@@ -194,7 +205,9 @@ sdgp_status sdgp_set_option(sdgp_ctx* ctx, const char* name, int64_t value);
  * shape of the context's last CG solve: "last_spmm_blocks",
  * "last_update_blocks", "last_union_spmm" (0/1), "last_fw_mfma" (0/1) and
  * "last_tuned" (0: options or defaults, 1: tuned shape read from the store,
- * 2: tuned during that call).  value: host.  Unknown name: INVALID_ARG. */
+ * 2: tuned during that call); "last_y_tail": iterations the last solve ran
+ * on y alone after every probe column had stopped (see probe_rtol).
+ * value: host.  Unknown name: INVALID_ARG. */
 sdgp_status sdgp_get_option(const sdgp_ctx* ctx, const char* name, int64_t* value);
 
 /* Persistent store of the autotuner: a JSON object in the file `path`

@@ -37,7 +37,7 @@ class KernelDesc(C.Structure):
 class Estimator(C.Structure):
     _fields_ = [("probes", C.c_int32), ("lanczos_steps", C.c_int32), ("kind", C.c_int32),
                 ("cg_max_iter", C.c_int32), ("seed", C.c_uint64), ("cg_rtol", C.c_double),
-                ("precond", C.c_int32), ("operator_form", C.c_int32)]
+                ("precond", C.c_int32), ("operator_form", C.c_int32), ("probe_rtol", C.c_double)]
 
 
 class Info(C.Structure):
@@ -207,9 +207,10 @@ def desc_of(d) -> KernelDesc:
 
 
 def estimator(probes=32, lanczos_steps=0, kind=PROBE_RADEMACHER, cg_max_iter=5000, seed=0,
-              cg_rtol=1e-10, precond=PRECOND_NONE, operator_form=OPERATOR_ASSEMBLED) -> Estimator:
+              cg_rtol=1e-10, precond=PRECOND_NONE, operator_form=OPERATOR_ASSEMBLED,
+              probe_rtol=0.0) -> Estimator:
     return Estimator(int(probes), int(lanczos_steps), int(kind), int(cg_max_iter), int(seed),
-                     float(cg_rtol), int(precond), int(operator_form))
+                     float(cg_rtol), int(precond), int(operator_form), float(probe_rtol))
 
 
 def exact_estimator(cg_max_iter=20000, cg_rtol=1e-13) -> Estimator:

@@ -112,6 +112,7 @@ void check_estimator(const sdgp_estimator* e, int64_t n) {
   if (e->kind == SDGP_PROBE_IDENTITY) require(n <= 16384, "identity probes need n <= 16384");
   require(e->cg_max_iter >= 1, "cg_max_iter must be >= 1");
   require(e->cg_rtol > 0.0 && std::isfinite(e->cg_rtol), "cg_rtol must be > 0");
+  require(e->probe_rtol >= 0.0 && std::isfinite(e->probe_rtol), "probe_rtol must be >= 0");
   require(e->lanczos_steps >= 0, "lanczos_steps must be >= 0");
   require(e->precond == SDGP_PRECOND_NONE || e->precond == SDGP_PRECOND_LOWRANK, "unknown preconditioner");
   require(e->operator_form == SDGP_OPERATOR_ASSEMBLED || e->operator_form == SDGP_OPERATOR_FACTORED,
@@ -160,7 +161,8 @@ sdgp_status evaluate(Ctx* c, const Sorted& s, const double* ys, const sdgp_kerne
     pc.lowrank_op = factored ? 1 : 0;
   }
   CgResult cg = block_cg(c, as.A, s, ys, kind, P, e.seed, e.cg_rtol, e.cg_max_iter, nullptr, 0,
-                         use_pc ? &pc : nullptr, grad_out != nullptr, &t);
+                         use_pc ? &pc : nullptr, grad_out != nullptr, &t,
+                         kind == PK_RADEMACHER ? e.probe_rtol : 0.0);
   if (cg.not_spd) throw Error(SDGP_ERR_NOT_SPD, "CG met p^T A p <= 0: the covariance is not positive definite");
   t.mark(6);
   const double yKy = dot_device(c, ys, 1, cg.X, cg.R, s.n);
@@ -473,7 +475,8 @@ sdgp_status sdgp_lml_grad_batched(sdgp_ctx* ctx, const sdgp_kernel_desc* desc, c
       cm[q].pc = use_pc ? &mem[q].pc : nullptr;
     }
     std::vector<CgResult> res = block_cg_multi(ctx, cm, s, ys, kind, P, est->seed, est->cg_rtol, est->cg_max_iter,
-                                               nullptr, 0, true, ctx->use_graph);
+                                               nullptr, 0, true, ctx->use_graph,
+                                               kind == PK_RADEMACHER ? est->probe_rtol : 0.0);
     for (size_t q = 0; q < mem.size(); ++q) {
       const Member& mb = mem[q];
       const int m = mb.idx;
@@ -560,6 +563,7 @@ sdgp_status sdgp_get_option(const sdgp_ctx* ctx, const char* name, int64_t* valu
   const std::string k(name);
   if (k == "timing") *value = ctx->timing ? 1 : 0;
   else if (k == "graph") *value = ctx->use_graph ? 1 : 0;
+  else if (k == "last_y_tail") *value = ctx->last_y_tail;
   else if (k == "staged_spmm") *value = ctx->staged_spmm ? 1 : 0;
   else if (k == "union_spmm") *value = ctx->union_spmm;
   else if (k == "fw_mfma") *value = ctx->fw_mfma;

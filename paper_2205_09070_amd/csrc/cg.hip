@@ -79,7 +79,8 @@ struct CgArgs {
   double inv_c, sqrt_c;
   int nbs, nbu;               // blocks of the SpMM / update kernels
   int max_iter;
-  double rtol2;
+  double rtol2;               // column 0 (y, or every column of caller right-hand sides)
+  double prtol2;              // probe columns 1 .. R-1
   double* s_part;             // [R][nbs] p.(A p) partials of the SpMM
   double* s_red;              // [R]
   double* u_part;             // [(1+n1) R][nbu]: r.r, then F^T r (row R + i R + c)
@@ -1300,7 +1301,7 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(NI <= 32 ? 3
         alpha = A.st.hist_a[(int64_t)it * A.R + rc];
         xa = 1;
         beta = rz_new / rz_old;
-        cont = !(rr_new <= A.rtol2 * A.st.bnorm2[rc]) ? 1 : 0;
+        cont = !(rr_new <= (rc == 0 ? A.rtol2 : A.prtol2) * A.st.bnorm2[rc]) ? 1 : 0;
       }
       if (blockIdx.x == 0) {
         A.st.rz[nxt * A.R + rc] = act ? rz_new : rz_old;
@@ -1941,7 +1942,8 @@ static TuneChoice run_tuner(Ctx* c, const std::vector<CgMember>& mem, const Sort
 
 std::vector<CgResult> block_cg_multi(Ctx* c, const std::vector<CgMember>& mem, const Sorted& s, const double* ys,
                                      int kind, int P, uint64_t seed, double rtol, int max_iter,
-                                     const double* dense_rhs, int dense_R, bool keep_v, bool use_graph) {
+                                     const double* dense_rhs, int dense_R, bool keep_v, bool use_graph,
+                                     double probe_rtol) {
   const int B = (int)mem.size();
   require(B >= 1 && B <= 65535, "1..65535 members");
   const int64_t n = s.n;
@@ -1954,6 +1956,10 @@ std::vector<CgResult> block_cg_multi(Ctx* c, const std::vector<CgMember>& mem, c
   require(R >= 1, "no right-hand sides");
   require(max_iter >= 1, "cg_max_iter must be >= 1");
   require(rtol > 0.0 && std::isfinite(rtol), "cg_rtol must be > 0");
+  require(probe_rtol >= 0.0 && std::isfinite(probe_rtol), "probe_rtol must be >= 0");
+  // probe columns (after y) converge at their own tolerance when one is given
+  const bool probe_cols = kind == PK_RADEMACHER || kind == PK_IDENTITY;
+  const double prt = (probe_cols && probe_rtol > 0.0) ? probe_rtol : rtol;
   require(kind != PK_DENSE || B == 1, "dense right-hand sides take one member");
   require(n <= 0x7fffffffLL, "n must fit a 32-bit column index");
   const Precond* pc0 = mem[0].pc;
@@ -2137,6 +2143,7 @@ std::vector<CgResult> block_cg_multi(Ctx* c, const std::vector<CgMember>& mem, c
     A.nbu = nbu;
     A.max_iter = max_iter;
     A.rtol2 = rtol * rtol;
+    A.prtol2 = prt * prt;
     A.s_part = s_part + (size_t)m * R * nbs;
     A.s_red = s_red + (size_t)m * R;
     A.u_part = u_part + (size_t)m * nu * R * nbu;
@@ -2209,6 +2216,35 @@ std::vector<CgResult> block_cg_multi(Ctx* c, const std::vector<CgMember>& mem, c
     }
     return true;
   };
+  // y alone: once every probe column of a single evaluation has stopped
+  // (they stop first when their tolerance is looser than y's), the rest of
+  // y's solve runs the column-0 kernels only -- the CSR SpMM of column 0
+  // and the column-0 blocks of the update kernels -- with the device
+  // arguments' slab count set to 0 (restored for the unpack).
+  const bool tail_ok = B == 1 && ns > 0 && probe_cols && prt > rtol && !c->in_trial && !staged;
+  bool tail = false;
+  int tail_from = 0;                              // iterations executed when y went alone
+  std::vector<int32_t> act_h((size_t)2 * R);
+  auto try_tail = [&](hipStream_t st) -> bool {   // true when switched
+    if (!tail_ok || tail || active.empty()) return false;
+    const int E = flags[2];                       // iterations executed (from the last poll)
+    SDGP_HIP(hipMemcpyAsync(act_h.data(), hA[0].st.act, 2 * R * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    SDGP_HIP(hipStreamSynchronize(st));
+    const int32_t* a = act_h.data() + (size_t)(E & 1) * R;   // state for iteration E
+    if (!a[0]) return false;
+    for (int r = 1; r < R; ++r)
+      if (a[r]) return false;
+    tail = true;
+    tail_from = E;
+    L.ns = 0;
+    L.uni = false;
+    L.fw = false;
+    hA[0].ns = 0;
+    SDGP_HIP(hipMemcpyAsync(dA, hA.data(), sizeof(CgArgs), hipMemcpyHostToDevice, st));
+    SDGP_HIP(hipStreamSynchronize(st));
+    hA[0].ns = ns;
+    return true;
+  };
   c->spmm_events.clear();
   int launched = 0;
   if (use_graph) {
@@ -2246,6 +2282,7 @@ std::vector<CgResult> block_cg_multi(Ctx* c, const std::vector<CgMember>& mem, c
         launched += k;
       }
       if (poll(gs) && !active.empty()) capture();
+      else if (try_tail(gs)) capture();
       every = std::min(every * 2, 8);
     }
     if (exec) (void)hipGraphExecDestroy(exec);
@@ -2264,6 +2301,7 @@ std::vector<CgResult> block_cg_multi(Ctx* c, const std::vector<CgMember>& mem, c
         SDGP_HIP(hipEventRecord(t0, c->stream));
       }
       poll(c->stream);
+      try_tail(c->stream);
       check = std::min(check * 2, 64);
     }
     // trial: timed only when no member converged before the end (the
@@ -2281,7 +2319,7 @@ std::vector<CgResult> block_cg_multi(Ctx* c, const std::vector<CgMember>& mem, c
     }
   }
   // every member's arguments again, for the unpack
-  if (L.B != B) {
+  if (L.B != B || tail) {
     SDGP_HIP(hipMemcpyAsync(dA, hA.data(), B * sizeof(CgArgs), hipMemcpyHostToDevice, c->stream));
     L.B = B;
   }
@@ -2340,18 +2378,19 @@ std::vector<CgResult> block_cg_multi(Ctx* c, const std::vector<CgMember>& mem, c
     }
     res.converged = conv && !res.not_spd;
   }
+  if (!c->in_trial) c->last_y_tail = tail ? std::max(0, out[0].iters - tail_from) : 0;
   return out;
 }
 
 CgResult block_cg(Ctx* c, const Csr& Am, const Sorted& s, const double* ys, int kind, int P, uint64_t seed,
                   double rtol, int max_iter, const double* dense_rhs, int dense_R, const Precond* pc,
-                  bool keep_v, PhaseTimer* t) {
+                  bool keep_v, PhaseTimer* t, double probe_rtol) {
   (void)t;
   std::vector<CgMember> mem(1);
   mem[0].A = Am;
   mem[0].pc = pc;
   return block_cg_multi(c, mem, s, ys, kind, P, seed, rtol, max_iter, dense_rhs, dense_R, keep_v,
-                        c->use_graph)[0];
+                        c->use_graph, probe_rtol)[0];
 }
 
 // Plain SpMM Y = A X for row-major X, Y [n][R] with R even (16-byte rows

@@ -126,6 +126,7 @@ struct Ctx {
   double trial_ms = -1.0;        // ms per timed iteration of the last trial (< 0: not measurable)
   TuneChoice last_shape;         // shape used by the last CG solve
   int last_tuned = 0;            // 0 defaults / options, 1 tuned shape from the store, 2 tuned in that call
+  int last_y_tail = 0;           // iterations the last solve ran on y alone (probe columns stopped)
   // Workspace limits.  cap_bytes > 0: get() refuses (SDGP_ERR_OOM) to grow
   // the context's workspace beyond that many bytes.  arena != nullptr
   // (static-workspace calls): get() hands out 256-byte aligned slices of the
@@ -315,10 +316,12 @@ enum ProbeKind { PK_RADEMACHER = 0, PK_IDENTITY = 2, PK_NONE = 3, PK_DENSE = 4 }
 
 // Block CG on A X = [y, z_1..z_P] (or caller dense RHS when kind==PK_DENSE).
 // pc (optional) preconditions every column; keep_v stores M^{-1} b.
+// probe_rtol > 0: the probe columns (after y) stop at that tolerance; when
+// they have all stopped before y, a single evaluation finishes y alone.
 CgResult block_cg(Ctx* c, const Csr& A, const Sorted& s, const double* ys,
                   int kind, int P, uint64_t seed, double rtol, int max_iter,
                   const double* dense_rhs, int dense_R, const Precond* pc,
-                  bool keep_v, PhaseTimer* t);
+                  bool keep_v, PhaseTimer* t, double probe_rtol = 0.0);
 // All members (own matrix and preconditioner, shared points, probes and
 // options) advance together: one launch per kernel with grid z = member.
 struct CgMember {
@@ -328,7 +331,7 @@ struct CgMember {
 std::vector<CgResult> block_cg_multi(Ctx* c, const std::vector<CgMember>& mem, const Sorted& s,
                                      const double* ys, int kind, int P, uint64_t seed, double rtol,
                                      int max_iter, const double* dense_rhs, int dense_R, bool keep_v,
-                                     bool use_graph);
+                                     bool use_graph, double probe_rtol = 0.0);
 Precond lowrank_precond(Ctx* c, const Sorted& s, const KParams& kp, const Bumps& b);
 // The same for every member of a population (one Gram launch, grid z =
 // member); the members' bump values are contiguous from F0 with stride

@@ -130,6 +130,22 @@ def case_ci(lib):
             gd = np.abs(g - g0).max() / np.abs(g0).max()
             log("operator %d %s call %d: lml rel %.2e, grad %.2e, iters %d" % (op, opts, rep, d, gd, info.cg_iters))
             ok &= d <= 1e-8 and gd <= 1e-6
+    # probe columns to a looser tolerance: y keeps cg_rtol (finished alone once
+    # the probes have stopped); the estimates move far less than their errors
+    for op in (0, 1):
+        c = EmuContext(lib)
+        base = dict(probes=4, seed=3, cg_max_iter=3000, precond=1, operator_form=op, cg_rtol=1e-11)
+        v1, g1, i1 = c.lml_grad(w.desc, w.x, w.y, w.h, _lib.estimator(**base))
+        v2, g2, i2 = c.lml_grad(w.desc, w.x, w.y, w.h, _lib.estimator(probe_rtol=1e-5, **base))
+        tail = c.get_option("last_y_tail")
+        d = abs(v2 - v1) / abs(v1)
+        gd = np.abs(g2 - g1).max() / np.abs(g1).max()
+        log("probe_rtol 1e-5, operator %d: iterations %d (y %d, %d of them alone) against %d; lml rel %.2e, "
+            "grad %.2e, yKy rel %.2e" % (op, i2.cg_iters, i2.cg_iters_y, tail, i1.cg_iters, d, gd,
+                                          abs(i2.yKy - i1.yKy) / abs(i1.yKy)))
+        ok &= tail > 0
+        ok &= d <= 1e-6 and gd <= 1e-4 and abs(i2.yKy - i1.yKy) <= 1e-9 * abs(i1.yKy)
+        ok &= i2.cg_iters == i2.cg_iters_y and i2.cg_iters_y >= i1.cg_iters_y - 2
     wp, H = population(200, 2, 2, 2, 3, 5)
     c = EmuContext(lib)
     c.set_option("graph", 1)

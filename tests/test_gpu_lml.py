@@ -402,3 +402,33 @@ def test_union_spmm_matches_oracle(probes, operator):
     assert abs(v - v0) <= 1e-7 * abs(v0)
     ok = gu.grad_close(g, g0, rel=1e-6)
     assert ok.all(), "grad mismatch at %s: gpu %s oracle %s" % (np.nonzero(~ok)[0], g[~ok], g0[~ok])
+
+
+@pytest.mark.parametrize("operator", [0, 1], ids=["assembled", "factored"])
+def test_probe_rtol_matches_oracle(operator):
+    """probe_rtol: the probe columns stop at 1e-7 while y keeps cg_rtol 1e-12
+    and, once every probe column has stopped, finishes alone with the
+    column-0 kernels (from the union-list SpMM to the CSR one); the LML and
+    the gradient still agree with the oracle's estimator on the same probes
+    (LML 1e-7, gradient 1e-6 relative), y^T K^{-1} y with the all-tight run
+    within 1e-10, and probe_rtol = cg_rtol is bitwise the default."""
+    gu.need_gpu()
+    import paper_2205_09070_amd as sd
+    w, (v0, g0, ld0, se0) = _union_oracle(33)
+    c = gu.ctx()
+    c.set_option("union_spmm", 1)
+    x, y = gu.dev(w.x), gu.dev(w.y)
+    base = dict(probes=33, seed=77, cg_rtol=1e-12, cg_max_iter=5000, precond=sd.PRECOND_LOWRANK,
+                operator_form=operator)
+    v1, g1, i1 = c.lml_grad(w.desc, x, y, w.h, sd.estimator(**base))
+    assert c.get_option("last_y_tail") == 0
+    v2, g2, i2 = c.lml_grad(w.desc, x, y, w.h, sd.estimator(probe_rtol=1e-7, **base))
+    tail = c.get_option("last_y_tail")
+    gu.log("probe_rtol 1e-7 operator=%d: iters %d (y %d, %d alone) against %d; lml %.15g tight %.15g oracle %.15g"
+           % (operator, i2.cg_iters, i2.cg_iters_y, tail, i1.cg_iters, v2, v1, v0))
+    assert tail > 0 and i2.cg_iters < i1.cg_iters
+    assert abs(i2.yKy - i1.yKy) <= 1e-10 * abs(i1.yKy)
+    assert abs(v2 - v0) <= 1e-7 * abs(v0)
+    assert gu.grad_close(g2, g0, rel=1e-6).all()
+    v3, g3, _ = c.lml_grad(w.desc, x, y, w.h, sd.estimator(probe_rtol=1e-12, **base))
+    assert v3 == v1 and np.array_equal(g3, g1)
