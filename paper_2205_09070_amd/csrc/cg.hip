@@ -1062,6 +1062,32 @@ __device__ __forceinline__ double frow_dot(const GL double* __restrict__ Fa, int
   return s;
 }
 
+// A row's F values into registers: 16-byte loads when the row holds
+// exactly NI (even) values, so its 16-byte alignment follows from F's.
+template <int NI>
+__device__ __forceinline__ void load_frow(const GL double* __restrict__ Fa, int n1, double* f) {
+  if (NI > 0 && n1 == NI) {
+#pragma unroll
+    for (int i = 0; i < (NI > 0 ? NI : 2); i += 2) {
+      const dv2 v = *reinterpret_cast<const GL dv2*>(Fa + i);
+      f[i] = v.x;
+      f[i + 1] = v.y;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < (NI > 0 ? NI : 1); ++i) f[i] = i < n1 ? Fa[i] : 0.0;
+  }
+}
+// sum_i f[i] w[i][.] (w in LDS, stride kSC); the order of frow_dot.
+template <int NI>
+__device__ __forceinline__ double freg_dot(const double* f, int n1, const double* w) {
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < (NI > 0 ? NI : 1); ++i)
+    if (i < n1) s += f[i] * w[i * kSC];
+  return s;
+}
+
 constexpr int kRed = 4 * 512;   // LDS doubles for the block reductions
 
 // alpha = r.z / p.A p (p.A p = p.K_core p + |F^T p|^2 with the factored
@@ -1129,16 +1155,17 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(NI <= 32 ? 3
       for (int64_t k = 0; k < steps; ++k) {
         const int64_t a = thread_row(A, true, k);
         if (a < 0) continue;
-        const GL double* Fa = G.F + a * (int64_t)A.n1;
+        double f[NI > 0 ? NI : 2];
+        if (lr || pc) load_frow<NI>(G.F + a * (int64_t)A.n1, A.n1, f);
         double q = G.Q[a];
-        if (lr) q += frow_dot<NI>(Fa, A.n1, s_gp);
+        if (lr) q += freg_dot<NI>(f, A.n1, s_gp);
         const double r = G.Rr[a] - al * q;
         G.Rr[a] = r;
         rr += r * r;
         if (pc) {
 #pragma unroll
           for (int i = 0; i < (NI > 0 ? NI : 1); ++i)
-            if (i < A.n1) gy[i] += Fa[i] * r;
+            if (i < A.n1) gy[i] += f[i] * r;
         }
       }
     put_y_partials<NI>(A, red, true, rr, 0, pc, gy, G.u_part, A.R);
@@ -1336,15 +1363,16 @@ __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(NI <= 32 ? 3
         const double p_old = G.P[a];
         G.X[a] += al * p_old;
         if (!cont) continue;
-        const GL double* Fa = G.F + a * (int64_t)A.n1;
+        double f[NI > 0 ? NI : 2];
+        if (lr || pc) load_frow<NI>(G.F + a * (int64_t)A.n1, A.n1, f);
         const double r = G.Rr[a];
-        const double z = pc ? (r - frow_dot<NI>(Fa, A.n1, s_u)) * A.inv_c : r;
+        const double z = pc ? (r - freg_dot<NI>(f, A.n1, s_u)) * A.inv_c : r;
         const double p = z + be * p_old;
         G.P[a] = p;
         if (lr) {
 #pragma unroll
           for (int i = 0; i < (NI > 0 ? NI : 1); ++i)
-            if (i < A.n1) gy[i] += Fa[i] * p;
+            if (i < A.n1) gy[i] += f[i] * p;
         }
       }
     if (lr) put_y_partials<NI>(A, red, false, 0.0, 0, true, gy, G.p_part, 0);

@@ -92,7 +92,7 @@ def case_ci(lib):
     population with graph replay, all on the oracle's probes."""
     from oracle import kernel as okn
     ok = True
-    w = wl.random_small(200, 2, 3, 2, 11, combine=1, per_row=12.0, noise_var=1e-2)
+    w = wl.random_small(200, 2, 8, 2, 11, combine=1, per_row=12.0, noise_var=1e-2)   # n1 = 8: full F rows
     for rep in range(2):   # the second call reuses the context's storage
         c = EmuContext(lib) if rep == 0 else c
         nnz = c.kernel_nnz(w.desc, w.x, w.h)
