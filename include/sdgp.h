@@ -162,16 +162,13 @@ sdgp_status sdgp_set_timing(sdgp_ctx* ctx, int enable);
  * run the CG iterations as a captured hipGraph of 8 iterations replayed
  * until every column (and every population member) has converged; the
  * iteration counters live on the device, so replays past convergence or
- * past cg_max_iter do nothing; "staged_spmm" (0/1, default 0): with at most
- * 33 right-hand sides the CG SpMM stages each 64-row block's neighbour rows
- * in LDS (lists built once per solve); "union_spmm" (-1 default: on from
+ * past cg_max_iter do nothing; "union_spmm" (-1 default: on from
  * 65536 points when the lists fit in half of the free device memory, 0 off,
  * 1 on): the
  * CG SpMM reads, for every 4 consecutive rows of its row order, one sorted
  * list of the 4 rows' distinct columns with 4 values per entry (0 where a
  * row lacks the column), so each neighbour row of P is gathered once for
- * the 4 rows (lists built once per solve; ignored when "staged_spmm" is
- * on); "fw_mfma" (-1 default = 1, 0, 1):
+ * the 4 rows (lists built once per solve); "fw_mfma" (-1 default = 1, 0, 1):
  * the preconditioner / factored-operator products
  * F w of the CG update kernels per 16-row tile on the matrix cores instead
  * of per-row broadcasts; "update_blocks" (0 default: one round of the
@@ -194,7 +191,7 @@ sdgp_status sdgp_set_timing(sdgp_ctx* ctx, int enable);
  * the context may hold; a call that would grow it further fails with
  * SDGP_ERR_OOM before allocating (its outputs are then unspecified, the
  * context stays usable).
- * "timing" and "graph" leave the results bitwise unchanged; "staged_spmm",
+ * "timing" and "graph" leave the results bitwise unchanged;
  * "union_spmm", "fw_mfma", "update_blocks" and "spmm_blocks" change only the
  * order of floating-point sums
  * (agreement to rounding).  Unknown names or

@@ -520,7 +520,6 @@ sdgp_status sdgp_set_option(sdgp_ctx* ctx, const char* name, int64_t value) {
   const std::string k(name);
   if (k == "timing") { ctx->timing = value != 0; return SDGP_OK; }
   if (k == "graph") { ctx->use_graph = value != 0; return SDGP_OK; }
-  if (k == "staged_spmm") { ctx->staged_spmm = value != 0; return SDGP_OK; }
   if (k == "union_spmm") {
     if (value < -1 || value > 1) { ctx->err = "union_spmm must be -1, 0 or 1"; return SDGP_ERR_INVALID_ARG; }
     ctx->union_spmm = (int)value;
@@ -564,7 +563,6 @@ sdgp_status sdgp_get_option(const sdgp_ctx* ctx, const char* name, int64_t* valu
   if (k == "timing") *value = ctx->timing ? 1 : 0;
   else if (k == "graph") *value = ctx->use_graph ? 1 : 0;
   else if (k == "last_y_tail") *value = ctx->last_y_tail;
-  else if (k == "staged_spmm") *value = ctx->staged_spmm ? 1 : 0;
   else if (k == "union_spmm") *value = ctx->union_spmm;
   else if (k == "fw_mfma") *value = ctx->fw_mfma;
   else if (k == "spmm_blocks") *value = ctx->spmm_blocks;

@@ -43,10 +43,6 @@ constexpr int kMaxNbs = 32768;   // SpMM blocks
 constexpr int kMaxNbu = 8192;    // upper bound on the update kernels' grid (default: one resident round)
 constexpr int kGS = 2;           // row-steps whose loads the update passes issue together
 constexpr int64_t kUnionMinRows = 65536;  // union-list SpMM by default from this many rows
-constexpr int kLRows = 64;       // rows per block of the staged SpMM
-constexpr int kLMax = 512;       // staged neighbour rows per block (LDS: 512 x 264 B)
-constexpr int kLT = 512;         // threads per staged SpMM / build block
-constexpr int kLItems = 8;       // entries per thread in the build (4096 per block)
 
 struct CgState {
   double* rz;       // [2][R] parity buffers of r.z (r.r unpreconditioned)
@@ -88,13 +84,6 @@ struct CgArgs {
   double* w_red;              // [(n1+1) R]: u = S^{-1} g (row i R + c), then g.u (row n1 R + c)
   double* p_part;             // [n1 R][nbu] F^T p (row i R + c)
   double* p_red;              // [n1 R]
-  // neighbourhood-staged SpMM (slab 0 only): per 64-row block of the
-  // schedule, the sorted distinct neighbour rows (lnb[b * kLMax ..], count
-  // lcnt[b], -1: block not staged) and each CSR entry's index in that list
-  const int32_t* lnb;
-  const int32_t* lcnt;
-  const uint16_t* lslot;
-  int nlb;                    // 64-row blocks
   // 4-row union lists of the shared-gather SpMM: group q = schedule rows
   // 4q .. 4q+3; entries urp[q] .. urp[q+1]-1 hold the group's distinct
   // columns (ascending, ucol) and their 4 values (uval[4e + r] for row 4q+r,
@@ -130,8 +119,6 @@ struct Gv {
   const GL int32_t* sched;
   const GL double* F;
   GL double *s_part, *u_part, *p_part;
-  const GL int32_t* lnb;
-  const GL uint16_t* lslot;
 };
 __device__ __forceinline__ Gv gview(const CgArgs& A) {
   Gv g;
@@ -148,8 +135,6 @@ __device__ __forceinline__ Gv gview(const CgArgs& A) {
   g.s_part = (GL double*)A.s_part;
   g.u_part = (GL double*)A.u_part;
   g.p_part = (GL double*)A.p_part;
-  g.lnb = (const GL int32_t*)A.lnb;
-  g.lslot = (const GL uint16_t*)A.lslot;
   return g;
 }
 
@@ -521,221 +506,6 @@ __global__ __launch_bounds__(kT) void k_cg_spmm_u(const CgArgs* __restrict__ AA)
       for (int q = 0; q < kTile; ++q) ty += redy[q];
       G.s_part[blockIdx.x] = ty;
     }
-  }
-}
-
-// ------------------------------------------------------------ staged SpMM
-// Build (once per solve) of the neighbourhood lists of the staged SpMM:
-// block b gathers the column indices of schedule rows 64b .. 64b+63, sorts
-// them (block radix sort), keeps the distinct ones as the block's list and
-// writes, for every CSR entry of those rows, the entry's position in the list
-// (16 bits).  Blocks with more than 4096 entries or 512 distinct neighbours
-// are marked -1 and take the global-gather path.
-__global__ __launch_bounds__(kLT) void k_local_build(int64_t n, const int64_t* __restrict__ row_ptr,
-                                                     const int32_t* __restrict__ col,
-                                                     const int32_t* __restrict__ sched, int32_t* __restrict__ lnb,
-                                                     int32_t* __restrict__ lcnt, uint16_t* __restrict__ lslot) {
-  typedef hipcub::BlockRadixSort<int, kLT, kLItems> Sort;
-  typedef hipcub::BlockScan<int, kLT> Scan;
-  __shared__ union {
-    typename Sort::TempStorage sort;
-    typename Scan::TempStorage scan;
-  } tmp;
-  __shared__ int64_t rs[kLRows + 1];
-  __shared__ int64_t rbeg[kLRows];
-  __shared__ int last[kLT];
-  __shared__ int list[kLMax];
-  const int b = blockIdx.x;
-  const int t = threadIdx.x;
-  if (t < kLRows) {
-    const int64_t p = (int64_t)b * kLRows + t;
-    int64_t len = 0, beg = 0;
-    if (p < n) {
-      const int64_t a = sched ? (int64_t)sched[p] : p;
-      beg = row_ptr[a];
-      len = row_ptr[a + 1] - beg;
-    }
-    rbeg[t] = beg;
-    rs[t + 1] = len;
-  }
-  __syncthreads();
-  if (t == 0) {
-    rs[0] = 0;
-    for (int r = 0; r < kLRows; ++r) rs[r + 1] += rs[r];
-  }
-  __syncthreads();
-  const int64_t E = rs[kLRows];
-  if (E > (int64_t)kLT * kLItems) {
-    if (t == 0) lcnt[b] = -1;
-    return;
-  }
-  auto entry = [&](int64_t e) -> int64_t {  // CSR index of the block's e-th entry
-    int lo = 0, hi = kLRows;                 // rs[lo] <= e < rs[hi]
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (rs[mid] <= e) lo = mid; else hi = mid;
-    }
-    return rbeg[lo] + (e - rs[lo]);
-  };
-  int keys[kLItems];
-#pragma unroll
-  for (int i = 0; i < kLItems; ++i) {
-    const int64_t e = (int64_t)t * kLItems + i;
-    keys[i] = e < E ? col[entry(e)] : INT_MAX;
-  }
-  Sort(tmp.sort).Sort(keys);
-  last[t] = keys[kLItems - 1];
-  __syncthreads();
-  int flags[kLItems];
-  int cnt = 0;
-#pragma unroll
-  for (int i = 0; i < kLItems; ++i) {
-    const int prev = i > 0 ? keys[i - 1] : (t > 0 ? last[t - 1] : INT_MIN);
-    flags[i] = (keys[i] != INT_MAX && keys[i] != prev) ? 1 : 0;
-    cnt += flags[i];
-  }
-  int off = 0, total = 0;
-  __syncthreads();
-  Scan(tmp.scan).ExclusiveSum(cnt, off, total);
-  if (total > kLMax) {
-    if (t == 0) lcnt[b] = -1;
-    return;
-  }
-#pragma unroll
-  for (int i = 0; i < kLItems; ++i)
-    if (flags[i]) {
-      list[off] = keys[i];
-      lnb[(int64_t)b * kLMax + off] = keys[i];
-      ++off;
-    }
-  if (t == 0) lcnt[b] = total;
-  __syncthreads();
-  for (int64_t e = t; e < E; e += kLT) {
-    const int64_t k = entry(e);
-    const int c = col[k];
-    int lo = 0, hi = total;  // first position with list[pos] >= c
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (list[mid] < c) lo = mid + 1; else hi = mid;
-    }
-    lslot[k] = (uint16_t)lo;
-  }
-}
-
-// slab_row over LDS-staged neighbour rows: entries carry 16-bit slots into
-// the block's list; sp: staged slab rows (32 doubles each, the lane's first
-// column at sp + 2j), sy: staged column-0 values.
-template <int... us>
-__device__ __forceinline__ void gather16_lds(int cj, double vj, const double* sp, double* acc,
-                                             std::integer_sequence<int, us...>) {
-  double vv[16];
-  dv2 xv[16];
-  ((vv[us] = bcast16_d<us>(vj), xv[us] = *reinterpret_cast<const dv2*>(sp + bcast16_i<us>(cj) * kSlab)), ...);
-#pragma unroll
-  for (int u = 0; u < 16; u += 4) {
-    acc[0] += vv[u] * xv[u].x;
-    acc[1] += vv[u] * xv[u].y;
-    acc[2] += vv[u + 1] * xv[u + 1].x;
-    acc[3] += vv[u + 1] * xv[u + 1].y;
-    acc[4] += vv[u + 2] * xv[u + 2].x;
-    acc[5] += vv[u + 2] * xv[u + 2].y;
-    acc[6] += vv[u + 3] * xv[u + 3].x;
-    acc[7] += vv[u + 3] * xv[u + 3].y;
-  }
-}
-__device__ __forceinline__ void slab_row_lds(int64_t k0, int64_t k1, const GL uint16_t* __restrict__ slot,
-                                             const GL double* __restrict__ val, const double* sp, const double* sy,
-                                             dv2& q, double& yacc) {
-  const int j = lane_id() & 15;
-  double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  int64_t kb = k0;
-  bool in = kb + j < k1;
-  int cj = in ? (int)slot[kb + j] : 0;
-  double vj = in ? val[kb + j] : 0.0;
-  while (__any(kb < k1)) {
-    const int64_t kn = kb + 16 + j;
-    const bool inn = kn < k1;
-    const int cn = inn ? (int)slot[kn] : 0;
-    const double vn = inn ? val[kn] : 0.0;
-    yacc += vj * sy[cj];
-    gather16_lds(cj, vj, sp + 2 * j, acc, std::make_integer_sequence<int, 16>{});
-    cj = cn;
-    vj = vn;
-    kb += 16;
-  }
-  q.x = (acc[0] + acc[2]) + (acc[4] + acc[6]);
-  q.y = (acc[1] + acc[3]) + (acc[5] + acc[7]);
-}
-
-// Q = A P for slab 0 and column 0 (ns == 1), 64 schedule rows per block:
-// the block's distinct neighbour rows of P are staged in LDS once and every
-// gather of the 64 rows reads LDS.  Unstaged blocks gather from global
-// memory.  Row-blocks are dealt XCD-aware (each XCD a contiguous eighth of
-// the schedule); per-block partials of p.q as in k_cg_spmm.
-__global__ __launch_bounds__(kLT) void k_cg_spmm_lds(const CgArgs* __restrict__ AA) {
-  const CgArgs& A = AA[blockIdx.z];
-  if (stopped(A)) return;
-  const Gv G = gview(A);
-  __shared__ double sp[kLMax * kSlab];
-  __shared__ double sy[kLMax];
-  __shared__ double red[(kLT / 16) * kSlab];
-  __shared__ double redy[kLT / 16];
-  const int t = threadIdx.x;
-  const int lane = lane_id(), j = lane & 15;
-  const int grp = t >> 4;                    // 32 groups of 16 lanes
-  const int64_t per = gridDim.x >> 3;
-  const int64_t b = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
-  const int64_t n = A.n;
-  const int u = b < A.nlb ? A.lcnt[b] : -1;
-  if (u > 0) {
-    for (int idx = t; idx < u * 16; idx += kLT) {
-      const int r = idx >> 4, l = idx & 15;
-      const int64_t src = (int64_t)G.lnb[b * kLMax + r];
-      *reinterpret_cast<dv2*>(sp + r * kSlab + 2 * l) =
-          *reinterpret_cast<const GL dv2*>(G.P + A.ny + src * kSlab + 2 * l);
-    }
-    for (int r = t; r < u; r += kLT) sy[r] = G.P[G.lnb[b * kLMax + r]];
-  }
-  __syncthreads();
-  const GL double* Ps = G.P + A.ny + 2 * j;
-  GL double* Qs = G.Q + A.ny + 2 * j;
-  double pq0 = 0.0, pq1 = 0.0, pqy = 0.0;
-#pragma unroll
-  for (int step = 0; step < kLRows / (kLT / 16); ++step) {
-    const int64_t p = b * kLRows + grp + step * (kLT / 16);
-    const bool live = b < A.nlb && p < n;
-    const int64_t a = live ? (G.sched ? (int64_t)G.sched[p] : p) : 0;
-    const int64_t k0 = live ? G.row_ptr[a] : 0, k1 = live ? G.row_ptr[a + 1] : 0;
-    dv2 q;
-    double yacc = 0.0;
-    if (u >= 0) slab_row_lds(k0, k1, G.lslot, G.val, sp, sy, q, yacc);
-    else slab_row<true>(k0, k1, (int32_t)a, G.col, G.val, Ps, kSlab, G.P, q, yacc);
-    yacc = row16_sum(yacc);
-    if (live) {
-      *reinterpret_cast<GL dv2*>(Qs + a * kSlab) = q;
-      const dv2 pv = *reinterpret_cast<const GL dv2*>(Ps + a * kSlab);
-      pq0 += pv.x * q.x;
-      pq1 += pv.y * q.y;
-      if (j == 0) {
-        G.Q[a] = yacc;
-        pqy += G.P[a] * yacc;
-      }
-    }
-  }
-  red[grp * kSlab + 2 * j] = pq0;
-  red[grp * kSlab + 2 * j + 1] = pq1;
-  if (j == 0) redy[grp] = pqy;
-  __syncthreads();
-  if (t < kSlab) {
-    double s2 = 0.0;
-    for (int q = 0; q < kLT / 16; ++q) s2 += red[q * kSlab + t];
-    const int rc = 1 + t;
-    if (rc < A.R) G.s_part[(int64_t)rc * A.nbs + blockIdx.x] = s2;
-  }
-  if (t == 0) {
-    double s2 = 0.0;
-    for (int q = 0; q < kLT / 16; ++q) s2 += redy[q];
-    G.s_part[blockIdx.x] = s2;
   }
 }
 
@@ -1740,7 +1510,6 @@ struct Launch {
   int nbs, nbu, ns, R, n1;
   bool use_pc, lowrank;
   int B;
-  bool staged;  // neighbourhood-staged SpMM (ns == 1)
   bool uni;     // SpMM over the 4-row union lists
   bool fw;      // F w products of the update kernels on the matrix cores
 };
@@ -1752,9 +1521,7 @@ void launch_iteration(hipStream_t st, const CgArgs* dA, const Launch& L, Ctx* c)
     e0 = c->event();
     SDGP_HIP(hipEventRecord(e0, st));
   }
-  if (L.staged) {
-    k_cg_spmm_lds<<<dim3(L.nbs, 1, L.B), kLT, 0, st>>>(dA);
-  } else if (L.ns == 0) {
+  if (L.ns == 0) {
     k_cg_spmm<0><<<dim3(L.nbs, 1, L.B), kT, 0, st>>>(dA);
   } else if (L.uni) {
     k_cg_spmm_u<1><<<dim3(L.nbs, 1, L.B), kT, 0, st>>>(dA);
@@ -2009,8 +1776,6 @@ std::vector<CgResult> block_cg_multi(Ctx* c, const std::vector<CgMember>& mem, c
   const size_t NV = (size_t)ny + (size_t)ns * n * kSlab;   // doubles per vector block
   require(NV >= (size_t)n * R, "layout");
   const int64_t tiles = (n + kTile - 1) / kTile;
-  const bool staged = c->staged_spmm && ns == 1;
-  const int64_t nlb = (n + kLRows - 1) / kLRows;
   // Launch shape: a tuner trial's candidate; else the context options when
   // any is set; else the tuned shape of this problem class (tuned now when
   // the store has none); else the defaults.
@@ -2024,7 +1789,7 @@ std::vector<CgResult> block_cg_multi(Ctx* c, const std::vector<CgMember>& mem, c
     sh.update_blocks = c->update_blocks;
     sh.union_spmm = c->union_spmm;
     sh.fw_mfma = c->fw_mfma;
-  } else if (!staged && (c->autotune == 2 || (c->autotune == 1 && n >= kTuneMinRows))) {
+  } else if (c->autotune == 2 || (c->autotune == 1 && n >= kTuneMinRows)) {
     int64_t nnz = 0;
     for (const auto& mm : mem) nnz = std::max<int64_t>(nnz, mm.A.nnz);
     const std::string key = tune_key(c, NI, ns, B, n, nnz, use_lr, use_pc);
@@ -2043,7 +1808,7 @@ std::vector<CgResult> block_cg_multi(Ctx* c, const std::vector<CgMember>& mem, c
     }
   }
   const int64_t nbs_cap = sh.spmm_blocks > 0 ? sh.spmm_blocks : kMaxNbs;
-  const int nbs = staged ? (int)round8(nlb) : (int)std::min<int64_t>(nbs_cap, round8(tiles));
+  const int nbs = (int)std::min<int64_t>(nbs_cap, round8(tiles));
   // F w products of the update kernels on the matrix cores (measured faster at
   // 16 and at 32 bump functions); 0 per-row broadcasts
   const bool fw = ns > 0 && n1 > 0 && sh.fw_mfma != 0;
@@ -2051,7 +1816,6 @@ std::vector<CgResult> block_cg_multi(Ctx* c, const std::vector<CgMember>& mem, c
                               ? sh.update_blocks
                               : std::min<int64_t>(kMaxNbu, (int64_t)update_blocks_per_cu(NI, fw) * c->cu_count);
   const int nbu = (int)std::max<int64_t>(1, std::min<int64_t>(nbu_cap, round8(tiles)));
-  require(!staged || nbs < 0x7fffffff, "too many row blocks");
   const int nu = 1 + (use_pc ? n1 : 0);
   double* X = c->get<double>(S_CG_X, NV * B);
   double* Rr = c->get<double>(S_CG_R, NV * B);
@@ -2065,28 +1829,11 @@ std::vector<CgResult> block_cg_multi(Ctx* c, const std::vector<CgMember>& mem, c
   double* w_red = use_pc ? c->get<double>(S_CG_WRED, (size_t)(n1 + 1) * R * B) : nullptr;
   double* p_part = use_lr ? c->get<double>(S_CG_PARTG, (size_t)n1 * R * nbu * B) : nullptr;
   double* p_red = use_lr ? c->get<double>(S_CG_GP, (size_t)n1 * R * B) : nullptr;
-  // neighbourhood lists of the staged SpMM (per member)
-  int32_t* lnb = nullptr;
-  int32_t* lcnt = nullptr;
-  uint16_t* lslot = nullptr;
-  std::vector<size_t> slot_off(B + 1, 0);
-  if (staged) {
-    for (int m = 0; m < B; ++m) slot_off[m + 1] = slot_off[m] + (size_t)std::max<int64_t>(mem[m].A.nnz, 1);
-    lnb = c->get<int32_t>(S_CG_LNB, (size_t)nlb * kLMax * B);
-    lcnt = c->get<int32_t>(S_CG_LCNT, (size_t)nlb * B);
-    lslot = c->get<uint16_t>(S_CG_LSLOT, slot_off[B]);
-    for (int m = 0; m < B; ++m) {
-      k_local_build<<<(unsigned)nlb, kLT, 0, c->stream>>>(n, mem[m].A.row_ptr, mem[m].A.col, s.sched,
-                                                          lnb + (size_t)m * nlb * kLMax, lcnt + (size_t)m * nlb,
-                                                          lslot + slot_off[m]);
-      SDGP_CHECK_LAUNCH();
-    }
-  }
   // 4-row union lists of the shared-gather SpMM (per member): lengths,
   // exclusive scan on the host (once per solve), columns and values
   // (automatic from kUnionMinRows rows: below that, building the lists costs
   // more than the solve saves)
-  bool uni = !staged && ns > 0 && (sh.union_spmm > 0 || (sh.union_spmm < 0 && n >= kUnionMinRows));
+  bool uni = ns > 0 && (sh.union_spmm > 0 || (sh.union_spmm < 0 && n >= kUnionMinRows));
   const int64_t ng = (n + 3) / 4;
   int64_t* urp = nullptr;
   int32_t* ucol = nullptr;
@@ -2179,10 +1926,6 @@ std::vector<CgResult> block_cg_multi(Ctx* c, const std::vector<CgMember>& mem, c
     A.w_red = w_red ? w_red + (size_t)m * (n1 + 1) * R : nullptr;
     A.p_part = p_part ? p_part + (size_t)m * n1 * R * nbu : nullptr;
     A.p_red = p_red ? p_red + (size_t)m * n1 * R : nullptr;
-    A.lnb = staged ? lnb + (size_t)m * nlb * kLMax : nullptr;
-    A.lcnt = staged ? lcnt + (size_t)m * nlb : nullptr;
-    A.lslot = staged ? lslot + slot_off[m] : nullptr;
-    A.nlb = (int)nlb;
     A.urp = uni ? urp + (size_t)m * (ng + 1) : nullptr;
     A.ucol = uni ? ucol + uoff[m] : nullptr;
     A.uval = uni ? uval + 4 * uoff[m] : nullptr;
@@ -2203,7 +1946,7 @@ std::vector<CgResult> block_cg_multi(Ctx* c, const std::vector<CgMember>& mem, c
   }
   CgArgs* dA = c->get<CgArgs>(S_CG_ARGS, B);
   SDGP_HIP(hipMemcpyAsync(dA, hA.data(), B * sizeof(CgArgs), hipMemcpyHostToDevice, c->stream));
-  Launch L{nbs, nbu, ns, R, n1, use_pc, use_lr, B, staged, uni, fw};
+  Launch L{nbs, nbu, ns, R, n1, use_pc, use_lr, B, uni, fw};
   if (!c->in_trial) {
     c->last_shape.spmm_blocks = nbs;
     c->last_shape.update_blocks = nbu;
@@ -2249,7 +1992,7 @@ std::vector<CgResult> block_cg_multi(Ctx* c, const std::vector<CgMember>& mem, c
   // y's solve runs the column-0 kernels only -- the CSR SpMM of column 0
   // and the column-0 blocks of the update kernels -- with the device
   // arguments' slab count set to 0 (restored for the unpack).
-  const bool tail_ok = B == 1 && ns > 0 && probe_cols && prt > rtol && !c->in_trial && !staged;
+  const bool tail_ok = B == 1 && ns > 0 && probe_cols && prt > rtol && !c->in_trial;
   bool tail = false;
   int tail_from = 0;                              // iterations executed when y went alone
   std::vector<int32_t> act_h((size_t)2 * R);

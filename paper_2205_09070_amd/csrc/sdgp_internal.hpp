@@ -95,7 +95,7 @@ enum Slot {
   S_RED_PART, S_RED_OUT, S_X0S, S_MISC, S_POST, S_COUNTER, S_MASK_CNT, S_MASK_PTR, S_MASK,
   S_CG_V, S_CG_PART2, S_CG_ARGS, S_CG_PARTG, S_CG_G, S_CG_GP, S_PC_PART, S_PC_SINV, S_LR_PART, S_LR_FX, S_LR_FV,
   S_MORTON_KEYS, S_MORTON_KEYS2, S_MORTON_IDS, S_MORTON_ORDER, S_MORTON_SZ, S_MORTON_OFF, S_SCHED,
-  S_CG_SRED, S_CG_WRED, S_CG_LNB, S_CG_LCNT, S_CG_LSLOT, S_CG_UCNT, S_CG_UPTR, S_CG_UCOL, S_CG_UVAL, S_QF, S_QM, S_KXX, S_QIV_CNT, S_QIV_PTR, S_QIV, S_QROW_NNZ, S_QROW_PTR, S_QCOL, S_QVAL,
+  S_CG_SRED, S_CG_WRED, S_CG_UCNT, S_CG_UPTR, S_CG_UCOL, S_CG_UVAL, S_QF, S_QM, S_KXX, S_QIV_CNT, S_QIV_PTR, S_QIV, S_QROW_NNZ, S_QROW_PTR, S_QCOL, S_QVAL,
   // population assembly (all members at once)
   S_POP_ARGS, S_POP_RARGS, S_POP_BP, S_POP_F, S_POP_M, S_POP_CM, S_POP_RUNCNT, S_POP_RUNPOS, S_POP_RUNPTR, S_POP_RUNS,
   S_POP_IVCNT, S_POP_IVPTR, S_POP_IV, S_POP_ROWNNZ, S_POP_SCAN, S_POP_ROWPTR, S_POP_COL, S_POP_VAL, S_POP_CAND,
@@ -114,7 +114,6 @@ struct Ctx {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> spmm_events;
   int cu_count = 256;
   bool use_graph = false;        // replay captured CG iterations (hipGraph)
-  bool staged_spmm = false;      // neighbourhood-staged CG SpMM when R <= 33 (opt-in)
   int union_spmm = -1;           // CG SpMM over the 4-row union lists: -1 auto, 0 off, 1 on
   int fw_mfma = -1;              // F w products on the matrix cores: -1 auto, 0 off, 1 on
   int update_blocks = 0;         // blocks of the CG update kernels (0: default cap)

@@ -317,30 +317,6 @@ def test_taylor_logdet_matches_oracle_estimator(terms):
     assert ld == pytest.approx(ld0, rel=1e-11, abs=1e-9)
 
 
-@pytest.mark.parametrize("operator,per_row", [(0, 20.0), (1, 20.0), (0, 90.0)],
-                         ids=["assembled", "factored", "assembled-dense"])
-def test_staged_spmm_matches_global_gathers(operator, per_row):
-    """The neighbourhood-staged SpMM (opt-in, <= 33 columns) computes the
-    same rows as the global-gather SpMM; only the blocking of the p.Ap
-    partial sums differs, so results agree to rounding.  The dense case
-    overflows the per-block lists (4096 entries), exercising unstaged blocks
-    inside the staged kernel too."""
-    gu.need_gpu()
-    import paper_2205_09070_amd as sd
-    w = wl.random_small(5000, 3, 4, 2, 13, per_row=per_row, noise_var=1e-3)
-    gu.log("staged spmm operator=%d per_row=%g" % (operator, per_row))
-    est = sd.estimator(probes=16, seed=4, cg_rtol=1e-11, cg_max_iter=5000, precond=1, operator_form=operator)
-    c = gu.ctx()
-    x, y = gu.dev(w.x), gu.dev(w.y)
-    c.set_option("staged_spmm", 1)
-    v1, g1, i1 = c.lml_grad(w.desc, x, y, w.h, est)
-    c.set_option("staged_spmm", 0)
-    v0, g0, i0 = c.lml_grad(w.desc, x, y, w.h, est)
-    assert abs(i1.cg_iters - i0.cg_iters) <= 2
-    assert abs(v1 - v0) <= 1e-10 * abs(v0)
-    assert gu.grad_close(g1, g0, rel=1e-8).all()
-
-
 @pytest.mark.parametrize("n1,operator", [(6, 1), (20, 1), (20, 0), (40, 1), (64, 1)],
                          ids=["n1=6-factored", "n1=20-factored", "n1=20-assembled", "n1=40-factored",
                               "n1=64-factored"])
