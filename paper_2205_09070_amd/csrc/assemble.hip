@@ -481,7 +481,8 @@ struct RowArgs {
 // instead of once per row.  The cell's intervals are read in windows of 256
 // (one per thread) with their exclusive length prefix from a block scan, so
 // every thread finds its candidate of a chunk by a binary search in LDS.
-// The row group's own points and masks are staged in LDS as well.
+// Each wavefront holds its rows' points, bump masks and output positions in
+// registers (one row per lane) and broadcasts them row by row.
 // Columns stay ascending (chunks follow the sorted disjoint intervals); each
 // row's output position persists in LDS across chunks.  Cells with more
 // than 64 rows are processed in row groups.
@@ -509,18 +510,15 @@ __device__ __forceinline__ double entry_value(const RowArgs& A, int64_t a, const
 
 // LDS of the row kernels.  The fill needs the compaction buffers (kCB = 2
 // wavefronts' worth of entries per wavefront); the count uses one entry.
-template <bool kFill, bool kList = false>
+template <bool kFill, bool kList, int kDim>
 struct CellLds {
   typedef hipcub::BlockScan<int, kBlock> Scan;
   static constexpr int kCB = kFill ? 2 * kWave : 1;
   static constexpr int kKL = kList ? kCC : 1;
   typename Scan::TempStorage scan_tmp;
-  double4 sx[kCC];
+  double sx[kDim][kCC];      // candidate coordinates, one array per axis
   uint64_t sm[kCC];
   int32_t sb[kCC];
-  int64_t spos[kCRows];
-  double4 rx[kCRows];        // the row group's points and bump masks
-  uint64_t rmk[kCRows];
   int32_t wb[kIvWin];        // window: first point of each interval
   int32_t wpre[kIvWin + 1];  // window: exclusive prefix of the lengths
   // fill: per wavefront, the kept entries of the current row compacted in
@@ -534,19 +532,33 @@ struct CellLds {
   int16_t kl[kBlock / kWave][kKL];
 };
 
+// Squared distance from a to staged candidate k (axis arrays in LDS: lanes
+// read consecutive doubles, free of bank conflicts), in the order of dist2.
+template <int kDim>
+__device__ __forceinline__ double dist2_lds(const double4& a, const double (&s)[kDim][kCC], int k) {
+  double dx = a.x - s[0][k];
+  double d2 = dx * dx;
+  if constexpr (kDim > 1) { double d = a.y - s[1][k]; d2 += d * d; }
+  if constexpr (kDim > 2) { double d = a.z - s[2][k]; d2 += d * d; }
+  if constexpr (kDim > 3) { double d = a.w - s[3][k]; d2 += d * d; }
+  return d2;
+}
+
 // Modes of the row body: the count (row_nnz[a] = stored entries of row a,
-// candidates added to cand_total, keep masks recorded when A.mask is set),
-// the fill that tests every candidate again (compacting each row's kept
-// entries in LDS), and the fill from the count's keep masks (the masks'
-// set bits are listed per row in LDS and every lane takes one listed
-// entry: no candidate is tested twice).
+// keep masks recorded when A.mask is set; the candidate tests as three
+// wavefront masks combined in scalar registers, over chunks padded to
+// whole 64-candidate steps), the fill that tests every candidate again
+// (compacting each row's kept entries in LDS), and the fill from the
+// count's keep masks (the masks' set bits are listed per row in LDS and
+// every lane takes one listed entry: no candidate is tested twice).  The
+// candidate pairs are counted apart from these kernels (k_mask_words): one
+// counter updated by every cell's workgroup serialised the whole count.
 constexpr int kRowCount = 0, kRowFillTest = 1, kRowFillMasked = 2;
 
-// Rows of cell c in mode kMode.  L: the block's LDS (a fill-sized one
-// serves every mode).
-template <int kMode, class Lds>
+// Rows of cell c in mode kMode for points of kDim coordinates.  L: the
+// block's LDS (a fill-sized one serves every mode).
+template <int kMode, int kDim, class Lds>
 __device__ __forceinline__ void cell_rows_body(const RowArgs& A, int64_t c, Lds& L, int64_t* __restrict__ row_nnz,
-                                               unsigned long long* __restrict__ cand_total,
                                                const int64_t* __restrict__ row_ptr,
                                                int32_t* __restrict__ col, double* __restrict__ val) {
   constexpr bool kFill = kMode != kRowCount;
@@ -555,9 +567,6 @@ __device__ __forceinline__ void cell_rows_body(const RowArgs& A, int64_t c, Lds&
   auto& sx = L.sx;
   auto& sm = L.sm;
   auto& sb = L.sb;
-  auto& spos = L.spos;
-  auto& rx = L.rx;
-  auto& rmk = L.rmk;
   auto& wb = L.wb;
   auto& wpre = L.wpre;
   auto& kb_col = L.kb_col;
@@ -568,17 +577,38 @@ __device__ __forceinline__ void cell_rows_body(const RowArgs& A, int64_t c, Lds&
   const int32_t i0 = A.iv_ptr[c], i1 = A.iv_ptr[c + 1];
   const int t = threadIdx.x, lane = lane_id(), w = t >> 6;
   constexpr int kWaves = kBlock / kWave;
-  unsigned long long ncand = 0;               // candidates per row (thread 0)
   const int64_t nrc = r1 - r0;                // rows of the cell (mask stride)
   const int64_t mbase = A.mask ? A.mask_ptr[c] : 0;
+  // stored-pattern predicate as two uniform flags: a core pair is kept
+  // unless the bumps must agree too (PRODUCT), a bump pair alone only
+  // under SUM; the diagonal always
+  const bool core_keeps = A.core_only || A.combine != 0;
+  const bool bump_keeps = !A.core_only && A.combine != 0;
   for (int32_t g0 = r0; g0 < r1; g0 += kCRows) {
     const int nr = min(r1 - g0, kCRows);
     int st0 = 0;                              // 64-candidate steps before the chunk (uniform)
-    for (int r = t; r < nr; r += kBlock) {
-      spos[r] = kFill ? row_ptr[g0 + r] : 0;
-      rx[r] = A.xs[g0 + r];
-      rmk[r] = A.M[g0 + r];
+    // rows of the group are dealt to the wavefronts in turn: this one's are
+    // g0 + w + kWaves * i for i < nrw, row i's point, bump mask and output
+    // position (fill) or kept count (count) held by lane i
+    const int nrw = nr > w ? (nr - w + kWaves - 1) / kWaves : 0;
+    double4 xr = make_double4(0.0, 0.0, 0.0, 0.0);
+    uint64_t mr = 0;
+    int64_t pr = 0;
+    if (lane < nrw) {
+      const int32_t a = g0 + w + kWaves * lane;
+      xr = A.xs[a];
+      mr = A.M[a];
+      if (kFill) pr = row_ptr[a];
     }
+    // row i's point and mask, uniform over the wavefront
+    auto row_point = [&](int i) {
+      double4 p;
+      p.x = readlane_f64(xr.x, i);
+      p.y = kDim > 1 ? readlane_f64(xr.y, i) : 0.0;
+      p.z = kDim > 2 ? readlane_f64(xr.z, i) : 0.0;
+      p.w = kDim > 3 ? readlane_f64(xr.w, i) : 0.0;
+      return p;
+    };
     for (int32_t q0 = i0; q0 < i1; q0 += kIvWin) {
       const int nw = min(i1 - q0, kIvWin);
       int len = 0;
@@ -590,10 +620,7 @@ __device__ __forceinline__ void cell_rows_body(const RowArgs& A, int64_t c, Lds&
       int pre = 0, tot = 0;
       Scan(scan_tmp).ExclusiveSum(len, pre, tot);
       if (t < nw) wpre[t] = pre;
-      if (t == 0) {
-        wpre[nw] = tot;
-        if (g0 == r0) ncand += (unsigned long long)tot;
-      }
+      if (t == 0) wpre[nw] = tot;
       __syncthreads();
       for (int k0 = 0; k0 < tot; k0 += kCC) {
         const int filled = min(kCC, tot - k0);
@@ -605,24 +632,62 @@ __device__ __forceinline__ void cell_rows_body(const RowArgs& A, int64_t c, Lds&
             if (wpre[mid] <= kk) lo = mid; else hi = mid;
           }
           const int32_t b = wb[lo] + (kk - wpre[lo]);
-          sx[k] = A.xs[b];
+          const double4 p = A.xs[b];
+          sx[0][k] = p.x;
+          if constexpr (kDim > 1) sx[1][k] = p.y;
+          if constexpr (kDim > 2) sx[2][k] = p.z;
+          if constexpr (kDim > 3) sx[3][k] = p.w;
           sm[k] = A.M[b];
           sb[k] = b;
         }
+        // pad the last 64-candidate step with candidates that are never
+        // kept (NaN distance, no bumps, no point index)
+        const int padded = min(kCC, (filled + kWave - 1) / kWave * kWave);
+        for (int k = filled + t; k < padded; k += kBlock) {
+          sx[0][k] = __builtin_nan("");
+          sm[k] = 0;
+          sb[k] = -1;
+        }
         __syncthreads();
         const int nsteps = (filled + kWave - 1) / kWave;   // <= kCC / 64
+        if constexpr (kMode == kRowCount) {
+          for (int i = 0; i < nrw; ++i) {
+            const int r = w + kWaves * i;
+            const int32_t a = g0 + r;
+            const double4 xa = row_point(i);
+            const uint64_t Ma = readlane_u64(mr, i);
+            int64_t kept = 0;                 // uniform
+            uint64_t mw = 0;                  // lane q: keep mask of step q
+            for (int q = 0; q < nsteps; ++q) {
+              const int k = q * kWave + lane; // a staged or padding candidate
+              const double d2 = dist2_lds<kDim>(xa, sx, k);
+              // the three tests as wavefront masks, combined in scalar registers
+              const uint64_t bd = ballot64(sb[k] == a);
+              const uint64_t bc = ballot64(d2 < A.rc2);
+              const uint64_t bb = ballot64((Ma & sm[k]) != 0);
+              const uint64_t bal = bd | (bc & (core_keeps ? ~0ull : bb)) | (bump_keeps ? bb : 0ull);
+              kept += __popcll(bal);
+              mw = lane == q ? bal : mw;
+            }
+            if (A.mask && lane < nsteps) A.mask[mbase + (int64_t)(st0 + lane) * nrc + (g0 - r0 + r)] = mw;
+            if (lane == i) pr += kept;
+          }
+          st0 += nsteps;
+          __syncthreads();
+          continue;
+        }
         if constexpr (kMode == kRowFillMasked) {
-          for (int r = w; r < nr; r += kWaves) {
+          for (int i = 0; i < nrw; ++i) {
+            const int r = w + kWaves * i;
             const int64_t a = (int64_t)g0 + r;
-            const double4 xa = rx[r];
-            const uint64_t Ma = A.core_only ? 0 : rmk[r];
+            const double4 xa = row_point(i);
+            const uint64_t Ma = A.core_only ? 0 : readlane_u64(mr, i);
             const double* Fa = A.F + a * (int64_t)A.n1;
-            const int64_t pos = spos[r];      // read by every lane before lane 0 moves it on
+            const int64_t pos = (int64_t)readlane_u64((uint64_t)pr, i);
             const uint64_t mw = lane < nsteps ? A.mask[mbase + (int64_t)(st0 + lane) * nrc + (g0 - r0 + r)] : 0;
             int nkeep = 0;                    // uniform
             for (int q = 0; q < nsteps; ++q) {
-              const uint64_t mq = ((uint64_t)(uint32_t)readlane_i32((int)(uint32_t)(mw >> 32), q) << 32) |
-                                  (uint32_t)readlane_i32((int)(uint32_t)mw, q);
+              const uint64_t mq = readlane_u64(mw, q);
               if (mq >> lane & 1) L.kl[w][nkeep + lanes_below(mq)] = (int16_t)(q * kWave + lane);
               nkeep += __popcll(mq);
             }
@@ -630,23 +695,23 @@ __device__ __forceinline__ void cell_rows_body(const RowArgs& A, int64_t c, Lds&
             for (int e = lane; e < nkeep; e += kWave) {
               const int k = L.kl[w][e];
               const int32_t b = sb[k];
-              const double d2 = dist2(xa, sx[k], A.dim);
+              const double d2 = dist2_lds<kDim>(xa, sx, k);
               col[pos + e] = b;
               val[pos + e] = entry_value(A, a, Fa, b, d2, Ma & sm[k]);
             }
             __builtin_amdgcn_wave_barrier();  // the list is the next row's
-            if (lane == 0) spos[r] = pos + nkeep;
+            if (lane == i) pr = pos + nkeep;
           }
           st0 += nsteps;
           __syncthreads();
           continue;
         }
-        for (int r = w; r < nr; r += kWaves) {
-          const int64_t a = (int64_t)g0 + r;
-          const double4 xa = rx[r];
-          const uint64_t Ma = rmk[r];
+        for (int i = 0; i < nrw; ++i) {
+          const int64_t a = (int64_t)g0 + w + kWaves * i;
+          const double4 xa = row_point(i);
+          const uint64_t Ma = readlane_u64(mr, i);
           const double* Fa = A.F + a * (int64_t)A.n1;
-          int64_t pos = spos[r];
+          int64_t pos = (int64_t)readlane_u64((uint64_t)pr, i);
           int nk = 0;                         // compacted kept entries (fill; uniform)
           for (int j0 = 0; j0 < filled; j0 += kWave) {
             const int k = j0 + lane;
@@ -656,19 +721,14 @@ __device__ __forceinline__ void cell_rows_body(const RowArgs& A, int64_t c, Lds&
             int32_t b = 0;
             if (k < filled) {
               b = sb[k];
-              d2 = dist2(xa, sx[k], A.dim);
+              d2 = dist2_lds<kDim>(xa, sx, k);
               core = d2 < A.rc2;
               mm = Ma & sm[k];
               const bool bump = mm != 0;
-              keep = (b == a) || (A.core_only ? core : (A.combine == 0 ? (core && bump) : (core || bump)));
+              keep = (b == a) | (core & (core_keeps | bump)) | (bump_keeps & bump);
               if (A.core_only) mm = 0;
             }
             const uint64_t bal = ballot64(keep);
-            if (!kFill) {
-              pos += __popcll(bal);
-              if (A.mask && lane == 0) A.mask[mbase + (int64_t)(st0 + j0 / kWave) * nrc + (g0 - r0 + r)] = bal;
-              continue;
-            }
             if (keep) {
               const int q = nk + lanes_below(bal);
               kb_col[w][q] = b;
@@ -709,38 +769,57 @@ __device__ __forceinline__ void cell_rows_body(const RowArgs& A, int64_t c, Lds&
             }
             pos += nk;
           }
-          if (lane == 0) spos[r] = pos;
+          if (lane == i) pr = pos;
         }
         st0 += nsteps;
         __syncthreads();
       }
       __syncthreads();                        // window storage and scan storage free again
     }
-    if (!kFill)
-      for (int r = t; r < nr; r += kBlock) row_nnz[g0 + r] = spos[r];
-    __syncthreads();
+    if (!kFill && lane < nrw) row_nnz[g0 + w + kWaves * lane] = pr;
   }
-  if (!kFill && t == 0) atomicAdd(cand_total, ncand * (unsigned long long)(r1 - r0));
 }
 
-template <int kMode>
+template <int kMode, int kDim>
 __global__ __launch_bounds__(kBlock) void k_cell_rows(RowArgs A, int64_t* __restrict__ row_nnz,
-                                                      unsigned long long* __restrict__ cand_total,
                                                       const int64_t* __restrict__ row_ptr,
                                                       int32_t* __restrict__ col, double* __restrict__ val) {
-  __shared__ CellLds<kMode == kRowFillTest, kMode == kRowFillMasked> L;
-  cell_rows_body<kMode>(A, blockIdx.x, L, row_nnz, cand_total, row_ptr, col, val);
+  __shared__ CellLds<kMode == kRowFillTest, kMode == kRowFillMasked, kDim> L;
+  cell_rows_body<kMode, kDim>(A, blockIdx.x, L, row_nnz, row_ptr, col, val);
 }
 
 // Population form: member z's rows (RowArgs[z] holds its kernel
 // parameters and inputs, PopMember[z] its outputs).
-template <bool kFill>
+template <bool kFill, int kDim>
 __global__ __launch_bounds__(kBlock) void k_cell_rows_pop(const RowArgs* __restrict__ ra,
                                                           const PopMember* __restrict__ pm) {
   const PopMember& P = pm[blockIdx.z];
-  __shared__ CellLds<kFill> L;
-  cell_rows_body<kFill ? kRowFillTest : kRowCount>(ra[blockIdx.z], blockIdx.x, L, P.row_nnz, P.cand, P.row_ptr,
-                                                   P.col, P.val);
+  __shared__ CellLds<kFill, false, kDim> L;
+  cell_rows_body<kFill ? kRowFillTest : kRowCount, kDim>(ra[blockIdx.z], blockIdx.x, L, P.row_nnz, P.row_ptr,
+                                                         P.col, P.val);
+}
+
+// Row-kernel launches for points of `dim` coordinates (1 to kMaxDim), one
+// workgroup per cell.
+template <int kMode>
+static void launch_cell_rows(int dim, unsigned grid, hipStream_t st, const RowArgs& A, int64_t* row_nnz,
+                             const int64_t* row_ptr, int32_t* col, double* val) {
+  switch (dim) {
+    case 1: k_cell_rows<kMode, 1><<<grid, kBlock, 0, st>>>(A, row_nnz, row_ptr, col, val); break;
+    case 2: k_cell_rows<kMode, 2><<<grid, kBlock, 0, st>>>(A, row_nnz, row_ptr, col, val); break;
+    case 3: k_cell_rows<kMode, 3><<<grid, kBlock, 0, st>>>(A, row_nnz, row_ptr, col, val); break;
+    default: k_cell_rows<kMode, 4><<<grid, kBlock, 0, st>>>(A, row_nnz, row_ptr, col, val); break;
+  }
+}
+
+template <bool kFill>
+static void launch_cell_rows_pop(int dim, dim3 grid, hipStream_t st, const RowArgs* ra, const PopMember* pm) {
+  switch (dim) {
+    case 1: k_cell_rows_pop<kFill, 1><<<grid, kBlock, 0, st>>>(ra, pm); break;
+    case 2: k_cell_rows_pop<kFill, 2><<<grid, kBlock, 0, st>>>(ra, pm); break;
+    case 3: k_cell_rows_pop<kFill, 3><<<grid, kBlock, 0, st>>>(ra, pm); break;
+    default: k_cell_rows_pop<kFill, 4><<<grid, kBlock, 0, st>>>(ra, pm); break;
+  }
 }
 
 // row_ptr of every member from one scan over the members' concatenated
@@ -1120,24 +1199,47 @@ static RowArgs row_args(const Sorted& s, const KParams& kp, const Bumps& b, cons
 // Keep-mask words of each cell: its rows times its 64-candidate steps (the
 // row body walks the cell's intervals in windows of kIvWin and each
 // window's candidates in chunks of kCC, a multiple of 64, so a window of
-// `tot` candidates takes ceil(tot / 64) steps).  words[nc] = 0.
+// `tot` candidates takes ceil(tot / 64) steps); words[nc] = 0.  Also the
+// candidate pairs (rows times candidates) of all cells, added to cand_total
+// once per wavefront (null words: the sum alone).
 __global__ void k_mask_words(const int32_t* __restrict__ cell_start, const int32_t* __restrict__ iv_ptr,
-                             const int2* __restrict__ iv, int64_t nc, int64_t* __restrict__ words) {
+                             const int2* __restrict__ iv, int64_t nc, int64_t* __restrict__ words,
+                             unsigned long long* __restrict__ cand_total) {
   const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (c > nc) return;
-  if (c == nc) {
+  int64_t pairs = 0;
+  if (c < nc) {
+    const int32_t i0 = iv_ptr[c], i1 = iv_ptr[c + 1];
+    const int64_t rows = cell_start[c + 1] - cell_start[c];
+    int64_t steps = 0, cands = 0;
+    for (int32_t q0 = i0; q0 < i1; q0 += kIvWin) {
+      const int32_t q1 = min(i1, q0 + kIvWin);
+      int64_t tot = 0;
+      for (int32_t q = q0; q < q1; ++q) tot += iv[q].y - iv[q].x;
+      steps += (tot + kWave - 1) / kWave;
+      cands += tot;
+    }
+    if (words) words[c] = rows * steps;
+    pairs = rows * cands;
+  } else if (c == nc && words) {
     words[nc] = 0;
-    return;
   }
-  const int32_t i0 = iv_ptr[c], i1 = iv_ptr[c + 1];
-  int64_t steps = 0;
-  for (int32_t q0 = i0; q0 < i1; q0 += kIvWin) {
-    const int32_t q1 = min(i1, q0 + kIvWin);
-    int64_t tot = 0;
-    for (int32_t q = q0; q < q1; ++q) tot += iv[q].y - iv[q].x;
-    steps += (tot + kWave - 1) / kWave;
+  pairs = wave_sum_i64(pairs);
+  if (lane_id() == 0 && pairs > 0) atomicAdd(cand_total, (unsigned long long)pairs);
+}
+
+// Population form: member z's candidate pairs (its own intervals).
+__global__ void k_cell_cands_pop(const int32_t* __restrict__ cell_start, int64_t nc,
+                                 const PopMember* __restrict__ pm) {
+  const PopMember& P = pm[blockIdx.z];
+  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int64_t pairs = 0;
+  if (c < nc) {
+    int64_t cands = 0;
+    for (int32_t q = P.iv_ptr[c]; q < P.iv_ptr[c + 1]; ++q) cands += P.iv[q].y - P.iv[q].x;
+    pairs = (int64_t)(cell_start[c + 1] - cell_start[c]) * cands;
   }
-  words[c] = (int64_t)(cell_start[c + 1] - cell_start[c]) * steps;
+  pairs = wave_sum_i64(pairs);
+  if (lane_id() == 0 && pairs > 0) atomicAdd(P.cand, (unsigned long long)pairs);
 }
 
 // Count (recording keep masks), device-wide scan, host read of nnz, fill
@@ -1146,9 +1248,13 @@ static Csr assemble_two_pass(Ctx* c, const Sorted& s, RowArgs A, int64_t* candid
                              const CsrOut* out) {
   const int64_t n = s.n;
   const int64_t ncell = s.grid.n_cells;
-  // keep masks of the count for the fill: offsets per cell, then storage
+  // keep masks of the count for the fill: offsets per cell, then storage;
+  // the candidate pairs on the way
   int64_t* mwords = c->get<int64_t>(S_MASK_CNT, ncell + 1);
-  k_mask_words<<<grid_for(ncell + 1, kBlock), kBlock, 0, c->stream>>>(s.cell_start, A.iv_ptr, A.iv, ncell, mwords);
+  unsigned long long* cand = c->get<unsigned long long>(S_COUNTER, 4);
+  SDGP_HIP(hipMemsetAsync(cand, 0, sizeof(unsigned long long), c->stream));
+  k_mask_words<<<grid_for(ncell + 1, kBlock), kBlock, 0, c->stream>>>(s.cell_start, A.iv_ptr, A.iv, ncell, mwords,
+                                                                      cand);
   SDGP_CHECK_LAUNCH();
   int64_t* mptr = c->get<int64_t>(S_MASK_PTR, ncell + 1);
   size_t tbm = 0;
@@ -1161,10 +1267,8 @@ static Csr assemble_two_pass(Ctx* c, const Sorted& s, RowArgs A, int64_t* candid
   A.mask_ptr = mptr;
   A.mask = c->get<uint64_t>(S_MASK, nwords > 0 ? nwords : 1);
   int64_t* row_nnz = c->get<int64_t>(S_ROW_NNZ, n + 1);
-  unsigned long long* cand = c->get<unsigned long long>(S_COUNTER, 4);
-  SDGP_HIP(hipMemsetAsync(cand, 0, sizeof(unsigned long long), c->stream));
   SDGP_HIP(hipMemsetAsync(row_nnz + n, 0, sizeof(int64_t), c->stream));
-  k_cell_rows<kRowCount><<<(unsigned)ncell, kBlock, 0, c->stream>>>(A, row_nnz, cand, nullptr, nullptr, nullptr);
+  launch_cell_rows<kRowCount>(A.dim, (unsigned)ncell, c->stream, A, row_nnz, nullptr, nullptr, nullptr);
   SDGP_CHECK_LAUNCH();
   int64_t* row_ptr = out ? out->row_ptr : c->get<int64_t>(S_ROW_PTR, n + 1);
   size_t tb = 0;
@@ -1185,7 +1289,7 @@ static Csr assemble_two_pass(Ctx* c, const Sorted& s, RowArgs A, int64_t* candid
   }
   int32_t* col = out ? out->col : c->get<int32_t>(S_COL, nnz);
   double* val = out ? out->val : c->get<double>(S_VAL, nnz);
-  k_cell_rows<kRowFillMasked><<<(unsigned)ncell, kBlock, 0, c->stream>>>(A, nullptr, nullptr, row_ptr, col, val);
+  launch_cell_rows<kRowFillMasked>(A.dim, (unsigned)ncell, c->stream, A, nullptr, row_ptr, col, val);
   SDGP_CHECK_LAUNCH();
   k.n = n; k.nnz = nnz; k.row_ptr = row_ptr; k.col = col; k.val = val;
   return k;
@@ -1313,7 +1417,9 @@ std::vector<PopAssembled> assemble_population(Ctx* c, const Sorted& s, const sdg
   RowArgs* dra = c->get<RowArgs>(S_POP_RARGS, B);
   SDGP_HIP(hipMemcpyAsync(dra, ra.data(), B * sizeof(RowArgs), hipMemcpyHostToDevice, c->stream));
   upload();
-  k_cell_rows_pop<false><<<dim3((unsigned)nc, 1, B), kBlock, 0, c->stream>>>(dra, dpm);
+  k_cell_cands_pop<<<dim3(gc, 1, B), kBlock, 0, c->stream>>>(s.cell_start, nc, dpm);
+  SDGP_CHECK_LAUNCH();
+  launch_cell_rows_pop<false>(s.grid.dim, dim3((unsigned)nc, 1, B), c->stream, dra, dpm);
   SDGP_CHECK_LAUNCH();
   int64_t* scan = c->get<int64_t>(S_POP_SCAN, (size_t)B * (n + 1));
   require((int64_t)B * (n + 1) < 0x7fffffffLL, "population too large for one row scan");
@@ -1352,7 +1458,7 @@ std::vector<PopAssembled> assemble_population(Ctx* c, const Sorted& s, const sdg
   }
   upload();
   SDGP_HIP(hipStreamSynchronize(c->stream));   // the host copies (snapshots, bp, row arguments) are done
-  k_cell_rows_pop<true><<<dim3((unsigned)nc, 1, B), kBlock, 0, c->stream>>>(dra, dpm);
+  launch_cell_rows_pop<true>(s.grid.dim, dim3((unsigned)nc, 1, B), c->stream, dra, dpm);
   SDGP_CHECK_LAUNCH();
   return out;
 }

@@ -130,6 +130,37 @@ def case_ci(lib):
             gd = np.abs(g - g0).max() / np.abs(g0).max()
             log("operator %d %s call %d: lml rel %.2e, grad %.2e, iters %d" % (op, opts, rep, d, gd, info.cg_iters))
             ok &= d <= 1e-8 and gd <= 1e-6
+    # assembly in every dimension and both combinations (the row kernels
+    # are compiled per dimension)
+    cases = [wl.random_small(nn, dim, 5, 2, 40 + dim, combine=comb, per_row=14.0, noise_var=1e-2)
+             for dim, comb, nn in ((1, 1, 90), (3, 0, 300), (4, 1, 260))]
+    # a cell with more than 64 rows (several row groups): 520 points in a
+    # cube of side 0.004 (at most 8 cells) over 100 uniform points
+    rng = np.random.default_rng(12)
+    dc = wl.KernelDesc(3, 2, 2, 0, 1)
+    cases.append(wl.Workload("crowded", dc, np.concatenate([0.5 + 0.004 * rng.random((520, 3)),
+                                                            rng.random((100, 3))]), np.zeros(620),
+                             wl.pack_hyper(dc, 1.0, 0.08, np.full((2, 2), 0.7), np.ones((2, 2)),
+                                           np.full((2, 2), 0.2), rng.random((2, 2, 3)), 1e-4)))
+    for wd in cases:
+        dim, comb = wd.desc.dim, wd.desc.combine
+        c = EmuContext(lib)
+        nnz = c.kernel_nnz(wd.desc, wd.x, wd.h)
+        rp, col, val, perm = c.kernel_assemble_sorted(wd.desc, wd.x, wd.h, nnz)
+        ix = np.ix_(perm, perm)
+        K = okn.kernel_matrix(wd.desc, wd.h, wd.x)[ix]
+        pat = okn.pattern(wd.desc, wd.h, wd.x)[ix]
+        bnd = okn.boundary_pairs(wd.desc, wd.h, wd.x)[ix]
+        gpat = np.zeros_like(pat)
+        Kg = np.zeros_like(K)
+        rows = np.repeat(np.arange(len(perm)), np.diff(rp))
+        gpat[rows, col] = True
+        Kg[rows, col] = val
+        same = not ((gpat != pat) & ~bnd).any()
+        d = np.abs(Kg - K).max() / np.abs(K).max()
+        log("assembly %s (%d-D, combine %d): nnz %d, pattern %s, max difference %.2e" % (wd.name, dim, comb, nnz,
+                                                                                           same, d))
+        ok &= same and d <= 1e-13 and rp[-1] == nnz
     # probe columns to a looser tolerance: y keeps cg_rtol (finished alone once
     # the probes have stopped); the estimates move far less than their errors
     for op in (0, 1):
@@ -152,6 +183,12 @@ def case_ci(lib):
     est = _lib.estimator(probes=4, seed=8, cg_rtol=1e-11, cg_max_iter=3000, precond=1)
     v, g, st, infos = c.lml_grad_batched(wp.desc, wp.x, wp.y, H, est)
     for m in range(H.shape[0]):
+        v1, _, i1 = EmuContext(lib).lml_grad(wp.desc, wp.x, wp.y, H[m], est)
+        log("population member %d: candidates %d (single call %d), nnz %d" % (m, infos[m].candidates,
+                                                                                i1.candidates, i1.nnz))
+        # member 0 has the largest core radius: its cell grid is the population's
+        ok &= infos[m].candidates == i1.candidates if m == 0 else True
+        ok &= i1.nnz <= i1.candidates <= wp.x.shape[0] ** 2 and infos[m].nnz <= infos[m].candidates
         vm, gm, _, _ = es.preconditioned_lml_grad(wp.desc, H[m], wp.x, wp.y, 8, 4, 400)
         d = abs(v[m] - vm) / abs(vm)
         gd = np.abs(g[m] - gm).max() / np.abs(gm).max()

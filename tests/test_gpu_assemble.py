@@ -125,6 +125,34 @@ def test_assemble_duplicate_points_and_degenerate_axis():
     assert np.all(gu.check_k_entries(S.toarray(), K, np.abs(np.diag(K)).max()))
 
 
+def test_assemble_crowded_cells():
+    """Cells holding more rows than one row group of the row kernels (64):
+    600 points in a cube of side 0.004 (at most 8 cells, so one holds at
+    least 75) over 300 uniform points, both combinations."""
+    gu.need_gpu()
+    rng = np.random.default_rng(12)
+    x = np.concatenate([0.5 + 0.004 * rng.random((600, 3)), rng.random((300, 3))])
+    for comb in (0, 1):
+        gu.log("assemble crowded cells, combine %d" % comb)
+        desc = wl.KernelDesc(3, 2, 2, 0, comb)
+        h = wl.pack_hyper(desc, 1.0, 0.08, np.full((2, 2), 0.7), np.ones((2, 2)),
+                          np.full((2, 2), 0.2), rng.random((2, 2, 3)), 1e-4)
+        c = gu.ctx()
+        n = x.shape[0]
+        rp, col, val = c.kernel_assemble(desc, gu.dev(x), h)
+        rpn, coln, valn, S = gu.csr_to_host(rp, col, val, n)
+        K = kn.kernel_matrix(desc, h, x)
+        pat = kn.pattern(desc, h, x)
+        bnd = kn.boundary_pairs(desc, h, x)
+        gpat = np.zeros((n, n), dtype=bool)
+        gpat[np.repeat(np.arange(n), np.diff(rpn)), coln] = True
+        assert not ((gpat != pat) & ~bnd).any()
+        for a in range(n):
+            assert np.all(np.diff(coln[rpn[a]:rpn[a + 1]]) > 0)
+        both = gpat & pat
+        assert np.all(gu.check_k_entries(S.toarray()[both], K[both], np.abs(np.diag(K)).max()))
+
+
 def test_assemble_rows_at_one_million_points_sampled():
     """Full-size (1,000,000 points in [0,1)^3, 16x4 bumps) assembly in the
     configuration the benchmark times: sampled rows compared one by one with

@@ -76,6 +76,12 @@ def test_batched_matches_single(precond, operator):
         gu.log("  member %d batched %.15g single %.15g iters %d/%d" % (m, v[m], v1, infos[m].cg_iters,
                                                                         i1.cg_iters))
         assert infos[m].nnz == i1.nnz
+        # candidate pairs: every stored pair is one; member 0 has the
+        # largest core radius, so its cell grid is the population's
+        assert i1.nnz <= i1.candidates <= w.x.shape[0] ** 2
+        assert infos[m].nnz <= infos[m].candidates <= w.x.shape[0] ** 2
+        if m == 0:
+            assert infos[m].candidates == i1.candidates
         if m == 0:
             assert v[m] == v1
             assert np.array_equal(g[m], g1)
