@@ -161,6 +161,21 @@ def case_ci(lib):
         log("assembly %s (%d-D, combine %d): nnz %d, pattern %s, max difference %.2e" % (wd.name, dim, comb, nnz,
                                                                                            same, d))
         ok &= same and d <= 1e-13 and rp[-1] == nnz
+    # union-list SpMM with few blocks (each wavefront walks many 4-row
+    # groups) on a denser matrix (lists of more than 64 entries)
+    wu = wl.random_small(300, 2, 4, 2, 17, combine=1, per_row=45.0, noise_var=1e-2)
+    vu0, gu0, _, _ = es.preconditioned_lml_grad(wu.desc, wu.h, wu.x, wu.y, 5, 4, 400)
+    c = EmuContext(lib)
+    for k, v in {"union_spmm": 1, "fw_mfma": 1, "spmm_blocks": 8}.items():
+        c.set_option(k, v)
+    vu, gu, iu = c.lml_grad(wu.desc, wu.x, wu.y, wu.h, _lib.estimator(probes=4, seed=5, cg_rtol=1e-11,
+                                                                        cg_max_iter=3000, precond=1,
+                                                                        operator_form=1))
+    d = abs(vu - vu0) / abs(vu0)
+    gd = np.abs(gu - gu0).max() / np.abs(gu0).max()
+    log("union SpMM, 8 blocks, %.1f entries per row: lml rel %.2e, grad %.2e, iters %d" % (iu.nnz / 300.0, d, gd,
+                                                                                          iu.cg_iters))
+    ok &= d <= 1e-8 and gd <= 1e-6
     # probe columns to a looser tolerance: y keeps cg_rtol (finished alone once
     # the probes have stopped); the estimates move far less than their errors
     for op in (0, 1):
