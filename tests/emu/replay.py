@@ -134,6 +134,9 @@ def case_ci(lib):
     # are compiled per dimension)
     cases = [wl.random_small(nn, dim, 5, 2, 40 + dim, combine=comb, per_row=14.0, noise_var=1e-2)
              for dim, comb, nn in ((1, 1, 90), (3, 0, 300), (4, 1, 260))]
+    # 20 bump functions of 40 balls: two function tiles, the first one's ball
+    # parameters staged in two chunks split inside a function
+    cases.append(wl.random_small(240, 3, 20, 40, 47, combine=1, per_row=10.0, noise_var=1e-2))
     # a cell with more than 64 rows (several row groups): 520 points in a
     # cube of side 0.004 (at most 8 cells) over 100 uniform points
     rng = np.random.default_rng(12)
