@@ -208,7 +208,7 @@ struct PopMember {
   uint64_t* M;               // [n]
   uint64_t* cm;              // [n_cells] cell masks
   const int32_t* run_ptr;    // [n1 + 1], offsets into runs
-  const int2* runs;          // bump-function cell runs of all members
+  const int4* runs;          // bump-function cell runs of all members
   int32_t* iv_cnt;           // [n_cells + 1]
   const int32_t* iv_ptr;     // [n_cells + 1]
   int2* iv;                  // candidate intervals
@@ -268,7 +268,7 @@ __global__ void k_run_flags(const uint64_t* __restrict__ cm, int64_t nc, int n1,
 }
 
 __global__ void k_run_write(const uint64_t* __restrict__ cm, int64_t nc, int n1, const int32_t* __restrict__ pos,
-                            int2* __restrict__ runs) {
+                            const int32_t* __restrict__ cell_start, int4* __restrict__ runs) {
   const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (c >= nc) return;
   const int i = blockIdx.y;
@@ -277,8 +277,14 @@ __global__ void k_run_write(const uint64_t* __restrict__ cm, int64_t nc, int n1,
   const bool fp = c > 0 && cell_bit(m, c - 1, i);
   const bool fn = c + 1 < nc && cell_bit(m, c + 1, i);
   const int32_t p = pos[((int64_t)blockIdx.z * n1 + i) * nc + c];
-  if (!fp) runs[p].x = (int)c;
-  if (!fn) runs[fp ? p - 1 : p].y = (int)c;
+  if (!fp) {
+    runs[p].x = (int)c;
+    runs[p].z = cell_start[c];
+  }
+  if (!fn) {
+    runs[fp ? p - 1 : p].y = (int)c;
+    runs[fp ? p - 1 : p].w = cell_start[c + 1];
+  }
 }
 
 // run_ptr[z (n1 + 1) + i] = pos[(z n1 + i) nc] for i <= n1 (offsets into
@@ -296,18 +302,29 @@ struct IvArgs {
   const int32_t* cell_start;
   const uint64_t* cm;
   const int32_t* run_ptr;   // [n1 + 1], null for PRODUCT
-  const int2* runs;
+  const int4* runs;         // cell runs (first cell, last cell) with their point bounds
   int use_bumps;
+  int n1 = 0;               // bump functions (0: the runs are not staged in LDS)
 };
+
+// Bump-function runs staged in LDS by the interval kernels (when they fit).
+constexpr int kRunLds = 2048;
 
 // Merged candidate intervals of one query (a training cell, or a test point
 // placed in its clamped cell).  Lists: the x-runs of the neighbouring cells
 // (ascending by construction) and, when bumps are used, the runs of every
 // bump function in `mask`.  A k-way merge emits maximal disjoint point
 // intervals in ascending order; returns their number and, when kFill, writes
-// them to out.
+// them to out.  Every run carries its point bounds (bump runs from their
+// construction, core runs loaded when the merge reaches them), so a merged
+// cell run is converted to points without further loads.  The bump runs are
+// read from `runs` at A.run_ptr offsets minus run_base (A.runs itself, or a
+// copy staged in LDS); up to kRegLists bump lists (all but rare cells) are
+// merged with their positions and next runs in registers (the general
+// path's per-list arrays live in scratch memory).
 template <bool kFill>
-__device__ int merge_intervals(const IvArgs& A, const int* cc, uint64_t mask, int2* __restrict__ out) {
+__device__ int merge_intervals(const IvArgs& A, const int* cc, uint64_t mask, const int4* runs, int run_base,
+                               int2* __restrict__ out) {
   const int dim = A.g.dim;
   // core x-runs enumerated with the highest axis outermost -> ascending
   int n_off = 1;
@@ -316,16 +333,34 @@ __device__ int merge_intervals(const IvArgs& A, const int* cc, uint64_t mask, in
   const int xhi = cc[0] + 1 < A.g.G[0] ? cc[0] + 1 : A.g.G[0] - 1;
 
   // bump lists of the query
-  int lst_pos[kMaxN1], lst_end[kMaxN1];
-  int nl = 0;
-  if (A.use_bumps) {
+  constexpr int kRegLists = 4;
+  const int nl = A.use_bumps ? __popcll(mask) : 0;
+  const bool in_regs = nl <= kRegLists;
+  int lst_pos[kMaxN1], lst_end[kMaxN1];    // more than kRegLists lists
+  int rpos[kRegLists], rend[kRegLists];    // up to kRegLists lists
+  int4 rhead[kRegLists];
+  {
     uint64_t m = mask;
-    while (m) {
-      const int i = __builtin_ctzll(m);
-      m &= m - 1;
-      lst_pos[nl] = A.run_ptr[i];
-      lst_end[nl] = A.run_ptr[i + 1];
-      ++nl;
+#pragma unroll
+    for (int l = 0; l < kRegLists; ++l) {
+      rpos[l] = rend[l] = 0;
+      rhead[l] = make_int4(0, 0, 0, 0);
+      if (in_regs && l < nl) {
+        const int i = __builtin_ctzll(m);
+        m &= m - 1;
+        rpos[l] = A.run_ptr[i] - run_base;
+        rend[l] = A.run_ptr[i + 1] - run_base;
+        if (rpos[l] < rend[l]) rhead[l] = runs[rpos[l]];
+      }
+    }
+    if (!in_regs) {
+      m = mask;
+      for (int l = 0; l < nl; ++l) {
+        const int i = __builtin_ctzll(m);
+        m &= m - 1;
+        lst_pos[l] = A.run_ptr[i] - run_base;
+        lst_end[l] = A.run_ptr[i + 1] - run_base;
+      }
     }
   }
   int core_k = 0;  // next core offset index
@@ -347,19 +382,27 @@ __device__ int merge_intervals(const IvArgs& A, const int* cc, uint64_t mask, in
     return true;
   };
   int64_t next_core_lo = -1, next_core_hi = -1;
+  int32_t next_core_s = 0, next_core_e = 0;
   auto advance_core = [&]() {
     next_core_lo = -1;
     while (core_k < n_off) {
       int64_t lo, hi;
       const bool ok = core_run(core_k, lo, hi);
       ++core_k;
-      if (ok) { next_core_lo = lo; next_core_hi = hi; return; }
+      if (ok) {
+        next_core_lo = lo;
+        next_core_hi = hi;
+        next_core_s = A.cell_start[lo];
+        next_core_e = A.cell_start[hi + 1];
+        return;
+      }
     }
   };
   advance_core();
 
   int count = 0;
   int64_t cur_lo = -1, cur_hi = -1;        // current merged cell run
+  int32_t cur_s = 0, cur_e = 0;            // its point bounds
   int32_t last_s = -1, last_e = -1;        // last point interval (pending)
   auto flush_point = [&](int32_t s, int32_t e) {
     if (e <= s) return;
@@ -371,27 +414,63 @@ __device__ int merge_intervals(const IvArgs& A, const int* cc, uint64_t mask, in
     last_s = s;
     last_e = e;
   };
-  auto emit_cells = [&](int64_t lo, int64_t hi) {
-    flush_point(A.cell_start[lo], A.cell_start[hi + 1]);
-  };
   for (;;) {
     // pick the list whose next run starts lowest
     int64_t best_lo = -1, best_hi = -1;
+    int32_t best_s = 0, best_e = 0;
     int best = -2;
-    if (next_core_lo >= 0) { best_lo = next_core_lo; best_hi = next_core_hi; best = -1; }
-    for (int l = 0; l < nl; ++l) {
-      if (lst_pos[l] < lst_end[l]) {
-        const int2 r = A.runs[lst_pos[l]];
-        if (best == -2 || r.x < best_lo) { best_lo = r.x; best_hi = r.y; best = l; }
+    if (next_core_lo >= 0) {
+      best_lo = next_core_lo;
+      best_hi = next_core_hi;
+      best_s = next_core_s;
+      best_e = next_core_e;
+      best = -1;
+    }
+    if (in_regs) {
+#pragma unroll
+      for (int l = 0; l < kRegLists; ++l) {
+        if (rpos[l] < rend[l] && (best == -2 || rhead[l].x < best_lo)) {
+          best_lo = rhead[l].x;
+          best_hi = rhead[l].y;
+          best_s = rhead[l].z;
+          best_e = rhead[l].w;
+          best = l;
+        }
+      }
+    } else {
+      for (int l = 0; l < nl; ++l) {
+        if (lst_pos[l] < lst_end[l]) {
+          const int4 r = runs[lst_pos[l]];
+          if (best == -2 || r.x < best_lo) {
+            best_lo = r.x;
+            best_hi = r.y;
+            best_s = r.z;
+            best_e = r.w;
+            best = l;
+          }
+        }
       }
     }
     if (best == -2) break;
-    if (best == -1) advance_core(); else ++lst_pos[best];
-    if (cur_lo < 0) { cur_lo = best_lo; cur_hi = best_hi; }
-    else if (best_lo <= cur_hi + 1) { if (best_hi > cur_hi) cur_hi = best_hi; }
-    else { emit_cells(cur_lo, cur_hi); cur_lo = best_lo; cur_hi = best_hi; }
+    if (best == -1) {
+      advance_core();
+    } else if (in_regs) {
+#pragma unroll
+      for (int l = 0; l < kRegLists; ++l)
+        if (l == best && ++rpos[l] < rend[l]) rhead[l] = runs[rpos[l]];
+    } else {
+      ++lst_pos[best];
+    }
+    if (cur_lo < 0) {
+      cur_lo = best_lo; cur_hi = best_hi; cur_s = best_s; cur_e = best_e;
+    } else if (best_lo <= cur_hi + 1) {
+      if (best_hi > cur_hi) { cur_hi = best_hi; cur_e = best_e; }
+    } else {
+      flush_point(cur_s, cur_e);
+      cur_lo = best_lo; cur_hi = best_hi; cur_s = best_s; cur_e = best_e;
+    }
   }
-  if (cur_lo >= 0) emit_cells(cur_lo, cur_hi);
+  if (cur_lo >= 0) flush_point(cur_s, cur_e);
   if (last_s >= 0) {
     if (kFill) out[count] = make_int2(last_s, last_e);
     ++count;
@@ -399,9 +478,26 @@ __device__ int merge_intervals(const IvArgs& A, const int* cc, uint64_t mask, in
   return count;
 }
 
+// The bump runs A.runs[A.run_ptr[0] .. A.run_ptr[n1]) in LDS when they fit
+// (every thread of the block calls this); returns the runs to read and sets
+// base to the offset to subtract from run_ptr values.
+__device__ __forceinline__ const int4* stage_runs(const IvArgs& A, int4* lds, int& base) {
+  base = 0;
+  if (!A.use_bumps || A.n1 <= 0) return A.runs;
+  const int b0 = A.run_ptr[0], total = A.run_ptr[A.n1] - b0;
+  if (total > kRunLds) return A.runs;
+  for (int e = threadIdx.x; e < total; e += blockDim.x) lds[e] = A.runs[b0 + e];
+  __syncthreads();
+  base = b0;
+  return lds;
+}
+
 template <bool kFill>
 __global__ void k_cell_intervals(IvArgs A, int32_t* __restrict__ iv_cnt,
                                  const int32_t* __restrict__ iv_ptr, int2* __restrict__ iv) {
+  __shared__ int4 sruns[kRunLds];
+  int base = 0;
+  const int4* runs = stage_runs(A, sruns, base);
   const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (c >= A.g.n_cells) return;
   int cc[kMaxDim];
@@ -410,7 +506,7 @@ __global__ void k_cell_intervals(IvArgs A, int32_t* __restrict__ iv_cnt,
     for (int k = 0; k < A.g.dim; ++k) { cc[k] = (int)(r % A.g.G[k]); r /= A.g.G[k]; }
   }
   const uint64_t mask = A.use_bumps ? A.cm[c] : 0ull;
-  const int cnt = merge_intervals<kFill>(A, cc, mask, kFill ? iv + iv_ptr[c] : nullptr);
+  const int cnt = merge_intervals<kFill>(A, cc, mask, runs, base, kFill ? iv + iv_ptr[c] : nullptr);
   if (!kFill) iv_cnt[c] = cnt;
 }
 
@@ -418,21 +514,24 @@ __global__ void k_cell_intervals(IvArgs A, int32_t* __restrict__ iv_cnt,
 // cell grid is shared).
 template <bool kFill>
 __global__ void k_cell_intervals_pop(IvArgs A, const PopMember* __restrict__ pm) {
-  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (c >= A.g.n_cells) return;
+  __shared__ int4 sruns[kRunLds];
   const PopMember& P = pm[blockIdx.z];
   A.cm = P.cm;
   if (A.use_bumps) {
     A.run_ptr = P.run_ptr;
     A.runs = P.runs;
   }
+  int base = 0;
+  const int4* runs = stage_runs(A, sruns, base);
+  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= A.g.n_cells) return;
   int cc[kMaxDim];
   {
     int64_t r = c;
     for (int k = 0; k < A.g.dim; ++k) { cc[k] = (int)(r % A.g.G[k]); r /= A.g.G[k]; }
   }
   const uint64_t mask = A.use_bumps ? A.cm[c] : 0ull;
-  const int cnt = merge_intervals<kFill>(A, cc, mask, kFill ? P.iv + P.iv_ptr[c] : nullptr);
+  const int cnt = merge_intervals<kFill>(A, cc, mask, runs, base, kFill ? P.iv + P.iv_ptr[c] : nullptr);
   if (!kFill) P.iv_cnt[c] = cnt;
 }
 
@@ -449,7 +548,7 @@ __global__ void k_query_intervals(IvArgs A, const double4* __restrict__ q, const
   int cc[kMaxDim];
   for (int k = 0; k < A.g.dim; ++k) cc[k] = cell_coord(comp(p, k), A.g.lo[k], A.g.inv_side[k], A.g.G[k]);
   const uint64_t mask = A.use_bumps ? qm[t] : 0ull;
-  const int cnt = merge_intervals<kFill>(A, cc, mask, kFill ? iv + iv_ptr[t] : nullptr);
+  const int cnt = merge_intervals<kFill>(A, cc, mask, A.runs, 0, kFill ? iv + iv_ptr[t] : nullptr);
   if (!kFill) iv_cnt[t] = cnt;
 }
 
@@ -1121,8 +1220,8 @@ Bumps bump_precompute(Ctx* c, const Sorted& s, const KParams& kp, const double* 
 // Bump-function cell runs of B members (masks cm[z nc + c]) with no host
 // round trip: flags, one scan, run pointers and runs (storage sized for the
 // most runs a function can have, ceil(nc / 2)).
-static void bump_runs(Ctx* c, const uint64_t* cm, int64_t nc, int n1, int B, Slot s_flag, Slot s_pos, Slot s_ptr,
-                      Slot s_runs, int32_t** run_ptr_out, int2** runs_out) {
+static void bump_runs(Ctx* c, const uint64_t* cm, const int32_t* cell_start, int64_t nc, int n1, int B,
+                      Slot s_flag, Slot s_pos, Slot s_ptr, Slot s_runs, int32_t** run_ptr_out, int4** runs_out) {
   const int64_t nflag = (int64_t)B * n1 * nc + 1;
   require(nflag < 0x7fffffffLL, "too many (member, bump function, cell) triples");
   int32_t* flag = c->get<int32_t>(s_flag, nflag);
@@ -1138,8 +1237,8 @@ static void bump_runs(Ctx* c, const uint64_t* cm, int64_t nc, int n1, int B, Slo
   int32_t* run_ptr = c->get<int32_t>(s_ptr, (size_t)B * (n1 + 1));
   k_run_ptr<<<(unsigned)grid_for((int64_t)B * (n1 + 1), kBlock), kBlock, 0, c->stream>>>(pos, nc, n1, B, run_ptr);
   SDGP_CHECK_LAUNCH();
-  int2* runs = c->get<int2>(s_runs, (size_t)B * n1 * ((nc + 1) / 2) + 1);
-  k_run_write<<<dim3(gc, n1, B), kBlock, 0, c->stream>>>(cm, nc, n1, pos, runs);
+  int4* runs = c->get<int4>(s_runs, (size_t)B * n1 * ((nc + 1) / 2) + 1);
+  k_run_write<<<dim3(gc, n1, B), kBlock, 0, c->stream>>>(cm, nc, n1, pos, cell_start, runs);
   SDGP_CHECK_LAUNCH();
   *run_ptr_out = run_ptr;
   *runs_out = runs;
@@ -1158,10 +1257,11 @@ void prune(Ctx* c, const Sorted& s, const KParams& kp, const Bumps& b, int32_t**
   A.run_ptr = nullptr;
   A.runs = nullptr;
   A.use_bumps = (kp.combine == SDGP_COMBINE_SUM && kp.n1 > 0 && !core_only) ? 1 : 0;
+  A.n1 = kp.n1;
   if (A.use_bumps) {
     int32_t* run_ptr = nullptr;
-    int2* runs = nullptr;
-    bump_runs(c, cm, nc, kp.n1, 1, S_RUN_CNT, S_RUN_POS, S_RUN_PTR, S_RUNS, &run_ptr, &runs);
+    int4* runs = nullptr;
+    bump_runs(c, cm, s.cell_start, nc, kp.n1, 1, S_RUN_CNT, S_RUN_POS, S_RUN_PTR, S_RUNS, &run_ptr, &runs);
     A.run_ptr = run_ptr;
     A.runs = runs;
   }
@@ -1360,10 +1460,12 @@ std::vector<PopAssembled> assemble_population(Ctx* c, const Sorted& s, const sdg
   A.run_ptr = nullptr;
   A.runs = nullptr;
   A.use_bumps = (d.combine == SDGP_COMBINE_SUM && n1 > 0) ? 1 : 0;
+  A.n1 = n1;
   if (A.use_bumps) {
     int32_t* run_ptr = nullptr;
-    int2* runs = nullptr;
-    bump_runs(c, cm, nc, n1, B, S_POP_RUNCNT, S_POP_RUNPOS, S_POP_RUNPTR, S_POP_RUNS, &run_ptr, &runs);
+    int4* runs = nullptr;
+    bump_runs(c, cm, s.cell_start, nc, n1, B, S_POP_RUNCNT, S_POP_RUNPOS, S_POP_RUNPTR, S_POP_RUNS, &run_ptr,
+              &runs);
     for (int m = 0; m < B; ++m) {
       pm[m].run_ptr = run_ptr + (size_t)m * (n1 + 1);
       pm[m].runs = runs;                     // run pointers index the one array of all members
@@ -1501,7 +1603,7 @@ Csr assemble_cross(Ctx* c, const Sorted& s, const KParams& kp, const Bumps& b, c
   A.cm = c->buf[S_CELLMASK].as<uint64_t>();
   A.use_bumps = (kp.combine == SDGP_COMBINE_SUM && kp.n1 > 0) ? 1 : 0;
   A.run_ptr = A.use_bumps ? c->buf[S_RUN_PTR].as<int32_t>() : nullptr;
-  A.runs = A.use_bumps ? c->buf[S_RUNS].as<int2>() : nullptr;
+  A.runs = A.use_bumps ? c->buf[S_RUNS].as<int4>() : nullptr;
   int32_t* iv_cnt = c->get<int32_t>(S_QIV_CNT, n0 + 1);
   SDGP_HIP(hipMemsetAsync(iv_cnt + n0, 0, sizeof(int32_t), c->stream));
   k_query_intervals<false><<<grid_for(n0, kBlock), kBlock, 0, c->stream>>>(A, q, qm, n0, iv_cnt, nullptr, nullptr);

@@ -54,9 +54,11 @@ struct dim3 {
 };
 
 struct __attribute__((aligned(8))) int2 { int x, y; };
+struct __attribute__((aligned(16))) int4 { int x, y, z, w; };
 struct __attribute__((aligned(16))) double2 { double x, y; };
 struct __attribute__((aligned(32))) double4 { double x, y, z, w; };
 inline int2 make_int2(int x, int y) { return int2{x, y}; }
+inline int4 make_int4(int x, int y, int z, int w) { return int4{x, y, z, w}; }
 inline double2 make_double2(double x, double y) { return double2{x, y}; }
 inline double4 make_double4(double x, double y, double z, double w) { return double4{x, y, z, w}; }
 
