@@ -699,7 +699,7 @@ __device__ __forceinline__ void cell_rows_body(const RowArgs& A, int64_t c, Lds&
       mr = A.M[a];
       if (kFill) pr = row_ptr[a];
     }
-    // row i's point and mask, uniform over the wavefront
+    // row i's point, uniform over the wavefront
     auto row_point = [&](int i) {
       double4 p;
       p.x = readlane_f64(xr.x, i);
