@@ -506,8 +506,216 @@ __global__ void k_cell_intervals(IvArgs A, int32_t* __restrict__ iv_cnt,
     for (int k = 0; k < A.g.dim; ++k) { cc[k] = (int)(r % A.g.G[k]); r /= A.g.G[k]; }
   }
   const uint64_t mask = A.use_bumps ? A.cm[c] : 0ull;
+  if (mask != 0) return;                      // k_cell_intervals_wave's cell
   const int cnt = merge_intervals<kFill>(A, cc, mask, runs, base, kFill ? iv + iv_ptr[c] : nullptr);
   if (!kFill) iv_cnt[c] = cnt;
+}
+
+// Cell run k of the 3^(dim-1) core runs of cell cc (x-runs xlo..xhi of the
+// neighbouring rows, the highest axis outermost: ascending in k); false when
+// the row lies outside the grid.
+__device__ __forceinline__ bool core_run_of(const IvArgs& A, const int* cc, int xlo, int xhi, int k, int64_t& lo,
+                                            int64_t& hi) {
+  int64_t base = 0;
+  int64_t mul = A.g.G[0];
+  int t = k;
+  for (int ax = 1; ax < A.g.dim; ++ax) {
+    const int o = t % 3 - 1;
+    t /= 3;
+    const int v = cc[ax] + o;
+    if (v < 0 || v >= A.g.G[ax]) return false;
+    base += (int64_t)v * mul;
+    mul *= A.g.G[ax];
+  }
+  lo = base + xlo;
+  hi = base + xhi;
+  return true;
+}
+
+// Inclusive prefix maximum over the wavefront's lanes.
+__device__ __forceinline__ int64_t wave_incl_max(int64_t v) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int64_t u = __shfl_up(v, o, kWave);
+    if (lane >= o) v = u > v ? u : v;
+  }
+  return v;
+}
+
+// The merged candidate intervals of one cell by a whole wavefront (every
+// lane calls it), with the serial merge's result: the cell's core runs and
+// bump lists (runs with their point bounds) are gathered into buf (LDS,
+// kWaveRuns entries), sorted by first cell (bitonic), merged into cell runs
+// by a prefix maximum of the last cells (a run starts a new merged run when
+// it begins more than one cell after every earlier run ends), and the merged
+// runs' point intervals are chained where they touch.  Returns -1 when the
+// runs do not fit in buf.
+constexpr int kWaveRuns = 512;
+template <bool kFill>
+__device__ int merge_wave(const IvArgs& A, const int* cc, uint64_t mask, int4* buf, int2* __restrict__ out) {
+  const int lane = lane_id();
+  int n_off = 1;
+  for (int k = 1; k < A.g.dim; ++k) n_off *= 3;
+  const int xlo = cc[0] > 0 ? cc[0] - 1 : 0;
+  const int xhi = cc[0] + 1 < A.g.G[0] ? cc[0] + 1 : A.g.G[0] - 1;
+  int T = n_off;                               // upper bound first: every core run
+  for (uint64_t m = mask; m; m &= m - 1) {
+    const int i = __builtin_ctzll(m);
+    T += A.run_ptr[i + 1] - A.run_ptr[i];
+  }
+  if (T > kWaveRuns) return -1;
+  // 1. gather: the core runs that exist, then every bump list
+  T = 0;
+  {
+    int64_t lo = 0, hi = 0;
+    const bool ok = lane < n_off && core_run_of(A, cc, xlo, xhi, lane, lo, hi);   // n_off <= 27
+    const uint64_t bal = ballot64(ok);
+    if (ok) buf[lanes_below(bal)] = make_int4((int)lo, (int)hi, A.cell_start[lo], A.cell_start[hi + 1]);
+    T = __popcll(bal);
+  }
+  for (uint64_t m = mask; m; m &= m - 1) {
+    const int i = __builtin_ctzll(m);
+    const int p0 = A.run_ptr[i], len = A.run_ptr[i + 1] - p0;
+    for (int e = lane; e < len; e += kWave) buf[T + e] = A.runs[p0 + e];
+    T += len;
+  }
+  // 2. bitonic sort by first cell over a power of two, padded with runs past every cell
+  int P = 1;
+  while (P < T) P <<= 1;
+  for (int e = T + lane; e < P; e += kWave) buf[e] = make_int4(0x7fffffff, 0x7fffffff, 0, 0);
+  __builtin_amdgcn_wave_barrier();
+  for (int k = 2; k <= P; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = lane; i < P; i += kWave) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const int4 a = buf[i], b = buf[ixj];
+          if ((a.x > b.x) == ((i & k) == 0)) {
+            buf[i] = b;
+            buf[ixj] = a;
+          }
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+  // 3. merged cell runs, written over buf from the front (group g <= run i):
+  // key = (last cell, its end point bound) so the maximum carries the bound
+  int64_t kmax = INT64_MIN;                    // over all runs so far (uniform)
+  int ng = 0;                                  // merged runs so far (uniform)
+  for (int c0 = 0; c0 < T; c0 += kWave) {
+    const int i = c0 + lane;
+    const bool valid = i < T;
+    const int4 r = valid ? buf[i] : make_int4(0, 0, 0, 0);
+    const int64_t key = valid ? ((int64_t)r.y << 32 | (uint32_t)r.w) : INT64_MIN;
+    const int64_t incl = wave_incl_max(key);
+    int64_t excl = __shfl_up(incl, 1, kWave);
+    if (lane == 0) excl = INT64_MIN;
+    if (kmax > excl) excl = kmax;
+    const bool start = valid && (excl == INT64_MIN || (excl >> 32) < (int64_t)r.x - 1);
+    const uint64_t sb = ballot64(start);
+    const int g = ng + lanes_below(sb);        // this run's merged run when it starts one
+    __builtin_amdgcn_wave_barrier();           // every run of the chunk is read
+    if (start) {
+      buf[g].x = r.x;                          // first cell and first point
+      buf[g].z = r.z;
+      if (g > 0) {                             // the previous merged run ends here
+        buf[g - 1].y = (int)(excl >> 32);
+        buf[g - 1].w = (int)(uint32_t)excl;
+      }
+    }
+    ng += __popcll(sb);
+    const int64_t cm = (int64_t)readlane_u64((uint64_t)incl, kWave - 1);
+    if (cm > kmax) kmax = cm;
+    __builtin_amdgcn_wave_barrier();
+  }
+  if (lane == 0 && ng > 0) {
+    buf[ng - 1].y = (int)(kmax >> 32);
+    buf[ng - 1].w = (int)(uint32_t)kmax;
+  }
+  __builtin_amdgcn_wave_barrier();
+  // 4. point intervals: empty merged runs dropped, touching ones chained
+  int64_t last_e = -1;                         // end of the last non-empty merged run (uniform)
+  int nout = 0;
+  for (int g0 = 0; g0 < ng; g0 += kWave) {
+    const int g = g0 + lane;
+    const bool valid = g < ng;
+    const int4 q = valid ? buf[g] : make_int4(0, 0, 0, 0);
+    const bool nonempty = valid && q.w > q.z;
+    const int64_t v = nonempty ? (int64_t)q.w : -1;
+    const int64_t incl = wave_incl_max(v);
+    int64_t excl = __shfl_up(incl, 1, kWave);
+    if (lane == 0) excl = -1;
+    if (last_e > excl) excl = last_e;
+    const bool start = nonempty && excl != (int64_t)q.z;
+    const uint64_t sb = ballot64(start);
+    const int o = nout + lanes_below(sb);
+    if (kFill && start) {
+      out[o].x = q.z;
+      if (o > 0) out[o - 1].y = (int)excl;
+    }
+    nout += __popcll(sb);
+    const int64_t cm = (int64_t)readlane_u64((uint64_t)incl, kWave - 1);
+    if (cm > last_e) last_e = cm;
+  }
+  if (kFill && lane == 0 && nout > 0) out[nout - 1].y = (int)last_e;
+  return nout;
+}
+
+// Cells with bump lists: one wavefront per cell (kWaveCells cells per
+// wavefront, in turn; one keeps the slowest wavefront at one cell), the
+// merge shared by the wavefront; cells whose runs do not fit in LDS are
+// merged serially by lane 0.
+constexpr int kWaveCells = 1;
+template <bool kFill>
+__device__ __forceinline__ void bump_cells_wave(const IvArgs& A, int32_t* __restrict__ iv_cnt,
+                                                const int32_t* __restrict__ iv_ptr, int2* __restrict__ iv,
+                                                int4* buf) {
+  const int lane = lane_id();
+  const int64_t c0 = ((int64_t)blockIdx.x * (kBlock / kWave) + (threadIdx.x >> 6)) * kWaveCells;
+  for (int u = 0; u < kWaveCells; ++u) {
+    const int64_t c = c0 + u;
+    if (c >= A.g.n_cells) break;
+    const uint64_t mask = A.cm[c];
+    if (mask == 0) continue;
+    int cc[kMaxDim];
+    {
+      int64_t r = c;
+      for (int k = 0; k < A.g.dim; ++k) { cc[k] = (int)(r % A.g.G[k]); r /= A.g.G[k]; }
+    }
+    int2* out = kFill ? iv + iv_ptr[c] : nullptr;
+    int cnt = merge_wave<kFill>(A, cc, mask, buf, out);
+    if (cnt < 0) {
+      if (lane == 0) cnt = merge_intervals<kFill>(A, cc, mask, A.runs, 0, out);
+      cnt = readlane_i32(cnt, 0);
+    }
+    if (!kFill && lane == 0) iv_cnt[c] = cnt;
+    __builtin_amdgcn_wave_barrier();           // buf is the next cell's
+  }
+}
+
+template <bool kFill>
+__global__ __launch_bounds__(kBlock) void k_cell_intervals_wave(IvArgs A, int32_t* __restrict__ iv_cnt,
+                                                                const int32_t* __restrict__ iv_ptr,
+                                                                int2* __restrict__ iv) {
+  __shared__ int4 buf[kBlock / kWave][kWaveRuns];
+  bump_cells_wave<kFill>(A, iv_cnt, iv_ptr, iv, buf[threadIdx.x >> 6]);
+}
+
+template <bool kFill>
+__global__ __launch_bounds__(kBlock) void k_cell_intervals_wave_pop(IvArgs A, const PopMember* __restrict__ pm) {
+  __shared__ int4 buf[kBlock / kWave][kWaveRuns];
+  const PopMember& P = pm[blockIdx.z];
+  A.cm = P.cm;
+  A.run_ptr = P.run_ptr;
+  A.runs = P.runs;
+  bump_cells_wave<kFill>(A, P.iv_cnt, P.iv_ptr, P.iv, buf[threadIdx.x >> 6]);
+}
+
+static unsigned wave_cell_grid(int64_t nc) {
+  const int64_t per_block = (int64_t)(kBlock / kWave) * kWaveCells;
+  return (unsigned)((nc + per_block - 1) / per_block);
 }
 
 // Population form: member z's intervals with its own masks and runs (the
@@ -531,6 +739,7 @@ __global__ void k_cell_intervals_pop(IvArgs A, const PopMember* __restrict__ pm)
     for (int k = 0; k < A.g.dim; ++k) { cc[k] = (int)(r % A.g.G[k]); r /= A.g.G[k]; }
   }
   const uint64_t mask = A.use_bumps ? A.cm[c] : 0ull;
+  if (mask != 0) return;                      // k_cell_intervals_wave_pop's cell
   const int cnt = merge_intervals<kFill>(A, cc, mask, runs, base, kFill ? P.iv + P.iv_ptr[c] : nullptr);
   if (!kFill) P.iv_cnt[c] = cnt;
 }
@@ -1268,6 +1477,10 @@ void prune(Ctx* c, const Sorted& s, const KParams& kp, const Bumps& b, int32_t**
   int32_t* iv_cnt = c->get<int32_t>(S_IV_CNT, nc + 1);
   k_cell_intervals<false><<<grid_for(nc, kBlock), kBlock, 0, c->stream>>>(A, iv_cnt, nullptr, nullptr);
   SDGP_CHECK_LAUNCH();
+  if (A.use_bumps) {
+    k_cell_intervals_wave<false><<<wave_cell_grid(nc), kBlock, 0, c->stream>>>(A, iv_cnt, nullptr, nullptr);
+    SDGP_CHECK_LAUNCH();
+  }
   int32_t* iv_ptr = c->get<int32_t>(S_IV_PTR, nc + 1);
   size_t tb = 0;
   SDGP_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, iv_cnt, iv_ptr, (int)(nc + 1), c->stream));
@@ -1281,6 +1494,10 @@ void prune(Ctx* c, const Sorted& s, const KParams& kp, const Bumps& b, int32_t**
   int2* iv = c->get<int2>(S_IV, total > 0 ? total : 1);
   k_cell_intervals<true><<<grid_for(nc, kBlock), kBlock, 0, c->stream>>>(A, nullptr, iv_ptr, iv);
   SDGP_CHECK_LAUNCH();
+  if (A.use_bumps) {
+    k_cell_intervals_wave<true><<<wave_cell_grid(nc), kBlock, 0, c->stream>>>(A, nullptr, iv_ptr, iv);
+    SDGP_CHECK_LAUNCH();
+  }
   *iv_ptr_out = iv_ptr;
   *iv_out = iv;
 }
@@ -1483,6 +1700,10 @@ std::vector<PopAssembled> assemble_population(Ctx* c, const Sorted& s, const sdg
   upload();
   k_cell_intervals_pop<false><<<dim3(gc, 1, B), kBlock, 0, c->stream>>>(A, dpm);
   SDGP_CHECK_LAUNCH();
+  if (A.use_bumps) {
+    k_cell_intervals_wave_pop<false><<<dim3(wave_cell_grid(nc), 1, B), kBlock, 0, c->stream>>>(A, dpm);
+    SDGP_CHECK_LAUNCH();
+  }
   require((int64_t)B * (nc + 1) < 0x7fffffffLL, "population too large for one interval scan");
   {
     size_t tb = 0;
@@ -1500,6 +1721,10 @@ std::vector<PopAssembled> assemble_population(Ctx* c, const Sorted& s, const sdg
   upload();
   k_cell_intervals_pop<true><<<dim3(gc, 1, B), kBlock, 0, c->stream>>>(A, dpm);
   SDGP_CHECK_LAUNCH();
+  if (A.use_bumps) {
+    k_cell_intervals_wave_pop<true><<<dim3(wave_cell_grid(nc), 1, B), kBlock, 0, c->stream>>>(A, dpm);
+    SDGP_CHECK_LAUNCH();
+  }
   // count: row lengths of every member; one scan; row pointers rebased per
   // member so that each member's CSR starts at 0
   int64_t* row_nnz = c->get<int64_t>(S_POP_ROWNNZ, (size_t)B * (n + 1));

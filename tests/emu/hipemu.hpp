@@ -298,6 +298,17 @@ inline T __shfl_xor(T v, int mask, int width = 64) {
   return ::emu::from_bits<T>(all[src]);
 }
 
+template <class T>
+inline T __shfl_up(T v, unsigned delta, int width = 64) {
+  uint64_t m;
+  const uint64_t* all = ::emu::wave_collect(::emu::to_bits(v), &m, ::emu::kShfl);
+  const int l = ::emu::lane();
+  if ((l & (width - 1)) < (int)delta) return v;
+  const int src = l - (int)delta;
+  if (!(m >> src & 1)) ::emu::fail("__shfl_up from lane %d, which is not live", src);
+  return ::emu::from_bits<T>(all[src]);
+}
+
 inline int __any(int p) {
   uint64_t m;
   const uint64_t* all = ::emu::wave_collect(p ? 1 : 0, &m, ::emu::kVote);
