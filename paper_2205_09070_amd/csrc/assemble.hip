@@ -800,10 +800,14 @@ constexpr int kIvWin = kBlock;  // intervals per window
 
 // Value of a stored entry (row a with bump values Fa, column b): the kernel
 // of the stored-pattern predicate's pair, plus the noise on the diagonal.
+// kDim: the points' dimension, which fixes the Wendland exponent
+// (l = d / 2 + 2, as A.ell).
+template <int kDim>
 __device__ __forceinline__ double entry_value(const RowArgs& A, int64_t a, const double* Fa, int32_t b, double d2,
                                               uint64_t mm) {
+  constexpr int kEll = kDim / 2 + 2;
   double psi = 0.0;
-  if (d2 < A.rc2) psi = core_psi(sqrt(d2) / A.r_core, A.core, A.ell);
+  if (d2 < A.rc2) psi = core_psi(sqrt(d2) / A.r_core, A.core, kEll);
   double B = 0.0;
   const double* Fb = A.F + (int64_t)b * A.n1;
   while (mm) {
@@ -1005,7 +1009,7 @@ __device__ __forceinline__ void cell_rows_body(const RowArgs& A, int64_t c, Lds&
               const int32_t b = sb[k];
               const double d2 = dist2_lds<kDim>(xa, sx, k);
               col[pos + e] = b;
-              val[pos + e] = entry_value(A, a, Fa, b, d2, Ma & sm[k]);
+              val[pos + e] = entry_value<kDim>(A, a, Fa, b, d2, Ma & sm[k]);
             }
             __builtin_amdgcn_wave_barrier();  // the list is the next row's
             if (lane == i) pr = pos + nkeep;
@@ -1048,7 +1052,7 @@ __device__ __forceinline__ void cell_rows_body(const RowArgs& A, int64_t c, Lds&
               __builtin_amdgcn_wave_barrier();
               const int32_t bb = kb_col[w][lane];
               col[pos + lane] = bb;
-              val[pos + lane] = entry_value(A, a, Fa, bb, kb_d2[w][lane], kb_mm[w][lane]);
+              val[pos + lane] = entry_value<kDim>(A, a, Fa, bb, kb_d2[w][lane], kb_mm[w][lane]);
               pos += kWave;
               nk -= kWave;
               __builtin_amdgcn_wave_barrier();
@@ -1073,7 +1077,7 @@ __device__ __forceinline__ void cell_rows_body(const RowArgs& A, int64_t c, Lds&
             if (lane < nk) {
               const int32_t bb = kb_col[w][lane];
               col[pos + lane] = bb;
-              val[pos + lane] = entry_value(A, a, Fa, bb, kb_d2[w][lane], kb_mm[w][lane]);
+              val[pos + lane] = entry_value<kDim>(A, a, Fa, bb, kb_d2[w][lane], kb_mm[w][lane]);
             }
             pos += nk;
           }
