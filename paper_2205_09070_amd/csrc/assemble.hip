@@ -771,7 +771,7 @@ struct RowArgs {
   const int32_t* iv_ptr;
   const int2* iv;
   int64_t n;
-  int dim, n1, core, ell, combine, add_noise;
+  int dim, n1, core, combine, add_noise;
   int core_only;   // keep only the core part (+ diagonal), values without B
   double sigma2, r_core, rc2, noise;
   // keep masks of the count (one 64-bit word per row and 64-candidate step;
@@ -801,7 +801,7 @@ constexpr int kIvWin = kBlock;  // intervals per window
 // Value of a stored entry (row a with bump values Fa, column b): the kernel
 // of the stored-pattern predicate's pair, plus the noise on the diagonal.
 // kDim: the points' dimension, which fixes the Wendland exponent
-// (l = d / 2 + 2, as A.ell).
+// (l = d / 2 + 2).
 template <int kDim>
 __device__ __forceinline__ double entry_value(const RowArgs& A, int64_t a, const double* Fa, int32_t b, double d2,
                                               uint64_t mm) {
@@ -1511,7 +1511,7 @@ static RowArgs row_args(const Sorted& s, const KParams& kp, const Bumps& b, cons
   RowArgs A;
   A.xs = s.xs; A.M = b.M; A.F = b.F; A.cell_of = s.cell_of; A.cell_start = s.cell_start;
   A.iv_ptr = iv_ptr; A.iv = iv;
-  A.n = s.n; A.dim = kp.dim; A.n1 = kp.n1; A.core = kp.core; A.ell = kp.dim / 2 + 2;
+  A.n = s.n; A.dim = kp.dim; A.n1 = kp.n1; A.core = kp.core;
   A.combine = kp.combine; A.add_noise = add_noise ? 1 : 0; A.core_only = core_only ? 1 : 0;
   A.sigma2 = kp.sigma2; A.r_core = kp.r_core; A.rc2 = kp.rc2; A.noise = kp.noise;
   return A;
