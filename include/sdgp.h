@@ -135,7 +135,8 @@ typedef struct {
  * [5] CG, [6] SLQ, [7] adjoint. */
 typedef struct {
   int64_t nnz;             /* stored entries of K */
-  int64_t candidates;      /* candidate pairs examined by the fill pass */
+  int64_t candidates;      /* candidate pairs the assembly's count pass tests
+                              (each row times the candidate points of its cell) */
   int32_t cg_iters;        /* block-CG iterations run */
   int32_t cg_iters_y;      /* iterations of the y column */
   double cg_relres_max;    /* max final relative residual over columns */
