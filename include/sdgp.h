@@ -115,8 +115,9 @@ typedef struct {
  * probe column has stopped while y still iterates, a single evaluation
  * finishes y with the column-0 kernels only (a sparse matrix-vector
  * product per iteration).  At the 1M-point workload probe_rtol 1e-6 moves
- * the LML by 2e-13 and the gradient by 5e-10 (relative) against 1e-10,
- * far inside the estimators' standard errors.  Batched evaluations apply
+ * the LML by less than 1e-12 and the gradient by less than 1e-9 (relative,
+ * in the runs measured) against 1e-10, far inside the estimators' standard
+ * errors.  Batched evaluations apply
  * the tolerance but keep every column in the launches. */
 typedef struct {
   int32_t probes;          /* P, 1..64 for Rademacher */
