@@ -153,6 +153,33 @@ def test_assemble_crowded_cells():
         assert np.all(gu.check_k_entries(S.toarray()[both], K[both], np.abs(np.diag(K)).max()))
 
 
+def test_assemble_cells_beyond_the_wavefront_merge():
+    """Bump-covered cells whose runs exceed what one wavefront merges in
+    LDS (512 runs): 6000 points in 3-D, 5 bump functions of 300 small balls
+    (radii 0.3-0.6 of the core radius), so a cell covered by several
+    functions carries 500-900 runs and is merged by the serial fallback,
+    the others by the wavefront merge; pattern and values against the
+    oracle."""
+    gu.need_gpu()
+    w = wl.random_small(6000, 3, 5, 300, 77, per_row=14.0)
+    p = wl.unpack_hyper(w.desc, w.h)
+    r = np.random.default_rng(5).uniform(0.3 * p["r_core"], 0.6 * p["r_core"], size=(5, 300))
+    h = wl.pack_hyper(w.desc, p["sigma2"], p["r_core"], p["a"], p["beta"], r, p["c"], p["noise_var"])
+    gu.log("assemble beyond the wavefront merge n=%d n1=5 n2=300" % w.x.shape[0])
+    c = gu.ctx()
+    n = w.x.shape[0]
+    rp, col, val = c.kernel_assemble(w.desc, gu.dev(w.x), h, add_noise=True)
+    rpn, coln, valn, S = gu.csr_to_host(rp, col, val, n)
+    K = kn.kernel_matrix(w.desc, h, w.x)
+    pat = kn.pattern(w.desc, h, w.x)
+    bnd = kn.boundary_pairs(w.desc, h, w.x)
+    gpat = np.zeros((n, n), dtype=bool)
+    gpat[np.repeat(np.arange(n), np.diff(rpn)), coln] = True
+    assert not ((gpat != pat) & ~bnd).any()
+    both = gpat & pat
+    assert np.all(gu.check_k_entries(S.toarray()[both], K[both], np.abs(np.diag(K)).max()))
+
+
 def test_assemble_rows_at_one_million_points_sampled():
     """Full-size (1,000,000 points in [0,1)^3, 16x4 bumps) assembly in the
     configuration the benchmark times: sampled rows compared one by one with
