@@ -105,8 +105,8 @@ __global__ __launch_bounds__(kAdjBlock) void k_adjoint_rows(AdjArgs A) {
         psi = core_psi(u, A.core, A.ell);
         dpsi_drc = -(u / A.r_core) * core_dpsi(u, A.core, A.ell);
       }
-      double B = 0.0;
-      {
+      double B = 0.0;  // shared-bump product, a factor of the PRODUCT combine only
+      if (A.combine == 0) {
         uint64_t t = mm;
         while (t) {
           const int i = __builtin_ctzll(t);
@@ -121,7 +121,18 @@ __global__ __launch_bounds__(kAdjBlock) void k_adjoint_rows(AdjArgs A) {
         const double* Wb = A.X + (int64_t)b * R + 1;
         const double* Vb = A.V + (int64_t)b * R + 1;
         double t1 = 0.0, t2 = 0.0;
-        for (int p = 0; p < A.P; ++p) {
+        // probes in steps of 8 with a fixed inner count, so that a step's 16
+        // loads are issued together (the compiler will not unroll a loop with
+        // a run-time count around the readlanes); the sums keep their order
+        int p = 0;
+        for (; p + 8 <= A.P; p += 8) {
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            t1 += readlane_f64(wa, p + q) * Vb[p + q];
+            t2 += Wb[p + q] * readlane_f64(va, p + q);
+          }
+        }
+        for (; p < A.P; ++p) {
           t1 += readlane_f64(wa, p) * Vb[p];
           t2 += Wb[p] * readlane_f64(va, p);
         }
@@ -130,7 +141,17 @@ __global__ __launch_bounds__(kAdjBlock) void k_adjoint_rows(AdjArgs A) {
         const uint64_t zb = A.zbits[b];
         const double* Wb = A.X + (int64_t)b * R + 1;
         double t1 = 0.0, t2 = 0.0;
-        for (int p = 0; p < A.P; ++p) {
+        int p = 0;
+        for (; p + 8 <= A.P; p += 8) {
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            const double wap = readlane_f64(wa, p + q);
+            t1 += ((zb >> (p + q)) & 1ull) ? -wap : wap;
+            const double wbp = Wb[p + q];
+            t2 += ((za >> (p + q)) & 1ull) ? -wbp : wbp;
+          }
+        }
+        for (; p < A.P; ++p) {
           const double wap = readlane_f64(wa, p);
           t1 += ((zb >> p) & 1ull) ? -wap : wap;
           const double wbp = Wb[p];
@@ -248,18 +269,37 @@ __global__ __launch_bounds__(256) void k_bump_grad(const double4* __restrict__ x
 }
 
 // Per-block partials of F^T Y (Y: [n][R] row-major), lane = column:
-// part[b][i][r]; grid (nb, chunks), 256 threads.
+// part[b][i][r]; grid (nb, chunks), 256 threads.  The wavefront's row index is
+// made uniform (readfirstlane), so each row of F comes in by scalar loads,
+// and when n1 fills the template width four rows are loaded before their
+// products are added (each accumulator still adds the rows in order); the
+// guarded per-element form serialised one load and wait per F element.
 template <int NI>
 __global__ __launch_bounds__(256) void k_ft_part(const double* __restrict__ F, const double* __restrict__ Y,
                                                  int64_t n, int n1, int R, double* __restrict__ part) {
   __shared__ double sh[4][kWave];
-  const int lane = lane_id(), w = threadIdx.x >> 6;
+  const int lane = lane_id(), w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int rc = blockIdx.y * kWave + lane;
   double acc[NI];
 #pragma unroll
   for (int i = 0; i < NI; ++i) acc[i] = 0.0;
+  const int64_t st = (int64_t)gridDim.x * 4;
+  int64_t a = blockIdx.x * 4 + w;
+  if (rc < R && n1 == NI) {
+    for (; a + 3 * st < n; a += 4 * st) {
+      double y[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) y[u] = Y[(a + u * st) * R + rc];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double* Fa = F + (a + u * st) * NI;
+#pragma unroll
+        for (int i = 0; i < NI; ++i) acc[i] += Fa[i] * y[u];
+      }
+    }
+  }
   if (rc < R)
-    for (int64_t a = blockIdx.x * 4 + w; a < n; a += (int64_t)gridDim.x * 4) {
+    for (; a < n; a += st) {
       const double y = Y[a * R + rc];
       const double* Fa = F + a * n1;
 #pragma unroll

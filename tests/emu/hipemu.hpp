@@ -232,6 +232,14 @@ inline int readlane(int v, int l) {
   return (int)(uint32_t)all[l];
 }
 
+// v_readfirstlane: the value of the lowest live lane, in every lane.
+inline int readfirstlane(int v) {
+  uint64_t m;
+  const uint64_t* all = wave_collect(to_bits((uint32_t)v), &m, kReadlane);
+  if (!m) fail("readfirstlane with no live lane");
+  return (int)(uint32_t)all[__builtin_ctzll(m)];
+}
+
 inline uint32_t mbcnt_lo(uint32_t mask, uint32_t acc) {
   const int l = lane();
   const uint32_t below = l >= 32 ? 0xffffffffu : ((1u << l) - 1u);
@@ -281,6 +289,7 @@ inline d4v mfma_f64_16x16x4(double a, double b, d4v c, int cbsz, int abid, int b
 
 #define __builtin_amdgcn_update_dpp(old, src, ctrl, rm, bm, bc) ::emu::update_dpp((old), (src), (ctrl), (rm), (bm), (bc))
 #define __builtin_amdgcn_readlane(v, l) ::emu::readlane((v), (l))
+#define __builtin_amdgcn_readfirstlane(v) ::emu::readfirstlane((v))
 #define __builtin_amdgcn_mbcnt_lo(m, a) ::emu::mbcnt_lo((m), (a))
 #define __builtin_amdgcn_mbcnt_hi(m, a) ::emu::mbcnt_hi((m), (a))
 #define __builtin_amdgcn_wave_barrier() ::emu::wave_barrier()
