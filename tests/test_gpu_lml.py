@@ -218,7 +218,9 @@ def test_preconditioned_posterior_matches():
     assert np.allclose(v.cpu().numpy(), v0, rtol=1e-7, atol=1e-10)
 
 
-@pytest.mark.parametrize("dim,n1", [(2, 3), (3, 12), (3, 40)])
+# n1 = 16 and 32 fill the F^T Y kernel's template width (its unguarded,
+# four-rows-at-a-time form); the others take its guarded form
+@pytest.mark.parametrize("dim,n1", [(2, 3), (3, 12), (3, 16), (2, 32), (3, 40)])
 def test_factored_operator_matches_oracle_and_assembled(dim, n1):
     gu.need_gpu()
     import paper_2205_09070_amd as sd
